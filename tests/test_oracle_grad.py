@@ -1,0 +1,108 @@
+"""Pins for the oracle gradients: central finite differences of the oracle's
+own forward, for every parameter group, in smooth mode (thresholds off) and
+with thresholds on at points whose discrete decisions stay fixed."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import render as R
+from oracle import grad as G
+from oracle import loss as Lm
+from paper_2603_08997_amd import scenes as S
+
+GROUPS = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+def _scene(seed, n, deg, ls=-1.6):
+    sc = S.tiny_scene(seed, n, log_scale_mean=ls, log_scale_std=0.3)
+    if deg > 0:
+        rng = np.random.default_rng(seed + 100)
+        k = (deg + 1) ** 2
+        sh = np.zeros((n, k, 3), np.float32)
+        sh[:, 0] = sc.sh[:, 0]
+        sh[:, 1:] = rng.normal(0, 0.3, (n, k - 1, 3))
+        sc = S.Scene(sc.means * 0.6, sc.log_scales, sc.quats, sc.opacity_logits, sh, deg)
+    return {k: np.asarray(v, np.float64) for k, v in G.scene_dict(sc).items()}
+
+
+def _forward_value(arrs, deg, cam, rp, ct):
+    with torch.no_grad():
+        out = R.render(arrs["means"], arrs["log_scales"], arrs["quats"], arrs["opacity_logits"],
+                       arrs["sh"], deg, cam, rp)
+    return float((out["rgb"] * torch.tensor(ct)).sum()), out
+
+
+def _decisions(out):
+    return (out["proj"]["ids"].numpy().tobytes(), out["n_blended"].numpy().tobytes(),
+            out["last"].numpy().tobytes(), out["proj"]["radius"].numpy().tobytes())
+
+
+@pytest.mark.parametrize("deg", [0, 3])
+@pytest.mark.parametrize("mode", ["smooth", "thresholds"])
+def test_gradient_matches_central_differences(deg, mode):
+    arrs = _scene(7 + deg, 24, deg)
+    cam = S.tetra_cameras(radius=3.0, width=28, height=22)[1]
+    rp = R.smooth_params() if mode == "smooth" else R.RasterParams()
+    rng = np.random.default_rng(1)
+    ct = rng.normal(0, 1, (3, cam.width * cam.height))
+    _, grads = G.render_vjp(arrs, deg, cam, rp, ct)
+    base_val, base_out = _forward_value(arrs, deg, cam, rp, ct)
+    base_dec = _decisions(base_out)
+    checked = 0
+    for grp in GROUPS:
+        a = arrs[grp]
+        flat_idx = rng.choice(a.size, size=min(a.size, 14), replace=False)
+        for fi in flat_idx:
+            idx = np.unravel_index(fi, a.shape)
+            h = 1e-6 * max(1.0, abs(a[idx]))
+            vals = []
+            ok = True
+            for sgn in (1, -1):
+                b = {k: v.copy() for k, v in arrs.items()}
+                b[grp][idx] += sgn * h
+                val, out = _forward_value(b, deg, cam, rp, ct)
+                if _decisions(out) != base_dec:
+                    ok = False
+                vals.append(val)
+            if not ok:
+                continue
+            fd = (vals[0] - vals[1]) / (2 * h)
+            an = grads[grp][idx]
+            scale = max(1e-6, np.abs(grads[grp]).max())
+            assert abs(fd - an) <= 2e-6 * scale + 1e-6 * abs(an), (grp, idx, fd, an)
+            checked += 1
+    assert checked >= 40
+
+
+def test_loss_gradient_end_to_end_matches_central_differences():
+    arrs = _scene(3, 20, 0)
+    cam = S.tetra_cameras(radius=3.0, width=24, height=24)[0]
+    rp = R.RasterParams()
+    tgt_sc = _scene(4, 20, 0)
+    with torch.no_grad():
+        tgt = R.render(tgt_sc["means"], tgt_sc["log_scales"], tgt_sc["quats"], tgt_sc["opacity_logits"],
+                       tgt_sc["sh"], 0, cam, rp)["rgb"].reshape(3, 24, 24)
+    L, img, dimg, grads, out = G.loss_and_grads(arrs, 0, cam, rp, tgt)
+    dec = _decisions(out)
+    rng = np.random.default_rng(2)
+    checked = 0
+    for grp in GROUPS:
+        a = arrs[grp]
+        for fi in rng.choice(a.size, size=min(a.size, 8), replace=False):
+            idx = np.unravel_index(fi, a.shape)
+            h = 1e-6 * max(1.0, abs(a[idx]))
+            vals, same = [], True
+            for sgn in (1, -1):
+                b = {k: v.copy() for k, v in arrs.items()}
+                b[grp][idx] += sgn * h
+                with torch.no_grad():
+                    o = R.render(b["means"], b["log_scales"], b["quats"], b["opacity_logits"], b["sh"], 0, cam, rp)
+                same &= _decisions(o) == dec
+                vals.append(Lm.photometric_loss(o["rgb"].reshape(3, 24, 24), tgt).item())
+            if not same:
+                continue
+            fd = (vals[0] - vals[1]) / (2 * h)
+            an = grads[grp][idx]
+            assert abs(fd - an) <= 1e-6 * max(np.abs(grads[grp]).max(), 1e-8) + 1e-9, (grp, idx, fd, an)
+            checked += 1
+    assert checked >= 25
