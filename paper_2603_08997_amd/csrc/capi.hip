@@ -1,0 +1,549 @@
+// The C ABI declared in include/skipgs.h: host-side validation, workspace
+// layout and the order of launches. Nothing here allocates device memory.
+#include <cmath>
+#include <cstdarg>
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "sgs_internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+sgs_status fail(sgs_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+sgs_status fail(sgs_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+sgs_status hip_fail(hipError_t e, const char* what) {
+    return fail(SGS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define SGS_HIP(call, what)                              \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+sgs_status check_raster(const sgs_raster_params* rp) {
+    if (!rp) return fail(SGS_ERR_INVALID_ARG, "raster params are null");
+    const bool ok = (rp->tile_w == 16 && rp->tile_h == 16) || (rp->tile_w == 8 && rp->tile_h == 8) ||
+                    (rp->tile_w == 32 && rp->tile_h == 8);
+    if (!ok) return fail(SGS_ERR_UNSUPPORTED, "tile shape %dx%d not in {16x16, 8x8, 32x8}",
+                         rp->tile_w, rp->tile_h);
+    if (!(rp->alpha_max > 0.f && rp->alpha_max <= 1.f) || !(rp->alpha_min >= 0.f) ||
+        !(rp->t_min >= 0.f && rp->t_min < 1.f) || !(rp->near_z >= 0.f) || !(rp->dilation >= 0.f) ||
+        !(rp->jac_clamp >= 0.f) || !std::isfinite(rp->bg[0]) || !std::isfinite(rp->bg[1]) ||
+        !std::isfinite(rp->bg[2]))
+        return fail(SGS_ERR_INVALID_ARG, "raster params out of range");
+    return SGS_OK;
+}
+
+struct Prepared {
+    sgs::Views views;
+    sgs::RasterDev rd;
+    sgs::Layout L;
+};
+
+sgs_status prepare(const sgs_raster_params* rp, int64_t n, const sgs_camera* cams, int32_t n_views,
+                   int64_t capacity, Prepared* P) {
+    sgs_status st = check_raster(rp);
+    if (st != SGS_OK) return st;
+    if (n < 0) return fail(SGS_ERR_INVALID_ARG, "n < 0");
+    if (!cams) return fail(SGS_ERR_INVALID_ARG, "cameras are null");
+    if (n_views < 1 || n_views > SGS_MAX_VIEWS)
+        return fail(SGS_ERR_INVALID_ARG, "n_views %d not in [1, %d]", n_views, SGS_MAX_VIEWS);
+    if (capacity < 0 || capacity > (int64_t)0x7fffffff)
+        return fail(SGS_ERR_INVALID_ARG, "pair_capacity %lld not in [0, 2^31)", (long long)capacity);
+    if (n * (int64_t)n_views > (int64_t)0x7fffffff)
+        return fail(SGS_ERR_INVALID_ARG, "n * n_views exceeds 2^31");
+    const char* err = nullptr;
+    if (!sgs::make_views(cams, n_views, rp, &P->views, &err)) return fail(SGS_ERR_INVALID_ARG, "%s", err);
+    P->rd = sgs::make_raster(rp);
+    sgs::make_layout(P->views, n, capacity, &P->L);
+    return SGS_OK;
+}
+
+sgs_status check_ws(const Prepared& P, const void* ws, size_t bytes) {
+    if (!ws) return fail(SGS_ERR_INVALID_ARG, "workspace is null");
+    if (!aligned(ws, 256)) return fail(SGS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+    if (bytes < P.L.total)
+        return fail(SGS_ERR_CAPACITY, "workspace has %zu bytes, needs %zu", bytes, P.L.total);
+    return SGS_OK;
+}
+
+sgs_status check_gaussians(const sgs_gaussians* g) {
+    if (!g) return fail(SGS_ERR_INVALID_ARG, "gaussians are null");
+    if (g->n < 0) return fail(SGS_ERR_INVALID_ARG, "n < 0");
+    if (g->sh_degree < 0 || g->sh_degree > 3)
+        return fail(SGS_ERR_INVALID_ARG, "sh_degree %d not in [0, 3]", g->sh_degree);
+    if (g->stride < g->n || g->stride % 64 != 0 || g->stride <= 0)
+        return fail(SGS_ERR_INVALID_ARG, "stride %lld must be >= n, > 0 and a multiple of 64",
+                    (long long)g->stride);
+    if (!g->data) return fail(SGS_ERR_INVALID_ARG, "parameter data is null");
+    if (!aligned(g->data, 16)) return fail(SGS_ERR_INVALID_ARG, "parameter data not 16-byte aligned");
+    return SGS_OK;
+}
+
+}  // namespace
+
+namespace sgs {
+
+bool make_views(const sgs_camera* cams, int n_views, const sgs_raster_params* rp, Views* out,
+                const char** err) {
+    std::memset(out, 0, sizeof(*out));
+    out->n = n_views;
+    int64_t tiles = 0, pixels = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const sgs_camera& c = cams[v];
+        if (c.width <= 0 || c.height <= 0 || c.width > 32768 || c.height > 32768) {
+            *err = "camera size not in [1, 32768]";
+            return false;
+        }
+        bool finite = std::isfinite(c.fx) && std::isfinite(c.fy) && std::isfinite(c.cx) &&
+                      std::isfinite(c.cy) && c.fx > 0.f && c.fy > 0.f;
+        for (int k = 0; k < 9; ++k) finite = finite && std::isfinite(c.R[k]);
+        for (int k = 0; k < 3; ++k) finite = finite && std::isfinite(c.t[k]);
+        if (!finite) {
+            *err = "camera has non-finite or non-positive intrinsics";
+            return false;
+        }
+        ViewDev& d = out->v[v];
+        std::memcpy(d.R, c.R, sizeof(d.R));
+        std::memcpy(d.t, c.t, sizeof(d.t));
+        d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+        for (int k = 0; k < 3; ++k) {
+            const double ck = -((double)c.R[k] * c.t[0] + (double)c.R[3 + k] * c.t[1] +
+                                (double)c.R[6 + k] * c.t[2]);
+            d.C[k] = (float)ck;
+        }
+        if (rp->jac_clamp > 0.f) {
+            d.lim_x = (float)((double)rp->jac_clamp * (c.width / 2.0) / (double)c.fx);
+            d.lim_y = (float)((double)rp->jac_clamp * (c.height / 2.0) / (double)c.fy);
+        } else {
+            d.lim_x = d.lim_y = INFINITY;
+        }
+        d.width = c.width;
+        d.height = c.height;
+        d.tiles_x = (c.width + rp->tile_w - 1) / rp->tile_w;
+        d.tiles_y = (c.height + rp->tile_h - 1) / rp->tile_h;
+        d.tile_offset = (int32_t)tiles;
+        d.px_offset = pixels;
+        tiles += (int64_t)d.tiles_x * d.tiles_y;
+        pixels += (int64_t)c.width * c.height;
+    }
+    if (tiles > (1 << 24)) {
+        *err = "more than 2^24 tiles in one batch";
+        return false;
+    }
+    out->total_tiles = (int32_t)tiles;
+    out->total_pixels = pixels;
+    return true;
+}
+
+RasterDev make_raster(const sgs_raster_params* rp) {
+    RasterDev r;
+    r.tile_w = rp->tile_w;
+    r.tile_h = rp->tile_h;
+    for (int k = 0; k < 3; ++k) r.bg[k] = rp->bg[k];
+    r.near_z = rp->near_z;
+    r.dilation = rp->dilation;
+    r.alpha_min = rp->alpha_min;
+    r.alpha_max = rp->alpha_max;
+    r.t_min = rp->t_min;
+    return r;
+}
+
+void make_layout(const Views& views, int64_t n, int64_t capacity, Layout* L) {
+    L->entries = n * views.n;
+    L->total_tiles = views.total_tiles;
+    L->total_pixels = views.total_pixels;
+    L->capacity = capacity;
+    L->scan_blocks = (L->entries + 2047) / 2048;
+    L->sort_blocks = radix_blocks(std::max(L->entries, capacity));
+    int bits = 0;
+    while ((int64_t(1) << bits) < L->total_tiles) ++bits;
+    L->tile_bits = bits;
+    L->tile_passes = radix_passes(bits);
+    L->tile_result = L->tile_passes & 1;
+    const int64_t E = L->entries;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    L->counters = take(sizeof(uint32_t) * kNumCounters);
+    L->records = take(sizeof(float) * kRecordFloats * (size_t)E);
+    L->accum = take(sizeof(float) * kAccumFloats * (size_t)E);
+    L->tiles = take(sizeof(uint32_t) * (size_t)E);
+    L->dkey[0] = take(sizeof(uint32_t) * (size_t)E);
+    L->dkey[1] = take(sizeof(uint32_t) * (size_t)E);
+    L->dval[0] = take(sizeof(uint32_t) * (size_t)E);
+    L->dval[1] = take(sizeof(uint32_t) * (size_t)E);
+    L->offsets = take(sizeof(uint32_t) * (size_t)E);
+    L->scan_sums = take(sizeof(uint32_t) * (size_t)(L->scan_blocks + 1));
+    L->pair_tile[0] = take(sizeof(uint32_t) * (size_t)capacity);
+    L->pair_tile[1] = take(sizeof(uint32_t) * (size_t)capacity);
+    L->pair_entry[0] = take(sizeof(uint32_t) * (size_t)capacity);
+    L->pair_entry[1] = take(sizeof(uint32_t) * (size_t)capacity);
+    L->sort_hist = take(sizeof(uint32_t) * 256 * (size_t)L->sort_blocks);
+    L->sort_totals = take(sizeof(uint32_t) * 256);
+    L->ranges = take(sizeof(uint32_t) * 2 * (size_t)L->total_tiles);
+    L->t_final = take(sizeof(float) * (size_t)L->total_pixels);
+    L->n_last = take(sizeof(uint32_t) * (size_t)L->total_pixels);
+    L->total = off;
+}
+
+}  // namespace sgs
+
+using sgs::Layout;
+
+extern "C" {
+
+const char* sgs_last_error(void) { return g_err.c_str(); }
+
+int32_t sgs_version(void) { return 100; }
+
+void sgs_default_raster_params(sgs_raster_params* rp) {
+    if (!rp) return;
+    rp->tile_w = 16;
+    rp->tile_h = 16;
+    rp->bg[0] = rp->bg[1] = rp->bg[2] = 0.f;
+    rp->near_z = 0.2f;
+    rp->dilation = 0.3f;
+    rp->alpha_min = 1.f / 255.f;
+    rp->alpha_max = 0.99f;
+    rp->t_min = 1e-4f;
+    rp->jac_clamp = 1.3f;
+}
+
+sgs_status sgs_forward_workspace_size(const sgs_raster_params* rp, int64_t n,
+                                      const sgs_camera* cams, int32_t n_views,
+                                      int64_t pair_capacity, size_t* bytes_out) {
+    if (!bytes_out) return fail(SGS_ERR_INVALID_ARG, "bytes_out is null");
+    Prepared P;
+    sgs_status st = prepare(rp, n, cams, n_views, pair_capacity, &P);
+    if (st != SGS_OK) return st;
+    *bytes_out = P.L.total;
+    return SGS_OK;
+}
+
+sgs_status sgs_get_workspace_layout(const sgs_raster_params* rp, int64_t n, const sgs_camera* cams,
+                                    int32_t n_views, int64_t pair_capacity,
+                                    sgs_workspace_layout* out) {
+    if (!out) return fail(SGS_ERR_INVALID_ARG, "out is null");
+    Prepared P;
+    sgs_status st = prepare(rp, n, cams, n_views, pair_capacity, &P);
+    if (st != SGS_OK) return st;
+    const Layout& L = P.L;
+    out->records = L.records;
+    out->tiles = L.tiles;
+    out->pair_tile = L.pair_tile[L.tile_result];
+    out->pair_entry = L.pair_entry[L.tile_result];
+    out->ranges = L.ranges;
+    out->t_final = L.t_final;
+    out->n_last = L.n_last;
+    out->accum = L.accum;
+    out->counters = L.counters;
+    out->entries = L.entries;
+    out->total_tiles = L.total_tiles;
+    out->total_pixels = L.total_pixels;
+    return SGS_OK;
+}
+
+sgs_status sgs_project(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_views,
+                       const sgs_raster_params* rp, void* workspace, size_t workspace_bytes,
+                       int64_t pair_capacity, void* stream) {
+    sgs_status st = check_gaussians(g);
+    if (st != SGS_OK) return st;
+    Prepared P;
+    if ((st = prepare(rp, g->n, cams, n_views, pair_capacity, &P)) != SGS_OK) return st;
+    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
+    char* ws = static_cast<char*>(workspace);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SGS_HIP(sgs::launch_project(g->data, g->n, g->stride, g->sh_degree, P.views, P.rd,
+                                reinterpret_cast<float*>(ws + P.L.records),
+                                reinterpret_cast<uint32_t*>(ws + P.L.tiles),
+                                reinterpret_cast<uint32_t*>(ws + P.L.counters), s),
+            "project");
+    return SGS_OK;
+}
+
+sgs_status sgs_load_records(const sgs_camera* cams, int32_t n_views, int64_t n,
+                            const sgs_raster_params* rp, void* workspace, size_t workspace_bytes,
+                            int64_t pair_capacity, const float* u, const float* v,
+                            const float* depth, const int32_t* radius, const float* conic,
+                            const float* opacity, const float* rgb, void* stream) {
+    Prepared P;
+    sgs_status st = prepare(rp, n, cams, n_views, pair_capacity, &P);
+    if (st != SGS_OK) return st;
+    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
+    if (P.L.entries > 0 && (!u || !v || !depth || !radius || !conic || !opacity || !rgb))
+        return fail(SGS_ERR_INVALID_ARG, "record arrays are null");
+    char* ws = static_cast<char*>(workspace);
+    SGS_HIP(sgs::launch_load_records(P.L.entries, u, v, depth, radius, conic, opacity, rgb, n,
+                                     P.views, P.rd, reinterpret_cast<float*>(ws + P.L.records),
+                                     reinterpret_cast<uint32_t*>(ws + P.L.tiles),
+                                     static_cast<hipStream_t>(stream)),
+            "load_records");
+    return SGS_OK;
+}
+
+sgs_status sgs_bin(const sgs_camera* cams, int32_t n_views, int64_t n, const sgs_raster_params* rp,
+                   void* workspace, size_t workspace_bytes, int64_t pair_capacity, void* stream) {
+    Prepared P;
+    sgs_status st = prepare(rp, n, cams, n_views, pair_capacity, &P);
+    if (st != SGS_OK) return st;
+    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
+    SGS_HIP(sgs::launch_bin(P.views, P.rd, n, P.L, static_cast<char*>(workspace),
+                            static_cast<hipStream_t>(stream)),
+            "bin");
+    return SGS_OK;
+}
+
+sgs_status sgs_rasterize(const sgs_camera* cams, int32_t n_views, int64_t n,
+                         const sgs_raster_params* rp, void* workspace, size_t workspace_bytes,
+                         int64_t pair_capacity, float* out_rgb, void* stream) {
+    Prepared P;
+    sgs_status st = prepare(rp, n, cams, n_views, pair_capacity, &P);
+    if (st != SGS_OK) return st;
+    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
+    if (!out_rgb) return fail(SGS_ERR_INVALID_ARG, "out_rgb is null");
+    SGS_HIP(sgs::launch_rasterize(P.views, P.rd, P.L, static_cast<char*>(workspace), out_rgb,
+                                  static_cast<hipStream_t>(stream)),
+            "rasterize");
+    return SGS_OK;
+}
+
+sgs_status sgs_render_forward(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_views,
+                              const sgs_raster_params* rp, void* workspace, size_t workspace_bytes,
+                              int64_t pair_capacity, float* out_rgb, void* stream) {
+    sgs_status st = check_gaussians(g);
+    if (st != SGS_OK) return st;
+    Prepared P;
+    if ((st = prepare(rp, g->n, cams, n_views, pair_capacity, &P)) != SGS_OK) return st;
+    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
+    if (!out_rgb) return fail(SGS_ERR_INVALID_ARG, "out_rgb is null");
+    char* ws = static_cast<char*>(workspace);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SGS_HIP(sgs::launch_project(g->data, g->n, g->stride, g->sh_degree, P.views, P.rd,
+                                reinterpret_cast<float*>(ws + P.L.records),
+                                reinterpret_cast<uint32_t*>(ws + P.L.tiles),
+                                reinterpret_cast<uint32_t*>(ws + P.L.counters), s),
+            "project");
+    SGS_HIP(sgs::launch_bin(P.views, P.rd, g->n, P.L, ws, s), "bin");
+    SGS_HIP(sgs::launch_rasterize(P.views, P.rd, P.L, ws, out_rgb, s), "rasterize");
+    return SGS_OK;
+}
+
+sgs_status sgs_rasterize_backward(const sgs_camera* cams, int32_t n_views, int64_t n,
+                                  const sgs_raster_params* rp, void* workspace,
+                                  size_t workspace_bytes, int64_t pair_capacity,
+                                  const float* dl_drgb, const int32_t* d_gate, void* stream) {
+    Prepared P;
+    sgs_status st = prepare(rp, n, cams, n_views, pair_capacity, &P);
+    if (st != SGS_OK) return st;
+    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
+    if (!dl_drgb) return fail(SGS_ERR_INVALID_ARG, "dl_drgb is null");
+    SGS_HIP(sgs::launch_rasterize_backward(P.views, P.rd, P.L, static_cast<char*>(workspace),
+                                           dl_drgb, d_gate, static_cast<hipStream_t>(stream)),
+            "rasterize_backward");
+    return SGS_OK;
+}
+
+sgs_status sgs_project_backward(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_views,
+                                const sgs_raster_params* rp, void* workspace,
+                                size_t workspace_bytes, int64_t pair_capacity,
+                                const int32_t* d_gate, float* grads, void* stream) {
+    sgs_status st = check_gaussians(g);
+    if (st != SGS_OK) return st;
+    Prepared P;
+    if ((st = prepare(rp, g->n, cams, n_views, pair_capacity, &P)) != SGS_OK) return st;
+    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
+    if (!grads || !aligned(grads, 16)) return fail(SGS_ERR_INVALID_ARG, "grads null or unaligned");
+    SGS_HIP(sgs::launch_project_backward(g->data, g->n, g->stride, g->sh_degree, P.views, P.rd, P.L,
+                                         static_cast<char*>(workspace), d_gate, grads,
+                                         static_cast<hipStream_t>(stream)),
+            "project_backward");
+    return SGS_OK;
+}
+
+sgs_status sgs_render_backward(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_views,
+                               const sgs_raster_params* rp, void* workspace,
+                               size_t workspace_bytes, int64_t pair_capacity,
+                               const float* dl_drgb, const int32_t* d_gate, float* grads,
+                               void* stream) {
+    sgs_status st = check_gaussians(g);
+    if (st != SGS_OK) return st;
+    Prepared P;
+    if ((st = prepare(rp, g->n, cams, n_views, pair_capacity, &P)) != SGS_OK) return st;
+    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
+    if (!dl_drgb) return fail(SGS_ERR_INVALID_ARG, "dl_drgb is null");
+    if (!grads || !aligned(grads, 16)) return fail(SGS_ERR_INVALID_ARG, "grads null or unaligned");
+    char* ws = static_cast<char*>(workspace);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SGS_HIP(sgs::launch_rasterize_backward(P.views, P.rd, P.L, ws, dl_drgb, d_gate, s),
+            "rasterize_backward");
+    SGS_HIP(sgs::launch_project_backward(g->data, g->n, g->stride, g->sh_degree, P.views, P.rd, P.L,
+                                         ws, d_gate, grads, s),
+            "project_backward");
+    return SGS_OK;
+}
+
+sgs_status sgs_read_status(const void* workspace, uint32_t* flags_out, int64_t* visible_out,
+                           int64_t* pairs_out, void* stream) {
+    if (!workspace) return fail(SGS_ERR_INVALID_ARG, "workspace is null");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SGS_HIP(hipStreamSynchronize(s), "stream sync");
+    uint32_t c[sgs::kNumCounters];
+    // the counters region sits at offset 0 of every forward workspace
+    SGS_HIP(hipMemcpy(c, workspace, sizeof(c), hipMemcpyDeviceToHost), "read counters");
+    if (flags_out) *flags_out = c[sgs::kStatus];
+    if (visible_out) *visible_out = c[sgs::kVisible];
+    if (pairs_out) *pairs_out = c[sgs::kPairs];
+    return SGS_OK;
+}
+
+sgs_status sgs_clear_status(void* workspace, void* stream) {
+    if (!workspace) return fail(SGS_ERR_INVALID_ARG, "workspace is null");
+    SGS_HIP(hipMemsetAsync(workspace, 0, sizeof(uint32_t), static_cast<hipStream_t>(stream)),
+            "clear status");
+    return SGS_OK;
+}
+
+sgs_status sgs_loss_workspace_size(int32_t width, int32_t height, size_t* bytes_out) {
+    if (!bytes_out) return fail(SGS_ERR_INVALID_ARG, "bytes_out is null");
+    if (width <= 0 || height <= 0 || width > 32768 || height > 32768)
+        return fail(SGS_ERR_INVALID_ARG, "image size not in [1, 32768]");
+    *bytes_out = sgs::loss_workspace_bytes(width, height);
+    return SGS_OK;
+}
+
+sgs_status sgs_photometric_loss(const float* rgb, const float* target, int32_t width,
+                                int32_t height, float lambda, void* workspace,
+                                size_t workspace_bytes, float* d_loss, void* stream) {
+    if (!rgb || !target || !d_loss || !workspace)
+        return fail(SGS_ERR_INVALID_ARG, "null pointer argument");
+    if (width <= 0 || height <= 0 || width > 32768 || height > 32768)
+        return fail(SGS_ERR_INVALID_ARG, "image size not in [1, 32768]");
+    if (!(lambda >= 0.f && lambda <= 1.f)) return fail(SGS_ERR_INVALID_ARG, "lambda not in [0, 1]");
+    if (workspace_bytes < sgs::loss_workspace_bytes(width, height))
+        return fail(SGS_ERR_CAPACITY, "loss workspace too small");
+    SGS_HIP(sgs::launch_loss_forward(rgb, target, width, height, lambda,
+                                     static_cast<char*>(workspace), d_loss,
+                                     static_cast<hipStream_t>(stream)),
+            "loss");
+    return SGS_OK;
+}
+
+sgs_status sgs_photometric_loss_backward(const float* rgb, const float* target, int32_t width,
+                                         int32_t height, float lambda, void* workspace,
+                                         size_t workspace_bytes, const int32_t* d_gate,
+                                         float* dl_drgb, void* stream) {
+    if (!rgb || !target || !dl_drgb || !workspace)
+        return fail(SGS_ERR_INVALID_ARG, "null pointer argument");
+    if (width <= 0 || height <= 0 || width > 32768 || height > 32768)
+        return fail(SGS_ERR_INVALID_ARG, "image size not in [1, 32768]");
+    if (!(lambda >= 0.f && lambda <= 1.f)) return fail(SGS_ERR_INVALID_ARG, "lambda not in [0, 1]");
+    if (workspace_bytes < sgs::loss_workspace_bytes(width, height))
+        return fail(SGS_ERR_CAPACITY, "loss workspace too small");
+    SGS_HIP(sgs::launch_loss_backward(rgb, target, width, height, lambda,
+                                      static_cast<char*>(workspace), d_gate, dl_drgb,
+                                      static_cast<hipStream_t>(stream)),
+            "loss backward");
+    return SGS_OK;
+}
+
+static sgs_status check_gate(const sgs_gate_params* p) {
+    if (!p) return fail(SGS_ERR_INVALID_ARG, "gate params are null");
+    if (p->n_views < 1) return fail(SGS_ERR_INVALID_ARG, "n_views < 1");
+    if (!(p->beta > 0.0 && p->beta < 1.0)) return fail(SGS_ERR_INVALID_ARG, "beta not in (0, 1)");
+    if (!(p->eps >= 0.0) || !std::isfinite(p->delta) || !(p->rho_lo >= 0.0 && p->rho_lo <= 1.0))
+        return fail(SGS_ERR_INVALID_ARG, "eps, delta or rho_lo out of range");
+    if (p->warmup < 0 || p->window < 0) return fail(SGS_ERR_INVALID_ARG, "warmup/window < 0");
+    return SGS_OK;
+}
+
+sgs_status sgs_gate_state_size(const sgs_gate_params* p, size_t* bytes_out) {
+    sgs_status st = check_gate(p);
+    if (st != SGS_OK) return st;
+    if (!bytes_out) return fail(SGS_ERR_INVALID_ARG, "bytes_out is null");
+    *bytes_out = sgs::gate_state_bytes(p);
+    return SGS_OK;
+}
+
+sgs_status sgs_gate_init(const sgs_gate_params* p, void* d_state, void* stream) {
+    sgs_status st = check_gate(p);
+    if (st != SGS_OK) return st;
+    if (!d_state || !aligned(d_state, 8)) return fail(SGS_ERR_INVALID_ARG, "state null or unaligned");
+    SGS_HIP(sgs::launch_gate_init(p, d_state, static_cast<hipStream_t>(stream)), "gate init");
+    return SGS_OK;
+}
+
+sgs_status sgs_gate_update(const sgs_gate_params* p, void* d_state, int32_t view,
+                           const float* d_loss, int32_t* d_gate, void* stream) {
+    sgs_status st = check_gate(p);
+    if (st != SGS_OK) return st;
+    if (!d_state || !d_loss || !d_gate) return fail(SGS_ERR_INVALID_ARG, "null pointer argument");
+    if (view < 0 || view >= p->n_views)
+        return fail(SGS_ERR_INVALID_ARG, "view %d not in [0, %d)", view, p->n_views);
+    SGS_HIP(sgs::launch_gate_update(p, d_state, view, d_loss, d_gate, static_cast<hipStream_t>(stream)),
+            "gate update");
+    return SGS_OK;
+}
+
+sgs_status sgs_gate_read(const sgs_gate_params* p, const void* d_state, sgs_gate_snapshot* out,
+                         double* ema_out, uint8_t* has_ema_out, void* stream) {
+    sgs_status st = check_gate(p);
+    if (st != SGS_OK) return st;
+    if (!d_state || !out) return fail(SGS_ERR_INVALID_ARG, "null pointer argument");
+    SGS_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "stream sync");
+    const char* base = static_cast<const char*>(d_state);
+    SGS_HIP(hipMemcpy(out, base, sizeof(*out), hipMemcpyDeviceToHost), "read gate");
+    if (ema_out)
+        SGS_HIP(hipMemcpy(ema_out, base + sizeof(sgs_gate_snapshot), sizeof(double) * p->n_views,
+                          hipMemcpyDeviceToHost),
+                "read ema");
+    if (has_ema_out)
+        SGS_HIP(hipMemcpy(has_ema_out,
+                          base + sizeof(sgs_gate_snapshot) + sizeof(double) * p->n_views,
+                          p->n_views, hipMemcpyDeviceToHost),
+                "read has_ema");
+    return SGS_OK;
+}
+
+sgs_status sgs_adam_step(const sgs_adam_params* p, float* params, float* grads, float* m,
+                         float* v, int64_t n, int64_t stride, int32_t n_planes, int32_t* d_step,
+                         const int32_t* d_gate, void* stream) {
+    if (!p || !params || !grads || !m || !v || !d_step)
+        return fail(SGS_ERR_INVALID_ARG, "null pointer argument");
+    if (n < 0 || stride < n || stride % 64 != 0 || stride <= 0)
+        return fail(SGS_ERR_INVALID_ARG, "stride must be >= n, > 0 and a multiple of 64");
+    if (n_planes < 1 || n_planes > SGS_MAX_PLANES)
+        return fail(SGS_ERR_INVALID_ARG, "n_planes %d not in [1, %d]", n_planes, SGS_MAX_PLANES);
+    if (!aligned(params, 16) || !aligned(grads, 16) || !aligned(m, 16) || !aligned(v, 16))
+        return fail(SGS_ERR_INVALID_ARG, "arrays must be 16-byte aligned");
+    if (!(p->beta1 >= 0.f && p->beta1 < 1.f) || !(p->beta2 >= 0.f && p->beta2 < 1.f) ||
+        !(p->eps >= 0.f))
+        return fail(SGS_ERR_INVALID_ARG, "Adam constants out of range");
+    SGS_HIP(sgs::launch_adam(p, params, grads, m, v, n, stride, n_planes, d_step, d_gate,
+                             static_cast<hipStream_t>(stream)),
+            "adam");
+    return SGS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// Device helpers for gfx950 (wave64): lane masks, wave-level scans and
+// reductions on DPP, block scans.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sgs {
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const int l = __lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int popc64(uint64_t m) { return __popcll(m); }
+
+// Sum over the 64 lanes of a wave, result valid in lane 63. DPP steps:
+// xor 1, xor 2 (quad permutes), rotate 4 and 8 within rows of 16, then the
+// row broadcasts of lane 15 and lane 31 (gfx9 wave64).
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xb1, 0xf, 0xf, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4e, 0xf, 0xf, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xf, 0xf, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xa, 0xf, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xc, 0xf, false));
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_to_lane63(v)), 63));
+}
+
+// Inclusive prefix sum over the lanes of a wave (Hillis-Steele on shuffles).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int l = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t o = __shfl_up(v, d, 64);
+        if (l >= d) v += o;
+    }
+    return v;
+}
+
+// Exclusive scan over the threads of a block of NT threads (NT multiple of
+// 64, <= 1024). Returns the exclusive prefix; *total gets the block sum.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* smem /* >= NT/64 + 1 */,
+                                                    uint32_t* total) {
+    constexpr int NW = NT / 64;
+    const int w = threadIdx.x / 64;
+    const int l = __lane_id();
+    uint32_t inc = wave_incl_scan(v);
+    if (l == 63) smem[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        uint32_t s = (l < NW) ? smem[l] : 0u;
+        uint32_t si = wave_incl_scan(s);
+        if (l < NW) smem[l] = si - s;
+        if (l == NW - 1) smem[NW] = si;
+    }
+    __syncthreads();
+    uint32_t r = smem[w] + inc - v;
+    *total = smem[NW];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ int floordiv(int a, int b) {
+    const int q = a / b;
+    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+
+// Tile rectangle [x0, x1) x [y0, y1) of the square |x - u| <= r, |y - v| <= r.
+// With r and the tile size integers, floor((u - r)/tw) = floor((floor(u) - r)/tw),
+// so the rectangle is exact in integer arithmetic on floor(u) (|u| < 2^24).
+__device__ __forceinline__ void tile_rect(float u, float v, int r, int tw, int th, int tx_n,
+                                          int ty_n, int* x0, int* x1, int* y0, int* y1) {
+    const int fu = (int)floorf(u), fv = (int)floorf(v);
+    *x0 = min(max(floordiv(fu - r, tw), 0), tx_n);
+    *x1 = min(max(floordiv(fu + r, tw) + 1, 0), tx_n);
+    *y0 = min(max(floordiv(fv - r, th), 0), ty_n);
+    *y1 = min(max(floordiv(fv + r, th) + 1, 0), ty_n);
+}
+
+__device__ __forceinline__ bool gate_closed(const int32_t* gate) {
+    return gate != nullptr && *gate == 0;
+}
+
+}  // namespace sgs

@@ -1,0 +1,111 @@
+// Internal declarations of the gfx950 hot path: device-side view table,
+// workspace layout, launch wrappers. Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/skipgs.h"
+
+namespace sgs {
+
+constexpr int kWave = 64;
+constexpr uint32_t kMaxExtent = 1u << 24;   // |u|, |v|, radius beyond this: degenerate, culled
+constexpr int kRecordFloats = 12;           // u v a b | c o radius depth | r g b tiles
+constexpr int kAccumFloats = 12;            // du dv da db | dc do dr dg | db - - -
+
+// Per-view constants, passed by value to every kernel of a multi-view batch.
+struct ViewDev {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    float C[3];          // camera centre in world coordinates, -R^T t
+    float lim_x, lim_y;  // clamp of tx/tz, ty/tz in the EWA Jacobian (inf: off)
+    int32_t width, height, tiles_x, tiles_y;
+    int32_t tile_offset; // first global tile index of the view
+    int32_t pad;
+    int64_t px_offset;   // first global pixel index of the view
+};
+
+struct Views {
+    ViewDev v[SGS_MAX_VIEWS];
+    int32_t n;
+    int32_t total_tiles;
+    int64_t total_pixels;
+};
+
+struct RasterDev {
+    int32_t tile_w, tile_h;
+    float bg[3];
+    float near_z, dilation, alpha_min, alpha_max, t_min;
+};
+
+// Counters region of the workspace (uint32 words).
+enum Counter : int {
+    kStatus = 0,        // SGS_STATUS_* bits
+    kVisible = 1,       // visible entries of the last forward
+    kPairs = 2,         // (tile, entry) pairs needed by the last forward
+    kPairsWritten = 3,  // min(pairs, capacity)
+    kNumCounters = 16
+};
+
+struct Layout {
+    int64_t entries, total_tiles, total_pixels, capacity;
+    int64_t scan_blocks, sort_blocks;
+    int tile_bits, tile_passes, tile_result;  // result buffer index (0/1) of the tile sort
+    size_t records, tiles, dkey[2], dval[2], offsets, scan_sums, pair_tile[2], pair_entry[2],
+        sort_hist, sort_totals, ranges, t_final, n_last, accum, counters, total;
+};
+
+bool make_views(const sgs_camera* cams, int n_views, const sgs_raster_params* rp, Views* out,
+                const char** err);
+void make_layout(const Views& views, int64_t n, int64_t capacity, Layout* L);
+RasterDev make_raster(const sgs_raster_params* rp);
+
+// ---- launch wrappers (all asynchronous on `s`) ----
+hipError_t launch_project(const float* planes, int64_t n, int64_t stride, int sh_degree,
+                          const Views& views, const RasterDev& rp, float* records,
+                          uint32_t* tiles, uint32_t* counters, hipStream_t s);
+hipError_t launch_load_records(int64_t entries, const float* u, const float* v,
+                               const float* depth, const int32_t* radius, const float* conic,
+                               const float* opacity, const float* rgb, int64_t n,
+                               const Views& views, const RasterDev& rp, float* records,
+                               uint32_t* tiles, hipStream_t s);
+hipError_t launch_bin(const Views& views, const RasterDev& rp, int64_t n, const Layout& L,
+                      char* ws, hipStream_t s);
+hipError_t launch_rasterize(const Views& views, const RasterDev& rp, const Layout& L, char* ws,
+                            float* out_rgb, hipStream_t s);
+hipError_t launch_rasterize_backward(const Views& views, const RasterDev& rp, const Layout& L,
+                                     char* ws, const float* dl_drgb, const int32_t* gate,
+                                     hipStream_t s);
+hipError_t launch_project_backward(const float* planes, int64_t n, int64_t stride,
+                                   int sh_degree, const Views& views, const RasterDev& rp,
+                                   const Layout& L, char* ws, const int32_t* gate, float* grads,
+                                   hipStream_t s);
+
+// Stable LSD radix sort of (key, value) uint32 pairs over bits [0, bits).
+// n is read on the device from *n_dev; n_max bounds it for the grid size.
+// Returns the index (0/1) of the buffer holding the result.
+int radix_passes(int bits);
+hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int64_t n_max,
+                      int bits, uint32_t* hist, uint32_t* totals, hipStream_t s, int* result);
+int64_t radix_blocks(int64_t n_max);
+
+// Loss / gate / Adam
+hipError_t launch_loss_forward(const float* rgb, const float* target, int w, int h, float lambda,
+                               char* ws, float* d_loss, hipStream_t s);
+hipError_t launch_loss_backward(const float* rgb, const float* target, int w, int h, float lambda,
+                                char* ws, const int32_t* gate, float* dl, hipStream_t s);
+size_t loss_workspace_bytes(int w, int h);
+
+hipError_t launch_gate_init(const sgs_gate_params* p, void* state, hipStream_t s);
+hipError_t launch_gate_update(const sgs_gate_params* p, void* state, int view, const float* loss,
+                              int32_t* gate, hipStream_t s);
+size_t gate_state_bytes(const sgs_gate_params* p);
+
+hipError_t launch_adam(const sgs_adam_params* p, float* params, float* grads, float* m, float* v,
+                       int64_t n, int64_t stride, int n_planes, int32_t* step,
+                       const int32_t* gate, hipStream_t s);
+
+}  // namespace sgs

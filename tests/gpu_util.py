@@ -1,0 +1,119 @@
+"""Helpers for the GPU parity tests: run the HIP path through the C ABI on
+seeded inputs and read back workspace regions. Inputs come from the seeded
+generators only; nothing here computes the method."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2603_08997_amd import scenes as S
+
+
+def sg():
+    from paper_2603_08997_amd import skipgs
+    return skipgs
+
+
+def require_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("a GPU test ran without a GPU")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a, dtype=None):
+    t = torch.as_tensor(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def region(ws: torch.Tensor, offset: int, count: int, dtype) -> np.ndarray:
+    nbytes = count * np.dtype(dtype).itemsize
+    raw = ws[offset:offset + nbytes].cpu().numpy()
+    return raw.view(dtype).copy()
+
+
+class GpuRender:
+    """One batch of views rendered through sgs_render_forward / backward."""
+
+    def __init__(self, scene: S.Scene, cams, rp=None, capacity=None):
+        m = sg()
+        self.scene = scene
+        self.cams = list(cams)
+        self.rp = rp or m.RasterParams()
+        self.n = scene.n
+        self.planes = to_dev(scene.to_planes())
+        self.capacity = capacity or max(4096, 64 * self.n * len(self.cams))
+        self.ws_bytes = m.forward_workspace_size(self.rp, self.n, self.cams, self.capacity)
+        self.ws = m.alloc_bytes(self.ws_bytes)
+        self.ws.zero_()
+        self.L = m.get_workspace_layout(self.rp, self.n, self.cams, self.capacity)
+        self.px = sum(c.width * c.height for c in self.cams)
+        self.rgb = torch.zeros(3 * self.px, dtype=torch.float32, device="cuda")
+
+    def forward(self):
+        m = sg()
+        m.render_forward(self.planes, self.n, self.scene.sh_degree, self.cams, self.rp, self.ws,
+                         self.capacity, self.rgb)
+        flags, vis, pairs = m.read_status(self.ws)
+        assert flags == 0, f"status flags {flags}"
+        self.visible, self.pairs = vis, pairs
+        return self.rgb
+
+    def backward(self, dl_drgb: torch.Tensor, gate=None):
+        m = sg()
+        grads = torch.zeros_like(self.planes)
+        m.render_backward(self.planes, self.n, self.scene.sh_degree, self.cams, self.rp, self.ws,
+                          self.capacity, dl_drgb, gate, grads)
+        torch.cuda.synchronize()
+        return grads
+
+    def images(self):
+        out, off = [], 0
+        flat = self.rgb.cpu().numpy()
+        for c in self.cams:
+            k = 3 * c.width * c.height
+            out.append(flat[off:off + k].reshape(3, c.height, c.width))
+            off += k
+        return out
+
+    def records(self):
+        return region(self.ws, self.L.records, 12 * self.L.entries, np.float32).reshape(-1, 12)
+
+    def t_final(self):
+        return region(self.ws, self.L.t_final, self.L.total_pixels, np.float32)
+
+    def n_last(self):
+        return region(self.ws, self.L.n_last, self.L.total_pixels, np.uint32)
+
+    def accum(self):
+        return region(self.ws, self.L.accum, 12 * self.L.entries, np.float32).reshape(-1, 12)
+
+
+def split_views(flat, cams, per_pixel=1):
+    out, off = [], 0
+    for c in cams:
+        k = per_pixel * c.width * c.height
+        out.append(flat[off:off + k])
+        off += k
+    return out
+
+
+def rel_max_err(got, ref):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    scale = max(np.abs(ref).max(), 1e-30)
+    return np.abs(got - ref).max() / scale
+
+
+def rel_norm_err(got, ref):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    return np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30)

@@ -1,0 +1,132 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+the header declares, and rejects bad arguments before touching the GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "skipgs.h")
+
+
+def _lib():
+    from paper_2603_08997_amd import skipgs
+    return skipgs
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sgs_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("sgs_render_forward", "sgs_render_backward", "sgs_gate_update", "sgs_adam_step",
+                 "sgs_photometric_loss"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    sg = _lib()
+    names = declared_functions()
+    missing = [n for n in names if not hasattr(sg.LIB, n)]
+    assert not missing, missing
+    assert sorted(sg.EXPORTS) == names
+
+
+def test_version():
+    assert _lib().version() == 100
+
+
+def test_default_raster_params():
+    sg = _lib()
+    rp = sg.RasterParamsC()
+    sg.LIB.sgs_default_raster_params(C.byref(rp))
+    assert (rp.tile_w, rp.tile_h) == (16, 16)
+    assert rp.alpha_max == pytest.approx(0.99) and rp.t_min == pytest.approx(1e-4)
+
+
+def _cam(w=64, h=48):
+    from paper_2603_08997_amd import scenes
+    return scenes.look_at_camera((3.0, 0.5, 1.0), w, h)
+
+
+def test_workspace_size_and_bad_tile_shape():
+    sg = _lib()
+    cams = [_cam()]
+    nbytes = sg.forward_workspace_size(sg.RasterParams(), 1000, cams, 50_000)
+    assert nbytes > 50_000 * 16
+    with pytest.raises(sg.SkipGSError) as e:
+        sg.forward_workspace_size(sg.RasterParams(tile_w=12, tile_h=12), 1000, cams, 10)
+    assert e.value.status == 2 and "tile shape" in str(e.value)
+
+
+def test_invalid_arguments_rejected_before_launch():
+    sg = _lib()
+    rp = sg.RasterParams().c()
+    cams = sg.cameras_c([_cam()])
+    g = sg.GaussiansC()
+    g.data = 256
+    g.n = 10
+    g.stride = 60        # not a multiple of 64
+    g.sh_degree = 0
+    st = sg.LIB.sgs_render_forward(C.byref(g), cams, 1, C.byref(rp), C.c_void_p(256), 1 << 20, 100,
+                                   C.c_void_p(256), None)
+    assert st == 1 and b"stride" in sg.LIB.sgs_last_error()
+    g.stride = 64
+    g.sh_degree = 4
+    st = sg.LIB.sgs_render_forward(C.byref(g), cams, 1, C.byref(rp), C.c_void_p(256), 1 << 20, 100,
+                                   C.c_void_p(256), None)
+    assert st == 1 and b"sh_degree" in sg.LIB.sgs_last_error()
+    g.sh_degree = 0
+    # workspace too small
+    st = sg.LIB.sgs_render_forward(C.byref(g), cams, 1, C.byref(rp), C.c_void_p(256), 16, 100,
+                                   C.c_void_p(256), None)
+    assert st == 3
+    # too many views
+    st = sg.LIB.sgs_render_forward(C.byref(g), cams, 17, C.byref(rp), C.c_void_p(256), 1 << 20, 100,
+                                   C.c_void_p(256), None)
+    assert st == 1
+    # gate: view out of range
+    gp = sg.GateParams(n_views=4).c()
+    st = sg.LIB.sgs_gate_update(C.byref(gp), C.c_void_p(256), 7, C.c_void_p(256), C.c_void_p(256), None)
+    assert st == 1 and b"view" in sg.LIB.sgs_last_error()
+    gp.beta = 1.5
+    out = C.c_size_t()
+    assert sg.LIB.sgs_gate_state_size(C.byref(gp), C.byref(out)) == 1
+    # adam: bad plane count
+    ap = sg.AdamParams(lr=(1e-3,)).c()
+    st = sg.LIB.sgs_adam_step(C.byref(ap), C.c_void_p(256), C.c_void_p(256), C.c_void_p(256),
+                              C.c_void_p(256), 10, 64, 60, C.c_void_p(256), None, None)
+    assert st == 1
+    # loss: bad lambda
+    st = sg.LIB.sgs_photometric_loss(C.c_void_p(256), C.c_void_p(256), 8, 8, C.c_float(1.5),
+                                     C.c_void_p(256), 1 << 20, C.c_void_p(256), None)
+    assert st == 1
+
+
+def test_gate_state_size():
+    sg = _lib()
+    assert sg.gate_state_size(sg.GateParams(n_views=200)) == 96 + 200 * 8 + 200
+    assert C.sizeof(sg.GateSnapshotC) == 96
+
+
+def test_layout_regions_fit_and_do_not_overlap():
+    sg = _lib()
+    cams = [_cam(64, 48), _cam(40, 24)]
+    rp = sg.RasterParams(tile_w=8, tile_h=8)
+    L = sg.get_workspace_layout(rp, 500, cams, 30_000)
+    total = sg.forward_workspace_size(rp, 500, cams, 30_000)
+    assert L.entries == 1000
+    assert L.total_tiles == 8 * 6 + 5 * 3
+    assert L.total_pixels == 64 * 48 + 40 * 24
+    regions = sorted([(L.records, 48 * 1000), (L.tiles, 4 * 1000), (L.pair_tile, 4 * 30_000),
+                      (L.pair_entry, 4 * 30_000), (L.ranges, 8 * L.total_tiles),
+                      (L.t_final, 4 * L.total_pixels), (L.n_last, 4 * L.total_pixels),
+                      (L.accum, 48 * 1000), (L.counters, 64)])
+    for (o1, s1), (o2, _) in zip(regions, regions[1:]):
+        assert o1 + s1 <= o2
+    assert regions[-1][0] + regions[-1][1] <= total
+    assert all(o % 256 == 0 for o, _ in regions)

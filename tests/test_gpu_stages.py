@@ -1,0 +1,194 @@
+"""Stage parity on identical float32 records: tile binning and sort (bit
+exact), compositing forward (1e-5) and backward (1e-3) against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import render as R
+from paper_2603_08997_amd import scenes as S
+from tests.gpu_util import (region, rel_max_err, rel_norm_err, require_gpu, say, sg, split_views,
+                            to_dev)
+
+pytestmark = pytest.mark.gpu
+
+TILES = [(16, 16), (8, 8), (32, 8)]
+
+
+def _views():
+    return [S.look_at_camera((3.0, 1.0, 1.0), 83, 61), S.look_at_camera((0.5, -3.0, 2.0), 48, 33)]
+
+
+def _records(n, cams, seed, **kw):
+    recs = [S.random_records(seed + v, n, c.width, c.height, **kw) for v, c in enumerate(cams)]
+    cat = {k: np.concatenate([r[k] for r in recs]) for k in recs[0]}
+    return recs, cat
+
+
+class Stage:
+    def __init__(self, n, cams, rp, cat, capacity):
+        m = sg()
+        self.m, self.n, self.cams, self.rp, self.cap = m, n, cams, rp, capacity
+        self.ws = m.alloc_bytes(m.forward_workspace_size(rp, n, cams, capacity))
+        self.ws.zero_()
+        self.L = m.get_workspace_layout(rp, n, cams, capacity)
+        d = {k: to_dev(v) for k, v in cat.items()}
+        m.load_records(cams, n, rp, self.ws, capacity, d["u"], d["v"], d["depth"], d["radius"],
+                       d["conic"], d["opacity"], d["rgb"])
+        m.bin(cams, n, rp, self.ws, capacity)
+        self.flags, self.vis, self.pairs = m.read_status(self.ws)
+
+    def lists(self):
+        P = self.pairs
+        tiles = region(self.ws, self.L.pair_tile, P, np.uint32)
+        ents = region(self.ws, self.L.pair_entry, P, np.uint32)
+        ranges = region(self.ws, self.L.ranges, 2 * self.L.total_tiles, np.uint32).reshape(-1, 2)
+        return tiles, ents, ranges
+
+    def rasterize(self):
+        px = sum(c.width * c.height for c in self.cams)
+        self.rgb = torch.zeros(3 * px, dtype=torch.float32, device="cuda")
+        self.m.rasterize(self.cams, self.n, self.rp, self.ws, self.cap, self.rgb)
+        torch.cuda.synchronize()
+        tf = region(self.ws, self.L.t_final, self.L.total_pixels, np.float32)
+        nl = region(self.ws, self.L.n_last, self.L.total_pixels, np.uint32)
+        return self.rgb.cpu().numpy(), tf, nl
+
+    def backward(self, dl):
+        self.m.rasterize_backward(self.cams, self.n, self.rp, self.ws, self.cap, to_dev(dl))
+        torch.cuda.synchronize()
+        return region(self.ws, self.L.accum, 12 * self.L.entries, np.float32).reshape(-1, 12)
+
+
+def _oracle_bins(recs, cams, n, tw, th):
+    keys, vals, ranges = [], [], []
+    off = 0
+    for v, (r, c) in enumerate(zip(recs, cams)):
+        k, val, rg = R.bin_and_sort(r["u"], r["v"], r["depth"], r["radius"], v * n + np.arange(n),
+                                    c.width, c.height, tw, th, tile_offset=off)
+        base = sum(len(x) for x in keys)
+        rg = np.where(rg[:, 1:2] > rg[:, 0:1], rg + base, 0)
+        keys.append(k); vals.append(val); ranges.append(rg)
+        off += ((c.width + tw - 1) // tw) * ((c.height + th - 1) // th)
+    return np.concatenate(keys), np.concatenate(vals), np.concatenate(ranges)
+
+
+@pytest.mark.parametrize("tile", TILES)
+@pytest.mark.parametrize("ties", [0.0, 0.4])
+def test_binning_bit_exact(tile, ties):
+    require_gpu()
+    m = sg()
+    tw, th = tile
+    cams = _views()
+    n = 1500
+    recs, cat = _records(n, cams, 100 + int(ties * 10), max_radius=20, tie_fraction=ties)
+    say(f"binning tile={tile} ties={ties} n={n}")
+    st = Stage(n, cams, m.RasterParams(tile_w=tw, tile_h=th), cat, 400_000)
+    assert st.flags == 0
+    keys, vals, ranges = _oracle_bins(recs, cams, n, tw, th)
+    tiles, ents, granges = st.lists()
+    assert st.pairs == len(keys)
+    assert np.array_equal(ents.astype(np.int64), vals)
+    assert np.array_equal(tiles.astype(np.int64), (keys >> np.uint64(32)).astype(np.int64))
+    assert np.array_equal(granges.astype(np.int64), ranges)
+
+
+def test_binning_empty_and_capacity_overflow():
+    require_gpu()
+    m = sg()
+    cams = _views()
+    n = 300
+    recs, cat = _records(n, cams, 7, max_radius=15)
+    cat["radius"][:] = 0                       # nothing visible
+    st = Stage(n, cams, m.RasterParams(), cat, 1000)
+    assert st.flags == 0 and st.vis == 0 and st.pairs == 0
+    _, _, ranges = st.lists()
+    assert not ranges.any()
+    recs, cat = _records(n, cams, 8, max_radius=15)
+    st = Stage(n, cams, m.RasterParams(), cat, 64)   # far too small
+    assert st.flags & m.STATUS_PAIR_OVERFLOW
+    assert st.pairs > 64
+
+
+def _oracle_composite(rec, cam, rp, n, view, leaf=False):
+    t = {k: torch.tensor(np.asarray(rec[k], np.float64), requires_grad=leaf)
+         for k in ("u", "v", "conic", "opacity", "rgb")}
+    uv = torch.stack([t["u"], t["v"]], 1)
+    out = R.composite(uv, t["conic"], t["opacity"], t["rgb"], torch.tensor(rec["depth"], dtype=torch.float64),
+                      torch.tensor(rec["radius"].astype(np.int64)), view * n + torch.arange(n),
+                      cam.width, cam.height, rp)
+    return out, t
+
+
+@pytest.mark.parametrize("tile", TILES)
+def test_raster_forward_and_backward_match_oracle(tile):
+    require_gpu()
+    m = sg()
+    tw, th = tile
+    cams = _views()
+    n = 900
+    recs, cat = _records(n, cams, 300, max_radius=14)
+    bg = (0.2, 0.4, 0.6)
+    say(f"raster tile={tile} n={n}")
+    st = Stage(n, cams, m.RasterParams(tile_w=tw, tile_h=th, bg=bg), cat, 400_000)
+    rgb, tf, nl = st.rasterize()
+    orp = R.RasterParams(tile_w=tw, tile_h=th, bg=bg)
+    keys, vals, ranges = _oracle_bins(recs, cams, n, tw, th)
+    rng = np.random.default_rng(5)
+    dls, flips_total = [], 0
+    for v, (rec, cam, img, T, NL) in enumerate(zip(recs, cams, split_views(rgb, cams, 3),
+                                                   split_views(tf, cams), split_views(nl, cams))):
+        out, _ = _oracle_composite(rec, cam, orp, n, v)
+        ref_img = out["rgb"].detach().numpy()
+        # list positions of the oracle's last blended Gaussian in the oracle's lists
+        px, py = R.pixel_grid(cam.width, cam.height)
+        tiles_x = (cam.width + tw - 1) // tw
+        toff = sum(((c.width + tw - 1) // tw) * ((c.height + th - 1) // th) for c in cams[:v])
+        pos = np.zeros(cam.width * cam.height, np.int64)
+        last = out["last"].numpy()
+        for k in range(len(pos)):
+            if last[k] < 0:
+                continue
+            t = toff + (py[k].item() // th) * tiles_x + px[k].item() // tw
+            s, e = ranges[t]
+            pos[k] = np.nonzero(vals[s:e] == last[k])[0][0] + 1
+        flips = pos != NL.astype(np.int64)
+        flips_total += int(flips.sum())
+        ok = ~flips
+        assert flips.mean() < 1e-3
+        assert rel_max_err(img.reshape(3, -1)[:, ok], ref_img[:, ok]) < 1e-5
+        assert rel_max_err(T[ok], out["T_final"].detach().numpy()[ok]) < 1e-5
+        dl = rng.normal(0, 1, (3, cam.width * cam.height))
+        dl[:, flips] = 0.0
+        dls.append(dl)
+    say(f"  decision flips: {flips_total}")
+    # backward on the same records, cotangents zero on flipped pixels
+    dl_all = np.concatenate([d.reshape(-1) for d in dls]).astype(np.float32)
+    acc = st.backward(dl_all)
+    for v, (rec, cam) in enumerate(zip(recs, cams)):
+        out, t = _oracle_composite(rec, cam, orp, n, v, leaf=True)
+        (out["rgb"] * torch.tensor(dls[v].astype(np.float32).astype(np.float64))).sum().backward()
+        a = acc[v * n:(v + 1) * n]
+        pairs = [("u", a[:, 0], t["u"].grad), ("v", a[:, 1], t["v"].grad),
+                 ("conic", a[:, 2:5], t["conic"].grad), ("opacity", a[:, 5], t["opacity"].grad),
+                 ("rgb", np.stack([a[:, 6], a[:, 7], a[:, 8]], 1), t["rgb"].grad)]
+        for name, got, ref in pairs:
+            ref = ref.numpy()
+            assert rel_norm_err(got, ref) < 1e-3, (v, name, rel_norm_err(got, ref))
+            assert rel_max_err(got, ref) < 1e-3, (v, name, rel_max_err(got, ref))
+
+
+def test_raster_backward_gate_closed_touches_nothing():
+    require_gpu()
+    m = sg()
+    cams = _views()[:1]
+    n = 200
+    recs, cat = _records(n, cams, 11, max_radius=10)
+    st = Stage(n, cams, m.RasterParams(), cat, 100_000)
+    st.rasterize()
+    acc_region = st.ws[st.L.accum:st.L.accum + 48 * n]
+    acc_region.fill_(7)
+    gate = torch.zeros(1, dtype=torch.int32, device="cuda")
+    m.rasterize_backward(cams, n, st.rp, st.ws, st.cap,
+                         torch.ones(3 * cams[0].width * cams[0].height, device="cuda"), gate)
+    torch.cuda.synchronize()
+    assert bool((acc_region == 7).all())
