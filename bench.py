@@ -1,0 +1,235 @@
+"""Benchmark: post-densification iterations/s of SkipGS-gated vs full-backward
+3DGS training on one MI355X, with the dominant kernel's roofline fraction
+and the FP64 oracle timed on the host as a CPU reference.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Workload (defaults): 3,000,000 Gaussians (SH degree 3, ground-plane + two
+clusters), 200 views at 1600x1060 on a hemisphere of radius 4-5, 16x16 tiles,
+targets rendered from the ground-truth set, training from a perturbed copy,
+uniform view sampling, loss 0.8 L1 + 0.2 (1 - SSIM), gate with EMA decay 0.9,
+skip within 2% of the view's EMA, >= 50% backward per 100 iterations, Adam
+(means lr 1.6e-4). One step = one training iteration: forward render, loss,
+gate, and (when the gate opens) loss backward, render backward and Adam.
+Inputs are resident in HBM before the timed region starts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+# FP32 operations per blended (pixel, Gaussian) pair in the compositing
+# kernels, counted from the arithmetic each pair performs (FMA = 2, exp = 1).
+FWD_FLOPS_PER_PAIR = 27
+BWD_FLOPS_PER_PAIR = 62
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=3_000_000)
+    ap.add_argument("--views", type=int, default=200)
+    ap.add_argument("--width", type=int, default=1600)
+    ap.add_argument("--height", type=int, default=1060)
+    ap.add_argument("--gate", choices=["windowed", "paper"], default="windowed")
+    ap.add_argument("--runs", default="gated,full")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-stage-events", action="store_true")
+    ap.add_argument("--eval-views", type=int, default=200)
+    return ap.parse_args()
+
+
+def cpu_baseline(gt, init, cam, crop=24):
+    """The FP64 oracle on a bounded sample of one iteration: projection of all
+    Gaussians (with autograd) plus compositing, loss and backward for a
+    crop x crop pixel window at the image centre; the per-pixel part is
+    scaled to the full image."""
+    from oracle import render as OR, loss as OL
+    threads = torch.get_num_threads()
+    arr = {k: torch.tensor(np.asarray(v, np.float64), requires_grad=True) for k, v in
+           dict(means=init.means, log_scales=init.log_scales, quats=init.quats,
+                opacity_logits=init.opacity_logits, sh=init.sh).items()}
+    t0 = time.perf_counter()
+    pr = OR.project(arr["means"], arr["log_scales"], arr["quats"], arr["opacity_logits"], arr["sh"],
+                    init.sh_degree, cam, OR.RasterParams())
+    t_proj = time.perf_counter() - t0
+    x0, y0 = cam.width // 2 - crop // 2, cam.height // 2 - crop // 2
+    ys, xs = np.meshgrid(np.arange(y0, y0 + crop), np.arange(x0, x0 + crop), indexing="ij")
+    px, py = torch.tensor(xs.reshape(-1)), torch.tensor(ys.reshape(-1))
+    with torch.no_grad():
+        gpr = OR.project(gt.means, gt.log_scales, gt.quats, gt.opacity_logits, gt.sh, gt.sh_degree,
+                         cam, OR.RasterParams())
+        tgt = OR.composite(gpr["uv"], gpr["conic"], gpr["opacity"], gpr["rgb"], gpr["depth"],
+                           gpr["radius"], gpr["ids"], cam.width, cam.height, OR.RasterParams(),
+                           px=px, py=py)["rgb"].reshape(3, crop, crop)
+    t1 = time.perf_counter()
+    out = OR.composite(pr["uv"], pr["conic"], pr["opacity"], pr["rgb"], pr["depth"], pr["radius"],
+                       pr["ids"], cam.width, cam.height, OR.RasterParams(), px=px, py=py)
+    L = OL.photometric_loss(out["rgb"].reshape(3, crop, crop), tgt)
+    t_pix = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    L.backward()
+    t_bwd = time.perf_counter() - t2
+    scale = (cam.width * cam.height) / float(crop * crop)
+    # projection runs once per iteration; compositing and its share of the
+    # backward scale with the pixel count
+    est = t_proj + (t_pix + t_bwd) * scale
+    return {"value": 1.0 / est, "unit": "iters/s", "cores": threads, "kind": "oracle",
+            "sample": (f"one view: FP64 projection of all {init.n} Gaussians with autograd "
+                       f"({t_proj:.1f} s) + compositing, loss and backward of a {crop}x{crop} "
+                       f"window ({t_pix + t_bwd:.1f} s) scaled x{scale:.0f} to the full "
+                       f"{cam.width}x{cam.height} view; torch CPU threads={threads}"),
+            "seconds_per_iter_estimate": est}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    from paper_2603_08997_amd import scenes as S
+    from paper_2603_08997_amd import skipgs as sk
+    from paper_2603_08997_amd.train import StageTimer, Trainer, measure_pairs, render_targets
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t_setup = time.perf_counter()
+    log(f"setup: scene n={args.n} views={args.views} {args.width}x{args.height}")
+    gt = S.mixture_scene(S.SEED_SCENE, args.n, sh_degree=3)
+    init = S.perturb(gt, S.SEED_INIT_PERTURB)
+    cams = S.hemisphere_cameras(S.SEED_CAMERAS, args.views, args.width, args.height)
+    seq = S.view_sequence(S.SEED_VIEW_SEQUENCE, args.views, args.warmup + args.steps)
+    rp = sk.RasterParams()
+    pairs = max(measure_pairs(gt, cams, rp), measure_pairs(init, cams, rp))
+    cap = int(pairs * 1.3) + 4096
+    log(f"setup: max pairs per view {pairs}, capacity {cap}")
+    targets = render_targets(gt, cams, rp, cap)
+    torch.cuda.synchronize()
+    log(f"setup done in {time.perf_counter() - t_setup:.1f} s")
+    gate = sk.windowed_gate(args.views) if args.gate == "windowed" else sk.paper_gate(args.views)
+    eval_views = list(range(min(args.views, args.eval_views)))
+
+    results = {}
+    for run in args.runs.split(","):
+        tr = Trainer(init, cams, targets, rp, gate, cap, gated=(run == "gated"))
+        gslots = torch.zeros(args.warmup + args.steps, dtype=torch.int32, device=dev)
+        for t in range(args.warmup):
+            tr.iteration(int(seq[t]), gslots[t:t + 1])
+        timer = None if args.no_stage_events else StageTimer()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(args.warmup, args.warmup + args.steps):
+            tr.iteration(int(seq[t]), gslots[t:t + 1], timer=timer)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        flags, vis, _ = tr.status()
+        if flags & sk.STATUS_PAIR_OVERFLOW:
+            raise RuntimeError("pair capacity overflow during the timed run")
+        g = gslots[args.warmup:].cpu().numpy()
+        res = {"iters_per_s": args.steps / dt, "ms_per_step": 1000 * dt / args.steps,
+               "backward_fraction": float(g.mean()), "seconds": dt}
+        if timer is not None:
+            res["stage_ms_all"] = timer.summary()
+            res["stage_ms_executed"] = timer.summary(mask=g == 1)
+            res["stage_ms_skipped"] = timer.summary(mask=g == 0) if (g == 0).any() else None
+        log(f"{run}: {res['iters_per_s']:.1f} it/s, backward fraction {res['backward_fraction']:.3f}")
+        res["final_mean_loss"] = tr.mean_loss(eval_views)
+        log(f"{run}: final mean loss over {len(eval_views)} views {res['final_mean_loss']:.6f}")
+        results[run] = res
+        res["_trainer"] = tr
+        res["_timer"] = timer
+
+    gated = results.get("gated")
+    full = results.get("full")
+    headline = gated or full
+
+    # dominant kernel: the compositing backward (per executed iteration) or
+    # forward, whichever takes longer in the headline run
+    roof = None
+    tr = headline["_trainer"]
+    timer = headline["_timer"]
+    if timer is not None:
+        # blended (pixel, Gaussian) pairs of one view, averaged over 8 views
+        blended = []
+        for v in range(min(8, args.views)):
+            tr.render(v, tr.rgb)
+            torch.cuda.synchronize()
+            blended.append(sk.read_counters(tr.ws)["blended"])
+        blended = float(np.mean(blended))
+        ex = headline["stage_ms_executed"]
+        allm = headline["stage_ms_all"]
+        tot_bwd = ex["raster_bwd"] * headline["backward_fraction"]
+        tot_fwd = allm["rasterize"]
+        if tot_bwd >= tot_fwd:
+            ms, flops_pp, name = ex["raster_bwd"], BWD_FLOPS_PER_PAIR, "raster_backward"
+        else:
+            ms, flops_pp, name = allm["rasterize"], FWD_FLOPS_PER_PAIR, "raster_forward"
+        achieved = blended * flops_pp / (ms * 1e-3) / 1e12
+        roof = {"kernel": name, "bound": "alu", "achieved": achieved,
+                "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                "avg_launch_ms": ms, "blended_pairs_per_launch": blended,
+                "flops_per_pair": flops_pp}
+
+    out = {
+        "metric": "post-densification iters/s (gated vs full) at 1 GPU",
+        "value": headline["iters_per_s"],
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": headline["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": (f"gated 3DGS post-densification training, {args.n} Gaussians SH3, "
+                                f"{args.views} views {args.width}x{args.height}, 16x16 tiles, "
+                                f"{args.gate} gate"),
+                   "gaussians": args.n, "views": args.views, "width": args.width,
+                   "height": args.height, "gate": args.gate},
+    }
+    if gated and full:
+        out["full_iters_per_s"] = full["iters_per_s"]
+        out["gated_over_full"] = gated["iters_per_s"] / full["iters_per_s"]
+        out["skip_fraction"] = 1.0 - gated["backward_fraction"]
+        out["final_loss_gated"] = gated["final_mean_loss"]
+        out["final_loss_full"] = full["final_mean_loss"]
+        out["final_loss_rel_diff"] = (gated["final_mean_loss"] - full["final_mean_loss"]) / \
+            full["final_mean_loss"]
+        if gated.get("stage_ms_skipped") and full.get("stage_ms_all"):
+            c = sum(gated["stage_ms_skipped"].values()) / sum(full["stage_ms_all"].values())
+            out["skipped_iteration_cost"] = c
+    for k, r in results.items():
+        out[f"stages_{k}"] = {kk: (round(vv, 4) if isinstance(vv, float) else vv)
+                              for kk, vv in r.get("stage_ms_executed", {}).items()}
+    if roof is not None:
+        out["roofline"] = roof
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(gt, init, cams[0])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

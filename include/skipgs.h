@@ -293,8 +293,8 @@ sgs_status sgs_gate_read(const sgs_gate_params* p, const void* d_state,
  * Predicated on d_gate; *d_step (device int32) is the executed-step count k.
  * ------------------------------------------------------------------------- */
 typedef struct {
-    float beta1, beta2, eps;
-    float lr[SGS_MAX_PLANES];  /* per plane; planes beyond n_planes ignored */
+    double beta1, beta2, eps;  /* 1 - beta is formed in binary64 before rounding */
+    float lr[SGS_MAX_PLANES];  /* per plane; planes beyond n_planes ignored     */
 } sgs_adam_params;
 
 sgs_status sgs_adam_step(const sgs_adam_params* p, float* params, float* grads, float* m,

@@ -10,7 +10,8 @@ namespace sgs {
 namespace {
 
 struct AdamArgs {
-    float beta1, beta2, eps;
+    float b1, b2, c1, c2, eps;  // beta, 1 - beta (formed in binary64), eps
+    double beta1, beta2;        // for the bias corrections
     float lr[SGS_MAX_PLANES];
 };
 
@@ -27,10 +28,10 @@ __global__ void __launch_bounds__(256) adam_kernel(AdamArgs a, float4* __restric
     if (gate_closed(gate)) return;
     const int plane = blockIdx.y;
     const int k = *step;
-    const float bc1 = (float)(1.0 - pow((double)a.beta1, (double)k));
-    const float bc2 = (float)(1.0 - pow((double)a.beta2, (double)k));
+    const float bc1 = (float)(1.0 - pow(a.beta1, (double)k));
+    const float bc2 = (float)(1.0 - pow(a.beta2, (double)k));
     const float lr = a.lr[plane];
-    const float b1 = a.beta1, b2 = a.beta2, c1 = 1.f - a.beta1, c2 = 1.f - a.beta2;
+    const float b1 = a.b1, b2 = a.b2, c1 = a.c1, c2 = a.c2;
     const int64_t base = (int64_t)plane * stride4;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < stride4;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -63,7 +64,11 @@ hipError_t launch_adam(const sgs_adam_params* prm, float* params, float* grads, 
     AdamArgs a;
     a.beta1 = prm->beta1;
     a.beta2 = prm->beta2;
-    a.eps = prm->eps;
+    a.b1 = (float)prm->beta1;
+    a.b2 = (float)prm->beta2;
+    a.c1 = (float)(1.0 - prm->beta1);
+    a.c2 = (float)(1.0 - prm->beta2);
+    a.eps = (float)prm->eps;
     for (int i = 0; i < SGS_MAX_PLANES; ++i) a.lr[i] = prm->lr[i];
     hipLaunchKernelGGL(adam_count_kernel, dim3(1), dim3(1), 0, s, step, gate);
     const int64_t stride4 = stride / 4;

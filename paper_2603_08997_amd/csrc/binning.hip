@@ -196,7 +196,8 @@ hipError_t launch_bin(const Views& views, const RasterDev& rp, int64_t n, const 
     hipError_t err;
 
     // visible entries -> (depth, entry), entry order; count -> counters[kVisible]
-    if ((err = fill_u32(counters + kVisible, 3, 0u, s)) != hipSuccess) return err;
+    if ((err = fill_u32(counters + kVisible, kEvaluated + 2 - kVisible, 0u, s)) != hipSuccess)
+        return err;
     if (E > 0) {
         err = device_scan(VisibleSrc{tiles, E}, CompactSink{tiles, rec, dkey[0], dval[0]}, E, sums,
                           counters + kVisible, s);

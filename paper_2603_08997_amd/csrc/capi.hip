@@ -537,8 +537,8 @@ sgs_status sgs_adam_step(const sgs_adam_params* p, float* params, float* grads, 
         return fail(SGS_ERR_INVALID_ARG, "n_planes %d not in [1, %d]", n_planes, SGS_MAX_PLANES);
     if (!aligned(params, 16) || !aligned(grads, 16) || !aligned(m, 16) || !aligned(v, 16))
         return fail(SGS_ERR_INVALID_ARG, "arrays must be 16-byte aligned");
-    if (!(p->beta1 >= 0.f && p->beta1 < 1.f) || !(p->beta2 >= 0.f && p->beta2 < 1.f) ||
-        !(p->eps >= 0.f))
+    if (!(p->beta1 >= 0.0 && p->beta1 < 1.0) || !(p->beta2 >= 0.0 && p->beta2 < 1.0) ||
+        !(p->eps >= 0.0))
         return fail(SGS_ERR_INVALID_ARG, "Adam constants out of range");
     SGS_HIP(sgs::launch_adam(p, params, grads, m, v, n, stride, n_planes, d_step, d_gate,
                              static_cast<hipStream_t>(stream)),

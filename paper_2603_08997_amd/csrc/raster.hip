@@ -55,11 +55,13 @@ template <int TW, int TH>
 __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
     Views views, RasterDev rp, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ pentry, const float4* __restrict__ rec,
-    float* __restrict__ out_rgb, float* __restrict__ t_final, uint32_t* __restrict__ n_last) {
+    float* __restrict__ out_rgb, float* __restrict__ t_final, uint32_t* __restrict__ n_last,
+    uint32_t* __restrict__ counters) {
     constexpr int NT = TW * TH;
     __shared__ float4 s_pos[NT];   // u, v, radius, opacity
     __shared__ float4 s_con[NT];   // a, b, c, -
     __shared__ float4 s_col[NT];   // r, g, b, -
+    __shared__ uint32_t s_cnt[2];
 
     const int tile = blockIdx.x;
     const ViewDev& V = views.v[view_of_tile(views, tile)];
@@ -72,8 +74,9 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
 
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-    uint32_t last = 0;
+    uint32_t last = 0, n_blend = 0, n_eval = 0;
     bool done = !inside;
+    if (tid < 2) s_cnt[tid] = 0;
     for (uint32_t b0 = start; b0 < end; b0 += NT) {
         if (__syncthreads_and(done)) break;
         const uint32_t idx = b0 + tid;
@@ -91,9 +94,11 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
                 const float4 P = s_pos[j];
                 const float4 Q = s_con[j];
                 Splat s;
+                ++n_eval;
                 if (!splat_alpha(px, py, P.x, P.y, P.z, P.w, Q.x, Q.y, Q.z, rp, s)) continue;
                 const float test = T * (1.f - s.alpha);
                 if (test < rp.t_min) { done = true; break; }
+                ++n_blend;
                 const float4 col = s_col[j];
                 const float w = s.alpha * T;
                 C0 = fmaf(col.x, w, C0);
@@ -113,6 +118,17 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
         img[2 * plane + pix] = fmaf(T, rp.bg[2], C2);
         t_final[V.px_offset + pix] = T;
         n_last[V.px_offset + pix] = last;
+    }
+    // work counters: one 64-bit atomic per workgroup
+    __syncthreads();
+    if (n_blend) atomicAdd(&s_cnt[0], n_blend);
+    if (n_eval) atomicAdd(&s_cnt[1], n_eval);
+    __syncthreads();
+    if (tid == 0) {
+        atomicAdd(reinterpret_cast<unsigned long long*>(counters + kBlended),
+                  (unsigned long long)s_cnt[0]);
+        atomicAdd(reinterpret_cast<unsigned long long*>(counters + kEvaluated),
+                  (unsigned long long)s_cnt[1]);
     }
 }
 
@@ -250,16 +266,17 @@ hipError_t launch_rasterize(const Views& views, const RasterDev& rp, const Layou
     const float4* rec = reinterpret_cast<const float4*>(ws + L.records);
     float* tf = reinterpret_cast<float*>(ws + L.t_final);
     uint32_t* nl = reinterpret_cast<uint32_t*>(ws + L.n_last);
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(ws + L.counters);
     const dim3 grid((unsigned)L.total_tiles);
     if (rp.tile_w == 16 && rp.tile_h == 16)
         hipLaunchKernelGGL((raster_forward_kernel<16, 16>), grid, dim3(256), 0, s, views, rp,
-                           ranges, pentry, rec, out_rgb, tf, nl);
+                           ranges, pentry, rec, out_rgb, tf, nl, cnt);
     else if (rp.tile_w == 8 && rp.tile_h == 8)
         hipLaunchKernelGGL((raster_forward_kernel<8, 8>), grid, dim3(64), 0, s, views, rp, ranges,
-                           pentry, rec, out_rgb, tf, nl);
+                           pentry, rec, out_rgb, tf, nl, cnt);
     else
         hipLaunchKernelGGL((raster_forward_kernel<32, 8>), grid, dim3(256), 0, s, views, rp,
-                           ranges, pentry, rec, out_rgb, tf, nl);
+                           ranges, pentry, rec, out_rgb, tf, nl, cnt);
     return hipGetLastError();
 }
 

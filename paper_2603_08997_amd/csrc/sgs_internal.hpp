@@ -47,6 +47,8 @@ enum Counter : int {
     kVisible = 1,       // visible entries of the last forward
     kPairs = 2,         // (tile, entry) pairs needed by the last forward
     kPairsWritten = 3,  // min(pairs, capacity)
+    kBlended = 4,       // uint64 at words 4-5: blended (pixel, Gaussian) pairs of the last rasterize
+    kEvaluated = 6,     // uint64 at words 6-7: (pixel, list entry) pairs the forward examined
     kNumCounters = 16
 };
 

@@ -67,7 +67,7 @@ class GateSnapshotC(C.Structure):
 
 
 class AdamParamsC(C.Structure):
-    _fields_ = [("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+    _fields_ = [("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
                 ("lr", C.c_float * MAX_PLANES)]
 
 
@@ -297,6 +297,18 @@ def read_status(workspace, stream=None):
     return flags.value, vis.value, pairs.value
 
 
+def read_counters(workspace, stream=None) -> dict:
+    """Synchronises and reads the workspace counters (offset 0): status bits,
+    visible entries, pairs, and the blended / examined (pixel, Gaussian)
+    pairs of the last bin + rasterize."""
+    s = torch.cuda.current_stream() if stream is None else stream
+    s.synchronize()
+    w = workspace[:64].cpu().numpy().view(np.uint32)
+    u64 = lambda i: int(w[i]) | (int(w[i + 1]) << 32)
+    return {"status": int(w[0]), "visible": int(w[1]), "pairs": int(w[2]),
+            "pairs_written": int(w[3]), "blended": u64(4), "evaluated": u64(6)}
+
+
 def clear_status(workspace, stream=None):
     _check(LIB.sgs_clear_status(_ptr(workspace), _stream(stream)))
 
@@ -403,3 +415,43 @@ def adam_step(p: AdamParams, params, grads, m, v, n, d_step, d_gate=None, stream
     _check(LIB.sgs_adam_step(C.byref(p.c()), _ptr(params), _ptr(grads), _ptr(m), _ptr(v), int(n),
                              int(params.shape[1]), int(params.shape[0]), _ptr(d_step),
                              _ptr(d_gate), _stream(stream)))
+
+
+class Prepared:
+    """Pre-marshalled arguments for repeated calls on the same views and
+    parameters (hot loops): C structs are built once, pointers are cached."""
+
+    def __init__(self, planes, n, sh_degree, cams, rp: RasterParams, workspace, pair_capacity):
+        self.g = gaussians_c(planes, n, sh_degree)
+        self.cams = [cameras_c([c]) for c in cams]
+        self.rp = rp.c()
+        self.n = int(n)
+        self.ws = _ptr(workspace)
+        self.ws_bytes = workspace.numel()
+        self.cap = int(pair_capacity)
+        self._keep = (planes, workspace)
+
+    def project(self, view, stream):
+        _check(LIB.sgs_project(C.byref(self.g), self.cams[view], 1, C.byref(self.rp), self.ws,
+                               self.ws_bytes, self.cap, stream))
+
+    def bin(self, view, stream):
+        _check(LIB.sgs_bin(self.cams[view], 1, self.n, C.byref(self.rp), self.ws, self.ws_bytes,
+                           self.cap, stream))
+
+    def rasterize(self, view, out_ptr, stream):
+        _check(LIB.sgs_rasterize(self.cams[view], 1, self.n, C.byref(self.rp), self.ws,
+                                 self.ws_bytes, self.cap, out_ptr, stream))
+
+    def render_forward(self, view, out_ptr, stream):
+        _check(LIB.sgs_render_forward(C.byref(self.g), self.cams[view], 1, C.byref(self.rp),
+                                      self.ws, self.ws_bytes, self.cap, out_ptr, stream))
+
+    def rasterize_backward(self, view, dl_ptr, gate_ptr, stream):
+        _check(LIB.sgs_rasterize_backward(self.cams[view], 1, self.n, C.byref(self.rp), self.ws,
+                                          self.ws_bytes, self.cap, dl_ptr, gate_ptr, stream))
+
+    def project_backward(self, view, gate_ptr, grads_ptr, stream):
+        _check(LIB.sgs_project_backward(C.byref(self.g), self.cams[view], 1, C.byref(self.rp),
+                                        self.ws, self.ws_bytes, self.cap, gate_ptr, grads_ptr,
+                                        stream))

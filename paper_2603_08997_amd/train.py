@@ -1,0 +1,179 @@
+"""Post-densification training loop with the SkipGS backward gate, driven
+through the C ABI. Per iteration (Algorithm 1): sample a view, render it,
+compute the loss, update the gate on the device, and, predicated on the
+gate's device flag, run the loss backward, the render backward and Adam.
+Nothing is read back to the host inside the loop.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import scenes as S
+from . import skipgs as sk
+
+
+@dataclass
+class StageTimer:
+    """Optional HIP events around each stage of an iteration (on the stream
+    the kernels run on)."""
+    names: tuple = ("project", "bin", "rasterize", "loss", "gate", "loss_bwd", "raster_bwd",
+                    "project_bwd", "adam")
+    events: list = field(default_factory=list)
+
+    def mark(self):
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        return e
+
+    def summary(self, mask=None):
+        """Mean ms per stage over the recorded iterations (optionally only those in mask)."""
+        out = {k: [] for k in self.names}
+        for it, evs in enumerate(self.events):
+            if mask is not None and not mask[it]:
+                continue
+            for k, (a, b) in evs.items():
+                out[k].append(a.elapsed_time(b))
+        return {k: (float(np.mean(v)) if v else 0.0) for k, v in out.items()}
+
+    def per_iter(self, name):
+        return np.array([evs[name][0].elapsed_time(evs[name][1]) if name in evs else np.nan
+                         for evs in self.events])
+
+
+class Trainer:
+    """Holds the device state of one training run: parameters, Adam moments,
+    gradient buffer, gate state, per-view targets and workspaces."""
+
+    def __init__(self, init: S.Scene, cams, targets: torch.Tensor, rp: sk.RasterParams,
+                 gate: sk.GateParams | None, capacity: int, lrs=None, gated: bool = True,
+                 device="cuda"):
+        self.dev = torch.device(device)
+        self.cams = list(cams)
+        self.rp = rp
+        self.n = init.n
+        self.deg = init.sh_degree
+        self.cap = int(capacity)
+        self.gated = gated
+        self.planes = torch.as_tensor(init.to_planes()).to(self.dev)
+        self.grads = torch.zeros_like(self.planes)
+        self.m = torch.zeros_like(self.planes)
+        self.v = torch.zeros_like(self.planes)
+        self.step_count = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        self.adam = sk.AdamParams(lr=lrs or sk.default_lrs(self.deg))
+        self.targets = targets            # [views][3 H W]
+        W, H = self.cams[0].width, self.cams[0].height
+        assert all(c.width == W and c.height == H for c in self.cams)
+        self.W, self.H = W, H
+        self.ws = sk.alloc_bytes(sk.forward_workspace_size(rp, self.n, [self.cams[0]], self.cap))
+        self.ws.zero_()
+        self.lws = sk.alloc_bytes(sk.loss_workspace_size(W, H)).zero_()
+        self.rgb = torch.zeros(3 * W * H, device=self.dev)
+        self.dl = torch.zeros_like(self.rgb)
+        self.loss = torch.zeros(1, device=self.dev)
+        self.gp = gate
+        if gated:
+            self.gstate = sk.alloc_bytes(sk.gate_state_size(gate))
+            sk.gate_init(gate, self.gstate)
+        self.ones = torch.ones(1, dtype=torch.int32, device=self.dev)
+        # pre-marshalled arguments for the hot loop
+        self.prep = sk.Prepared(self.planes, self.n, self.deg, self.cams, rp, self.ws, self.cap)
+        self.rgb_p, self.dl_p = self.rgb.data_ptr(), self.dl.data_ptr()
+        self.lws_p, self.lws_n = self.lws.data_ptr(), self.lws.numel()
+        self.planes_p, self.grads_p = self.planes.data_ptr(), self.grads.data_ptr()
+        self.m_p, self.v_p = self.m.data_ptr(), self.v.data_ptr()
+        self.step_p = self.step_count.data_ptr()
+        self.stride, self.F = int(self.planes.shape[1]), int(self.planes.shape[0])
+        self.adamc = self.adam.c()
+        if gated:
+            self.gpc = gate.c()
+            self.gstate_p = self.gstate.data_ptr()
+
+    def iteration(self, view: int, gate_slot: torch.Tensor, loss_slot: torch.Tensor | None = None,
+                  timer: StageTimer | None = None):
+        """Enqueue one iteration. gate_slot: a device int32[1] that receives
+        the decision (forced to 1 in a full run)."""
+        P, s = self.prep, torch.cuda.current_stream().cuda_stream
+        gate = gate_slot.data_ptr()
+        loss = self.loss if loss_slot is None else loss_slot
+        lossp = loss.data_ptr()
+        tgt = self.targets[view].data_ptr()
+        mark = timer.mark if timer is not None else (lambda: None)
+        e0 = mark()
+        P.project(view, s)
+        e1 = mark()
+        P.bin(view, s)
+        e2 = mark()
+        P.rasterize(view, self.rgb_p, s)
+        e3 = mark()
+        sk._check(sk.LIB.sgs_photometric_loss(self.rgb_p, tgt, self.W, self.H, C.c_float(0.2),
+                                              self.lws_p, self.lws_n, lossp, s))
+        e4 = mark()
+        if self.gated:
+            sk._check(sk.LIB.sgs_gate_update(C.byref(self.gpc), self.gstate_p, int(view), lossp,
+                                             gate, s))
+        else:
+            gate_slot.fill_(1)
+        e5 = mark()
+        sk._check(sk.LIB.sgs_photometric_loss_backward(self.rgb_p, tgt, self.W, self.H,
+                                                       C.c_float(0.2), self.lws_p, self.lws_n,
+                                                       gate, self.dl_p, s))
+        e6 = mark()
+        P.rasterize_backward(view, self.dl_p, gate, s)
+        e7 = mark()
+        P.project_backward(view, gate, self.grads_p, s)
+        e8 = mark()
+        sk._check(sk.LIB.sgs_adam_step(C.byref(self.adamc), self.planes_p, self.grads_p, self.m_p,
+                                       self.v_p, self.n, self.stride, self.F, self.step_p, gate,
+                                       s))
+        e9 = mark()
+        if timer is not None:
+            es = [e0, e1, e2, e3, e4, e5, e6, e7, e8, e9]
+            timer.events.append({k: (es[i], es[i + 1]) for i, k in enumerate(timer.names)})
+
+    def render(self, view: int, out: torch.Tensor):
+        self.prep.render_forward(view, out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+
+    def mean_loss(self, views) -> float:
+        """Forward-only sweep: mean photometric loss over the given views."""
+        vals = torch.zeros(len(views), device=self.dev)
+        for i, v in enumerate(views):
+            self.render(v, self.rgb)
+            sk.photometric_loss(self.rgb, self.targets[v], self.W, self.H, 0.2, self.lws,
+                                vals[i:i + 1])
+        return float(vals.mean().item())
+
+    def status(self):
+        return sk.read_status(self.ws)
+
+
+def render_targets(gt: S.Scene, cams, rp, capacity, device="cuda") -> torch.Tensor:
+    """Ground-truth images of every view, rendered from the ground-truth set."""
+    planes = torch.as_tensor(gt.to_planes()).to(device)
+    W, H = cams[0].width, cams[0].height
+    ws = sk.alloc_bytes(sk.forward_workspace_size(rp, gt.n, [cams[0]], capacity)).zero_()
+    out = torch.zeros(len(cams), 3 * W * H, device=device)
+    for i, c in enumerate(cams):
+        sk.render_forward(planes, gt.n, gt.sh_degree, [c], rp, ws, capacity, out[i])
+    flags, _, _ = sk.read_status(ws)
+    if flags:
+        raise RuntimeError(f"target rendering overflowed pair capacity ({flags})")
+    return out
+
+
+def measure_pairs(scene: S.Scene, cams, rp, device="cuda", probe_capacity=None) -> int:
+    """Largest number of (tile, Gaussian) pairs over the views (one sync per view)."""
+    planes = torch.as_tensor(scene.to_planes()).to(device)
+    cap = probe_capacity or 1
+    ws = sk.alloc_bytes(sk.forward_workspace_size(rp, scene.n, [cams[0]], cap)).zero_()
+    best = 0
+    for c in cams:
+        sk.project(planes, scene.n, scene.sh_degree, [c], rp, ws, cap)
+        sk.bin([c], scene.n, rp, ws, cap)
+        _, _, pairs = sk.read_status(ws)
+        sk.clear_status(ws)
+        best = max(best, pairs)
+    return best
