@@ -301,6 +301,29 @@ sgs_status sgs_adam_step(const sgs_adam_params* p, float* params, float* grads, 
                          float* v, int64_t n, int64_t stride, int32_t n_planes,
                          int32_t* d_step, const int32_t* d_gate, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Fused training step: the projection backward and the Adam update in one
+ * pass over all Gaussians (dense Adam: Gaussians visible in no view get a
+ * zero gradient and are still updated). Each Gaussian's gradient stays in
+ * registers; no gradient array is read or written. Gives the same result as
+ * sgs_project_backward into a zeroed gradient array followed by
+ * sgs_adam_step. g->data is updated in place; m, v have its layout.
+ * ------------------------------------------------------------------------- */
+sgs_status sgs_project_backward_adam(const sgs_gaussians* g, const sgs_camera* cams,
+                                     int32_t n_views, const sgs_raster_params* rp,
+                                     void* workspace, size_t workspace_bytes,
+                                     int64_t pair_capacity, const sgs_adam_params* adam,
+                                     float* m, float* v, int32_t* d_step,
+                                     const int32_t* d_gate, void* stream);
+
+/* sgs_rasterize_backward followed by sgs_project_backward_adam. */
+sgs_status sgs_render_backward_adam(const sgs_gaussians* g, const sgs_camera* cams,
+                                    int32_t n_views, const sgs_raster_params* rp, void* workspace,
+                                    size_t workspace_bytes, int64_t pair_capacity,
+                                    const float* dl_drgb, const sgs_adam_params* adam, float* m,
+                                    float* v, int32_t* d_step, const int32_t* d_gate,
+                                    void* stream);
+
 #ifdef __cplusplus
 }
 #endif

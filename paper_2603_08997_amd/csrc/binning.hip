@@ -27,13 +27,12 @@ struct VisibleSrc {  // 1 for every visible entry
     __device__ uint32_t operator()(int64_t e) const { return tiles[e] ? 1u : 0u; }
 };
 struct CompactSink {  // visible entries -> (depth bits, entry), in entry order
-    const uint32_t* tiles;
-    const float4* rec;
+    const uint32_t* depth;
     uint32_t* dkey;
     uint32_t* dval;
     __device__ void operator()(int64_t e, uint32_t v, uint32_t pos) const {
         if (v) {
-            dkey[pos] = __float_as_uint(rec[3 * e + 1].w);
+            dkey[pos] = depth[e];
             dval[pos] = (uint32_t)e;
         }
     }
@@ -124,46 +123,110 @@ __global__ void capacity_kernel(uint32_t* counters, int64_t capacity) {
     }
 }
 
-__global__ void __launch_bounds__(256) emit_kernel(const uint32_t* __restrict__ sorted_entry,
-                                                   const uint32_t* __restrict__ offsets,
-                                                   const float4* __restrict__ rec,
-                                                   const uint32_t* __restrict__ counters,
-                                                   int64_t n, Views views, RasterDev rp,
-                                                   int64_t capacity, uint32_t* __restrict__ ptile,
-                                                   uint32_t* __restrict__ pentry) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= (int64_t)counters[kVisible]) return;
-    const uint32_t e = sorted_entry[k];
-    const ViewDev& V = views.v[(int)(e / n)];
-    const float4 r0 = rec[3 * (int64_t)e], r1 = rec[3 * (int64_t)e + 1];
-    int x0, x1, y0, y1;
-    tile_rect(r0.x, r0.y, (int)r1.z, rp.tile_w, rp.tile_h, V.tiles_x, V.tiles_y, &x0, &x1, &y0, &y1);
-    int64_t off = offsets[k];
-    for (int ty = y0; ty < y1; ++ty) {
-        const uint32_t row = (uint32_t)(V.tile_offset + ty * V.tiles_x);
-        for (int tx = x0; tx < x1; ++tx, ++off) {
-            if (off < capacity) {
-                ptile[off] = row + (uint32_t)tx;
-                pentry[off] = e;
-            }
-        }
+// Pair emission, load balanced over pairs: each workgroup writes a fixed
+// window of kEmitTile consecutive pairs. The Gaussians (in depth order) whose
+// pair ranges meet the window are found by binary search in the offsets, their
+// tile rectangles staged in LDS, and every thread expands its pairs to
+// (tile, entry) with coalesced stores. Pair q of a Gaussian is tile
+// (x0 + q % w, y0 + q / w) of its rectangle, row-major.
+constexpr int kEmitThreads = 256;
+constexpr int kEmitItems = 8;
+constexpr int kEmitTile = kEmitThreads * kEmitItems;
+
+__device__ __forceinline__ uint32_t upper_bound_u32(const uint32_t* a, uint32_t n, uint32_t x) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] <= x) lo = mid + 1; else hi = mid;
     }
+    return lo;
+}
+
+__global__ void __launch_bounds__(kEmitThreads) emit_kernel(
+    const uint32_t* __restrict__ sorted_entry, const uint32_t* __restrict__ offsets,
+    const float4* __restrict__ rec, const uint32_t* __restrict__ counters, int64_t n, Views views,
+    RasterDev rp, uint32_t* __restrict__ ptile, uint32_t* __restrict__ pentry) {
+    __shared__ uint32_t s_off[kEmitTile + 1];
+    __shared__ uint32_t s_ent[kEmitTile];
+    __shared__ uint32_t s_base[kEmitTile];   // global tile of the rectangle's first tile
+    __shared__ uint16_t s_w[kEmitTile];      // rectangle width in tiles
+    __shared__ uint16_t s_tx[kEmitTile];     // tiles per row of the Gaussian's view
+    __shared__ uint32_t s_k0, s_cnt;
+    const uint32_t P = counters[kPairsWritten];
+    const uint32_t nvis = counters[kVisible];
+    const uint32_t p0 = blockIdx.x * (uint32_t)kEmitTile;
+    if (p0 >= P) return;   // uniform across the workgroup
+    const uint32_t p_last = min(p0 + (uint32_t)kEmitTile, P) - 1u;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        const uint32_t k0 = upper_bound_u32(offsets, nvis, p0) - 1u;
+        const uint32_t k1 = upper_bound_u32(offsets, nvis, p_last) - 1u;
+        s_k0 = k0;
+        s_cnt = k1 - k0 + 1u;
+        s_off[k1 - k0 + 1u] = (k1 + 1u < nvis) ? offsets[k1 + 1u] : 0xffffffffu;
+    }
+    __syncthreads();
+    const uint32_t k0 = s_k0, cnt = s_cnt;
+    for (uint32_t j = tid; j < cnt; j += kEmitThreads) {
+        const uint32_t k = k0 + j;
+        const uint32_t e = sorted_entry[k];
+        const ViewDev& V = views.v[(int)(e / n)];
+        const float4 r0 = rec[3 * (int64_t)e], r1 = rec[3 * (int64_t)e + 1];
+        int x0, x1, y0, y1;
+        tile_rect(r0.x, r0.y, (int)r1.z, rp.tile_w, rp.tile_h, V.tiles_x, V.tiles_y, &x0, &x1, &y0,
+                  &y1);
+        s_off[j] = offsets[k];
+        s_ent[j] = e;
+        s_base[j] = (uint32_t)(V.tile_offset + y0 * V.tiles_x + x0);
+        s_w[j] = (uint16_t)(x1 - x0);
+        s_tx[j] = (uint16_t)V.tiles_x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kEmitItems; ++it) {
+        const uint32_t p = p0 + (uint32_t)(it * kEmitThreads + tid);
+        if (p > p_last) break;
+        // Gaussian j of the window with s_off[j] <= p < s_off[j + 1]
+        uint32_t lo = 0, hi = cnt;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s_off[mid] <= p) lo = mid; else hi = mid;
+        }
+        const uint32_t q = p - s_off[lo];
+        const uint32_t w = s_w[lo];
+        ptile[p] = s_base[lo] + (q / w) * s_tx[lo] + (q % w);
+        pentry[p] = s_ent[lo];
+    }
+}
+
+// [start, end) of every tile by binary search in the sorted tile keys
+// (empty tiles: [0, 0)).
+__global__ void __launch_bounds__(256) ranges_kernel(const uint32_t* __restrict__ ptile,
+                                                     const uint32_t* __restrict__ counters,
+                                                     int64_t total_tiles,
+                                                     uint32_t* __restrict__ ranges) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total_tiles) return;
+    const uint32_t P = counters[kPairsWritten];
+    uint32_t lo = 0, hi = P;
+    while (lo < hi) {  // first key >= t
+        const uint32_t mid = (lo + hi) >> 1;
+        if (ptile[mid] < (uint32_t)t) lo = mid + 1; else hi = mid;
+    }
+    const uint32_t a = lo;
+    hi = P;
+    while (lo < hi) {  // first key > t
+        const uint32_t mid = (lo + hi) >> 1;
+        if (ptile[mid] <= (uint32_t)t) lo = mid + 1; else hi = mid;
+    }
+    const bool empty = lo == a;
+    ranges[2 * t] = empty ? 0u : a;
+    ranges[2 * t + 1] = empty ? 0u : lo;
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
-}
-
-__global__ void __launch_bounds__(256) ranges_kernel(const uint32_t* __restrict__ ptile,
-                                                     const uint32_t* __restrict__ counters,
-                                                     uint32_t* __restrict__ ranges) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t P = counters[kPairsWritten];
-    if (i >= P) return;
-    const uint32_t t = ptile[i];
-    if (i == 0 || ptile[i - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)i;
-    if (i == P - 1 || ptile[i + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(i + 1);
 }
 
 }  // namespace
@@ -199,8 +262,10 @@ hipError_t launch_bin(const Views& views, const RasterDev& rp, int64_t n, const 
     if ((err = fill_u32(counters + kVisible, kEvaluated + 2 - kVisible, 0u, s)) != hipSuccess)
         return err;
     if (E > 0) {
-        err = device_scan(VisibleSrc{tiles, E}, CompactSink{tiles, rec, dkey[0], dval[0]}, E, sums,
-                          counters + kVisible, s);
+        err = device_scan(VisibleSrc{tiles, E},
+                          CompactSink{reinterpret_cast<const uint32_t*>(ws + L.depth), dkey[0],
+                                      dval[0]},
+                          E, sums, counters + kVisible, s);
         if (err != hipSuccess) return err;
         // stable sort by depth: ties keep ascending entry order
         int res = 0;
@@ -211,9 +276,10 @@ hipError_t launch_bin(const Views& views, const RasterDev& rp, int64_t n, const 
                           E, sums, counters + kPairs, s);
         if (err != hipSuccess) return err;
         hipLaunchKernelGGL(capacity_kernel, dim3(1), dim3(1), 0, s, counters, L.capacity);
-        hipLaunchKernelGGL(emit_kernel, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, s,
-                           dval[res], offsets, rec, counters, n, views, rp, L.capacity, ptile[0],
-                           pentry[0]);
+        if (L.capacity > 0)
+            hipLaunchKernelGGL(emit_kernel, dim3((unsigned)((L.capacity + kEmitTile - 1) / kEmitTile)),
+                               dim3(kEmitThreads), 0, s, dval[res], offsets, rec, counters, n, views,
+                               rp, ptile[0], pentry[0]);
         if ((err = hipGetLastError()) != hipSuccess) return err;
         // stable sort of the pairs by tile
         int tres = 0;
@@ -221,11 +287,9 @@ hipError_t launch_bin(const Views& views, const RasterDev& rp, int64_t n, const 
                          totals, s, &tres);
         if (err != hipSuccess) return err;
     }
-    if ((err = fill_u32(ranges, 2 * L.total_tiles, 0u, s)) != hipSuccess) return err;
-    if (E > 0 && L.capacity > 0) {
-        hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((L.capacity + 255) / 256)), dim3(256), 0,
-                           s, ptile[L.tile_result], counters, ranges);
-    }
+    if (L.total_tiles > 0)
+        hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((L.total_tiles + 255) / 256)), dim3(256),
+                           0, s, ptile[L.tile_result], counters, L.total_tiles, ranges);
     return hipGetLastError();
 }
 

@@ -190,6 +190,7 @@ void make_layout(const Views& views, int64_t n, int64_t capacity, Layout* L) {
     L->records = take(sizeof(float) * kRecordFloats * (size_t)E);
     L->accum = take(sizeof(float) * kAccumFloats * (size_t)E);
     L->tiles = take(sizeof(uint32_t) * (size_t)E);
+    L->depth = take(sizeof(uint32_t) * (size_t)E);
     L->dkey[0] = take(sizeof(uint32_t) * (size_t)E);
     L->dkey[1] = take(sizeof(uint32_t) * (size_t)E);
     L->dval[0] = take(sizeof(uint32_t) * (size_t)E);
@@ -278,7 +279,7 @@ sgs_status sgs_project(const sgs_gaussians* g, const sgs_camera* cams, int32_t n
     SGS_HIP(sgs::launch_project(g->data, g->n, g->stride, g->sh_degree, P.views, P.rd,
                                 reinterpret_cast<float*>(ws + P.L.records),
                                 reinterpret_cast<uint32_t*>(ws + P.L.tiles),
-                                reinterpret_cast<uint32_t*>(ws + P.L.counters), s),
+                                reinterpret_cast<uint32_t*>(ws + P.L.depth), s),
             "project");
     return SGS_OK;
 }
@@ -298,6 +299,7 @@ sgs_status sgs_load_records(const sgs_camera* cams, int32_t n_views, int64_t n,
     SGS_HIP(sgs::launch_load_records(P.L.entries, u, v, depth, radius, conic, opacity, rgb, n,
                                      P.views, P.rd, reinterpret_cast<float*>(ws + P.L.records),
                                      reinterpret_cast<uint32_t*>(ws + P.L.tiles),
+                                     reinterpret_cast<uint32_t*>(ws + P.L.depth),
                                      static_cast<hipStream_t>(stream)),
             "load_records");
     return SGS_OK;
@@ -343,7 +345,7 @@ sgs_status sgs_render_forward(const sgs_gaussians* g, const sgs_camera* cams, in
     SGS_HIP(sgs::launch_project(g->data, g->n, g->stride, g->sh_degree, P.views, P.rd,
                                 reinterpret_cast<float*>(ws + P.L.records),
                                 reinterpret_cast<uint32_t*>(ws + P.L.tiles),
-                                reinterpret_cast<uint32_t*>(ws + P.L.counters), s),
+                                reinterpret_cast<uint32_t*>(ws + P.L.depth), s),
             "project");
     SGS_HIP(sgs::launch_bin(P.views, P.rd, g->n, P.L, ws, s), "bin");
     SGS_HIP(sgs::launch_rasterize(P.views, P.rd, P.L, ws, out_rgb, s), "rasterize");
@@ -526,9 +528,12 @@ sgs_status sgs_gate_read(const sgs_gate_params* p, const void* d_state, sgs_gate
     return SGS_OK;
 }
 
+static sgs_status check_adam(const sgs_adam_params* p);
+
 sgs_status sgs_adam_step(const sgs_adam_params* p, float* params, float* grads, float* m,
                          float* v, int64_t n, int64_t stride, int32_t n_planes, int32_t* d_step,
                          const int32_t* d_gate, void* stream) {
+    sgs_status st;
     if (!p || !params || !grads || !m || !v || !d_step)
         return fail(SGS_ERR_INVALID_ARG, "null pointer argument");
     if (n < 0 || stride < n || stride % 64 != 0 || stride <= 0)
@@ -537,12 +542,62 @@ sgs_status sgs_adam_step(const sgs_adam_params* p, float* params, float* grads, 
         return fail(SGS_ERR_INVALID_ARG, "n_planes %d not in [1, %d]", n_planes, SGS_MAX_PLANES);
     if (!aligned(params, 16) || !aligned(grads, 16) || !aligned(m, 16) || !aligned(v, 16))
         return fail(SGS_ERR_INVALID_ARG, "arrays must be 16-byte aligned");
-    if (!(p->beta1 >= 0.0 && p->beta1 < 1.0) || !(p->beta2 >= 0.0 && p->beta2 < 1.0) ||
-        !(p->eps >= 0.0))
-        return fail(SGS_ERR_INVALID_ARG, "Adam constants out of range");
+    if ((st = check_adam(p)) != SGS_OK) return st;
     SGS_HIP(sgs::launch_adam(p, params, grads, m, v, n, stride, n_planes, d_step, d_gate,
                              static_cast<hipStream_t>(stream)),
             "adam");
+    return SGS_OK;
+}
+
+static sgs_status check_adam(const sgs_adam_params* p) {
+    if (!p) return fail(SGS_ERR_INVALID_ARG, "adam params are null");
+    if (!(p->beta1 >= 0.0 && p->beta1 < 1.0) || !(p->beta2 >= 0.0 && p->beta2 < 1.0) ||
+        !(p->eps >= 0.0))
+        return fail(SGS_ERR_INVALID_ARG, "Adam constants out of range");
+    return SGS_OK;
+}
+
+sgs_status sgs_project_backward_adam(const sgs_gaussians* g, const sgs_camera* cams,
+                                     int32_t n_views, const sgs_raster_params* rp,
+                                     void* workspace, size_t workspace_bytes,
+                                     int64_t pair_capacity, const sgs_adam_params* adam,
+                                     float* m, float* v, int32_t* d_step,
+                                     const int32_t* d_gate, void* stream) {
+    sgs_status st = check_gaussians(g);
+    if (st != SGS_OK) return st;
+    if ((st = check_adam(adam)) != SGS_OK) return st;
+    Prepared P;
+    if ((st = prepare(rp, g->n, cams, n_views, pair_capacity, &P)) != SGS_OK) return st;
+    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
+    if (!m || !v || !d_step) return fail(SGS_ERR_INVALID_ARG, "m, v or step is null");
+    SGS_HIP(sgs::launch_project_backward_adam(g->data, g->n, g->stride, g->sh_degree, P.views,
+                                              P.rd, P.L, static_cast<char*>(workspace), adam, m, v,
+                                              d_step, d_gate, static_cast<hipStream_t>(stream)),
+            "project_backward_adam");
+    return SGS_OK;
+}
+
+sgs_status sgs_render_backward_adam(const sgs_gaussians* g, const sgs_camera* cams,
+                                    int32_t n_views, const sgs_raster_params* rp, void* workspace,
+                                    size_t workspace_bytes, int64_t pair_capacity,
+                                    const float* dl_drgb, const sgs_adam_params* adam, float* m,
+                                    float* v, int32_t* d_step, const int32_t* d_gate,
+                                    void* stream) {
+    sgs_status st = check_gaussians(g);
+    if (st != SGS_OK) return st;
+    if ((st = check_adam(adam)) != SGS_OK) return st;
+    Prepared P;
+    if ((st = prepare(rp, g->n, cams, n_views, pair_capacity, &P)) != SGS_OK) return st;
+    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
+    if (!dl_drgb) return fail(SGS_ERR_INVALID_ARG, "dl_drgb is null");
+    if (!m || !v || !d_step) return fail(SGS_ERR_INVALID_ARG, "m, v or step is null");
+    char* ws = static_cast<char*>(workspace);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SGS_HIP(sgs::launch_rasterize_backward(P.views, P.rd, P.L, ws, dl_drgb, d_gate, s),
+            "rasterize_backward");
+    SGS_HIP(sgs::launch_project_backward_adam(g->data, g->n, g->stride, g->sh_degree, P.views,
+                                              P.rd, P.L, ws, adam, m, v, d_step, d_gate, s),
+            "project_backward_adam");
     return SGS_OK;
 }
 

@@ -4,6 +4,8 @@
 #include "sgs_internal.hpp"
 #include "sgs_device.hpp"
 
+#include <utility>
+
 namespace sgs {
 
 namespace {
@@ -150,7 +152,8 @@ template <int sh_degree>
 __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ planes, int64_t n,
                                                       int64_t stride, Views views,
                                                       RasterDev rp, float4* __restrict__ rec,
-                                                      uint32_t* __restrict__ tiles) {
+                                                      uint32_t* __restrict__ tiles,
+                                                      uint32_t* __restrict__ dkey) {
     const int64_t entries = n * views.n;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= entries) return;
@@ -202,8 +205,10 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
                 ntiles = (uint32_t)((x1 - x0) * (y1 - y0));
                 r0 = make_float4(u, v, ca, cb);
                 r1 = make_float4(cc, o, rf, G.tz);
+                const uint32_t mask = (col[0] >= 0.f ? 1u : 0u) | (col[1] >= 0.f ? 2u : 0u) |
+                                      (col[2] >= 0.f ? 4u : 0u);
                 r2 = make_float4(fmaxf(col[0], 0.f), fmaxf(col[1], 0.f), fmaxf(col[2], 0.f),
-                                 __uint_as_float(ntiles));
+                                 __uint_as_float(mask));
             }
         }
     }
@@ -211,6 +216,7 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
     rec[3 * e + 1] = r1;
     rec[3 * e + 2] = r2;
     tiles[e] = ntiles;
+    dkey[e] = __float_as_uint(r1.w);
 }
 
 __global__ void __launch_bounds__(256) load_records_kernel(
@@ -218,7 +224,7 @@ __global__ void __launch_bounds__(256) load_records_kernel(
     const float* __restrict__ depth, const int32_t* __restrict__ radius,
     const float* __restrict__ conic, const float* __restrict__ opacity,
     const float* __restrict__ rgb, Views views, RasterDev rp, float4* __restrict__ rec,
-    uint32_t* __restrict__ tiles) {
+    uint32_t* __restrict__ tiles, uint32_t* __restrict__ dkey) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= entries) return;
     int64_t i;
@@ -234,26 +240,205 @@ __global__ void __launch_bounds__(256) load_records_kernel(
             ntiles = (uint32_t)((x1 - x0) * (y1 - y0));
             r0 = make_float4(u[e], v[e], conic[3 * e], conic[3 * e + 1]);
             r1 = make_float4(conic[3 * e + 2], opacity[e], (float)r, depth[e]);
-            r2 = make_float4(rgb[3 * e], rgb[3 * e + 1], rgb[3 * e + 2], __uint_as_float(ntiles));
+            r2 = make_float4(rgb[3 * e], rgb[3 * e + 1], rgb[3 * e + 2], __uint_as_float(7u));
         }
     }
     rec[3 * e + 0] = r0;
     rec[3 * e + 1] = r1;
     rec[3 * e + 2] = r2;
     tiles[e] = ntiles;
+    dkey[e] = __float_as_uint(r1.w);
 }
 
-// Adjoint of the projection. One thread per Gaussian; sums the per-view
-// record gradients of every view in which the Gaussian is visible, then adds
-// the parameter gradient to grads.
-template <int sh_degree>
-__global__ void __launch_bounds__(256) project_backward_kernel(
-    const float* __restrict__ planes, int64_t n, int64_t stride, Views views,
-    RasterDev rp, const float4* __restrict__ rec, const uint32_t* __restrict__ tiles,
-    const float4* __restrict__ acc, const int32_t* __restrict__ gate, float* __restrict__ grads) {
-    if (gate_closed(gate)) return;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// Y_k and its gradient for a compile-time index k (the unrolled SH loops fold
+// the switch away).
+template <int k>
+__device__ __forceinline__ float sh_k(float x, float y, float z) {
+    switch (k) {
+        case 0: return kY0;
+        case 1: return -kY1 * y;
+        case 2: return kY1 * z;
+        case 3: return -kY1 * x;
+        case 4: return kY2a * x * y;
+        case 5: return -kY2a * y * z;
+        case 6: return kY2b * (2.f * z * z - x * x - y * y);
+        case 7: return -kY2a * x * z;
+        case 8: return kY2c * (x * x - y * y);
+        case 9: return -kY3a * y * (3.f * x * x - y * y);
+        case 10: return kY3b * x * y * z;
+        case 11: return -kY3c * y * (4.f * z * z - x * x - y * y);
+        case 12: return kY3d * z * (2.f * z * z - 3.f * x * x - 3.f * y * y);
+        case 13: return -kY3c * x * (4.f * z * z - x * x - y * y);
+        case 14: return kY3e * z * (x * x - y * y);
+        default: return -kY3a * x * (x * x - 3.f * y * y);
+    }
+}
+
+template <int k>
+__device__ __forceinline__ void sh_k_grad(float x, float y, float z, float g[3]) {
+    float w[16] = {0.f};
+    w[k] = 1.f;
+    sh_grad_dir(k < 1 ? 0 : (k < 4 ? 1 : (k < 9 ? 2 : 3)), x, y, z, w, g);
+}
+
+// Per-view quantities of one visible entry that the SH part of the backward
+// needs: unit view direction d, |mu - C|, and dL/d(raw colour) (zero on
+// channels the forward clamped at 0).
+struct ViewSH {
+    float d[3], dn, draw[3];
+};
+
+__device__ __forceinline__ void view_sh(const float mu[3], const ViewDev& V, float4 a1, float4 a2,
+                                        float4 r2, ViewSH& o) {
+    const float dir[3] = {mu[0] - V.C[0], mu[1] - V.C[1], mu[2] - V.C[2]};
+    o.dn = sqrtf(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) o.d[c] = dir[c] / o.dn;
+    const uint32_t mask = __float_as_uint(r2.w);
+    o.draw[0] = (mask & 1u) ? a1.z : 0.f;
+    o.draw[1] = (mask & 2u) ? a1.w : 0.f;
+    o.draw[2] = (mask & 4u) ? a2.x : 0.f;
+}
+
+// Gradient of the non-SH raw parameters of one visible entry (mean through
+// the projection, log-scale, quaternion, opacity logit), ADDED to the outputs.
+// Returns false if the geometry is culled (never for a visible entry).
+__device__ __forceinline__ bool geom_grads(const float mu[3], const float ls[3], const float q[4],
+                                           float logit, const ViewDev& V, const RasterDev& rp,
+                                           float4 a0, float4 a1, float g_mu[3], float g_ls[3],
+                                           float g_q[4], float* g_logit) {
+    const float d_u = a0.x, d_v = a0.y, d_ca = a0.z, d_cb = a0.w, d_cc = a1.x, d_o = a1.y;
+    Geometry G;
+    if (!compute_geometry(mu, ls, q, V, rp, G)) return false;
+    // opacity = sigmoid(logit)
+    const float o = sigmoidf(logit);
+    *g_logit += d_o * o * (1.f - o);
+    // conic = inverse of Sigma2D': dSigma' = -Q G Q with G the symmetric
+    // gradient [[da, db/2], [db/2, dc]].
+    const float det = G.sxx * G.syy - G.sxy * G.sxy;
+    const float A = G.syy / det, B = -G.sxy / det, C = G.sxx / det;
+    const float g00 = d_ca, g01 = 0.5f * d_cb, g11 = d_cc;
+    const float p00 = A * g00 + B * g01, p01 = A * g01 + B * g11;
+    const float p10 = B * g00 + C * g01, p11 = B * g01 + C * g11;
+    const float d_sxx = -(p00 * A + p01 * B);
+    const float d_sxy = -2.f * (p00 * B + p01 * C);   // symmetric entry counted twice
+    const float d_syy = -(p10 * B + p11 * C);
+    // Sigma2D = T Sigma T^T: dSigma = T^T H T, dT = 2 H T Sigma, H = [[dxx, dxy/2],[dxy/2, dyy]]
+    const float h00 = d_sxx, h01 = 0.5f * d_sxy, h11 = d_syy;
+    const float* T = G.T;
+    float HT[6];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        HT[c] = h00 * T[c] + h01 * T[3 + c];
+        HT[3 + c] = h01 * T[c] + h11 * T[3 + c];
+    }
+    float dS[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dS[3 * r + c] = T[r] * HT[c] + T[3 + r] * HT[3 + c];
+    const float* S = G.Sig;
+    const float Sm[9] = {S[0], S[1], S[2], S[1], S[3], S[4], S[2], S[4], S[5]};
+    float dT[6];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            dT[3 * r + c] = 2.f * (HT[3 * r] * Sm[c] + HT[3 * r + 1] * Sm[3 + c] +
+                                   HT[3 * r + 2] * Sm[6 + c]);
+    // T = J W: dJ = dT W^T (only J00, J02, J11, J12 vary)
+    const float dJ00 = dT[0] * V.R[0] + dT[1] * V.R[1] + dT[2] * V.R[2];
+    const float dJ02 = dT[0] * V.R[6] + dT[1] * V.R[7] + dT[2] * V.R[8];
+    const float dJ11 = dT[3] * V.R[3] + dT[4] * V.R[4] + dT[5] * V.R[5];
+    const float dJ12 = dT[3] * V.R[6] + dT[4] * V.R[7] + dT[5] * V.R[8];
+    const float tz = G.tz, tz2 = tz * tz;
+    float d_tx = 0.f, d_ty = 0.f, d_tz = 0.f;
+    d_tz += -dJ00 * V.fx / tz2 + dJ02 * V.fx * G.xr / tz2 - dJ11 * V.fy / tz2 +
+            dJ12 * V.fy * G.yr / tz2;
+    const float d_xr = -dJ02 * V.fx / tz, d_yr = -dJ12 * V.fy / tz;
+    if (!G.clx) { d_tx += d_xr / tz; d_tz += -d_xr * G.tx / tz2; }
+    if (!G.cly) { d_ty += d_yr / tz; d_tz += -d_yr * G.ty / tz2; }
+    // pixel centre u = fx tx/tz + cx, v = fy ty/tz + cy
+    d_tx += d_u * V.fx / tz;
+    d_ty += d_v * V.fy / tz;
+    d_tz += -d_u * V.fx * G.tx / tz2 - d_v * V.fy * G.ty / tz2;
+    // t = R mu + t0
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g_mu[c] += V.R[c] * d_tx + V.R[3 + c] * d_ty + V.R[6 + c] * d_tz;
+    // Sigma = M M^T, M = Rq diag(s): dM = 2 dSigma M; dRq = dM diag(s); ds_j = sum_i dM_ij Rq_ij
+    float M[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) M[3 * r + c] = G.Rq[3 * r + c] * G.s[c];
+    float dM[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            dM[3 * r + c] = 2.f * (dS[3 * r] * M[c] + dS[3 * r + 1] * M[3 + c] +
+                                   dS[3 * r + 2] * M[6 + c]);
+    float dR[9];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float ds = 0.f;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            dR[3 * r + c] = dM[3 * r + c] * G.s[c];
+            ds += dM[3 * r + c] * G.Rq[3 * r + c];
+        }
+        g_ls[c] += ds * G.s[c];
+    }
+    // Rq(qn): derivative of the unit-quaternion rotation matrix
+    const float w = G.qn[0], x = G.qn[1], y = G.qn[2], z = G.qn[3];
+    float dqn[4];
+    dqn[0] = 2.f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    dqn[1] = 2.f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.f * x * dR[4] - w * dR[5] +
+                    z * dR[6] + w * dR[7] - 2.f * x * dR[8]);
+    dqn[2] = 2.f * (-2.f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] -
+                    w * dR[6] + z * dR[7] - 2.f * y * dR[8]);
+    dqn[3] = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] +
+                    y * dR[5] + x * dR[6] + y * dR[7]);
+    // qn = q/|q|
+    const float dot = dqn[0] * w + dqn[1] * x + dqn[2] * y + dqn[3] * z;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) g_q[c] += (dqn[c] - G.qn[c] * dot) / G.qnorm;
+    return true;
+}
+
+// SH part of the backward for coefficient k of one view: dL/df_{k,c} is
+// d_raw[c] Y_k(d), and the colour's dependence on the view direction adds
+// (sum_c d_raw[c] f_{k,c}) grad Y_k(d), projected orthogonally to d and
+// divided by |mu - C|, to the mean gradient.
+template <int sh_degree, int k>
+__device__ __forceinline__ void sh_term(const ViewSH& o, const float f[3], float gk[3],
+                                        float g_mu[3]) {
+    const float Yk = sh_k<k>(o.d[0], o.d[1], o.d[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gk[c] += o.draw[c] * Yk;
+    if constexpr (k > 0) {
+        const float wk = o.draw[0] * f[0] + o.draw[1] * f[1] + o.draw[2] * f[2];
+        float gd[3];
+        sh_k_grad<k>(o.d[0], o.d[1], o.d[2], gd);
+        const float dot = gd[0] * o.d[0] + gd[1] * o.d[1] + gd[2] * o.d[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) g_mu[c] += wk * (gd[c] - o.d[c] * dot) / o.dn;
+    }
+}
+
+// The per-Gaussian backward, streaming its SH coefficients. kFused: apply Adam
+// to every plane (dense: also when the Gaussian is visible in no view);
+// otherwise add the gradient to grads (visible Gaussians only).
+template <int sh_degree, bool kFused, bool kMulti>
+__device__ __forceinline__ void gaussian_backward(float* __restrict__ planes, int64_t n,
+                                                  int64_t stride, int64_t i, const Views& views,
+                                                  const RasterDev& rp,
+                                                  const float4* __restrict__ rec,
+                                                  const uint32_t* __restrict__ tiles,
+                                                  const float4* __restrict__ acc,
+                                                  float* __restrict__ grads, const AdamDev* ad,
+                                                  const AdamStep* as, float* __restrict__ m,
+                                                  float* __restrict__ v) {
     constexpr int K = (sh_degree + 1) * (sh_degree + 1);
     float mu[3], ls[3], q[4];
 #pragma unroll
@@ -263,185 +448,114 @@ __global__ void __launch_bounds__(256) project_backward_kernel(
 #pragma unroll
     for (int k = 0; k < 4; ++k) q[k] = planes[(6 + k) * stride + i];
     const float logit = planes[10 * stride + i];
-
     float g_mu[3] = {0.f, 0.f, 0.f}, g_ls[3] = {0.f, 0.f, 0.f}, g_q[4] = {0.f, 0.f, 0.f, 0.f};
     float g_logit = 0.f;
-    float g_sh[3 * K];
-#pragma unroll
-    for (int k = 0; k < 3 * K; ++k) g_sh[k] = 0.f;
     bool any = false;
-
+    ViewSH one;  // the single view's SH quantities (kMulti == false)
     for (int vi = 0; vi < views.n; ++vi) {
         const int64_t e = (int64_t)vi * n + i;
         if (tiles[e] == 0) continue;
-        const float4 a0 = acc[3 * e], a1 = acc[3 * e + 1], a2 = acc[3 * e + 2];
-        const float d_u = a0.x, d_v = a0.y, d_ca = a0.z, d_cb = a0.w, d_cc = a1.x, d_o = a1.y;
-        const float d_rgb[3] = {a1.z, a1.w, a2.x};
-        const ViewDev& V = views.v[vi];
-        Geometry G;
-        if (!compute_geometry(mu, ls, q, V, rp, G)) continue;
-        any = true;
-
-        // opacity = sigmoid(logit)
-        const float o = sigmoidf(logit);
-        g_logit += d_o * o * (1.f - o);
-
-        // colour = max(0, sum_k f_k Y_k(d) + 0.5), d = (mu - C)/|mu - C|
-        float dir[3] = {mu[0] - V.C[0], mu[1] - V.C[1], mu[2] - V.C[2]};
-        const float dn = sqrtf(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
-        const float d[3] = {dir[0] / dn, dir[1] / dn, dir[2] / dn};
-        float Y[16];
-        sh_eval(sh_degree, d[0], d[1], d[2], Y);
-        float raw[3] = {0.5f, 0.5f, 0.5f};
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) raw[c] += planes[(11 + 3 * k + c) * stride + i] * Y[k];
-        float d_raw[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) d_raw[c] = raw[c] >= 0.f ? d_rgb[c] : 0.f;
-        float wY[16];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            float s = 0.f;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                g_sh[3 * k + c] += d_raw[c] * Y[k];
-                s += d_raw[c] * planes[(11 + 3 * k + c) * stride + i];
-            }
-            wY[k] = s;
+        const float4 a0 = acc[3 * e], a1 = acc[3 * e + 1];
+        if (geom_grads(mu, ls, q, logit, views.v[vi], rp, a0, a1, g_mu, g_ls, g_q, &g_logit)) {
+            any = true;
+            if constexpr (!kMulti) view_sh(mu, views.v[vi], a1, acc[3 * e + 2], rec[3 * e + 2], one);
         }
-        if (sh_degree > 0) {
-            float gd[3];
-            sh_grad_dir(sh_degree, d[0], d[1], d[2], wY, gd);
-            const float dot = gd[0] * d[0] + gd[1] * d[1] + gd[2] * d[2];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) g_mu[c] += (gd[c] - d[c] * dot) / dn;
-        }
-
-        // conic = inverse of Sigma2D': dSigma' = -Q G Q with G the symmetric
-        // gradient [[da, db/2], [db/2, dc]].
-        const float det = G.sxx * G.syy - G.sxy * G.sxy;
-        const float A = G.syy / det, B = -G.sxy / det, C = G.sxx / det;
-        const float g00 = d_ca, g01 = 0.5f * d_cb, g11 = d_cc;
-        // P = Q G
-        const float p00 = A * g00 + B * g01, p01 = A * g01 + B * g11;
-        const float p10 = B * g00 + C * g01, p11 = B * g01 + C * g11;
-        const float d_sxx = -(p00 * A + p01 * B);
-        const float d_sxy = -2.f * (p00 * B + p01 * C);   // symmetric entry counted twice
-        const float d_syy = -(p10 * B + p11 * C);
-        // Sigma2D = T Sigma T^T: dSigma = T^T H T, dT = 2 H T Sigma, H = [[dxx, dxy/2],[dxy/2, dyy]]
-        const float h00 = d_sxx, h01 = 0.5f * d_sxy, h11 = d_syy;
-        const float* T = G.T;
-        float HT[6];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            HT[c] = h00 * T[c] + h01 * T[3 + c];
-            HT[3 + c] = h01 * T[c] + h11 * T[3 + c];
-        }
-        // dSigma (full symmetric 3x3) = T^T (H T)
-        float dS[9];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) dS[3 * r + c] = T[r] * HT[c] + T[3 + r] * HT[3 + c];
-        // dT = 2 (H T) Sigma
-        const float* S = G.Sig;
-        const float Sm[9] = {S[0], S[1], S[2], S[1], S[3], S[4], S[2], S[4], S[5]};
-        float dT[6];
-#pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                dT[3 * r + c] = 2.f * (HT[3 * r] * Sm[c] + HT[3 * r + 1] * Sm[3 + c] +
-                                       HT[3 * r + 2] * Sm[6 + c]);
-        // T = J W: dJ = dT W^T (only J00, J02, J11, J12 vary)
-        const float dJ00 = dT[0] * V.R[0] + dT[1] * V.R[1] + dT[2] * V.R[2];
-        const float dJ02 = dT[0] * V.R[6] + dT[1] * V.R[7] + dT[2] * V.R[8];
-        const float dJ11 = dT[3] * V.R[3] + dT[4] * V.R[4] + dT[5] * V.R[5];
-        const float dJ12 = dT[3] * V.R[6] + dT[4] * V.R[7] + dT[5] * V.R[8];
-        const float tz = G.tz, tz2 = tz * tz;
-        float d_tx = 0.f, d_ty = 0.f, d_tz = 0.f;
-        d_tz += -dJ00 * V.fx / tz2 + dJ02 * V.fx * G.xr / tz2 - dJ11 * V.fy / tz2 +
-                dJ12 * V.fy * G.yr / tz2;
-        const float d_xr = -dJ02 * V.fx / tz, d_yr = -dJ12 * V.fy / tz;
-        if (!G.clx) { d_tx += d_xr / tz; d_tz += -d_xr * G.tx / tz2; }
-        if (!G.cly) { d_ty += d_yr / tz; d_tz += -d_yr * G.ty / tz2; }
-        // pixel centre u = fx tx/tz + cx, v = fy ty/tz + cy
-        d_tx += d_u * V.fx / tz;
-        d_ty += d_v * V.fy / tz;
-        d_tz += -d_u * V.fx * G.tx / tz2 - d_v * V.fy * G.ty / tz2;
-        // t = R mu + t0
-#pragma unroll
-        for (int c = 0; c < 3; ++c) g_mu[c] += V.R[c] * d_tx + V.R[3 + c] * d_ty + V.R[6 + c] * d_tz;
-
-        // Sigma = M M^T, M = Rq diag(s): dM = 2 dSigma M; dRq = dM diag(s); ds_j = sum_i dM_ij Rq_ij
-        float M[9];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) M[3 * r + c] = G.Rq[3 * r + c] * G.s[c];
-        float dM[9];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                dM[3 * r + c] = 2.f * (dS[3 * r] * M[c] + dS[3 * r + 1] * M[3 + c] +
-                                       dS[3 * r + 2] * M[6 + c]);
-        float dR[9];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            float ds = 0.f;
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                dR[3 * r + c] = dM[3 * r + c] * G.s[c];
-                ds += dM[3 * r + c] * G.Rq[3 * r + c];
-            }
-            g_ls[c] += ds * G.s[c];
-        }
-        // Rq(qn): derivative of the unit-quaternion rotation matrix
-        const float w = G.qn[0], x = G.qn[1], y = G.qn[2], z = G.qn[3];
-        float dqn[4];
-        dqn[0] = 2.f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
-        dqn[1] = 2.f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.f * x * dR[4] - w * dR[5] +
-                        z * dR[6] + w * dR[7] - 2.f * x * dR[8]);
-        dqn[2] = 2.f * (-2.f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] -
-                        w * dR[6] + z * dR[7] - 2.f * y * dR[8]);
-        dqn[3] = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] +
-                        y * dR[5] + x * dR[6] + y * dR[7]);
-        // qn = q/|q|
-        const float dot = dqn[0] * w + dqn[1] * x + dqn[2] * y + dqn[3] * z;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) g_q[c] += (dqn[c] - G.qn[c] * dot) / G.qnorm;
     }
-    if (!any) return;
+    if (!kFused && !any) return;
+    auto apply = [&](int plane, float g, float p) {
+        const int64_t j = plane * stride + i;
+        if constexpr (kFused) {
+            float mm = m[j], vv = v[j];
+            adam_update(g, p, mm, vv, ad->lr[plane], *ad, *as);
+            planes[j] = p;
+            m[j] = mm;
+            v[j] = vv;
+        } else {
+            grads[j] += g;
+        }
+    };
+    // SH coefficients, one at a time
+    [&]<int... ks>(std::integer_sequence<int, ks...>) {
+        (([&] {
+             constexpr int k = ks;
+             float f[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) grads[k * stride + i] += g_mu[k];
+             for (int c = 0; c < 3; ++c) f[c] = planes[(11 + 3 * k + c) * stride + i];
+             float gk[3] = {0.f, 0.f, 0.f};
+             if (any) {
+                 if constexpr (kMulti) {
+                     for (int vi = 0; vi < views.n; ++vi) {
+                         const int64_t e = (int64_t)vi * n + i;
+                         if (tiles[e] == 0) continue;
+                         ViewSH o;
+                         view_sh(mu, views.v[vi], acc[3 * e + 1], acc[3 * e + 2], rec[3 * e + 2], o);
+                         sh_term<sh_degree, k>(o, f, gk, g_mu);
+                     }
+                 } else {
+                     sh_term<sh_degree, k>(one, f, gk, g_mu);
+                 }
+             }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) grads[(3 + k) * stride + i] += g_ls[k];
+             for (int c = 0; c < 3; ++c) apply(11 + 3 * k + c, gk[c], f[c]);
+         }()),
+         ...);
+    }(std::make_integer_sequence<int, K>{});
 #pragma unroll
-    for (int k = 0; k < 4; ++k) grads[(6 + k) * stride + i] += g_q[k];
-    grads[10 * stride + i] += g_logit;
+    for (int k = 0; k < 3; ++k) apply(k, g_mu[k], mu[k]);
 #pragma unroll
-    for (int k = 0; k < 3 * K; ++k) grads[(11 + k) * stride + i] += g_sh[k];
+    for (int k = 0; k < 3; ++k) apply(3 + k, g_ls[k], ls[k]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) apply(6 + k, g_q[k], q[k]);
+    apply(10, g_logit, logit);
+}
+
+// Adjoint of the projection: one thread per Gaussian, gradient ADDED to grads.
+template <int sh_degree, bool kMulti>
+__global__ void __launch_bounds__(256) project_backward_kernel(
+    const float* __restrict__ planes, int64_t n, int64_t stride, Views views, RasterDev rp,
+    const float4* __restrict__ rec, const uint32_t* __restrict__ tiles,
+    const float4* __restrict__ acc, const int32_t* __restrict__ gate, float* __restrict__ grads) {
+    if (gate_closed(gate)) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    gaussian_backward<sh_degree, false, kMulti>(const_cast<float*>(planes), n, stride, i, views,
+                                                rp, rec, tiles, acc, grads, nullptr, nullptr,
+                                                nullptr, nullptr);
+}
+
+// Adjoint of the projection fused with the Adam step: every Gaussian (visible
+// or not, as in dense Adam) gets its gradient computed in registers and its
+// parameters, first and second moments updated in place; no gradient array
+// is written or read.
+template <int sh_degree, bool kMulti>
+__global__ void __launch_bounds__(256) project_backward_adam_kernel(
+    float* __restrict__ planes, int64_t n, int64_t stride, Views views, RasterDev rp,
+    const float4* __restrict__ rec, const uint32_t* __restrict__ tiles,
+    const float4* __restrict__ acc, AdamDev ad, float* __restrict__ m, float* __restrict__ v,
+    const int32_t* __restrict__ step, const int32_t* __restrict__ gate) {
+    if (gate_closed(gate)) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const AdamStep as = adam_bias_correction(ad, *step);
+    gaussian_backward<sh_degree, true, kMulti>(planes, n, stride, i, views, rp, rec, tiles, acc,
+                                               nullptr, &ad, &as, m, v);
 }
 
 }  // namespace
 
 hipError_t launch_project(const float* planes, int64_t n, int64_t stride, int sh_degree,
                           const Views& views, const RasterDev& rp, float* records,
-                          uint32_t* tiles, uint32_t* counters, hipStream_t s) {
-    (void)counters;
+                          uint32_t* tiles, uint32_t* dkey, hipStream_t s) {
     const int64_t entries = n * views.n;
     if (entries == 0) return hipSuccess;
     const int nt = 256;
     const int64_t nb = (entries + nt - 1) / nt;
     float4* rec = reinterpret_cast<float4*>(records);
     switch (sh_degree) {
-        case 0: hipLaunchKernelGGL(project_kernel<0>, dim3((unsigned)nb), dim3(nt), 0, s, planes, n, stride, views, rp, rec, tiles); break;
-        case 1: hipLaunchKernelGGL(project_kernel<1>, dim3((unsigned)nb), dim3(nt), 0, s, planes, n, stride, views, rp, rec, tiles); break;
-        case 2: hipLaunchKernelGGL(project_kernel<2>, dim3((unsigned)nb), dim3(nt), 0, s, planes, n, stride, views, rp, rec, tiles); break;
-        default: hipLaunchKernelGGL(project_kernel<3>, dim3((unsigned)nb), dim3(nt), 0, s, planes, n, stride, views, rp, rec, tiles); break;
+        case 0: hipLaunchKernelGGL(project_kernel<0>, dim3((unsigned)nb), dim3(nt), 0, s, planes, n, stride, views, rp, rec, tiles, dkey); break;
+        case 1: hipLaunchKernelGGL(project_kernel<1>, dim3((unsigned)nb), dim3(nt), 0, s, planes, n, stride, views, rp, rec, tiles, dkey); break;
+        case 2: hipLaunchKernelGGL(project_kernel<2>, dim3((unsigned)nb), dim3(nt), 0, s, planes, n, stride, views, rp, rec, tiles, dkey); break;
+        default: hipLaunchKernelGGL(project_kernel<3>, dim3((unsigned)nb), dim3(nt), 0, s, planes, n, stride, views, rp, rec, tiles, dkey); break;
     }
     return hipGetLastError();
 }
@@ -450,15 +564,23 @@ hipError_t launch_load_records(int64_t entries, const float* u, const float* v,
                                const float* depth, const int32_t* radius, const float* conic,
                                const float* opacity, const float* rgb, int64_t n,
                                const Views& views, const RasterDev& rp, float* records,
-                               uint32_t* tiles, hipStream_t s) {
+                               uint32_t* tiles, uint32_t* dkey, hipStream_t s) {
     if (entries == 0) return hipSuccess;
     const int nt = 256;
     const int64_t nb = (entries + nt - 1) / nt;
     hipLaunchKernelGGL(load_records_kernel, dim3((unsigned)nb), dim3(nt), 0, s, entries, n, u, v,
                        depth, radius, conic, opacity, rgb, views, rp,
-                       reinterpret_cast<float4*>(records), tiles);
+                       reinterpret_cast<float4*>(records), tiles, dkey);
     return hipGetLastError();
 }
+
+#define SGS_DISPATCH_DEG(MACRO, multi)                                      \
+    switch (sh_degree) {                                                    \
+        case 0: if (multi) MACRO(0, true); else MACRO(0, false); break;    \
+        case 1: if (multi) MACRO(1, true); else MACRO(1, false); break;    \
+        case 2: if (multi) MACRO(2, true); else MACRO(2, false); break;    \
+        default: if (multi) MACRO(3, true); else MACRO(3, false); break;   \
+    }
 
 hipError_t launch_project_backward(const float* planes, int64_t n, int64_t stride,
                                    int sh_degree, const Views& views, const RasterDev& rp,
@@ -470,12 +592,31 @@ hipError_t launch_project_backward(const float* planes, int64_t n, int64_t strid
     const float4* rec = reinterpret_cast<const float4*>(ws + L.records);
     const uint32_t* tl = reinterpret_cast<const uint32_t*>(ws + L.tiles);
     const float4* acc = reinterpret_cast<const float4*>(ws + L.accum);
-    switch (sh_degree) {
-        case 0: hipLaunchKernelGGL(project_backward_kernel<0>, dim3((unsigned)nb), dim3(nt), 0, s, planes, n, stride, views, rp, rec, tl, acc, gate, grads); break;
-        case 1: hipLaunchKernelGGL(project_backward_kernel<1>, dim3((unsigned)nb), dim3(nt), 0, s, planes, n, stride, views, rp, rec, tl, acc, gate, grads); break;
-        case 2: hipLaunchKernelGGL(project_backward_kernel<2>, dim3((unsigned)nb), dim3(nt), 0, s, planes, n, stride, views, rp, rec, tl, acc, gate, grads); break;
-        default: hipLaunchKernelGGL(project_backward_kernel<3>, dim3((unsigned)nb), dim3(nt), 0, s, planes, n, stride, views, rp, rec, tl, acc, gate, grads); break;
-    }
+#define SGS_PB(D, M)                                                                              \
+    hipLaunchKernelGGL((project_backward_kernel<D, M>), dim3((unsigned)nb), dim3(nt), 0, s, planes, \
+                       n, stride, views, rp, rec, tl, acc, gate, grads)
+    SGS_DISPATCH_DEG(SGS_PB, views.n > 1)
+#undef SGS_PB
+    return hipGetLastError();
+}
+
+hipError_t launch_project_backward_adam(float* planes, int64_t n, int64_t stride, int sh_degree,
+                                        const Views& views, const RasterDev& rp, const Layout& L,
+                                        char* ws, const sgs_adam_params* prm, float* m, float* v,
+                                        int32_t* step, const int32_t* gate, hipStream_t s) {
+    hipError_t err = launch_adam_count(step, gate, s);
+    if (err != hipSuccess || n == 0) return err;
+    const AdamDev ad = make_adam(prm);
+    const int nt = 256;
+    const int64_t nb = (n + nt - 1) / nt;
+    const float4* rec = reinterpret_cast<const float4*>(ws + L.records);
+    const uint32_t* tl = reinterpret_cast<const uint32_t*>(ws + L.tiles);
+    const float4* acc = reinterpret_cast<const float4*>(ws + L.accum);
+#define SGS_PBA(D, M)                                                                         \
+    hipLaunchKernelGGL((project_backward_adam_kernel<D, M>), dim3((unsigned)nb), dim3(nt), 0, s, \
+                       planes, n, stride, views, rp, rec, tl, acc, ad, m, v, step, gate)
+    SGS_DISPATCH_DEG(SGS_PBA, views.n > 1)
+#undef SGS_PBA
     return hipGetLastError();
 }
 

@@ -1,23 +1,28 @@
 // Front-to-back compositing (paper Sec. 3, Eqs. 4-5) over the per-tile
 // depth-ordered lists, and its reverse-order adjoint.
 //
-// One workgroup per tile, one thread per pixel. The tile's list is staged
-// through LDS in batches of one record per thread; every thread then walks the
-// batch (LDS broadcast reads). The forward keeps, per pixel, only the final
-// transmittance and the list position of the last blended Gaussian; the
-// backward walks the list again from that position towards the front,
-// recovering T_i = T_{i+1} / (1 - alpha'_i) and the colour accumulated behind
-// each Gaussian, so no per-pixel blend list is ever stored.
+// One wavefront (64 lanes) per tile; each lane owns TW*TH/64 pixels of the
+// tile (pixel k of lane l is tile-local index l + 64 k, so every per-pixel
+// load or store of the wave is a run of contiguous row segments). The tile's
+// list is staged through LDS 64 records at a time; every lane then walks the
+// batch with broadcast LDS reads, reusing each record for all its pixels.
 //
-// Per-Gaussian gradients are summed over the 64 pixels of a wavefront with
-// DPP before one lane issues the hardware float atomics, and waves with no
-// contribution for a Gaussian skip both.
+// The forward keeps, per pixel, only the final transmittance and the list
+// position of the last blended Gaussian. The backward walks the list again
+// from that position towards the front, recovering T_i = T_{i+1} / (1 -
+// alpha'_i) and the colour accumulated behind each Gaussian, so no per-pixel
+// blend list is stored. A Gaussian's gradient is summed over the lane's
+// pixels in registers, then over the 64 lanes with one DPP reduction, and one
+// lane issues the 9 hardware float atomics of that (tile, Gaussian) pair;
+// Gaussians that touch no pixel of the tile skip both.
 #include "sgs_internal.hpp"
 #include "sgs_device.hpp"
 
 namespace sgs {
 
 namespace {
+
+constexpr int kLanes = 64;
 
 struct Splat {
     float alpha;   // alpha' after the clamp
@@ -51,34 +56,57 @@ __device__ __forceinline__ int view_of_tile(const Views& views, int tile) {
     return vi;
 }
 
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, d, 64));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_add_u32(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v += (uint32_t)__shfl_xor((int)v, d, 64);
+    return v;
+}
+
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
+__global__ void __launch_bounds__(kLanes) raster_forward_kernel(
     Views views, RasterDev rp, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ pentry, const float4* __restrict__ rec,
     float* __restrict__ out_rgb, float* __restrict__ t_final, uint32_t* __restrict__ n_last,
     uint32_t* __restrict__ counters) {
-    constexpr int NT = TW * TH;
-    __shared__ float4 s_pos[NT];   // u, v, radius, opacity
-    __shared__ float4 s_con[NT];   // a, b, c, -
-    __shared__ float4 s_col[NT];   // r, g, b, -
-    __shared__ uint32_t s_cnt[2];
+    constexpr int PIX = TW * TH / kLanes;
+    __shared__ float4 s_pos[kLanes];   // u, v, radius, opacity
+    __shared__ float4 s_con[kLanes];   // a, b, c, -
+    __shared__ float4 s_col[kLanes];   // r, g, b, -
 
     const int tile = blockIdx.x;
     const ViewDev& V = views.v[view_of_tile(views, tile)];
     const int local = tile - V.tile_offset;
     const int tx = local % V.tiles_x, ty = local / V.tiles_x;
     const int tid = threadIdx.x;
-    const int x = tx * TW + tid % TW, y = ty * TH + tid / TW;
-    const bool inside = x < V.width && y < V.height;
-    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
 
-    float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-    uint32_t last = 0, n_blend = 0, n_eval = 0;
-    bool done = !inside;
-    if (tid < 2) s_cnt[tid] = 0;
-    for (uint32_t b0 = start; b0 < end; b0 += NT) {
-        if (__syncthreads_and(done)) break;
+    float px[PIX], py[PIX], T[PIX], C0[PIX], C1[PIX], C2[PIX];
+    uint32_t last[PIX];
+    bool done[PIX], inside[PIX];
+    bool lane_done = true;
+#pragma unroll
+    for (int k = 0; k < PIX; ++k) {
+        const int li = tid + kLanes * k;
+        const int x = tx * TW + li % TW, y = ty * TH + li / TW;
+        inside[k] = x < V.width && y < V.height;
+        px[k] = (float)x + 0.5f;
+        py[k] = (float)y + 0.5f;
+        T[k] = 1.f;
+        C0[k] = C1[k] = C2[k] = 0.f;
+        last[k] = 0;
+        done[k] = !inside[k];
+        lane_done = lane_done && done[k];
+    }
+    uint32_t n_blend = 0, n_eval = 0;
+    for (uint32_t b0 = start; b0 < end; b0 += kLanes) {
+        if (ballot(!lane_done) == 0) break;
+        __syncthreads();
         const uint32_t idx = b0 + tid;
         if (idx < end) {
             const int64_t e = pentry[idx];
@@ -88,62 +116,70 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
             s_col[tid] = r2;
         }
         __syncthreads();
-        const int cnt = (int)min((uint32_t)NT, end - b0);
-        if (!done) {
-            for (int j = 0; j < cnt; ++j) {
-                const float4 P = s_pos[j];
-                const float4 Q = s_con[j];
-                Splat s;
-                ++n_eval;
-                if (!splat_alpha(px, py, P.x, P.y, P.z, P.w, Q.x, Q.y, Q.z, rp, s)) continue;
-                const float test = T * (1.f - s.alpha);
-                if (test < rp.t_min) { done = true; break; }
-                ++n_blend;
-                const float4 col = s_col[j];
-                const float w = s.alpha * T;
-                C0 = fmaf(col.x, w, C0);
-                C1 = fmaf(col.y, w, C1);
-                C2 = fmaf(col.z, w, C2);
-                T = test;
-                last = b0 + (uint32_t)j + 1u - start;
+        const int cnt = (int)min((uint32_t)kLanes, end - b0);
+        for (int j = 0; j < cnt && !lane_done; ++j) {
+            const float4 P = s_pos[j];
+            const float4 Q = s_con[j];
+            lane_done = true;
+#pragma unroll
+            for (int k = 0; k < PIX; ++k) {
+                if (!done[k]) {
+                    ++n_eval;
+                    Splat s;
+                    if (splat_alpha(px[k], py[k], P.x, P.y, P.z, P.w, Q.x, Q.y, Q.z, rp, s)) {
+                        const float test = T[k] * (1.f - s.alpha);
+                        if (test < rp.t_min) {
+                            done[k] = true;
+                        } else {
+                            const float4 col = s_col[j];
+                            const float w = s.alpha * T[k];
+                            C0[k] = fmaf(col.x, w, C0[k]);
+                            C1[k] = fmaf(col.y, w, C1[k]);
+                            C2[k] = fmaf(col.z, w, C2[k]);
+                            T[k] = test;
+                            last[k] = b0 + (uint32_t)j + 1u - start;
+                            ++n_blend;
+                        }
+                    }
+                }
+                lane_done = lane_done && done[k];
             }
         }
     }
-    if (inside) {
-        const int64_t plane = (int64_t)V.width * V.height;
-        const int64_t pix = (int64_t)y * V.width + x;
-        float* img = out_rgb + 3 * V.px_offset;
-        img[pix] = fmaf(T, rp.bg[0], C0);
-        img[plane + pix] = fmaf(T, rp.bg[1], C1);
-        img[2 * plane + pix] = fmaf(T, rp.bg[2], C2);
-        t_final[V.px_offset + pix] = T;
-        n_last[V.px_offset + pix] = last;
+    const int64_t plane = (int64_t)V.width * V.height;
+    float* img = out_rgb + 3 * V.px_offset;
+#pragma unroll
+    for (int k = 0; k < PIX; ++k) {
+        if (!inside[k]) continue;
+        const int li = tid + kLanes * k;
+        const int64_t pix = (int64_t)(ty * TH + li / TW) * V.width + (tx * TW + li % TW);
+        img[pix] = fmaf(T[k], rp.bg[0], C0[k]);
+        img[plane + pix] = fmaf(T[k], rp.bg[1], C1[k]);
+        img[2 * plane + pix] = fmaf(T[k], rp.bg[2], C2[k]);
+        t_final[V.px_offset + pix] = T[k];
+        n_last[V.px_offset + pix] = last[k];
     }
-    // work counters: one 64-bit atomic per workgroup
-    __syncthreads();
-    if (n_blend) atomicAdd(&s_cnt[0], n_blend);
-    if (n_eval) atomicAdd(&s_cnt[1], n_eval);
-    __syncthreads();
+    // work counters: one 64-bit atomic each per tile
+    const uint32_t nb = wave_add_u32(n_blend), ne = wave_add_u32(n_eval);
     if (tid == 0) {
         atomicAdd(reinterpret_cast<unsigned long long*>(counters + kBlended),
-                  (unsigned long long)s_cnt[0]);
+                  (unsigned long long)nb);
         atomicAdd(reinterpret_cast<unsigned long long*>(counters + kEvaluated),
-                  (unsigned long long)s_cnt[1]);
+                  (unsigned long long)ne);
     }
 }
 
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW* TH) raster_backward_kernel(
+__global__ void __launch_bounds__(kLanes) raster_backward_kernel(
     Views views, RasterDev rp, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ pentry, const float4* __restrict__ rec,
     const float* __restrict__ t_final, const uint32_t* __restrict__ n_last,
     const float* __restrict__ dl_drgb, const int32_t* __restrict__ gate,
     float* __restrict__ accum) {
-    constexpr int NT = TW * TH;
-    __shared__ float4 s_pos[NT];   // u, v, radius, opacity
-    __shared__ float4 s_con[NT];   // a, b, c, entry (bits)
-    __shared__ float4 s_col[NT];   // r, g, b, -
-    __shared__ uint32_t s_max;
+    constexpr int PIX = TW * TH / kLanes;
+    __shared__ float4 s_pos[kLanes];   // u, v, radius, opacity
+    __shared__ float4 s_con[kLanes];   // a, b, c, entry (bits)
+    __shared__ float4 s_col[kLanes];   // r, g, b, -
     if (gate_closed(gate)) return;
 
     const int tile = blockIdx.x;
@@ -151,33 +187,40 @@ __global__ void __launch_bounds__(TW* TH) raster_backward_kernel(
     const int local = tile - V.tile_offset;
     const int tx = local % V.tiles_x, ty = local / V.tiles_x;
     const int tid = threadIdx.x;
-    const int x = tx * TW + tid % TW, y = ty * TH + tid / TW;
-    const bool inside = x < V.width && y < V.height;
-    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
 
-    float T = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
-    uint32_t last = 0;
-    if (inside) {
-        const int64_t plane = (int64_t)V.width * V.height;
-        const int64_t pix = (int64_t)y * V.width + x;
-        const float* dl = dl_drgb + 3 * V.px_offset;
-        g0 = dl[pix];
-        g1 = dl[plane + pix];
-        g2 = dl[2 * plane + pix];
-        T = t_final[V.px_offset + pix];
-        last = n_last[V.px_offset + pix];
+    const int64_t plane = (int64_t)V.width * V.height;
+    const float* dl = dl_drgb + 3 * V.px_offset;
+    float px[PIX], py[PIX], T[PIX], G0[PIX], G1[PIX], G2[PIX], S0[PIX], S1[PIX], S2[PIX];
+    uint32_t last[PIX];
+    uint32_t my_max = 0;
+#pragma unroll
+    for (int k = 0; k < PIX; ++k) {
+        const int li = tid + kLanes * k;
+        const int x = tx * TW + li % TW, y = ty * TH + li / TW;
+        px[k] = (float)x + 0.5f;
+        py[k] = (float)y + 0.5f;
+        T[k] = 1.f;
+        G0[k] = G1[k] = G2[k] = 0.f;
+        last[k] = 0;
+        if (x < V.width && y < V.height) {
+            const int64_t pix = (int64_t)y * V.width + x;
+            G0[k] = dl[pix];
+            G1[k] = dl[plane + pix];
+            G2[k] = dl[2 * plane + pix];
+            T[k] = t_final[V.px_offset + pix];
+            last[k] = n_last[V.px_offset + pix];
+        }
+        // colour composited behind the current Gaussian, background included
+        S0[k] = rp.bg[0] * T[k];
+        S1[k] = rp.bg[1] * T[k];
+        S2[k] = rp.bg[2] * T[k];
+        my_max = max(my_max, last[k]);
     }
-    // colour composited behind the current Gaussian, background included
-    float S0 = rp.bg[0] * T, S1 = rp.bg[1] * T, S2 = rp.bg[2] * T;
-    if (tid == 0) s_max = 0;
-    __syncthreads();
-    if (last) atomicMax(&s_max, last);
-    __syncthreads();
-    const uint32_t stop = start + min(s_max, end - start);
+    const uint32_t stop = start + min(wave_max_u32(my_max), end - start);
 
     for (uint32_t b_end = stop; b_end > start;) {
-        const uint32_t b0 = (b_end - start > (uint32_t)NT) ? b_end - NT : start;
+        const uint32_t b0 = (b_end - start > (uint32_t)kLanes) ? b_end - kLanes : start;
         const int cnt = (int)(b_end - b0);
         __syncthreads();
         if (tid < cnt) {
@@ -197,31 +240,36 @@ __global__ void __launch_bounds__(TW* TH) raster_backward_kernel(
             bool contrib = false;
             const float4 P = s_pos[j];
             const float4 Q = s_con[j];
-            Splat s;
-            if (rel < last && splat_alpha(px, py, P.x, P.y, P.z, P.w, Q.x, Q.y, Q.z, rp, s)) {
-                const float4 col = s_col[j];
-                const float om = 1.f - s.alpha;
-                const float Ti = T / om;
-                const float w = s.alpha * Ti;
-                d_r = g0 * w;
-                d_g = g1 * w;
-                d_bl = g2 * w;
-                const float d_alpha = g0 * (col.x * Ti - S0 / om) + g1 * (col.y * Ti - S1 / om) +
-                                      g2 * (col.z * Ti - S2 / om);
-                S0 = fmaf(col.x, w, S0);
-                S1 = fmaf(col.y, w, S1);
-                S2 = fmaf(col.z, w, S2);
-                T = Ti;
-                if (!s.clamped) {
-                    const float dP = d_alpha * s.alpha;
-                    d_o = d_alpha * s.ex;
-                    d_a = -0.5f * dP * s.dx * s.dx;
-                    d_b = -dP * s.dx * s.dy;
-                    d_c = -0.5f * dP * s.dy * s.dy;
-                    d_u = dP * (Q.x * s.dx + Q.y * s.dy);
-                    d_v = dP * (Q.y * s.dx + Q.z * s.dy);
+#pragma unroll
+            for (int k = 0; k < PIX; ++k) {
+                Splat s;
+                if (rel < last[k] &&
+                    splat_alpha(px[k], py[k], P.x, P.y, P.z, P.w, Q.x, Q.y, Q.z, rp, s)) {
+                    const float4 col = s_col[j];
+                    const float om = 1.f - s.alpha;
+                    const float Ti = T[k] / om;
+                    const float w = s.alpha * Ti;
+                    d_r = fmaf(G0[k], w, d_r);
+                    d_g = fmaf(G1[k], w, d_g);
+                    d_bl = fmaf(G2[k], w, d_bl);
+                    const float d_alpha = G0[k] * (col.x * Ti - S0[k] / om) +
+                                          G1[k] * (col.y * Ti - S1[k] / om) +
+                                          G2[k] * (col.z * Ti - S2[k] / om);
+                    S0[k] = fmaf(col.x, w, S0[k]);
+                    S1[k] = fmaf(col.y, w, S1[k]);
+                    S2[k] = fmaf(col.z, w, S2[k]);
+                    T[k] = Ti;
+                    if (!s.clamped) {
+                        const float dP = d_alpha * s.alpha;
+                        d_o = fmaf(d_alpha, s.ex, d_o);
+                        d_a -= 0.5f * dP * s.dx * s.dx;
+                        d_b -= dP * s.dx * s.dy;
+                        d_c -= 0.5f * dP * s.dy * s.dy;
+                        d_u += dP * (Q.x * s.dx + Q.y * s.dy);
+                        d_v += dP * (Q.y * s.dx + Q.z * s.dy);
+                    }
+                    contrib = true;
                 }
-                contrib = true;
             }
             if (ballot(contrib) == 0) continue;
             d_u = wave_sum_to_lane63(d_u);
@@ -233,7 +281,7 @@ __global__ void __launch_bounds__(TW* TH) raster_backward_kernel(
             d_r = wave_sum_to_lane63(d_r);
             d_g = wave_sum_to_lane63(d_g);
             d_bl = wave_sum_to_lane63(d_bl);
-            if (lane_id() == 63) {
+            if (tid == 63) {
                 float* acc = accum + (int64_t)kAccumFloats * __float_as_uint(Q.w);
                 unsafeAtomicAdd(acc + 0, d_u);
                 unsafeAtomicAdd(acc + 1, d_v);
@@ -267,16 +315,16 @@ hipError_t launch_rasterize(const Views& views, const RasterDev& rp, const Layou
     float* tf = reinterpret_cast<float*>(ws + L.t_final);
     uint32_t* nl = reinterpret_cast<uint32_t*>(ws + L.n_last);
     uint32_t* cnt = reinterpret_cast<uint32_t*>(ws + L.counters);
-    const dim3 grid((unsigned)L.total_tiles);
+    const dim3 grid((unsigned)L.total_tiles), block(kLanes);
     if (rp.tile_w == 16 && rp.tile_h == 16)
-        hipLaunchKernelGGL((raster_forward_kernel<16, 16>), grid, dim3(256), 0, s, views, rp,
-                           ranges, pentry, rec, out_rgb, tf, nl, cnt);
+        hipLaunchKernelGGL((raster_forward_kernel<16, 16>), grid, block, 0, s, views, rp, ranges,
+                           pentry, rec, out_rgb, tf, nl, cnt);
     else if (rp.tile_w == 8 && rp.tile_h == 8)
-        hipLaunchKernelGGL((raster_forward_kernel<8, 8>), grid, dim3(64), 0, s, views, rp, ranges,
+        hipLaunchKernelGGL((raster_forward_kernel<8, 8>), grid, block, 0, s, views, rp, ranges,
                            pentry, rec, out_rgb, tf, nl, cnt);
     else
-        hipLaunchKernelGGL((raster_forward_kernel<32, 8>), grid, dim3(256), 0, s, views, rp,
-                           ranges, pentry, rec, out_rgb, tf, nl, cnt);
+        hipLaunchKernelGGL((raster_forward_kernel<32, 8>), grid, block, 0, s, views, rp, ranges,
+                           pentry, rec, out_rgb, tf, nl, cnt);
     return hipGetLastError();
 }
 
@@ -294,16 +342,16 @@ hipError_t launch_rasterize_backward(const Views& views, const RasterDev& rp, co
     const float4* rec = reinterpret_cast<const float4*>(ws + L.records);
     const float* tf = reinterpret_cast<const float*>(ws + L.t_final);
     const uint32_t* nl = reinterpret_cast<const uint32_t*>(ws + L.n_last);
-    const dim3 grid((unsigned)L.total_tiles);
+    const dim3 grid((unsigned)L.total_tiles), block(kLanes);
     if (rp.tile_w == 16 && rp.tile_h == 16)
-        hipLaunchKernelGGL((raster_backward_kernel<16, 16>), grid, dim3(256), 0, s, views, rp,
-                           ranges, pentry, rec, tf, nl, dl_drgb, gate, acc);
+        hipLaunchKernelGGL((raster_backward_kernel<16, 16>), grid, block, 0, s, views, rp, ranges,
+                           pentry, rec, tf, nl, dl_drgb, gate, acc);
     else if (rp.tile_w == 8 && rp.tile_h == 8)
-        hipLaunchKernelGGL((raster_backward_kernel<8, 8>), grid, dim3(64), 0, s, views, rp, ranges,
+        hipLaunchKernelGGL((raster_backward_kernel<8, 8>), grid, block, 0, s, views, rp, ranges,
                            pentry, rec, tf, nl, dl_drgb, gate, acc);
     else
-        hipLaunchKernelGGL((raster_backward_kernel<32, 8>), grid, dim3(256), 0, s, views, rp,
-                           ranges, pentry, rec, tf, nl, dl_drgb, gate, acc);
+        hipLaunchKernelGGL((raster_backward_kernel<32, 8>), grid, block, 0, s, views, rp, ranges,
+                           pentry, rec, tf, nl, dl_drgb, gate, acc);
     return hipGetLastError();
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sgs_internal.hpp"
+
 namespace sgs {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -85,6 +87,23 @@ __device__ __forceinline__ void tile_rect(float u, float v, int r, int tw, int t
     *x1 = min(max(floordiv(fu + r, tw) + 1, 0), tx_n);
     *y0 = min(max(floordiv(fv - r, th), 0), ty_n);
     *y1 = min(max(floordiv(fv + r, th) + 1, 0), ty_n);
+}
+
+// Adam element update, shared by the plain step and the fused backward step
+// so both give identical results.
+__device__ __forceinline__ AdamStep adam_bias_correction(const AdamDev& a, int k) {
+    AdamStep s;
+    s.bc1 = (float)(1.0 - pow(a.beta1, (double)k));
+    s.bc2 = (float)(1.0 - pow(a.beta2, (double)k));
+    return s;
+}
+
+__device__ __forceinline__ void adam_update(float g, float& p, float& m, float& v, float lr,
+                                            const AdamDev& a, const AdamStep& s) {
+    m = a.b1 * m + a.c1 * g;
+    v = a.b2 * v + a.c2 * g * g;
+    const float mh = m / s.bc1, vh = v / s.bc2;
+    p = p - lr * mh / (sqrtf(vh) + a.eps);
 }
 
 __device__ __forceinline__ bool gate_closed(const int32_t* gate) {

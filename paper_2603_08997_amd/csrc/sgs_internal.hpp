@@ -41,6 +41,17 @@ struct RasterDev {
     float near_z, dilation, alpha_min, alpha_max, t_min;
 };
 
+// Adam constants: beta and 1 - beta formed in binary64, then rounded.
+struct AdamDev {
+    float b1, b2, c1, c2, eps;
+    double beta1, beta2;  // for the bias corrections
+    float lr[SGS_MAX_PLANES];
+};
+struct AdamStep {
+    float bc1, bc2;  // 1 - beta^k
+};
+AdamDev make_adam(const sgs_adam_params* p);
+
 // Counters region of the workspace (uint32 words).
 enum Counter : int {
     kStatus = 0,        // SGS_STATUS_* bits
@@ -56,7 +67,7 @@ struct Layout {
     int64_t entries, total_tiles, total_pixels, capacity;
     int64_t scan_blocks, sort_blocks;
     int tile_bits, tile_passes, tile_result;  // result buffer index (0/1) of the tile sort
-    size_t records, tiles, dkey[2], dval[2], offsets, scan_sums, pair_tile[2], pair_entry[2],
+    size_t records, tiles, depth, dkey[2], dval[2], offsets, scan_sums, pair_tile[2], pair_entry[2],
         sort_hist, sort_totals, ranges, t_final, n_last, accum, counters, total;
 };
 
@@ -68,12 +79,12 @@ RasterDev make_raster(const sgs_raster_params* rp);
 // ---- launch wrappers (all asynchronous on `s`) ----
 hipError_t launch_project(const float* planes, int64_t n, int64_t stride, int sh_degree,
                           const Views& views, const RasterDev& rp, float* records,
-                          uint32_t* tiles, uint32_t* counters, hipStream_t s);
+                          uint32_t* tiles, uint32_t* dkey, hipStream_t s);
 hipError_t launch_load_records(int64_t entries, const float* u, const float* v,
                                const float* depth, const int32_t* radius, const float* conic,
                                const float* opacity, const float* rgb, int64_t n,
                                const Views& views, const RasterDev& rp, float* records,
-                               uint32_t* tiles, hipStream_t s);
+                               uint32_t* tiles, uint32_t* dkey, hipStream_t s);
 hipError_t launch_bin(const Views& views, const RasterDev& rp, int64_t n, const Layout& L,
                       char* ws, hipStream_t s);
 hipError_t launch_rasterize(const Views& views, const RasterDev& rp, const Layout& L, char* ws,
@@ -109,5 +120,10 @@ size_t gate_state_bytes(const sgs_gate_params* p);
 hipError_t launch_adam(const sgs_adam_params* p, float* params, float* grads, float* m, float* v,
                        int64_t n, int64_t stride, int n_planes, int32_t* step,
                        const int32_t* gate, hipStream_t s);
+hipError_t launch_adam_count(int32_t* step, const int32_t* gate, hipStream_t s);
+hipError_t launch_project_backward_adam(float* planes, int64_t n, int64_t stride, int sh_degree,
+                                        const Views& views, const RasterDev& rp, const Layout& L,
+                                        char* ws, const sgs_adam_params* prm, float* m, float* v,
+                                        int32_t* step, const int32_t* gate, hipStream_t s);
 
 }  // namespace sgs

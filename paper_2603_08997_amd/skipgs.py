@@ -78,6 +78,7 @@ EXPORTS = [
     "sgs_project_backward", "sgs_get_workspace_layout", "sgs_loss_workspace_size",
     "sgs_photometric_loss", "sgs_photometric_loss_backward", "sgs_gate_state_size",
     "sgs_gate_init", "sgs_gate_update", "sgs_gate_read", "sgs_adam_step",
+    "sgs_project_backward_adam", "sgs_render_backward_adam",
 ]
 
 
@@ -117,6 +118,10 @@ def _load():
         "sgs_gate_update": (i32, [P(GateParamsC), vp, i32, vp, vp, vp]),
         "sgs_gate_read": (i32, [P(GateParamsC), vp, P(GateSnapshotC), vp, vp, vp]),
         "sgs_adam_step": (i32, [P(AdamParamsC), vp, vp, vp, vp, i64, i64, i32, vp, vp, vp]),
+        "sgs_project_backward_adam": (i32, [P(GaussiansC), P(CameraC), i32, P(RasterParamsC), vp,
+                                            sz, i64, P(AdamParamsC), vp, vp, vp, vp, vp]),
+        "sgs_render_backward_adam": (i32, [P(GaussiansC), P(CameraC), i32, P(RasterParamsC), vp,
+                                           sz, i64, vp, P(AdamParamsC), vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -411,6 +416,24 @@ def default_lrs(sh_degree: int, means_lr: float = 1.6e-4) -> tuple:
                  + [1.25e-4] * (3 * (k - 1)))
 
 
+def project_backward_adam(planes, n, sh_degree, cams, rp, workspace, pair_capacity,
+                          adam: AdamParams, m, v, d_step, d_gate=None, stream=None):
+    g = gaussians_c(planes, n, sh_degree)
+    _check(LIB.sgs_project_backward_adam(C.byref(g), cameras_c(cams), len(cams), C.byref(rp.c()),
+                                         _ptr(workspace), workspace.numel(), pair_capacity,
+                                         C.byref(adam.c()), _ptr(m), _ptr(v), _ptr(d_step),
+                                         _ptr(d_gate), _stream(stream)))
+
+
+def render_backward_adam(planes, n, sh_degree, cams, rp, workspace, pair_capacity, dl_drgb,
+                         adam: AdamParams, m, v, d_step, d_gate=None, stream=None):
+    g = gaussians_c(planes, n, sh_degree)
+    _check(LIB.sgs_render_backward_adam(C.byref(g), cameras_c(cams), len(cams), C.byref(rp.c()),
+                                        _ptr(workspace), workspace.numel(), pair_capacity,
+                                        _ptr(dl_drgb), C.byref(adam.c()), _ptr(m), _ptr(v),
+                                        _ptr(d_step), _ptr(d_gate), _stream(stream)))
+
+
 def adam_step(p: AdamParams, params, grads, m, v, n, d_step, d_gate=None, stream=None):
     _check(LIB.sgs_adam_step(C.byref(p.c()), _ptr(params), _ptr(grads), _ptr(m), _ptr(v), int(n),
                              int(params.shape[1]), int(params.shape[0]), _ptr(d_step),
@@ -450,6 +473,11 @@ class Prepared:
     def rasterize_backward(self, view, dl_ptr, gate_ptr, stream):
         _check(LIB.sgs_rasterize_backward(self.cams[view], 1, self.n, C.byref(self.rp), self.ws,
                                           self.ws_bytes, self.cap, dl_ptr, gate_ptr, stream))
+
+    def project_backward_adam(self, view, adam_c, m_ptr, v_ptr, step_ptr, gate_ptr, stream):
+        _check(LIB.sgs_project_backward_adam(C.byref(self.g), self.cams[view], 1, C.byref(self.rp),
+                                             self.ws, self.ws_bytes, self.cap, C.byref(adam_c),
+                                             m_ptr, v_ptr, step_ptr, gate_ptr, stream))
 
     def project_backward(self, view, gate_ptr, grads_ptr, stream):
         _check(LIB.sgs_project_backward(C.byref(self.g), self.cams[view], 1, C.byref(self.rp),

@@ -50,7 +50,7 @@ class Trainer:
 
     def __init__(self, init: S.Scene, cams, targets: torch.Tensor, rp: sk.RasterParams,
                  gate: sk.GateParams | None, capacity: int, lrs=None, gated: bool = True,
-                 device="cuda"):
+                 fused: bool = True, device="cuda"):
         self.dev = torch.device(device)
         self.cams = list(cams)
         self.rp = rp
@@ -58,6 +58,7 @@ class Trainer:
         self.deg = init.sh_degree
         self.cap = int(capacity)
         self.gated = gated
+        self.fused = fused
         self.planes = torch.as_tensor(init.to_planes()).to(self.dev)
         self.grads = torch.zeros_like(self.planes)
         self.m = torch.zeros_like(self.planes)
@@ -124,11 +125,16 @@ class Trainer:
         e6 = mark()
         P.rasterize_backward(view, self.dl_p, gate, s)
         e7 = mark()
-        P.project_backward(view, gate, self.grads_p, s)
-        e8 = mark()
-        sk._check(sk.LIB.sgs_adam_step(C.byref(self.adamc), self.planes_p, self.grads_p, self.m_p,
-                                       self.v_p, self.n, self.stride, self.F, self.step_p, gate,
-                                       s))
+        if self.fused:
+            # projection backward and Adam in one pass; no gradient array
+            P.project_backward_adam(view, self.adamc, self.m_p, self.v_p, self.step_p, gate, s)
+            e8 = mark()
+        else:
+            P.project_backward(view, gate, self.grads_p, s)
+            e8 = mark()
+            sk._check(sk.LIB.sgs_adam_step(C.byref(self.adamc), self.planes_p, self.grads_p,
+                                           self.m_p, self.v_p, self.n, self.stride, self.F,
+                                           self.step_p, gate, s))
         e9 = mark()
         if timer is not None:
             es = [e0, e1, e2, e3, e4, e5, e6, e7, e8, e9]
