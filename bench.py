@@ -78,10 +78,10 @@ def cpu_baseline(gt, init, cam, crop=24):
         gpr = OR.project(gt.means, gt.log_scales, gt.quats, gt.opacity_logits, gt.sh, gt.sh_degree,
                          cam, OR.RasterParams())
         tgt = OR.composite(gpr["uv"], gpr["conic"], gpr["opacity"], gpr["rgb"], gpr["depth"],
-                           gpr["radius"], gpr["ids"], cam.width, cam.height, OR.RasterParams(),
+                           gpr["extent"], gpr["ids"], cam.width, cam.height, OR.RasterParams(),
                            px=px, py=py)["rgb"].reshape(3, crop, crop)
     t1 = time.perf_counter()
-    out = OR.composite(pr["uv"], pr["conic"], pr["opacity"], pr["rgb"], pr["depth"], pr["radius"],
+    out = OR.composite(pr["uv"], pr["conic"], pr["opacity"], pr["rgb"], pr["depth"], pr["extent"],
                        pr["ids"], cam.width, cam.height, OR.RasterParams(), px=px, py=py)
     L = OL.photometric_loss(out["rgb"].reshape(3, crop, crop), tgt)
     t_pix = time.perf_counter() - t1

@@ -21,7 +21,13 @@ thresholds unstated; the readings used here (fixed in ``RasterParams``) are:
   +-jac_clamp * (image half-extent) / focal (0 disables the clamp);
 * Sigma2D gets a low-pass dilation h * I; det <= 0 culls;
 * radius r = ceil(3 sqrt(lambda_max(Sigma2D))) pixels;
-* a Gaussian overlaps pixel p iff |p_x - u| <= r and |p_y - v| <= r;
+* a Gaussian overlaps pixel p iff |p_x - u| <= r_x and |p_y - v| <= r_y with
+  r_x = min(r, ceil(sqrt(2 ln(o/alpha_min) Sigma2D_xx))), r_y likewise with
+  Sigma2D_yy: outside that box (p - mu)^T Sigma2D^-1 (p - mu) > 2 ln(o/alpha_min),
+  so o exp(P) < alpha_min and the pixel would skip the Gaussian anyway. With
+  alpha_min = 0 the box is the square r_x = r_y = r; a Gaussian with
+  o < alpha_min overlaps nothing;
+* Gaussians whose centre or radius exceeds 2^24 pixels are degenerate and culled;
 * alpha' = min(alpha_max, o exp(P)), P = -1/2 dp^T conic dp; P > 0 or
   alpha' < alpha_min skips the Gaussian for that pixel; compositing stops
   before a Gaussian that would take the transmittance below t_min;
@@ -157,6 +163,7 @@ def project(means, log_scales, quats, opacity_logits, sh, sh_degree: int, cam,
     Returns a dict over the *visible* Gaussians (ascending index ``ids``):
     ``uv`` (n,2), ``depth`` (n,), ``cov2d`` (n,3) = (xx, xy, yy) incl. dilation,
     ``conic`` (n,3) = (a, b, c) of the inverse, ``radius`` (n,) int64,
+    ``extent`` (n,2) int64 = (r_x, r_y) of the overlap box,
     ``opacity`` (n,), ``rgb`` (n,3), ``rgb_raw`` (n,3) before the clamp at 0.
     Tensors keep autograd history to the inputs.
     """
@@ -206,11 +213,16 @@ def project(means, log_scales, quats, opacity_logits, sh, sh_degree: int, cam,
     with torch.no_grad():
         mid = 0.5 * (sxx + syy)
         lam = mid + torch.sqrt(torch.clamp(mid * mid - det, min=0.0))
-        radius = torch.ceil(3.0 * torch.sqrt(torch.clamp(lam, min=0.0))).to(torch.int64)
-        ok = (det > 0) & torch.isfinite(u) & torch.isfinite(v)
+        rf = torch.ceil(3.0 * torch.sqrt(torch.clamp(lam, min=0.0)))
+        ok = (det > 0) & torch.isfinite(u) & torch.isfinite(v) & torch.isfinite(rf)
+        ok &= (u.abs() < MAX_EXTENT) & (v.abs() < MAX_EXTENT) & (rf < MAX_EXTENT)
+        radius = torch.where(ok, rf, torch.zeros_like(rf)).to(torch.int64)
+        o_all = torch.sigmoid(opacity_logits[idx])
+        ext = overlap_extent(radius, o_all, sxx, syy, rp.alpha_min)
+        ok &= ext[:, 0] >= 0
         tiles_x = (W_img + rp.tile_w - 1) // rp.tile_w
         tiles_y = (H_img + rp.tile_h - 1) // rp.tile_h
-        x0, x1, y0, y1 = tile_rect(u, v, radius, rp.tile_w, rp.tile_h, tiles_x, tiles_y)
+        x0, x1, y0, y1 = tile_rect(u, v, ext, rp.tile_w, rp.tile_h, tiles_x, tiles_y)
         ok &= (x1 > x0) & (y1 > y0)
     sel = torch.nonzero(ok).flatten()
 
@@ -229,24 +241,48 @@ def project(means, log_scales, quats, opacity_logits, sh, sh_degree: int, cam,
     opacity = torch.sigmoid(opacity_logits[idx][sel])
     return dict(ids=idx[sel], uv=torch.stack([u[sel], v[sel]], 1), depth=tz[sel],
                 cov2d=torch.stack([sxx[sel], sxy[sel], syy[sel]], 1), conic=conic,
-                radius=radius[sel], opacity=opacity, rgb=rgb, rgb_raw=rgb_raw,
+                radius=radius[sel], extent=ext[sel], opacity=opacity, rgb=rgb, rgb_raw=rgb_raw,
                 tiles_x=tiles_x, tiles_y=tiles_y)
 
 
 # ---------------------------------------------------------------------------
 # Tile binning: the order-defining step of the tile-based rasteriser
 # ---------------------------------------------------------------------------
-def tile_rect(u, v, radius, tile_w, tile_h, tiles_x, tiles_y):
-    """Tiles [x0, x1) x [y0, y1) covered by the square |x-u| <= r, |y-v| <= r:
-    x0 = clamp(floor((u - r)/tile_w), 0, tiles_x), x1 = clamp(floor((u + r)/tile_w) + 1, 0, tiles_x),
-    likewise in y. Computed in float64 on the given u, v (exact for float32 inputs)."""
+MAX_EXTENT = float(2 ** 24)
+
+
+def overlap_extent(radius, opacity, sxx, syy, alpha_min):
+    """(r_x, r_y) of the overlap box: min(r, ceil(sqrt(2 ln(o/alpha_min) Sigma_xx)))
+    and likewise in y; r_x = r_y = r when alpha_min = 0; (-1, -1) when
+    o < alpha_min (the Gaussian reaches alpha_min nowhere)."""
+    r = torch.as_tensor(radius).to(DT)
+    if alpha_min <= 0:
+        return torch.stack([r, r], 1).to(torch.int64)
+    o = torch.as_tensor(opacity, dtype=DT).detach()
+    tau = torch.log(o / alpha_min)
+    t = torch.clamp(tau, min=0.0)
+    ex = torch.ceil(torch.sqrt(2.0 * t * torch.as_tensor(sxx, dtype=DT).detach()))
+    ey = torch.ceil(torch.sqrt(2.0 * t * torch.as_tensor(syy, dtype=DT).detach()))
+    ext = torch.stack([torch.minimum(r, ex), torch.minimum(r, ey)], 1)
+    ext = torch.where((tau >= 0)[:, None], ext, torch.full_like(ext, -1.0))
+    return ext.to(torch.int64)
+
+
+def tile_rect(u, v, extent, tile_w, tile_h, tiles_x, tiles_y):
+    """Tiles [x0, x1) x [y0, y1) covered by the box |x-u| <= r_x, |y-v| <= r_y
+    (extent (n,2) = (r_x, r_y)): x0 = clamp(floor((u - r_x)/tile_w), 0, tiles_x),
+    x1 = clamp(floor((u + r_x)/tile_w) + 1, 0, tiles_x), likewise in y. Computed
+    in float64 on the given u, v (exact for float32 inputs)."""
     u = torch.as_tensor(u, dtype=DT)
     v = torch.as_tensor(v, dtype=DT)
-    r = torch.as_tensor(radius).to(DT)
-    x0 = torch.clamp(torch.floor((u - r) / tile_w), 0, tiles_x).to(torch.int64)
-    x1 = torch.clamp(torch.floor((u + r) / tile_w) + 1, 0, tiles_x).to(torch.int64)
-    y0 = torch.clamp(torch.floor((v - r) / tile_h), 0, tiles_y).to(torch.int64)
-    y1 = torch.clamp(torch.floor((v + r) / tile_h) + 1, 0, tiles_y).to(torch.int64)
+    e = torch.as_tensor(extent).to(DT).reshape(-1, 2)
+    rx, ry = e[:, 0], e[:, 1]
+    x0 = torch.clamp(torch.floor((u - rx) / tile_w), 0, tiles_x).to(torch.int64)
+    x1 = torch.clamp(torch.floor((u + rx) / tile_w) + 1, 0, tiles_x).to(torch.int64)
+    y0 = torch.clamp(torch.floor((v - ry) / tile_h), 0, tiles_y).to(torch.int64)
+    y1 = torch.clamp(torch.floor((v + ry) / tile_h) + 1, 0, tiles_y).to(torch.int64)
+    empty = (rx < 0) | (ry < 0)
+    x1 = torch.where(empty, x0, x1)
     return x0, x1, y0, y1
 
 
@@ -254,7 +290,7 @@ def float32_bits(x) -> np.ndarray:
     return np.asarray(x, dtype=np.float32).view(np.uint32)
 
 
-def bin_and_sort(u32, v32, depth32, radius, ids, width, height, tile_w, tile_h,
+def bin_and_sort(u32, v32, depth32, extent, ids, width, height, tile_w, tile_h,
                  tile_offset: int = 0):
     """The per-tile depth-ordered lists.
 
@@ -267,12 +303,12 @@ def bin_and_sort(u32, v32, depth32, radius, ids, width, height, tile_w, tile_h,
     u32 = np.asarray(u32, dtype=np.float32)
     v32 = np.asarray(v32, dtype=np.float32)
     dbits = float32_bits(depth32).astype(np.uint64)
-    radius = np.asarray(radius, dtype=np.int64)
+    extent = np.asarray(extent, dtype=np.int64).reshape(-1, 2)
     ids = np.asarray(ids, dtype=np.int64)
     tx_n = (width + tile_w - 1) // tile_w
     ty_n = (height + tile_h - 1) // tile_h
     x0, x1, y0, y1 = (a.numpy() for a in tile_rect(u32.astype(np.float64), v32.astype(np.float64),
-                                                     radius, tile_w, tile_h, tx_n, ty_n))
+                                                     extent, tile_w, tile_h, tx_n, ty_n))
     keys, vals = [], []
     for k in range(len(ids)):
         for ty in range(y0[k], y1[k]):
@@ -310,7 +346,7 @@ def pixel_grid(width: int, height: int):
     return xs.flatten(), ys.flatten()
 
 
-def composite(uv, conic, opacity, rgb, depth, radius, ids, width, height,
+def composite(uv, conic, opacity, rgb, depth, extent, ids, width, height,
               rp: RasterParams, px=None, py=None, max_elems: int = 4_000_000) -> dict:
     """Front-to-back compositing of Eq. 4 with alpha' from Eq. 5.
 
@@ -337,7 +373,8 @@ def composite(uv, conic, opacity, rgb, depth, radius, ids, width, height,
     a, b, c = conic[order, 0], conic[order, 1], conic[order, 2]
     o = opacity[order]
     col = rgb[order]
-    r = torch.as_tensor(radius)[order].to(DT)
+    ext = torch.as_tensor(extent).reshape(-1, 2)[order].to(DT)
+    rx, ry = ext[:, 0], ext[:, 1]
     gid = ids[order]
     bg = torch.tensor(rp.bg, dtype=DT)
 
@@ -352,18 +389,18 @@ def composite(uv, conic, opacity, rgb, depth, radius, ids, width, height,
         pcx = px[sl].to(DT) + 0.5
         pcy = py[sl].to(DT) + 0.5
         with torch.no_grad():
-            cand = ((u + r >= pcx.min()) & (u - r <= pcx.max()) &
-                    (v + r >= pcy.min()) & (v - r <= pcy.max()))
+            cand = ((u + rx >= pcx.min()) & (u - rx <= pcx.max()) &
+                    (v + ry >= pcy.min()) & (v - ry <= pcy.max()))
             ci = torch.nonzero(cand).flatten()
         res = _composite_block(pcx, pcy, u[ci], v[ci], a[ci], b[ci], c[ci], o[ci],
-                               col[ci], r[ci], gid[ci], bg, rp)
+                               col[ci], rx[ci], ry[ci], gid[ci], bg, rp)
         out_rgb.append(res[0]); out_T.append(res[1]); out_n.append(res[2]); out_last.append(res[3])
         start += chunk
     return dict(rgb=torch.cat(out_rgb, 1), T_final=torch.cat(out_T), n_blended=torch.cat(out_n),
                 last=torch.cat(out_last))
 
 
-def _composite_block(pcx, pcy, u, v, a, b, c, o, col, r, gid, bg, rp):
+def _composite_block(pcx, pcy, u, v, a, b, c, o, col, rx, ry, gid, bg, rp):
     npx = pcx.shape[0]
     if u.shape[0] == 0:
         T = torch.ones(npx, dtype=DT)
@@ -374,7 +411,7 @@ def _composite_block(pcx, pcy, u, v, a, b, c, o, col, r, gid, bg, rp):
     power = -0.5 * (a[None, :] * dx * dx + c[None, :] * dy * dy) - b[None, :] * dx * dy
     alpha = torch.clamp(o[None, :] * torch.exp(power), max=rp.alpha_max)
     with torch.no_grad():
-        member = (dx.abs() <= r[None, :]) & (dy.abs() <= r[None, :])
+        member = (dx.abs() <= rx[None, :]) & (dy.abs() <= ry[None, :])
         active = member & (power <= 0) & (alpha >= rp.alpha_min)
         a_act = torch.where(active, alpha, torch.zeros_like(alpha))
         # Transmittance after each Gaussian (front to back) counting every
@@ -402,7 +439,7 @@ def render(means, log_scales, quats, opacity_logits, sh, sh_degree, cam, rp: Ras
     """Project and composite: the forward image of one view (3, H*W) plus
     per-pixel T_final, blended count and last blended Gaussian."""
     pr = project(means, log_scales, quats, opacity_logits, sh, sh_degree, cam, rp)
-    out = composite(pr["uv"], pr["conic"], pr["opacity"], pr["rgb"], pr["depth"], pr["radius"],
+    out = composite(pr["uv"], pr["conic"], pr["opacity"], pr["rgb"], pr["depth"], pr["extent"],
                     pr["ids"], cam.width, cam.height, rp, px=px, py=py)
     out["proj"] = pr
     return out

@@ -280,9 +280,10 @@ def random_records(seed: int, n: int, width: int, height: int, max_radius: int =
     """Projected-Gaussian records drawn directly (no projection involved), for
     exercising binning, sorting and compositing on identical float32 inputs.
 
-    Fields: u, v (pixel coords), depth, radius (int32), conic (a, b, c) with
-    a, c > 0 and b^2 < a c, opacity in (0, 1), rgb in [0, 1]. A fraction of
-    depths can be forced to repeat to exercise the tie-break."""
+    Fields: u, v (pixel coords), depth, extent (n, 2) int32 half-sizes of the
+    overlap box (each between r/2 and r for a drawn radius r), conic (a, b, c)
+    with a, c > 0 and b^2 < a c, opacity in (0, 1), rgb in [0, 1]. A fraction
+    of depths can be forced to repeat to exercise the tie-break."""
     rng = np.random.default_rng(seed)
     u = rng.uniform(-margin, width + margin, n)
     v = rng.uniform(-margin, height + margin, n)
@@ -299,6 +300,8 @@ def random_records(seed: int, n: int, width: int, height: int, max_radius: int =
     b = rng.uniform(-0.9, 0.9, n) * np.sqrt(a * c)
     opacity = rng.uniform(0.05, 0.999, n)
     rgb = rng.uniform(0.0, 1.0, (n, 3))
+    ext = np.stack([rng.integers((radius + 1) // 2, radius + 1),
+                    rng.integers((radius + 1) // 2, radius + 1)], axis=1)
     f32 = lambda x: np.asarray(x, dtype=np.float32)
-    return dict(u=f32(u), v=f32(v), depth=f32(depth), radius=radius.astype(np.int32),
+    return dict(u=f32(u), v=f32(v), depth=f32(depth), extent=ext.astype(np.int32),
                 conic=f32(np.stack([a, b, c], axis=1)), opacity=f32(opacity), rgb=f32(rgb))

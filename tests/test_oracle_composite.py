@@ -17,7 +17,7 @@ def _records(seed, n, w, h, **kw):
     t = lambda x: torch.tensor(np.asarray(x, np.float64))
     return dict(uv=t(np.stack([rec["u"], rec["v"]], 1)), conic=t(rec["conic"]),
                 opacity=t(rec["opacity"]), rgb=t(rec["rgb"]), depth=t(rec["depth"]),
-                radius=torch.tensor(rec["radius"].astype(np.int64)), ids=torch.arange(n)), rec
+                extent=torch.tensor(rec["extent"].astype(np.int64)), ids=torch.arange(n)), rec
 
 
 def _brute_force_pixel(x, y, rec, rp):
@@ -28,8 +28,9 @@ def _brute_force_pixel(x, y, rec, rp):
     px, py = x + 0.5, y + 0.5
     alpha = {}
     for i in range(n):
-        u, v, r = float(rec["u"][i]), float(rec["v"][i]), int(rec["radius"][i])
-        if abs(px - u) > r or abs(py - v) > r:
+        u, v = float(rec["u"][i]), float(rec["v"][i])
+        rx, ry = (int(x) for x in rec["extent"][i])
+        if abs(px - u) > rx or abs(py - v) > ry:
             continue
         a, b, c = (float(z) for z in rec["conic"][i])
         dx, dy = px - u, py - v
@@ -63,7 +64,7 @@ def _brute_force_pixel(x, y, rec, rp):
 def test_sorted_compositing_equals_brute_force(rp, ties):
     w, h = 20, 14
     t, rec = _records(21, 60, w, h, max_radius=9, tie_fraction=ties)
-    out = R.composite(t["uv"], t["conic"], t["opacity"], t["rgb"], t["depth"], t["radius"], t["ids"],
+    out = R.composite(t["uv"], t["conic"], t["opacity"], t["rgb"], t["depth"], t["extent"], t["ids"],
                       w, h, rp)
     img = out["rgb"].numpy().reshape(3, h, w)
     T = out["T_final"].numpy().reshape(h, w)
@@ -83,7 +84,7 @@ def test_weights_and_final_transmittance_sum_to_one():
     t, _ = _records(4, 300, w, h, max_radius=12)
     t["rgb"] = torch.ones_like(t["rgb"])
     for rp in (R.RasterParams(), R.smooth_params()):
-        out = R.composite(t["uv"], t["conic"], t["opacity"], t["rgb"], t["depth"], t["radius"],
+        out = R.composite(t["uv"], t["conic"], t["opacity"], t["rgb"], t["depth"], t["extent"],
                           t["ids"], w, h, rp)
         wsum = out["rgb"][0].numpy()
         assert np.all(wsum <= 1 + 1e-12)
@@ -94,7 +95,7 @@ def test_final_transmittance_is_product_over_blended():
     w, h = 16, 16
     t, rec = _records(5, 40, w, h, max_radius=10)
     rp = R.RasterParams()
-    out = R.composite(t["uv"], t["conic"], t["opacity"], t["rgb"], t["depth"], t["radius"], t["ids"],
+    out = R.composite(t["uv"], t["conic"], t["opacity"], t["rgb"], t["depth"], t["extent"], t["ids"],
                       w, h, rp)
     assert (out["T_final"] >= R.f32(rp.t_min)).all()
     assert (out["T_final"] <= 1.0).all()
@@ -110,8 +111,8 @@ def test_two_gaussians_at_their_centre_closed_form():
     bg = (0.25, 0.5, 0.75)
     rp = R.RasterParams(bg=bg)
     for depth, near in (([1.0, 2.0], 0), ([3.0, 2.0], 1)):
-        out = R.composite(uv, conic, o, rgb, torch.tensor(depth, dtype=DT), torch.tensor([4, 4]),
-                          torch.arange(2), 11, 11, rp, px=[5], py=[5])
+        out = R.composite(uv, conic, o, rgb, torch.tensor(depth, dtype=DT),
+                          torch.tensor([[4, 4], [4, 4]]), torch.arange(2), 11, 11, rp, px=[5], py=[5])
         far = 1 - near
         o1, o2 = [0.6, 0.7][near], [0.6, 0.7][far]
         c1, c2 = rgb[near].numpy(), rgb[far].numpy()
@@ -125,8 +126,9 @@ def test_equal_depth_ties_break_by_index():
     conic = torch.tensor([[0.5, 0.0, 0.5]] * 2, dtype=DT)
     o = torch.tensor([0.5, 0.5], dtype=DT)
     rgb = torch.tensor([[1.0, 0, 0], [0, 1.0, 0]], dtype=DT)
-    out = R.composite(uv, conic, o, rgb, torch.tensor([2.0, 2.0], dtype=DT), torch.tensor([3, 3]),
-                      torch.tensor([7, 3]), 8, 8, R.RasterParams(), px=[3], py=[3])
+    out = R.composite(uv, conic, o, rgb, torch.tensor([2.0, 2.0], dtype=DT),
+                      torch.tensor([[3, 3], [3, 3]]), torch.tensor([7, 3]), 8, 8, R.RasterParams(),
+                      px=[3], py=[3])
     # index 3 (green) is in front of index 7 (red)
     assert np.allclose(out["rgb"][:, 0].numpy(), [0.25, 0.5, 0.0], atol=1e-15)
     assert out["last"].item() == 7
@@ -169,7 +171,7 @@ def test_single_isotropic_splat_closed_form():
 def test_bins_cover_exactly_the_rect_and_sort_by_depth_then_index():
     w, h, tw, th = 53, 37, 16, 8
     rec = S.random_records(9, 80, w, h, max_radius=15, tie_fraction=0.25)
-    keys, vals, ranges = R.bin_and_sort(rec["u"], rec["v"], rec["depth"], rec["radius"], np.arange(80),
+    keys, vals, ranges = R.bin_and_sort(rec["u"], rec["v"], rec["depth"], rec["extent"], np.arange(80),
                                         w, h, tw, th, tile_offset=0)
     tx_n, ty_n = (w + tw - 1) // tw, (h + th - 1) // th
     dbits = R.float32_bits(rec["depth"])
@@ -178,8 +180,9 @@ def test_bins_cover_exactly_the_rect_and_sort_by_depth_then_index():
         tx, ty = t % tx_n, t // tx_n
         expect = []
         for i in range(80):
-            u, v, r = float(rec["u"][i]), float(rec["v"][i]), int(rec["radius"][i])
-            if (u + r >= tx * tw and u - r < (tx + 1) * tw and v + r >= ty * th and v - r < (ty + 1) * th):
+            u, v = float(rec["u"][i]), float(rec["v"][i])
+            rx, ry = (int(x) for x in rec["extent"][i])
+            if (u + rx >= tx * tw and u - rx < (tx + 1) * tw and v + ry >= ty * th and v - ry < (ty + 1) * th):
                 expect.append(i)
         s, e = ranges[t]
         got = list(vals[s:e])
@@ -195,7 +198,7 @@ def test_tile_lists_contain_every_overlapping_gaussian():
     so compositing over tile lists equals compositing over all Gaussians."""
     w, h, tw, th = 40, 30, 8, 8
     rec = S.random_records(13, 120, w, h, max_radius=11)
-    keys, vals, ranges = R.bin_and_sort(rec["u"], rec["v"], rec["depth"], rec["radius"], np.arange(120),
+    keys, vals, ranges = R.bin_and_sort(rec["u"], rec["v"], rec["depth"], rec["extent"], np.arange(120),
                                         w, h, tw, th)
     tx_n = (w + tw - 1) // tw
     for y in range(h):
@@ -203,7 +206,7 @@ def test_tile_lists_contain_every_overlapping_gaussian():
             t = (y // th) * tx_n + x // tw
             lst = set(vals[ranges[t, 0]:ranges[t, 1]].tolist())
             for i in range(120):
-                if abs(x + 0.5 - rec["u"][i]) <= rec["radius"][i] and abs(y + 0.5 - rec["v"][i]) <= rec["radius"][i]:
+                if abs(x + 0.5 - rec["u"][i]) <= rec["extent"][i, 0] and abs(y + 0.5 - rec["v"][i]) <= rec["extent"][i, 1]:
                     assert i in lst
 
 
@@ -216,3 +219,38 @@ def test_image_independent_of_tile_shape_in_full_render():
         out = R.render(sc.means, sc.log_scales, sc.quats, sc.opacity_logits, sc.sh, 0, cam, rp)
         imgs.append(out["rgb"].detach().numpy())
     assert np.array_equal(imgs[0], imgs[1]) and np.array_equal(imgs[0], imgs[2])
+
+
+def test_overlap_box_contains_every_pixel_that_can_pass_alpha_min():
+    """Eq. 5 evaluated directly on the whole 3-sigma square: every pixel where
+    o exp(P) >= alpha_min lies in the overlap box, and the box is never larger
+    than the square."""
+    sc = S.mixture_scene(2, 3000, sh_degree=0, log_scale_mean=-2.8)
+    cam = S.look_at_camera((3.0, -2.0, 2.5), 160, 120)
+    rp = R.RasterParams()
+    pr = R.project(sc.means, sc.log_scales, sc.quats, sc.opacity_logits, sc.sh, 0, cam, rp)
+    amin = R.f32(rp.alpha_min)
+    uv = pr["uv"].detach().numpy()
+    con = pr["conic"].detach().numpy()
+    o = pr["opacity"].detach().numpy()
+    r = pr["radius"].numpy()
+    ext = pr["extent"].numpy()
+    assert np.all(ext <= r[:, None]) and np.all(ext >= 0)
+    assert (ext < r[:, None]).any()          # the box does cut the square
+    checked = 0
+    for i in range(0, len(r), 7):
+        ri = int(r[i])
+        if ri > 40:
+            continue
+        off = np.arange(-ri, ri + 1, dtype=np.float64)
+        px = np.floor(uv[i, 0]) + 0.5 + off
+        py = np.floor(uv[i, 1]) + 0.5 + off
+        dx = px[None, :] - uv[i, 0]
+        dy = py[:, None] - uv[i, 1]
+        a, b, c = con[i]
+        P = -0.5 * (a * dx * dx + c * dy * dy) - b * dx * dy
+        passes = (o[i] * np.exp(P) >= amin) & (np.abs(dx) <= ri) & (np.abs(dy) <= ri)
+        inbox = (np.abs(dx) <= ext[i, 0]) & (np.abs(dy) <= ext[i, 1])
+        assert not (passes & ~inbox).any(), i
+        checked += 1
+    assert checked > 100
