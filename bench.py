@@ -169,11 +169,15 @@ def main():
     timer = headline["_timer"]
     if timer is not None:
         # blended (pixel, Gaussian) pairs of one view, averaged over 8 views
-        blended = []
+        blended, evaluated, pairs, visible = [], [], [], []
         for v in range(min(8, args.views)):
             tr.render(v, tr.rgb)
             torch.cuda.synchronize()
-            blended.append(sk.read_counters(tr.ws)["blended"])
+            cnt = sk.read_counters(tr.ws)
+            blended.append(cnt["blended"])
+            evaluated.append(cnt["evaluated"])
+            pairs.append(cnt["pairs"])
+            visible.append(cnt["visible"])
         blended = float(np.mean(blended))
         ex = headline["stage_ms_executed"]
         allm = headline["stage_ms_all"]
@@ -188,7 +192,9 @@ def main():
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
                 "avg_launch_ms": ms, "blended_pairs_per_launch": blended,
-                "flops_per_pair": flops_pp}
+                "evaluated_pairs_per_launch": float(np.mean(evaluated)),
+                "tile_pairs_per_view": float(np.mean(pairs)),
+                "visible_per_view": float(np.mean(visible)), "flops_per_pair": flops_pp}
 
     out = {
         "metric": "post-densification iters/s (gated vs full) at 1 GPU",

@@ -168,13 +168,14 @@ sgs_status sgs_project(const sgs_gaussians* g, const sgs_camera* cams, int32_t n
 
 /* Writes projected records directly (bypassing sgs_project) for n_views x n
  * entries: entry e = v n + i. Device arrays of n_views * n elements: u, v
- * (pixel coords), depth (> 0), radius (int32, < 0 or 0 = not visible),
- * conic (3 per entry: a, b, c of the inverse screen covariance), opacity,
- * rgb (3 per entry). */
+ * (pixel coords), depth (> 0), extent (int32, 2 per entry: half-sizes r_x,
+ * r_y of the overlap box; negative = not visible), conic (3 per entry: a, b, c
+ * of the inverse screen covariance), opacity, rgb (3 per entry, used as the
+ * colour with no clamp). */
 sgs_status sgs_load_records(const sgs_camera* cams, int32_t n_views, int64_t n,
                             const sgs_raster_params* rp, void* workspace, size_t workspace_bytes,
                             int64_t pair_capacity, const float* u, const float* v,
-                            const float* depth, const int32_t* radius, const float* conic,
+                            const float* depth, const int32_t* extent, const float* conic,
                             const float* opacity, const float* rgb, void* stream);
 
 /* Tile binning: depth-ordered, per-tile lists of every visible entry,
@@ -203,8 +204,9 @@ sgs_status sgs_project_backward(const sgs_gaussians* g, const sgs_camera* cams, 
                                 const int32_t* d_gate, float* grads, void* stream);
 
 /* Byte offsets of the workspace regions, for inspection (host struct).
- * records:    float32 [entries][12]  u v a b | c o radius depth | r g b tiles
+ * records:    float32 [entries][12]  u v a b | c o rx ry | r g b clamp-mask(bits)
  * tiles:      uint32  [entries]      tiles touched (0 = not visible)
+ * depth:      float32 [entries]      camera depth (the sort key) of visible entries
  * pair_tile:  uint32  [pair_capacity] sorted global tile index per pair
  * pair_entry: uint32  [pair_capacity] entry index per pair (sorted with tiles)
  * ranges:     uint32  [total_tiles][2] [start, end) into the pair arrays
@@ -213,7 +215,7 @@ sgs_status sgs_project_backward(const sgs_gaussians* g, const sgs_camera* cams, 
  * accum:      float32 [entries][12]   du dv da db | dc do dr dg | db 0 0 0
  * counters:   uint32  [8]             status, visible, pairs, ... */
 typedef struct {
-    size_t records, tiles, pair_tile, pair_entry, ranges, t_final, n_last, accum, counters;
+    size_t records, tiles, depth, pair_tile, pair_entry, ranges, t_final, n_last, accum, counters;
     int64_t entries, total_tiles, total_pixels;
 } sgs_workspace_layout;
 

@@ -173,8 +173,8 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
         const ViewDev& V = views.v[(int)(e / n)];
         const float4 r0 = rec[3 * (int64_t)e], r1 = rec[3 * (int64_t)e + 1];
         int x0, x1, y0, y1;
-        tile_rect(r0.x, r0.y, (int)r1.z, rp.tile_w, rp.tile_h, V.tiles_x, V.tiles_y, &x0, &x1, &y0,
-                  &y1);
+        tile_rect(r0.x, r0.y, (int)r1.z, (int)r1.w, rp.tile_w, rp.tile_h, V.tiles_x, V.tiles_y,
+                  &x0, &x1, &y0, &y1);
         s_off[j] = offsets[k];
         s_ent[j] = e;
         s_base[j] = (uint32_t)(V.tile_offset + y0 * V.tiles_x + x0);

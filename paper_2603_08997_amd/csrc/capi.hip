@@ -253,6 +253,7 @@ sgs_status sgs_get_workspace_layout(const sgs_raster_params* rp, int64_t n, cons
     const Layout& L = P.L;
     out->records = L.records;
     out->tiles = L.tiles;
+    out->depth = L.depth;
     out->pair_tile = L.pair_tile[L.tile_result];
     out->pair_entry = L.pair_entry[L.tile_result];
     out->ranges = L.ranges;
@@ -287,16 +288,16 @@ sgs_status sgs_project(const sgs_gaussians* g, const sgs_camera* cams, int32_t n
 sgs_status sgs_load_records(const sgs_camera* cams, int32_t n_views, int64_t n,
                             const sgs_raster_params* rp, void* workspace, size_t workspace_bytes,
                             int64_t pair_capacity, const float* u, const float* v,
-                            const float* depth, const int32_t* radius, const float* conic,
+                            const float* depth, const int32_t* extent, const float* conic,
                             const float* opacity, const float* rgb, void* stream) {
     Prepared P;
     sgs_status st = prepare(rp, n, cams, n_views, pair_capacity, &P);
     if (st != SGS_OK) return st;
     if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
-    if (P.L.entries > 0 && (!u || !v || !depth || !radius || !conic || !opacity || !rgb))
+    if (P.L.entries > 0 && (!u || !v || !depth || !extent || !conic || !opacity || !rgb))
         return fail(SGS_ERR_INVALID_ARG, "record arrays are null");
     char* ws = static_cast<char*>(workspace);
-    SGS_HIP(sgs::launch_load_records(P.L.entries, u, v, depth, radius, conic, opacity, rgb, n,
+    SGS_HIP(sgs::launch_load_records(P.L.entries, u, v, depth, extent, conic, opacity, rgb, n,
                                      P.views, P.rd, reinterpret_cast<float*>(ws + P.L.records),
                                      reinterpret_cast<uint32_t*>(ws + P.L.tiles),
                                      reinterpret_cast<uint32_t*>(ws + P.L.depth),

@@ -170,6 +170,7 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
     const float logit = planes[10 * stride + i];
 
     uint32_t ntiles = 0;
+    float depth = 0.f;
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
     Geometry G;
     if (compute_geometry(mu, ls, q, V, rp, G)) {
@@ -194,21 +195,32 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
         }
         const float o = sigmoidf(logit);
         const float ca = G.syy / det, cb = -G.sxy / det, cc = G.sxx / det;
-        bool ok = det > 0.f && isfinite(u) && isfinite(v) && fabsf(u) < (float)kMaxExtent &&
-                  fabsf(v) < (float)kMaxExtent && rf < (float)kMaxExtent && isfinite(ca) &&
-                  isfinite(cb) && isfinite(cc) && isfinite(o) && isfinite(col[0]) &&
-                  isfinite(col[1]) && isfinite(col[2]);
+        // overlap box: where o exp(P) can reach alpha_min, within the square r
+        float ex = rf, ey = rf;
+        bool reach = true;
+        if (rp.alpha_min > 0.f) {
+            const float tau = logf(o / rp.alpha_min);
+            reach = tau >= 0.f;
+            ex = fminf(rf, ceilf(sqrtf(2.f * fmaxf(tau, 0.f) * G.sxx)));
+            ey = fminf(rf, ceilf(sqrtf(2.f * fmaxf(tau, 0.f) * G.syy)));
+        }
+        bool ok = det > 0.f && reach && isfinite(u) && isfinite(v) &&
+                  fabsf(u) < (float)kMaxExtent && fabsf(v) < (float)kMaxExtent &&
+                  rf < (float)kMaxExtent && isfinite(ca) && isfinite(cb) && isfinite(cc) &&
+                  isfinite(o) && isfinite(col[0]) && isfinite(col[1]) && isfinite(col[2]);
         if (ok) {
             int x0, x1, y0, y1;
-            tile_rect(u, v, (int)rf, rp.tile_w, rp.tile_h, V.tiles_x, V.tiles_y, &x0, &x1, &y0, &y1);
+            tile_rect(u, v, (int)ex, (int)ey, rp.tile_w, rp.tile_h, V.tiles_x, V.tiles_y, &x0, &x1,
+                      &y0, &y1);
             if (x1 > x0 && y1 > y0) {
                 ntiles = (uint32_t)((x1 - x0) * (y1 - y0));
-                r0 = make_float4(u, v, ca, cb);
-                r1 = make_float4(cc, o, rf, G.tz);
                 const uint32_t mask = (col[0] >= 0.f ? 1u : 0u) | (col[1] >= 0.f ? 2u : 0u) |
                                       (col[2] >= 0.f ? 4u : 0u);
+                r0 = make_float4(u, v, ca, cb);
+                r1 = make_float4(cc, o, ex, ey);
                 r2 = make_float4(fmaxf(col[0], 0.f), fmaxf(col[1], 0.f), fmaxf(col[2], 0.f),
                                  __uint_as_float(mask));
+                depth = G.tz;
             }
         }
     }
@@ -216,12 +228,12 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
     rec[3 * e + 1] = r1;
     rec[3 * e + 2] = r2;
     tiles[e] = ntiles;
-    dkey[e] = __float_as_uint(r1.w);
+    dkey[e] = __float_as_uint(depth);
 }
 
 __global__ void __launch_bounds__(256) load_records_kernel(
     int64_t entries, int64_t n, const float* __restrict__ u, const float* __restrict__ v,
-    const float* __restrict__ depth, const int32_t* __restrict__ radius,
+    const float* __restrict__ depth, const int32_t* __restrict__ extent,
     const float* __restrict__ conic, const float* __restrict__ opacity,
     const float* __restrict__ rgb, Views views, RasterDev rp, float4* __restrict__ rec,
     uint32_t* __restrict__ tiles, uint32_t* __restrict__ dkey) {
@@ -229,17 +241,18 @@ __global__ void __launch_bounds__(256) load_records_kernel(
     if (e >= entries) return;
     int64_t i;
     const ViewDev& V = views.v[find_view(views, e, n, &i)];
-    const int r = radius[e];
+    const int rx = extent[2 * e], ry = extent[2 * e + 1];
     uint32_t ntiles = 0;
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
-    if (r > 0 && r < (int)kMaxExtent && fabsf(u[e]) < (float)kMaxExtent &&
-        fabsf(v[e]) < (float)kMaxExtent) {
+    if (rx >= 0 && ry >= 0 && rx < (int)kMaxExtent && ry < (int)kMaxExtent &&
+        fabsf(u[e]) < (float)kMaxExtent && fabsf(v[e]) < (float)kMaxExtent) {
         int x0, x1, y0, y1;
-        tile_rect(u[e], v[e], r, rp.tile_w, rp.tile_h, V.tiles_x, V.tiles_y, &x0, &x1, &y0, &y1);
+        tile_rect(u[e], v[e], rx, ry, rp.tile_w, rp.tile_h, V.tiles_x, V.tiles_y, &x0, &x1, &y0,
+                  &y1);
         if (x1 > x0 && y1 > y0) {
             ntiles = (uint32_t)((x1 - x0) * (y1 - y0));
             r0 = make_float4(u[e], v[e], conic[3 * e], conic[3 * e + 1]);
-            r1 = make_float4(conic[3 * e + 2], opacity[e], (float)r, depth[e]);
+            r1 = make_float4(conic[3 * e + 2], opacity[e], (float)rx, (float)ry);
             r2 = make_float4(rgb[3 * e], rgb[3 * e + 1], rgb[3 * e + 2], __uint_as_float(7u));
         }
     }
@@ -247,7 +260,7 @@ __global__ void __launch_bounds__(256) load_records_kernel(
     rec[3 * e + 1] = r1;
     rec[3 * e + 2] = r2;
     tiles[e] = ntiles;
-    dkey[e] = __float_as_uint(r1.w);
+    dkey[e] = __float_as_uint(ntiles ? depth[e] : 0.f);
 }
 
 // Y_k and its gradient for a compile-time index k (the unrolled SH loops fold
@@ -561,7 +574,7 @@ hipError_t launch_project(const float* planes, int64_t n, int64_t stride, int sh
 }
 
 hipError_t launch_load_records(int64_t entries, const float* u, const float* v,
-                               const float* depth, const int32_t* radius, const float* conic,
+                               const float* depth, const int32_t* extent, const float* conic,
                                const float* opacity, const float* rgb, int64_t n,
                                const Views& views, const RasterDev& rp, float* records,
                                uint32_t* tiles, uint32_t* dkey, hipStream_t s) {
@@ -569,7 +582,7 @@ hipError_t launch_load_records(int64_t entries, const float* u, const float* v,
     const int nt = 256;
     const int64_t nb = (entries + nt - 1) / nt;
     hipLaunchKernelGGL(load_records_kernel, dim3((unsigned)nb), dim3(nt), 0, s, entries, n, u, v,
-                       depth, radius, conic, opacity, rgb, views, rp,
+                       depth, extent, conic, opacity, rgb, views, rp,
                        reinterpret_cast<float4*>(records), tiles, dkey);
     return hipGetLastError();
 }

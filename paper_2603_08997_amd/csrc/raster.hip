@@ -34,11 +34,11 @@ struct Splat {
 // Overlap test, Gaussian falloff and alpha' of one (pixel, Gaussian) pair.
 // Forward and backward call this same function, so their skip decisions agree
 // bit for bit. Returns false when the Gaussian does not contribute.
-__device__ __forceinline__ bool splat_alpha(float px, float py, float u, float v, float r,
-                                            float o, float a, float b, float c,
+__device__ __forceinline__ bool splat_alpha(float px, float py, float u, float v, float rx,
+                                            float ry, float o, float a, float b, float c,
                                             const RasterDev& rp, Splat& s) {
-    // |p - mean| <= r per axis; p +- r is exact for half-integer p, integer r
-    if (!(px - r <= u && u <= px + r && py - r <= v && v <= py + r)) return false;
+    // overlap box |p - mean| <= (rx, ry); p +- r is exact for half-integer p, integer r
+    if (!(px - rx <= u && u <= px + rx && py - ry <= v && v <= py + ry)) return false;
     s.dx = px - u;
     s.dy = py - v;
     const float power = -0.5f * fmaf(a, s.dx * s.dx, c * (s.dy * s.dy)) - b * (s.dx * s.dy);
@@ -75,8 +75,8 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
     float* __restrict__ out_rgb, float* __restrict__ t_final, uint32_t* __restrict__ n_last,
     uint32_t* __restrict__ counters) {
     constexpr int PIX = TW * TH / kLanes;
-    __shared__ float4 s_pos[kLanes];   // u, v, radius, opacity
-    __shared__ float4 s_con[kLanes];   // a, b, c, -
+    __shared__ float4 s_pos[kLanes];   // u, v, rx, ry
+    __shared__ float4 s_con[kLanes];   // a, b, c, opacity
     __shared__ float4 s_col[kLanes];   // r, g, b, -
 
     const int tile = blockIdx.x;
@@ -111,8 +111,8 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
         if (idx < end) {
             const int64_t e = pentry[idx];
             const float4 r0 = rec[3 * e], r1 = rec[3 * e + 1], r2 = rec[3 * e + 2];
-            s_pos[tid] = make_float4(r0.x, r0.y, r1.z, r1.y);
-            s_con[tid] = make_float4(r0.z, r0.w, r1.x, 0.f);
+            s_pos[tid] = make_float4(r0.x, r0.y, r1.z, r1.w);
+            s_con[tid] = make_float4(r0.z, r0.w, r1.x, r1.y);
             s_col[tid] = r2;
         }
         __syncthreads();
@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
                 if (!done[k]) {
                     ++n_eval;
                     Splat s;
-                    if (splat_alpha(px[k], py[k], P.x, P.y, P.z, P.w, Q.x, Q.y, Q.z, rp, s)) {
+                    if (splat_alpha(px[k], py[k], P.x, P.y, P.z, P.w, Q.w, Q.x, Q.y, Q.z, rp, s)) {
                         const float test = T[k] * (1.f - s.alpha);
                         if (test < rp.t_min) {
                             done[k] = true;
@@ -177,9 +177,9 @@ __global__ void __launch_bounds__(kLanes) raster_backward_kernel(
     const float* __restrict__ dl_drgb, const int32_t* __restrict__ gate,
     float* __restrict__ accum) {
     constexpr int PIX = TW * TH / kLanes;
-    __shared__ float4 s_pos[kLanes];   // u, v, radius, opacity
-    __shared__ float4 s_con[kLanes];   // a, b, c, entry (bits)
-    __shared__ float4 s_col[kLanes];   // r, g, b, -
+    __shared__ float4 s_pos[kLanes];   // u, v, rx, ry
+    __shared__ float4 s_con[kLanes];   // a, b, c, opacity
+    __shared__ float4 s_col[kLanes];   // r, g, b, entry (bits)
     if (gate_closed(gate)) return;
 
     const int tile = blockIdx.x;
@@ -228,9 +228,9 @@ __global__ void __launch_bounds__(kLanes) raster_backward_kernel(
             const uint32_t e = pentry[idx];
             const float4 r0 = rec[3 * (int64_t)e], r1 = rec[3 * (int64_t)e + 1],
                          r2 = rec[3 * (int64_t)e + 2];
-            s_pos[tid] = make_float4(r0.x, r0.y, r1.z, r1.y);
-            s_con[tid] = make_float4(r0.z, r0.w, r1.x, __uint_as_float(e));
-            s_col[tid] = r2;
+            s_pos[tid] = make_float4(r0.x, r0.y, r1.z, r1.w);
+            s_con[tid] = make_float4(r0.z, r0.w, r1.x, r1.y);
+            s_col[tid] = make_float4(r2.x, r2.y, r2.z, __uint_as_float(e));
         }
         __syncthreads();
         for (int j = 0; j < cnt; ++j) {
@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(kLanes) raster_backward_kernel(
             for (int k = 0; k < PIX; ++k) {
                 Splat s;
                 if (rel < last[k] &&
-                    splat_alpha(px[k], py[k], P.x, P.y, P.z, P.w, Q.x, Q.y, Q.z, rp, s)) {
+                    splat_alpha(px[k], py[k], P.x, P.y, P.z, P.w, Q.w, Q.x, Q.y, Q.z, rp, s)) {
                     const float4 col = s_col[j];
                     const float om = 1.f - s.alpha;
                     const float Ti = T[k] / om;
@@ -282,7 +282,7 @@ __global__ void __launch_bounds__(kLanes) raster_backward_kernel(
             d_g = wave_sum_to_lane63(d_g);
             d_bl = wave_sum_to_lane63(d_bl);
             if (tid == 63) {
-                float* acc = accum + (int64_t)kAccumFloats * __float_as_uint(Q.w);
+                float* acc = accum + (int64_t)kAccumFloats * __float_as_uint(s_col[j].w);
                 unsafeAtomicAdd(acc + 0, d_u);
                 unsafeAtomicAdd(acc + 1, d_v);
                 unsafeAtomicAdd(acc + 2, d_a);

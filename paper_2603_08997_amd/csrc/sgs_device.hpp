@@ -77,16 +77,18 @@ __device__ __forceinline__ int floordiv(int a, int b) {
     return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
 }
 
-// Tile rectangle [x0, x1) x [y0, y1) of the square |x - u| <= r, |y - v| <= r.
-// With r and the tile size integers, floor((u - r)/tw) = floor((floor(u) - r)/tw),
-// so the rectangle is exact in integer arithmetic on floor(u) (|u| < 2^24).
-__device__ __forceinline__ void tile_rect(float u, float v, int r, int tw, int th, int tx_n,
-                                          int ty_n, int* x0, int* x1, int* y0, int* y1) {
+// Tile rectangle [x0, x1) x [y0, y1) of the box |x - u| <= rx, |y - v| <= ry.
+// With rx, ry and the tile size integers, floor((u - rx)/tw) =
+// floor((floor(u) - rx)/tw), so the rectangle is exact in integer arithmetic
+// on floor(u) (|u| < 2^24).
+__device__ __forceinline__ void tile_rect(float u, float v, int rx, int ry, int tw, int th,
+                                          int tx_n, int ty_n, int* x0, int* x1, int* y0,
+                                          int* y1) {
     const int fu = (int)floorf(u), fv = (int)floorf(v);
-    *x0 = min(max(floordiv(fu - r, tw), 0), tx_n);
-    *x1 = min(max(floordiv(fu + r, tw) + 1, 0), tx_n);
-    *y0 = min(max(floordiv(fv - r, th), 0), ty_n);
-    *y1 = min(max(floordiv(fv + r, th) + 1, 0), ty_n);
+    *x0 = min(max(floordiv(fu - rx, tw), 0), tx_n);
+    *x1 = min(max(floordiv(fu + rx, tw) + 1, 0), tx_n);
+    *y0 = min(max(floordiv(fv - ry, th), 0), ty_n);
+    *y1 = min(max(floordiv(fv + ry, th) + 1, 0), ty_n);
 }
 
 // Adam element update, shared by the plain step and the fused backward step

@@ -12,7 +12,7 @@ namespace sgs {
 
 constexpr int kWave = 64;
 constexpr uint32_t kMaxExtent = 1u << 24;   // |u|, |v|, radius beyond this: degenerate, culled
-constexpr int kRecordFloats = 12;           // u v a b | c o radius depth | r g b tiles
+constexpr int kRecordFloats = 12;           // u v a b | c o rx ry | r g b clamp-mask
 constexpr int kAccumFloats = 12;            // du dv da db | dc do dr dg | db - - -
 
 // Per-view constants, passed by value to every kernel of a multi-view batch.
@@ -81,7 +81,7 @@ hipError_t launch_project(const float* planes, int64_t n, int64_t stride, int sh
                           const Views& views, const RasterDev& rp, float* records,
                           uint32_t* tiles, uint32_t* dkey, hipStream_t s);
 hipError_t launch_load_records(int64_t entries, const float* u, const float* v,
-                               const float* depth, const int32_t* radius, const float* conic,
+                               const float* depth, const int32_t* extent, const float* conic,
                                const float* opacity, const float* rgb, int64_t n,
                                const Views& views, const RasterDev& rp, float* records,
                                uint32_t* tiles, uint32_t* dkey, hipStream_t s);

@@ -36,30 +36,44 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int bits
     return peers;
 }
 
+// Digit counts of one block's keys. Counting does not depend on order, so the
+// keys are read as uint4 and counted into per-wave LDS histograms.
 __global__ void __launch_bounds__(kThreads) radix_hist_kernel(const uint32_t* __restrict__ keys,
                                                               const uint32_t* __restrict__ n_dev,
                                                               int shift, int bits,
                                                               uint32_t* __restrict__ hist,
                                                               int nblocks) {
-    __shared__ uint32_t cnt[kRadix];
-    const int tid = threadIdx.x;
-    cnt[tid] = 0;
+    __shared__ uint32_t cnt[kWaves][kRadix];
+    const int tid = threadIdx.x, w = tid / 64;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) cnt[k][tid] = 0;
     __syncthreads();
     const uint32_t n = *n_dev;
     const uint32_t mask = (1u << bits) - 1u;
     const int64_t base = (int64_t)blockIdx.x * kTile;
     if (base < (int64_t)n) {
-#pragma unroll 4
-        for (int it = 0; it < kItems; ++it) {
-            const int64_t idx = base + (int64_t)it * kThreads + tid;
-            const bool valid = idx < (int64_t)n;
-            const uint32_t d = valid ? digit_of(keys[idx], shift, mask) : 0u;
-            const uint64_t peers = match_digit(d, valid, bits);
-            if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&cnt[d], (uint32_t)popc64(peers));
+        const uint4* k4 = reinterpret_cast<const uint4*>(keys + base);
+        const int64_t left = (int64_t)n - base;
+#pragma unroll
+        for (int it = 0; it < kItems / 4; ++it) {
+            const int64_t j = (int64_t)(it * kThreads + tid) * 4;
+            if (j + 3 < left) {
+                const uint4 q = k4[it * kThreads + tid];
+                atomicAdd(&cnt[w][digit_of(q.x, shift, mask)], 1u);
+                atomicAdd(&cnt[w][digit_of(q.y, shift, mask)], 1u);
+                atomicAdd(&cnt[w][digit_of(q.z, shift, mask)], 1u);
+                atomicAdd(&cnt[w][digit_of(q.w, shift, mask)], 1u);
+            } else {
+                for (int64_t t = j; t < left && t < j + 4; ++t)
+                    atomicAdd(&cnt[w][digit_of(keys[base + t], shift, mask)], 1u);
+            }
         }
     }
     __syncthreads();
-    hist[(int64_t)tid * nblocks + blockIdx.x] = cnt[tid];
+    uint32_t total = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) total += cnt[k][tid];
+    hist[(int64_t)tid * nblocks + blockIdx.x] = total;
 }
 
 // Exclusive scan of each digit row hist[d][0..nblocks) in place; totals[d] = row sum.
@@ -178,14 +192,25 @@ int64_t radix_blocks(int64_t n_max) { return n_max <= 0 ? 1 : (n_max + kTile - 1
 
 int radix_passes(int bits) { return bits <= 0 ? 0 : (bits + 7) / 8; }
 
+// Bits of pass p when `bits` are sorted in radix_passes(bits) passes of
+// near-equal width (13 bits: 7 + 6).
+static int pass_bits(int bits, int p, int* shift) {
+    const int passes = radix_passes(bits);
+    const int base = bits / passes, extra = bits % passes;
+    int sh = 0;
+    for (int q = 0; q < p; ++q) sh += base + (q < extra ? 1 : 0);
+    *shift = sh;
+    return base + (p < extra ? 1 : 0);
+}
+
 hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int64_t n_max,
                       int bits, uint32_t* hist, uint32_t* totals, hipStream_t s, int* result) {
     const int passes = radix_passes(bits);
     const int nb = (int)radix_blocks(n_max);
     int cur = 0;
     for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
-        const int pb = min(8, bits - shift);
+        int shift;
+        const int pb = pass_bits(bits, p, &shift);
         hipLaunchKernelGGL(radix_hist_kernel, dim3(nb), dim3(kThreads), 0, s, keys[cur], n_dev,
                            shift, pb, hist, nb);
         hipLaunchKernelGGL(radix_scan_kernel, dim3(kRadix), dim3(kScanThreads), 0, s, hist, nb,

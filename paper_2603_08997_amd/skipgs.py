@@ -48,8 +48,9 @@ class RasterParamsC(C.Structure):
 
 
 class WorkspaceLayoutC(C.Structure):
-    _fields_ = [(k, C.c_size_t) for k in ("records", "tiles", "pair_tile", "pair_entry", "ranges",
-                                            "t_final", "n_last", "accum", "counters")] + \
+    _fields_ = [(k, C.c_size_t) for k in ("records", "tiles", "depth", "pair_tile", "pair_entry",
+                                            "ranges", "t_final", "n_last", "accum",
+                                            "counters")] + \
                [("entries", C.c_int64), ("total_tiles", C.c_int64), ("total_pixels", C.c_int64)]
 
 
@@ -261,11 +262,11 @@ def project(planes, n, sh_degree, cams, rp, workspace, pair_capacity, stream=Non
                            _ptr(workspace), workspace.numel(), pair_capacity, _stream(stream)))
 
 
-def load_records(cams, n, rp, workspace, pair_capacity, u, v, depth, radius, conic, opacity, rgb,
+def load_records(cams, n, rp, workspace, pair_capacity, u, v, depth, extent, conic, opacity, rgb,
                  stream=None):
     _check(LIB.sgs_load_records(cameras_c(cams), len(cams), n, C.byref(rp.c()), _ptr(workspace),
                                 workspace.numel(), pair_capacity, _ptr(u), _ptr(v), _ptr(depth),
-                                _ptr(radius), _ptr(conic), _ptr(opacity), _ptr(rgb),
+                                _ptr(extent), _ptr(conic), _ptr(opacity), _ptr(rgb),
                                 _stream(stream)))
 
 

@@ -87,6 +87,9 @@ class GpuRender:
     def records(self):
         return region(self.ws, self.L.records, 12 * self.L.entries, np.float32).reshape(-1, 12)
 
+    def depth(self):
+        return region(self.ws, self.L.depth, self.L.entries, np.float32)
+
     def t_final(self):
         return region(self.ws, self.L.t_final, self.L.total_pixels, np.float32)
 

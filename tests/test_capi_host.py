@@ -122,7 +122,8 @@ def test_layout_regions_fit_and_do_not_overlap():
     assert L.entries == 1000
     assert L.total_tiles == 8 * 6 + 5 * 3
     assert L.total_pixels == 64 * 48 + 40 * 24
-    regions = sorted([(L.records, 48 * 1000), (L.tiles, 4 * 1000), (L.pair_tile, 4 * 30_000),
+    regions = sorted([(L.records, 48 * 1000), (L.tiles, 4 * 1000), (L.depth, 4 * 1000),
+                      (L.pair_tile, 4 * 30_000),
                       (L.pair_entry, 4 * 30_000), (L.ranges, 8 * L.total_tiles),
                       (L.t_final, 4 * L.total_pixels), (L.n_last, 4 * L.total_pixels),
                       (L.accum, 48 * 1000), (L.counters, 64)])

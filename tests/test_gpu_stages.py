@@ -32,7 +32,7 @@ class Stage:
         self.ws.zero_()
         self.L = m.get_workspace_layout(rp, n, cams, capacity)
         d = {k: to_dev(v) for k, v in cat.items()}
-        m.load_records(cams, n, rp, self.ws, capacity, d["u"], d["v"], d["depth"], d["radius"],
+        m.load_records(cams, n, rp, self.ws, capacity, d["u"], d["v"], d["depth"], d["extent"],
                        d["conic"], d["opacity"], d["rgb"])
         m.bin(cams, n, rp, self.ws, capacity)
         self.flags, self.vis, self.pairs = m.read_status(self.ws)
@@ -63,7 +63,7 @@ def _oracle_bins(recs, cams, n, tw, th):
     keys, vals, ranges = [], [], []
     off = 0
     for v, (r, c) in enumerate(zip(recs, cams)):
-        k, val, rg = R.bin_and_sort(r["u"], r["v"], r["depth"], r["radius"], v * n + np.arange(n),
+        k, val, rg = R.bin_and_sort(r["u"], r["v"], r["depth"], r["extent"], v * n + np.arange(n),
                                     c.width, c.height, tw, th, tile_offset=off)
         base = sum(len(x) for x in keys)
         rg = np.where(rg[:, 1:2] > rg[:, 0:1], rg + base, 0)
@@ -98,7 +98,7 @@ def test_binning_empty_and_capacity_overflow():
     cams = _views()
     n = 300
     recs, cat = _records(n, cams, 7, max_radius=15)
-    cat["radius"][:] = 0                       # nothing visible
+    cat["extent"][:] = -1                      # nothing visible
     st = Stage(n, cams, m.RasterParams(), cat, 1000)
     assert st.flags == 0 and st.vis == 0 and st.pairs == 0
     _, _, ranges = st.lists()
@@ -114,7 +114,7 @@ def _oracle_composite(rec, cam, rp, n, view, leaf=False):
          for k in ("u", "v", "conic", "opacity", "rgb")}
     uv = torch.stack([t["u"], t["v"]], 1)
     out = R.composite(uv, t["conic"], t["opacity"], t["rgb"], torch.tensor(rec["depth"], dtype=torch.float64),
-                      torch.tensor(rec["radius"].astype(np.int64)), view * n + torch.arange(n),
+                      torch.tensor(rec["extent"].astype(np.int64)), view * n + torch.arange(n),
                       cam.width, cam.height, rp)
     return out, t
 
