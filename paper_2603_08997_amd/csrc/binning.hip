@@ -125,9 +125,10 @@ __global__ void capacity_kernel(uint32_t* counters, int64_t capacity) {
 
 // Pair emission, load balanced over pairs: each workgroup writes a fixed
 // window of kEmitTile consecutive pairs. The Gaussians (in depth order) whose
-// pair ranges meet the window are found by binary search in the offsets, their
-// tile rectangles staged in LDS, and every thread expands its pairs to
-// (tile, entry) with coalesced stores. Pair q of a Gaussian is tile
+// pair ranges meet the window are found by binary search in the offsets and
+// their tile rectangles staged in LDS; a max-scan of their start positions
+// gives every window position its Gaussian, and every thread expands its pairs
+// to (tile, entry) with coalesced stores. Pair q of a Gaussian is tile
 // (x0 + q % w, y0 + q / w) of its rectangle, row-major.
 constexpr int kEmitThreads = 256;
 constexpr int kEmitItems = 8;
@@ -151,6 +152,8 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     __shared__ uint32_t s_base[kEmitTile];   // global tile of the rectangle's first tile
     __shared__ uint16_t s_w[kEmitTile];      // rectangle width in tiles
     __shared__ uint16_t s_tx[kEmitTile];     // tiles per row of the Gaussian's view
+    __shared__ uint32_t s_own[kEmitTile];    // window position -> owning Gaussian
+    __shared__ uint32_t s_scan[kEmitThreads / 64 + 1];
     __shared__ uint32_t s_k0, s_cnt;
     const uint32_t P = counters[kPairsWritten];
     const uint32_t nvis = counters[kVisible];
@@ -165,6 +168,8 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
         s_cnt = k1 - k0 + 1u;
         s_off[k1 - k0 + 1u] = (k1 + 1u < nvis) ? offsets[k1 + 1u] : 0xffffffffu;
     }
+#pragma unroll
+    for (int it = 0; it < kEmitItems; ++it) s_own[it * kEmitThreads + tid] = 0u;
     __syncthreads();
     const uint32_t k0 = s_k0, cnt = s_cnt;
     for (uint32_t j = tid; j < cnt; j += kEmitThreads) {
@@ -175,27 +180,41 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
         int x0, x1, y0, y1;
         tile_rect(r0.x, r0.y, (int)r1.z, (int)r1.w, rp.tile_w, rp.tile_h, V.tiles_x, V.tiles_y,
                   &x0, &x1, &y0, &y1);
-        s_off[j] = offsets[k];
+        const uint32_t off = offsets[k];
+        s_off[j] = off;
         s_ent[j] = e;
         s_base[j] = (uint32_t)(V.tile_offset + y0 * V.tiles_x + x0);
         s_w[j] = (uint16_t)(x1 - x0);
         s_tx[j] = (uint16_t)V.tiles_x;
+        // mark where this Gaussian's pairs start inside the window
+        if (j > 0) s_own[off - p0] = j;
+    }
+    __syncthreads();
+    // owner of every window position = the last Gaussian starting at or
+    // before it: inclusive max-scan of the start marks (thread t scans
+    // positions 8t .. 8t+7, then the block combines the per-thread maxima)
+    {
+        uint32_t run[kEmitItems];
+        uint32_t m = 0;
+#pragma unroll
+        for (int i = 0; i < kEmitItems; ++i) {
+            m = max(m, s_own[tid * kEmitItems + i]);
+            run[i] = m;
+        }
+        const uint32_t before = block_excl_max_scan<kEmitThreads>(m, s_scan);
+#pragma unroll
+        for (int i = 0; i < kEmitItems; ++i) s_own[tid * kEmitItems + i] = max(before, run[i]);
     }
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < kEmitItems; ++it) {
         const uint32_t p = p0 + (uint32_t)(it * kEmitThreads + tid);
         if (p > p_last) break;
-        // Gaussian j of the window with s_off[j] <= p < s_off[j + 1]
-        uint32_t lo = 0, hi = cnt;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (s_off[mid] <= p) lo = mid; else hi = mid;
-        }
-        const uint32_t q = p - s_off[lo];
-        const uint32_t w = s_w[lo];
-        ptile[p] = s_base[lo] + (q / w) * s_tx[lo] + (q % w);
-        pentry[p] = s_ent[lo];
+        const uint32_t j = s_own[it * kEmitThreads + tid];
+        const uint32_t q = p - s_off[j];
+        const uint32_t w = s_w[j];
+        ptile[p] = s_base[j] + (q / w) * s_tx[j] + (q % w);
+        pentry[p] = s_ent[j];
     }
 }
 

@@ -246,15 +246,17 @@ __global__ void __launch_bounds__(kLanes) raster_backward_kernel(
                 if (rel < last[k] &&
                     splat_alpha(px[k], py[k], P.x, P.y, P.z, P.w, Q.w, Q.x, Q.y, Q.z, rp, s)) {
                     const float4 col = s_col[j];
-                    const float om = 1.f - s.alpha;
-                    const float Ti = T[k] / om;
+                    // 1 - alpha' >= 1 - alpha_max > 0: one hardware reciprocal
+                    // (1 ulp) serves the transmittance recovery and dC/dalpha'
+                    const float inv_om = __builtin_amdgcn_rcpf(1.f - s.alpha);
+                    const float Ti = T[k] * inv_om;
                     const float w = s.alpha * Ti;
                     d_r = fmaf(G0[k], w, d_r);
                     d_g = fmaf(G1[k], w, d_g);
                     d_bl = fmaf(G2[k], w, d_bl);
-                    const float d_alpha = G0[k] * (col.x * Ti - S0[k] / om) +
-                                          G1[k] * (col.y * Ti - S1[k] / om) +
-                                          G2[k] * (col.z * Ti - S2[k] / om);
+                    const float d_alpha = G0[k] * (col.x * Ti - S0[k] * inv_om) +
+                                          G1[k] * (col.y * Ti - S1[k] * inv_om) +
+                                          G2[k] * (col.z * Ti - S2[k] * inv_om);
                     S0[k] = fmaf(col.x, w, S0[k]);
                     S1[k] = fmaf(col.y, w, S1[k]);
                     S2[k] = fmaf(col.z, w, S2[k]);

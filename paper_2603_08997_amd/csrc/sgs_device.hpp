@@ -72,6 +72,27 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* smem /
     return r;
 }
 
+// Exclusive max-scan over the threads of a block (identity 0).
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_max_scan(uint32_t v, uint32_t* smem) {
+    const int w = threadIdx.x / 64;
+    const int l = __lane_id();
+    uint32_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(inc, d, 64);
+        if (l >= d) inc = max(inc, o);
+    }
+    if (l == 63) smem[w] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int k = 0; k < w; ++k) before = max(before, smem[k]);
+    uint32_t ex = __shfl_up(inc, 1, 64);
+    if (l == 0) ex = 0;
+    __syncthreads();
+    return max(before, ex);
+}
+
 __device__ __forceinline__ int floordiv(int a, int b) {
     const int q = a / b;
     return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
