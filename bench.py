@@ -100,6 +100,28 @@ def cpu_baseline(gt, init, cam, crop=24):
             "seconds_per_iter_estimate": est}
 
 
+def hbm_copy_probe(nbytes=1 << 30, reps=20):
+    """Streaming copy of nbytes through a plain elementwise kernel (torch's
+    multiply by 1 into another buffer, so that it runs on the compute units
+    rather than as a DMA transfer) timed with HIP events: bytes read plus
+    bytes written per second, the practical ceiling of a kernel that reads
+    and writes equal amounts. The same copies are the known-size reference
+    for the HBM byte counters."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    b.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    return gbs
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -162,13 +184,15 @@ def main():
     full = results.get("full")
     headline = gated or full
 
-    # dominant kernel: the compositing backward (per executed iteration) or
-    # forward, whichever takes longer in the headline run
+    # dominant kernel: of the compositing forward, the compositing backward
+    # and the fused projection backward + Adam, the one with the largest
+    # time per iteration in the headline run (backward kernels weighted by
+    # the fraction of iterations that run them)
     roof = None
     tr = headline["_trainer"]
     timer = headline["_timer"]
     if timer is not None:
-        # blended (pixel, Gaussian) pairs of one view, averaged over 8 views
+        # per-view counters, averaged over 8 views
         blended, evaluated, pairs, visible = [], [], [], []
         for v in range(min(8, args.views)):
             tr.render(v, tr.rgb)
@@ -179,22 +203,43 @@ def main():
             pairs.append(cnt["pairs"])
             visible.append(cnt["visible"])
         blended = float(np.mean(blended))
+        vis = float(np.mean(visible))
         ex = headline["stage_ms_executed"]
         allm = headline["stage_ms_all"]
-        tot_bwd = ex["raster_bwd"] * headline["backward_fraction"]
-        tot_fwd = allm["rasterize"]
-        if tot_bwd >= tot_fwd:
-            ms, flops_pp, name = ex["raster_bwd"], BWD_FLOPS_PER_PAIR, "raster_backward"
-        else:
-            ms, flops_pp, name = allm["rasterize"], FWD_FLOPS_PER_PAIR, "raster_forward"
-        achieved = blended * flops_pp / (ms * 1e-3) / 1e12
-        roof = {"kernel": name, "bound": "alu", "achieved": achieved,
-                "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
-                "avg_launch_ms": ms, "blended_pairs_per_launch": blended,
+        bf = headline["backward_fraction"]
+        F = 11 + 3 * 16
+        # algorithmic HBM bytes of one fused launch: parameters, first and
+        # second moments read and written once per plane of every Gaussian,
+        # the visibility word of every Gaussian, and the 48-byte gradient
+        # accumulator plus the 16-byte colour record of every visible one
+        fused_bytes = args.n * (F * 4 * 6 + 4) + vis * (48 + 16)
+        cands = {
+            "raster_forward": dict(ms=allm["rasterize"], weight=1.0, bound="alu",
+                                   work=blended * FWD_FLOPS_PER_PAIR / 1e12, unit="TFLOP/s",
+                                   peak=FP32_VECTOR_PEAK_TFLOPS),
+            "raster_backward": dict(ms=ex["raster_bwd"], weight=bf, bound="alu",
+                                    work=blended * BWD_FLOPS_PER_PAIR / 1e12, unit="TFLOP/s",
+                                    peak=FP32_VECTOR_PEAK_TFLOPS),
+            "project_backward_adam": dict(ms=ex["project_bwd"], weight=bf, bound="hbm",
+                                          work=fused_bytes / 1e9, unit="GB/s",
+                                          peak=HBM_PEAK_GBS),
+        }
+        summary = {}
+        for k, c in cands.items():
+            ach = c["work"] / (c["ms"] * 1e-3) if c["ms"] > 0 else 0.0
+            summary[k] = {"avg_launch_ms": c["ms"], "ms_per_iteration": c["ms"] * c["weight"],
+                          "bound": c["bound"], "achieved": ach, "unit": c["unit"],
+                          "frac": ach / c["peak"]}
+        name = max(summary, key=lambda k: summary[k]["ms_per_iteration"])
+        c, sm = cands[name], summary[name]
+        roof = {"kernel": name, "bound": c["bound"], "achieved": sm["achieved"], "peak": c["peak"],
+                "unit": c["unit"], "frac": sm["frac"], "traffic": None,
+                "avg_launch_ms": c["ms"], "blended_pairs_per_launch": blended,
                 "evaluated_pairs_per_launch": float(np.mean(evaluated)),
-                "tile_pairs_per_view": float(np.mean(pairs)),
-                "visible_per_view": float(np.mean(visible)), "flops_per_pair": flops_pp}
+                "tile_pairs_per_view": float(np.mean(pairs)), "visible_per_view": vis,
+                "fused_bytes_per_launch": fused_bytes,
+                "flops_per_pair": {"forward": FWD_FLOPS_PER_PAIR, "backward": BWD_FLOPS_PER_PAIR},
+                "kernels": summary}
 
     out = {
         "metric": "post-densification iters/s (gated vs full) at 1 GPU",
@@ -231,6 +276,7 @@ def main():
                               for kk, vv in r.get("stage_ms_executed", {}).items()}
     if roof is not None:
         out["roofline"] = roof
+    out["hbm_copy_GBps"] = hbm_copy_probe()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(gt, init, cams[0])

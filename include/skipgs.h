@@ -27,7 +27,7 @@
  *   planes 0-2 mean xyz | 3-5 log-scale xyz | 6-9 quaternion wxyz (any norm)
  *   | 10 opacity logit | 11 + 3k + c: SH coefficient k, colour channel c.
  *   Gradients and Adam moments use the identical layout and stride.
- *   stride >= n and a multiple of 64; data 256-byte aligned.
+ *   stride >= n, a multiple of 64 and < 2^29; data 256-byte aligned.
  *
  * Images: planar float32 [3][H][W] per view; a multi-view call concatenates
  * the views in order (view v starts at 3 * sum_{u<v} H_u W_u floats).
@@ -69,7 +69,7 @@ int32_t sgs_version(void);
 typedef struct {
     float* data;        /* device, [F][stride] float32, planes as above        */
     int64_t n;          /* number of Gaussians, >= 0                           */
-    int64_t stride;     /* plane stride in elements, >= n, multiple of 64      */
+    int64_t stride;     /* plane stride in elements, >= n, multiple of 64, < 2^29 */
     int32_t sh_degree;  /* D in {0, 1, 2, 3}                                    */
 } sgs_gaussians;
 

@@ -7,6 +7,9 @@ Every HIP source is compiled with:
   (the gate's binary64 arithmetic and the forward/backward skip decisions
   depend on it; kernels use explicit fmaf where a fused multiply-add is meant);
 * -munsafe-fp-atomics: float atomics become hardware L2 atomics, not CAS loops;
+* no atomic optimizer: kernels reduce across the wave themselves before the
+  one lane that issues an atomic, so the compiler's own per-atomic wave
+  reduction would only add instructions;
 * packed FP32 instructions disabled (-packed-fp32-ops).
 """
 from __future__ import annotations
@@ -27,6 +30,7 @@ ARCH = "gfx950"
 FLAGS = [
     "-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}",
     "-ffp-contract=off", "-munsafe-fp-atomics",
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
 ]

@@ -22,7 +22,10 @@ __global__ void __launch_bounds__(256) adam_kernel(AdamDev a, float4* __restrict
                                                    const int32_t* __restrict__ gate) {
     if (gate_closed(gate)) return;
     const int plane = blockIdx.y;
-    const AdamStep as = adam_bias_correction(a, *step);
+    __shared__ AdamStep s_as;
+    if (threadIdx.x == 0) s_as = adam_bias_correction(a, *step);
+    __syncthreads();
+    const AdamStep as = s_as;
     const float lr = a.lr[plane];
     const int64_t base = (int64_t)plane * stride4;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < stride4;

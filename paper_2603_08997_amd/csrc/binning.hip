@@ -44,9 +44,20 @@ struct PairCountSrc {  // tiles touched, in depth order
     __device__ int64_t count() const { return *n_dev; }
     __device__ uint32_t operator()(int64_t k) const { return tiles[sorted_entry[k]]; }
 };
+// Pair offset of every Gaussian in depth order, and for every emission window
+// (kEmitWindow consecutive pairs, windows 0 .. n_windows) the Gaussian whose
+// pair range holds the window's first pair.
 struct OffsetSink {
     uint32_t* offsets;
-    __device__ void operator()(int64_t k, uint32_t, uint32_t pos) const { offsets[k] = pos; }
+    uint32_t* window_first;
+    uint32_t n_windows;
+    __device__ void operator()(int64_t k, uint32_t v, uint32_t pos) const {
+        offsets[k] = pos;
+        const uint32_t end = pos + v;
+        for (uint32_t w = (pos + (uint32_t)kEmitWindow - 1u) / (uint32_t)kEmitWindow;
+             w <= n_windows && (uint64_t)w * kEmitWindow < end; ++w)
+            window_first[w] = (uint32_t)k;
+    }
 };
 
 template <class Src>
@@ -125,53 +136,47 @@ __global__ void capacity_kernel(uint32_t* counters, int64_t capacity) {
 
 // Pair emission, load balanced over pairs: each workgroup writes a fixed
 // window of kEmitTile consecutive pairs. The Gaussians (in depth order) whose
-// pair ranges meet the window are found by binary search in the offsets and
-// their tile rectangles staged in LDS; a max-scan of their start positions
-// gives every window position its Gaussian, and every thread expands its pairs
-// to (tile, entry) with coalesced stores. Pair q of a Gaussian is tile
-// (x0 + q % w, y0 + q / w) of its rectangle, row-major.
+// pair ranges meet the window run from the one holding the window's first pair
+// to the one holding the next window's first pair (both recorded by the offset
+// scan); their tile rectangles are staged in LDS, a max-scan of their start
+// positions gives every window position its Gaussian, and every thread expands
+// its pairs to (tile, entry) with coalesced stores. Pair q of a Gaussian is
+// tile (x0 + q % w, y0 + q / w) of its rectangle, row-major.
 constexpr int kEmitThreads = 256;
 constexpr int kEmitItems = 8;
 constexpr int kEmitTile = kEmitThreads * kEmitItems;
-
-__device__ __forceinline__ uint32_t upper_bound_u32(const uint32_t* a, uint32_t n, uint32_t x) {
-    uint32_t lo = 0, hi = n;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (a[mid] <= x) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
+static_assert(kEmitTile == kEmitWindow, "emission window size");
+// Gaussians meeting one window: at most one per pair plus the next window's first.
+constexpr int kEmitMaxG = kEmitTile + 1;
 
 __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     const uint32_t* __restrict__ sorted_entry, const uint32_t* __restrict__ offsets,
-    const float4* __restrict__ rec, const uint32_t* __restrict__ counters, int64_t n, Views views,
-    RasterDev rp, uint32_t* __restrict__ ptile, uint32_t* __restrict__ pentry) {
-    __shared__ uint32_t s_off[kEmitTile + 1];
-    __shared__ uint32_t s_ent[kEmitTile];
-    __shared__ uint32_t s_base[kEmitTile];   // global tile of the rectangle's first tile
-    __shared__ uint16_t s_w[kEmitTile];      // rectangle width in tiles
-    __shared__ uint16_t s_tx[kEmitTile];     // tiles per row of the Gaussian's view
+    const uint32_t* __restrict__ window_first, const float4* __restrict__ rec,
+    const uint32_t* __restrict__ counters, int64_t n, Views views, RasterDev rp,
+    uint32_t* __restrict__ ptile, uint32_t* __restrict__ pentry) {
+    __shared__ uint32_t s_off[kEmitMaxG];
+    __shared__ uint32_t s_ent[kEmitMaxG];
+    __shared__ uint32_t s_base[kEmitMaxG];   // global tile of the rectangle's first tile
+    __shared__ uint16_t s_w[kEmitMaxG];      // rectangle width in tiles
+    __shared__ uint16_t s_tx[kEmitMaxG];     // tiles per row of the Gaussian's view
     __shared__ uint32_t s_own[kEmitTile];    // window position -> owning Gaussian
     __shared__ uint32_t s_scan[kEmitThreads / 64 + 1];
-    __shared__ uint32_t s_k0, s_cnt;
     const uint32_t P = counters[kPairsWritten];
+    const uint32_t total = counters[kPairs];
     const uint32_t nvis = counters[kVisible];
     const uint32_t p0 = blockIdx.x * (uint32_t)kEmitTile;
     if (p0 >= P) return;   // uniform across the workgroup
     const uint32_t p_last = min(p0 + (uint32_t)kEmitTile, P) - 1u;
     const int tid = threadIdx.x;
-    if (tid == 0) {
-        const uint32_t k0 = upper_bound_u32(offsets, nvis, p0) - 1u;
-        const uint32_t k1 = upper_bound_u32(offsets, nvis, p_last) - 1u;
-        s_k0 = k0;
-        s_cnt = k1 - k0 + 1u;
-        s_off[k1 - k0 + 1u] = (k1 + 1u < nvis) ? offsets[k1 + 1u] : 0xffffffffu;
-    }
+    const uint32_t k0 = window_first[blockIdx.x];
+    // the next window's first Gaussian exists whenever pairs continue past
+    // this window; otherwise the window ends with the last visible Gaussian
+    const uint32_t k1 = (uint64_t)p0 + kEmitTile < total ? window_first[blockIdx.x + 1]
+                                                          : nvis - 1u;
+    const uint32_t cnt = k1 - k0 + 1u;
 #pragma unroll
     for (int it = 0; it < kEmitItems; ++it) s_own[it * kEmitThreads + tid] = 0u;
     __syncthreads();
-    const uint32_t k0 = s_k0, cnt = s_cnt;
     for (uint32_t j = tid; j < cnt; j += kEmitThreads) {
         const uint32_t k = k0 + j;
         const uint32_t e = sorted_entry[k];
@@ -187,7 +192,7 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
         s_w[j] = (uint16_t)(x1 - x0);
         s_tx[j] = (uint16_t)V.tiles_x;
         // mark where this Gaussian's pairs start inside the window
-        if (j > 0) s_own[off - p0] = j;
+        if (j > 0 && off - p0 < (uint32_t)kEmitTile) s_own[off - p0] = j;
     }
     __syncthreads();
     // owner of every window position = the last Gaussian starting at or
@@ -267,6 +272,7 @@ hipError_t launch_bin(const Views& views, const RasterDev& rp, int64_t n, const 
     uint32_t* dval[2] = {reinterpret_cast<uint32_t*>(ws + L.dval[0]),
                          reinterpret_cast<uint32_t*>(ws + L.dval[1])};
     uint32_t* offsets = reinterpret_cast<uint32_t*>(ws + L.offsets);
+    uint32_t* window_first = reinterpret_cast<uint32_t*>(ws + L.window_first);
     uint32_t* sums = reinterpret_cast<uint32_t*>(ws + L.scan_sums);
     uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.sort_hist);
     uint32_t* totals = reinterpret_cast<uint32_t*>(ws + L.sort_totals);
@@ -291,14 +297,16 @@ hipError_t launch_bin(const Views& views, const RasterDev& rp, int64_t n, const 
         err = radix_sort(dkey, dval, counters + kVisible, E, 32, hist, totals, s, &res);
         if (err != hipSuccess) return err;
         // pair offsets in depth order; total -> counters[kPairs]
-        err = device_scan(PairCountSrc{tiles, dval[res], counters + kVisible}, OffsetSink{offsets},
-                          E, sums, counters + kPairs, s);
+        const uint32_t n_windows = (uint32_t)((L.capacity + kEmitWindow - 1) / kEmitWindow);
+        err = device_scan(PairCountSrc{tiles, dval[res], counters + kVisible},
+                          OffsetSink{offsets, window_first, n_windows}, E, sums,
+                          counters + kPairs, s);
         if (err != hipSuccess) return err;
         hipLaunchKernelGGL(capacity_kernel, dim3(1), dim3(1), 0, s, counters, L.capacity);
         if (L.capacity > 0)
             hipLaunchKernelGGL(emit_kernel, dim3((unsigned)((L.capacity + kEmitTile - 1) / kEmitTile)),
-                               dim3(kEmitThreads), 0, s, dval[res], offsets, rec, counters, n, views,
-                               rp, ptile[0], pentry[0]);
+                               dim3(kEmitThreads), 0, s, dval[res], offsets, window_first, rec,
+                               counters, n, views, rp, ptile[0], pentry[0]);
         if ((err = hipGetLastError()) != hipSuccess) return err;
         // stable sort of the pairs by tile
         int tres = 0;

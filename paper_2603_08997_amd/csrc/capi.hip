@@ -90,8 +90,9 @@ sgs_status check_gaussians(const sgs_gaussians* g) {
     if (g->n < 0) return fail(SGS_ERR_INVALID_ARG, "n < 0");
     if (g->sh_degree < 0 || g->sh_degree > 3)
         return fail(SGS_ERR_INVALID_ARG, "sh_degree %d not in [0, 3]", g->sh_degree);
-    if (g->stride < g->n || g->stride % 64 != 0 || g->stride <= 0)
-        return fail(SGS_ERR_INVALID_ARG, "stride %lld must be >= n, > 0 and a multiple of 64",
+    if (g->stride < g->n || g->stride % 64 != 0 || g->stride <= 0 || g->stride >= (1ll << 29))
+        return fail(SGS_ERR_INVALID_ARG,
+                    "stride %lld must be >= n, > 0, < 2^29 and a multiple of 64",
                     (long long)g->stride);
     if (!g->data) return fail(SGS_ERR_INVALID_ARG, "parameter data is null");
     if (!aligned(g->data, 16)) return fail(SGS_ERR_INVALID_ARG, "parameter data not 16-byte aligned");
@@ -196,6 +197,7 @@ void make_layout(const Views& views, int64_t n, int64_t capacity, Layout* L) {
     L->dval[0] = take(sizeof(uint32_t) * (size_t)E);
     L->dval[1] = take(sizeof(uint32_t) * (size_t)E);
     L->offsets = take(sizeof(uint32_t) * (size_t)E);
+    L->window_first = take(sizeof(uint32_t) * (size_t)((capacity + kEmitWindow - 1) / kEmitWindow + 1));
     L->scan_sums = take(sizeof(uint32_t) * (size_t)(L->scan_blocks + 1));
     L->pair_tile[0] = take(sizeof(uint32_t) * (size_t)capacity);
     L->pair_tile[1] = take(sizeof(uint32_t) * (size_t)capacity);

@@ -4,8 +4,6 @@
 #include "sgs_internal.hpp"
 #include "sgs_device.hpp"
 
-#include <utility>
-
 namespace sgs {
 
 namespace {
@@ -160,14 +158,16 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
     int64_t i;
     const int vi = find_view(views, e, n, &i);
     const ViewDev& V = views.v[vi];
+    const PlaneBuf P{const_cast<float*>(planes), stride};
+    const uint32_t off = (uint32_t)i * 4u;
     float mu[3], ls[3], q[4];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) mu[k] = planes[k * stride + i];
+    for (int k = 0; k < 3; ++k) mu[k] = P.load(k, off);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) ls[k] = planes[(3 + k) * stride + i];
+    for (int k = 0; k < 3; ++k) ls[k] = P.load(3 + k, off);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) q[k] = planes[(6 + k) * stride + i];
-    const float logit = planes[10 * stride + i];
+    for (int k = 0; k < 4; ++k) q[k] = P.load(6 + k, off);
+    const float logit = P.load(10, off);
 
     uint32_t ntiles = 0;
     float depth = 0.f;
@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
 #pragma unroll
         for (int k = 0; k < K; ++k) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) col[c] += planes[(11 + 3 * k + c) * stride + i] * Y[k];
+            for (int c = 0; c < 3; ++c) col[c] += P.load(11 + 3 * k + c, off) * Y[k];
         }
         const float o = sigmoidf(logit);
         const float ca = G.syy / det, cb = -G.sxy / det, cc = G.sxx / det;
@@ -261,37 +261,6 @@ __global__ void __launch_bounds__(256) load_records_kernel(
     rec[3 * e + 2] = r2;
     tiles[e] = ntiles;
     dkey[e] = __float_as_uint(ntiles ? depth[e] : 0.f);
-}
-
-// Y_k and its gradient for a compile-time index k (the unrolled SH loops fold
-// the switch away).
-template <int k>
-__device__ __forceinline__ float sh_k(float x, float y, float z) {
-    switch (k) {
-        case 0: return kY0;
-        case 1: return -kY1 * y;
-        case 2: return kY1 * z;
-        case 3: return -kY1 * x;
-        case 4: return kY2a * x * y;
-        case 5: return -kY2a * y * z;
-        case 6: return kY2b * (2.f * z * z - x * x - y * y);
-        case 7: return -kY2a * x * z;
-        case 8: return kY2c * (x * x - y * y);
-        case 9: return -kY3a * y * (3.f * x * x - y * y);
-        case 10: return kY3b * x * y * z;
-        case 11: return -kY3c * y * (4.f * z * z - x * x - y * y);
-        case 12: return kY3d * z * (2.f * z * z - 3.f * x * x - 3.f * y * y);
-        case 13: return -kY3c * x * (4.f * z * z - x * x - y * y);
-        case 14: return kY3e * z * (x * x - y * y);
-        default: return -kY3a * x * (x * x - 3.f * y * y);
-    }
-}
-
-template <int k>
-__device__ __forceinline__ void sh_k_grad(float x, float y, float z, float g[3]) {
-    float w[16] = {0.f};
-    w[k] = 1.f;
-    sh_grad_dir(k < 1 ? 0 : (k < 4 ? 1 : (k < 9 ? 2 : 3)), x, y, z, w, g);
 }
 
 // Per-view quantities of one visible entry that the SH part of the backward
@@ -419,29 +388,54 @@ __device__ __forceinline__ bool geom_grads(const float mu[3], const float ls[3],
     return true;
 }
 
-// SH part of the backward for coefficient k of one view: dL/df_{k,c} is
-// d_raw[c] Y_k(d), and the colour's dependence on the view direction adds
-// (sum_c d_raw[c] f_{k,c}) grad Y_k(d), projected orthogonally to d and
-// divided by |mu - C|, to the mean gradient.
-template <int sh_degree, int k>
-__device__ __forceinline__ void sh_term(const ViewSH& o, const float f[3], float gk[3],
-                                        float g_mu[3]) {
-    const float Yk = sh_k<k>(o.d[0], o.d[1], o.d[2]);
+// Threads per workgroup of the per-Gaussian backward kernels, and planes per
+// batch of the update loop.
+#ifndef SGS_BACKWARD_THREADS
+#define SGS_BACKWARD_THREADS 256
+#endif
+#ifndef SGS_UPDATE_BATCH
+#define SGS_UPDATE_BATCH 8
+#endif
+constexpr int kBackwardThreads = SGS_BACKWARD_THREADS;
+constexpr int kUpdateBatch = SGS_UPDATE_BATCH;
+
+// dL/d(mean) through the view direction of one view: with w_k = sum_c
+// d_raw[c] f_{k,c}, the gradient of sum_k w_k Y_k(d) projected orthogonally to
+// d and divided by |mu - C|. Added to g_mu.
+template <int sh_degree>
+__device__ __forceinline__ void sh_mean_grad(const ViewSH& o, const float* f, float g_mu[3]) {
+    constexpr int K = (sh_degree + 1) * (sh_degree + 1);
+    if constexpr (sh_degree > 0) {
+        float w[16];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) gk[c] += o.draw[c] * Yk;
-    if constexpr (k > 0) {
-        const float wk = o.draw[0] * f[0] + o.draw[1] * f[1] + o.draw[2] * f[2];
+        for (int k = 0; k < K; ++k)
+            w[k] = o.draw[0] * f[3 * k] + o.draw[1] * f[3 * k + 1] + o.draw[2] * f[3 * k + 2];
         float gd[3];
-        sh_k_grad<k>(o.d[0], o.d[1], o.d[2], gd);
+        sh_grad_dir(sh_degree, o.d[0], o.d[1], o.d[2], w, gd);
         const float dot = gd[0] * o.d[0] + gd[1] * o.d[1] + gd[2] * o.d[2];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) g_mu[c] += wk * (gd[c] - o.d[c] * dot) / o.dn;
+        for (int c = 0; c < 3; ++c) g_mu[c] += (gd[c] - o.d[c] * dot) / o.dn;
     }
 }
 
-// The per-Gaussian backward, streaming its SH coefficients. kFused: apply Adam
-// to every plane (dense: also when the Gaussian is visible in no view);
-// otherwise add the gradient to grads (visible Gaussians only).
+// dL/d f_{k,c} of one view: d_raw[c] Y_k(d).
+template <int sh_degree>
+__device__ __forceinline__ void sh_coef_grad(const ViewSH& o, float* g_sh) {
+    constexpr int K = (sh_degree + 1) * (sh_degree + 1);
+    float Y[16];
+    sh_eval(sh_degree, o.d[0], o.d[1], o.d[2], Y);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) g_sh[3 * k + c] += o.draw[c] * Y[k];
+}
+
+// The per-Gaussian backward. All parameters of the Gaussian are loaded at
+// once; the gradient stays in registers, and the update (kFused: Adam on every
+// plane, dense as in the paper's optimiser, also for Gaussians visible in no
+// view; otherwise: gradient ADDED to grads, visible Gaussians only) runs over
+// the planes in batches whose moment (or gradient) loads are issued one batch
+// ahead, so that each thread keeps several memory requests in flight.
 template <int sh_degree, bool kFused, bool kMulti>
 __device__ __forceinline__ void gaussian_backward(float* __restrict__ planes, int64_t n,
                                                   int64_t stride, int64_t i, const Views& views,
@@ -453,78 +447,97 @@ __device__ __forceinline__ void gaussian_backward(float* __restrict__ planes, in
                                                   const AdamStep* as, float* __restrict__ m,
                                                   float* __restrict__ v) {
     constexpr int K = (sh_degree + 1) * (sh_degree + 1);
-    float mu[3], ls[3], q[4];
+    constexpr int NP = 11 + 3 * K;
+    const PlaneBuf P{planes, stride}, M{m, stride}, Vb{v, stride}, G{grads, stride};
+    const uint32_t off = (uint32_t)i * 4u;
+    float p[NP];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) mu[k] = planes[k * stride + i];
+    for (int j = 0; j < NP; ++j) p[j] = P.load(j, off);
+    const float* mu = p;
+    const float* ls = p + 3;
+    const float* q = p + 6;
+    const float* f = p + 11;
+    float g[11];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) ls[k] = planes[(3 + k) * stride + i];
+    for (int j = 0; j < 11; ++j) g[j] = 0.f;
+    // SH coefficient gradients: kept per plane for several views, recomputed
+    // from the one view's direction otherwise
+    float g_sh[kMulti ? 3 * K : 1];
+    if constexpr (kMulti) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) q[k] = planes[(6 + k) * stride + i];
-    const float logit = planes[10 * stride + i];
-    float g_mu[3] = {0.f, 0.f, 0.f}, g_ls[3] = {0.f, 0.f, 0.f}, g_q[4] = {0.f, 0.f, 0.f, 0.f};
-    float g_logit = 0.f;
+        for (int j = 0; j < 3 * K; ++j) g_sh[j] = 0.f;
+    }
     bool any = false;
-    ViewSH one;  // the single view's SH quantities (kMulti == false)
+    ViewSH one;
     for (int vi = 0; vi < views.n; ++vi) {
         const int64_t e = (int64_t)vi * n + i;
         if (tiles[e] == 0) continue;
         const float4 a0 = acc[3 * e], a1 = acc[3 * e + 1];
-        if (geom_grads(mu, ls, q, logit, views.v[vi], rp, a0, a1, g_mu, g_ls, g_q, &g_logit)) {
+        if (geom_grads(mu, ls, q, p[10], views.v[vi], rp, a0, a1, g, g + 3, g + 6, g + 10)) {
             any = true;
-            if constexpr (!kMulti) view_sh(mu, views.v[vi], a1, acc[3 * e + 2], rec[3 * e + 2], one);
+            ViewSH o;
+            view_sh(mu, views.v[vi], a1, acc[3 * e + 2], rec[3 * e + 2], o);
+            sh_mean_grad<sh_degree>(o, f, g);
+            if constexpr (kMulti) sh_coef_grad<sh_degree>(o, g_sh);
+            else one = o;
         }
     }
     if (!kFused && !any) return;
-    auto apply = [&](int plane, float g, float p) {
-        const int64_t j = plane * stride + i;
-        if constexpr (kFused) {
-            float mm = m[j], vv = v[j];
-            adam_update(g, p, mm, vv, ad->lr[plane], *ad, *as);
-            planes[j] = p;
-            m[j] = mm;
-            v[j] = vv;
+    float Y[16];
+    if constexpr (!kMulti) {
+        if (any) sh_eval(sh_degree, one.d[0], one.d[1], one.d[2], Y);
+    }
+    auto grad_of = [&](int j) -> float {
+        if (j < 11) return g[j];
+        if constexpr (kMulti) {
+            return g_sh[j - 11];
         } else {
-            grads[j] += g;
+            return any ? one.draw[(j - 11) % 3] * Y[(j - 11) / 3] : 0.f;
         }
     };
-    // SH coefficients, one at a time
-    [&]<int... ks>(std::integer_sequence<int, ks...>) {
-        (([&] {
-             constexpr int k = ks;
-             float f[3];
+    constexpr int B = kUpdateBatch;
+    constexpr int NB = (NP + B - 1) / B;
+    float ma[2][B], va[2][B];
+    auto load = [&](int b, int buf) {
 #pragma unroll
-             for (int c = 0; c < 3; ++c) f[c] = planes[(11 + 3 * k + c) * stride + i];
-             float gk[3] = {0.f, 0.f, 0.f};
-             if (any) {
-                 if constexpr (kMulti) {
-                     for (int vi = 0; vi < views.n; ++vi) {
-                         const int64_t e = (int64_t)vi * n + i;
-                         if (tiles[e] == 0) continue;
-                         ViewSH o;
-                         view_sh(mu, views.v[vi], acc[3 * e + 1], acc[3 * e + 2], rec[3 * e + 2], o);
-                         sh_term<sh_degree, k>(o, f, gk, g_mu);
-                     }
-                 } else {
-                     sh_term<sh_degree, k>(one, f, gk, g_mu);
-                 }
-             }
+        for (int t = 0; t < B; ++t) {
+            const int j = b * B + t;
+            if (j < NP) {
+                if constexpr (kFused) {
+                    ma[buf][t] = M.load(j, off);
+                    va[buf][t] = Vb.load(j, off);
+                } else {
+                    ma[buf][t] = G.load(j, off);
+                }
+            }
+        }
+    };
+    load(0, 0);
 #pragma unroll
-             for (int c = 0; c < 3; ++c) apply(11 + 3 * k + c, gk[c], f[c]);
-         }()),
-         ...);
-    }(std::make_integer_sequence<int, K>{});
+    for (int b = 0; b < NB; ++b) {
+        if (b + 1 < NB) load(b + 1, (b + 1) & 1);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) apply(k, g_mu[k], mu[k]);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) apply(3 + k, g_ls[k], ls[k]);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) apply(6 + k, g_q[k], q[k]);
-    apply(10, g_logit, logit);
+        for (int t = 0; t < B; ++t) {
+            const int j = b * B + t;
+            if (j < NP) {
+                const float gj = grad_of(j);
+                if constexpr (kFused) {
+                    float pj = p[j], mm = ma[b & 1][t], vv = va[b & 1][t];
+                    adam_update(gj, pj, mm, vv, ad->lr[j], *ad, *as);
+                    P.store(j, off, pj);
+                    M.store(j, off, mm);
+                    Vb.store(j, off, vv);
+                } else {
+                    G.store(j, off, ma[b & 1][t] + gj);
+                }
+            }
+        }
+    }
 }
 
 // Adjoint of the projection: one thread per Gaussian, gradient ADDED to grads.
 template <int sh_degree, bool kMulti>
-__global__ void __launch_bounds__(256) project_backward_kernel(
+__global__ void __launch_bounds__(kBackwardThreads) project_backward_kernel(
     const float* __restrict__ planes, int64_t n, int64_t stride, Views views, RasterDev rp,
     const float4* __restrict__ rec, const uint32_t* __restrict__ tiles,
     const float4* __restrict__ acc, const int32_t* __restrict__ gate, float* __restrict__ grads) {
@@ -541,15 +554,18 @@ __global__ void __launch_bounds__(256) project_backward_kernel(
 // parameters, first and second moments updated in place; no gradient array
 // is written or read.
 template <int sh_degree, bool kMulti>
-__global__ void __launch_bounds__(256) project_backward_adam_kernel(
+__global__ void __launch_bounds__(kBackwardThreads) project_backward_adam_kernel(
     float* __restrict__ planes, int64_t n, int64_t stride, Views views, RasterDev rp,
     const float4* __restrict__ rec, const uint32_t* __restrict__ tiles,
     const float4* __restrict__ acc, AdamDev ad, float* __restrict__ m, float* __restrict__ v,
     const int32_t* __restrict__ step, const int32_t* __restrict__ gate) {
     if (gate_closed(gate)) return;
+    __shared__ AdamStep s_as;
+    if (threadIdx.x == 0) s_as = adam_bias_correction(ad, *step);
+    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const AdamStep as = adam_bias_correction(ad, *step);
+    const AdamStep as = s_as;
     gaussian_backward<sh_degree, true, kMulti>(planes, n, stride, i, views, rp, rec, tiles, acc,
                                                nullptr, &ad, &as, m, v);
 }
@@ -600,7 +616,7 @@ hipError_t launch_project_backward(const float* planes, int64_t n, int64_t strid
                                    const Layout& L, char* ws, const int32_t* gate, float* grads,
                                    hipStream_t s) {
     if (n == 0) return hipSuccess;
-    const int nt = 256;
+    const int nt = kBackwardThreads;
     const int64_t nb = (n + nt - 1) / nt;
     const float4* rec = reinterpret_cast<const float4*>(ws + L.records);
     const uint32_t* tl = reinterpret_cast<const uint32_t*>(ws + L.tiles);
@@ -620,7 +636,7 @@ hipError_t launch_project_backward_adam(float* planes, int64_t n, int64_t stride
     hipError_t err = launch_adam_count(step, gate, s);
     if (err != hipSuccess || n == 0) return err;
     const AdamDev ad = make_adam(prm);
-    const int nt = 256;
+    const int nt = kBackwardThreads;
     const int64_t nb = (n + nt - 1) / nt;
     const float4* rec = reinterpret_cast<const float4*>(ws + L.records);
     const uint32_t* tl = reinterpret_cast<const uint32_t*>(ws + L.tiles);

@@ -33,21 +33,22 @@ struct Splat {
 
 // Overlap test, Gaussian falloff and alpha' of one (pixel, Gaussian) pair.
 // Forward and backward call this same function, so their skip decisions agree
-// bit for bit. Returns false when the Gaussian does not contribute.
+// bit for bit. Branch-free: every quantity is computed and the return value
+// says whether the Gaussian contributes. exp(P) is the hardware 2^x of
+// P log2(e) (about 2 ulp over the range where alpha' can reach alpha_min).
 __device__ __forceinline__ bool splat_alpha(float px, float py, float u, float v, float rx,
                                             float ry, float o, float a, float b, float c,
                                             const RasterDev& rp, Splat& s) {
     // overlap box |p - mean| <= (rx, ry); p +- r is exact for half-integer p, integer r
-    if (!(px - rx <= u && u <= px + rx && py - ry <= v && v <= py + ry)) return false;
+    const bool inbox = (px - rx <= u) & (u <= px + rx) & (py - ry <= v) & (v <= py + ry);
     s.dx = px - u;
     s.dy = py - v;
     const float power = -0.5f * fmaf(a, s.dx * s.dx, c * (s.dy * s.dy)) - b * (s.dx * s.dy);
-    if (power > 0.f) return false;
-    s.ex = expf(power);
+    s.ex = __builtin_amdgcn_exp2f(power * 1.44269504088896341f);
     const float raw = o * s.ex;
     s.clamped = raw > rp.alpha_max;
     s.alpha = s.clamped ? rp.alpha_max : raw;
-    return s.alpha >= rp.alpha_min;
+    return inbox & (power <= 0.f) & (s.alpha >= rp.alpha_min);
 }
 
 __device__ __forceinline__ int view_of_tile(const Views& views, int tile) {
@@ -121,28 +122,29 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
             const float4 P = s_pos[j];
             const float4 Q = s_con[j];
             lane_done = true;
+            const uint32_t pos = b0 + (uint32_t)j + 1u - start;
 #pragma unroll
             for (int k = 0; k < PIX; ++k) {
-                if (!done[k]) {
-                    ++n_eval;
-                    Splat s;
-                    if (splat_alpha(px[k], py[k], P.x, P.y, P.z, P.w, Q.w, Q.x, Q.y, Q.z, rp, s)) {
-                        const float test = T[k] * (1.f - s.alpha);
-                        if (test < rp.t_min) {
-                            done[k] = true;
-                        } else {
-                            const float4 col = s_col[j];
-                            const float w = s.alpha * T[k];
-                            C0[k] = fmaf(col.x, w, C0[k]);
-                            C1[k] = fmaf(col.y, w, C1[k]);
-                            C2[k] = fmaf(col.z, w, C2[k]);
-                            T[k] = test;
-                            last[k] = b0 + (uint32_t)j + 1u - start;
-                            ++n_blend;
-                        }
-                    }
+                n_eval += done[k] ? 0u : 1u;
+                Splat s;
+                const bool hit =
+                    !done[k] & splat_alpha(px[k], py[k], P.x, P.y, P.z, P.w, Q.w, Q.x, Q.y, Q.z, rp, s);
+                if (hit) {
+                    // a pixel whose transmittance would fall below t_min stops
+                    // before this Gaussian; otherwise the Gaussian is blended
+                    const float test = T[k] * (1.f - s.alpha);
+                    const bool stop = test < rp.t_min;
+                    const float4 col = s_col[j];
+                    const float w = stop ? 0.f : s.alpha * T[k];
+                    C0[k] = fmaf(col.x, w, C0[k]);
+                    C1[k] = fmaf(col.y, w, C1[k]);
+                    C2[k] = fmaf(col.z, w, C2[k]);
+                    T[k] = stop ? T[k] : test;
+                    last[k] = stop ? last[k] : pos;
+                    n_blend += stop ? 0u : 1u;
+                    done[k] = stop;
                 }
-                lane_done = lane_done && done[k];
+                lane_done = lane_done & done[k];
             }
         }
     }
@@ -243,8 +245,9 @@ __global__ void __launch_bounds__(kLanes) raster_backward_kernel(
 #pragma unroll
             for (int k = 0; k < PIX; ++k) {
                 Splat s;
-                if (rel < last[k] &&
-                    splat_alpha(px[k], py[k], P.x, P.y, P.z, P.w, Q.w, Q.x, Q.y, Q.z, rp, s)) {
+                const bool hit = (rel < last[k]) &
+                                 splat_alpha(px[k], py[k], P.x, P.y, P.z, P.w, Q.w, Q.x, Q.y, Q.z, rp, s);
+                if (hit) {
                     const float4 col = s_col[j];
                     // 1 - alpha' >= 1 - alpha_max > 0: one hardware reciprocal
                     // (1 ulp) serves the transmittance recovery and dC/dalpha'
@@ -261,15 +264,16 @@ __global__ void __launch_bounds__(kLanes) raster_backward_kernel(
                     S1[k] = fmaf(col.y, w, S1[k]);
                     S2[k] = fmaf(col.z, w, S2[k]);
                     T[k] = Ti;
-                    if (!s.clamped) {
-                        const float dP = d_alpha * s.alpha;
-                        d_o = fmaf(d_alpha, s.ex, d_o);
-                        d_a -= 0.5f * dP * s.dx * s.dx;
-                        d_b -= dP * s.dx * s.dy;
-                        d_c -= 0.5f * dP * s.dy * s.dy;
-                        d_u += dP * (Q.x * s.dx + Q.y * s.dy);
-                        d_v += dP * (Q.y * s.dx + Q.z * s.dy);
-                    }
+                    // alpha' = o exp(P) unless clamped at alpha_max (then it
+                    // depends on neither o nor the geometry)
+                    const float dA = s.clamped ? 0.f : d_alpha;
+                    const float dP = dA * s.alpha;
+                    d_o = fmaf(dA, s.ex, d_o);
+                    d_a -= 0.5f * dP * s.dx * s.dx;
+                    d_b -= dP * s.dx * s.dy;
+                    d_c -= 0.5f * dP * s.dy * s.dy;
+                    d_u += dP * (Q.x * s.dx + Q.y * s.dy);
+                    d_v += dP * (Q.y * s.dx + Q.z * s.dy);
                     contrib = true;
                 }
             }

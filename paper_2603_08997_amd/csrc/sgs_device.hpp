@@ -93,6 +93,39 @@ __device__ __forceinline__ uint32_t block_excl_max_scan(uint32_t v, uint32_t* sm
     return max(before, ex);
 }
 
+// One plane array of the [F][stride] layout seen through buffer descriptors:
+// plane j is a descriptor built in scalar registers from base + j * stride,
+// and lane i addresses it with the 32-bit offset 4 i, so a thread that reads
+// and writes many planes holds one offset register instead of a 64-bit
+// address per plane. Requires stride * 4 < 2^31; accesses past the plane
+// read 0 and are dropped on write.
+// Cache policy of the plane loads and stores: non-temporal (the nt bit of the
+// gfx950 cache-policy field). Each plane element is touched once per pass, so
+// the lines are streamed rather than kept in L2 and the last-level cache.
+#ifndef SGS_PLANE_CPOL
+#define SGS_PLANE_CPOL 2
+#endif
+struct PlaneBuf {
+    float* base;
+    int64_t stride;
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int j) const {
+        // the empty asm makes the compiler rebuild the descriptor at each use
+        // (a few scalar instructions) instead of keeping one per plane live
+        float* b = base;
+        asm volatile("" : "+s"(b));
+        return __builtin_amdgcn_make_buffer_rsrc(b + (int64_t)j * stride, (short)0,
+                                                 (int)(stride * 4), 0x00020000);
+    }
+    __device__ __forceinline__ float load(int j, uint32_t lane_off) const {
+        return __uint_as_float(
+            __builtin_amdgcn_raw_buffer_load_b32(rsrc(j), (int)lane_off, 0, SGS_PLANE_CPOL));
+    }
+    __device__ __forceinline__ void store(int j, uint32_t lane_off, float x) const {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), rsrc(j), (int)lane_off, 0,
+                                              SGS_PLANE_CPOL);
+    }
+};
+
 __device__ __forceinline__ int floordiv(int a, int b) {
     const int q = a / b;
     return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
@@ -113,11 +146,13 @@ __device__ __forceinline__ void tile_rect(float u, float v, int rx, int ry, int 
 }
 
 // Adam element update, shared by the plain step and the fused backward step
-// so both give identical results.
+// so both give identical results. The bias corrections enter as reciprocals
+// formed once per step; the square root and the final reciprocal use the
+// hardware's single-instruction forms (about 1 ulp each).
 __device__ __forceinline__ AdamStep adam_bias_correction(const AdamDev& a, int k) {
     AdamStep s;
-    s.bc1 = (float)(1.0 - pow(a.beta1, (double)k));
-    s.bc2 = (float)(1.0 - pow(a.beta2, (double)k));
+    s.ibc1 = (float)(1.0 / (1.0 - pow(a.beta1, (double)k)));
+    s.ibc2 = (float)(1.0 / (1.0 - pow(a.beta2, (double)k)));
     return s;
 }
 
@@ -125,8 +160,8 @@ __device__ __forceinline__ void adam_update(float g, float& p, float& m, float& 
                                             const AdamDev& a, const AdamStep& s) {
     m = a.b1 * m + a.c1 * g;
     v = a.b2 * v + a.c2 * g * g;
-    const float mh = m / s.bc1, vh = v / s.bc2;
-    p = p - lr * mh / (sqrtf(vh) + a.eps);
+    const float mh = m * s.ibc1, vh = v * s.ibc2;
+    p = p - lr * mh * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(vh) + a.eps);
 }
 
 __device__ __forceinline__ bool gate_closed(const int32_t* gate) {

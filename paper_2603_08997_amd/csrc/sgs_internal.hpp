@@ -48,7 +48,7 @@ struct AdamDev {
     float lr[SGS_MAX_PLANES];
 };
 struct AdamStep {
-    float bc1, bc2;  // 1 - beta^k
+    float ibc1, ibc2;  // 1 / (1 - beta^k), formed in binary64
 };
 AdamDev make_adam(const sgs_adam_params* p);
 
@@ -63,11 +63,15 @@ enum Counter : int {
     kNumCounters = 16
 };
 
+// Pairs written by one workgroup of the emission kernel.
+constexpr int64_t kEmitWindow = 2048;
+
 struct Layout {
     int64_t entries, total_tiles, total_pixels, capacity;
     int64_t scan_blocks, sort_blocks;
     int tile_bits, tile_passes, tile_result;  // result buffer index (0/1) of the tile sort
-    size_t records, tiles, depth, dkey[2], dval[2], offsets, scan_sums, pair_tile[2], pair_entry[2],
+    size_t records, tiles, depth, dkey[2], dval[2], offsets, window_first, scan_sums, pair_tile[2],
+        pair_entry[2],
         sort_hist, sort_totals, ranges, t_final, n_last, accum, counters, total;
 };
 
