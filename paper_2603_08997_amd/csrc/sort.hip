@@ -2,9 +2,10 @@
 // pairs, 8-bit digits, reduce-then-scan:
 //   hist:    per-block digit counts, stored digit-major [256][blocks];
 //   scan:    one block per digit row scans the row and records its total;
-//   scatter: each block ranks its keys stably (wave64 ballots find the lanes
-//            sharing a digit; per-wave counts give the order across waves),
-//            sorts them into LDS, and writes digit runs out coalesced.
+//   scatter: each block ranks its keys stably (each wave ranks a contiguous
+//            quarter of the block with ballots and its own digit counters;
+//            per-wave counts give the order across waves), sorts them into
+//            LDS, and writes digit runs out coalesced.
 // Each block owns a contiguous range of kTile keys, so equal digits keep
 // their input order and the sort is stable; no pass waits on another block.
 #include "sgs_internal.hpp"
@@ -94,6 +95,14 @@ __global__ void __launch_bounds__(kScanThreads) radix_scan_kernel(uint32_t* __re
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
+// Scatter of one block's kTile keys. Wave w owns the contiguous key range
+// [w kTile/kWaves, (w+1) kTile/kWaves) and ranks it in kItems rounds of 64
+// consecutive keys with its own LDS digit counters, so ranking needs no
+// block barrier: within a round, lanes with the same digit are found with
+// ballots and ordered by lane; across rounds the wave's counter carries the
+// count. One barrier later, the digit's start in the block plus the counts of
+// the earlier waves give every key its block-local position; keys are sorted
+// into LDS and written out in digit runs.
 __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
@@ -101,86 +110,82 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
     const uint32_t* __restrict__ totals, int nblocks) {
     __shared__ uint32_t lkeys[kTile];
     __shared__ uint32_t lvals[kTile];
-    __shared__ uint32_t gbase[kRadix];     // global output start of this block's digit run
-    __shared__ uint32_t dstart[kRadix];    // block-local start of each digit
-    __shared__ uint32_t run[2][kRadix];    // keys of each digit in earlier rounds
-    __shared__ uint32_t wcnt[2][kWaves][kRadix];  // (round tag << 16) | count, per wave
+    __shared__ uint32_t gbase[kRadix];          // global start of this block's digit run
+    __shared__ uint32_t wcnt[kWaves][kRadix];   // keys of each digit per wave
     __shared__ uint32_t smem[kThreads / 64 + 1];
 
     const uint32_t n = *n_dev;
     const int64_t base = (int64_t)blockIdx.x * kTile;
     if (base >= (int64_t)n) return;  // uniform across the block
-    const int tid = threadIdx.x, w = tid / 64;
+    const int tid = threadIdx.x, w = tid / 64, lane = tid % 64;
     const uint32_t mask = (1u << bits) - 1u;
     const int nvalid = (int)min((int64_t)kTile, (int64_t)n - base);
+    constexpr int kPerWave = kTile / kWaves;
 
-    // global base of each digit for this block: exclusive scan of the row totals
+    // all loads first: wave w, round it, lane l holds key w*kPerWave + 64*it + l
+    uint32_t key[kItems], val[kItems];
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        const int li = w * kPerWave + it * 64 + lane;
+        const bool valid = li < nvalid;
+        key[it] = valid ? keys_in[base + li] : 0xffffffffu;
+        val[it] = valid ? vals_in[base + li] : 0u;
+    }
     {
         uint32_t tot;
         const uint32_t ex = block_excl_scan<kThreads>(totals[tid], smem, &tot);
         gbase[tid] = ex + hist[(int64_t)tid * nblocks + blockIdx.x];
     }
-    run[0][tid] = 0;
 #pragma unroll
-    for (int k = 0; k < kWaves; ++k) { wcnt[0][k][tid] = 0; wcnt[1][k][tid] = 0; }
+    for (int k = 0; k < kWaves; ++k) wcnt[k][tid] = 0;
     __syncthreads();
 
-    uint32_t key[kItems], val[kItems], rank[kItems];
+    // wave-private stable ranking
+    uint32_t rank[kItems];
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
-        const int li = it * kThreads + tid;
+        const int li = w * kPerWave + it * 64 + lane;
         const bool valid = li < nvalid;
-        key[it] = valid ? keys_in[base + li] : 0xffffffffu;
-        val[it] = valid ? vals_in[base + li] : 0u;
         const uint32_t d = digit_of(key[it], shift, mask);
         const uint64_t peers = match_digit(d, valid, bits);
-        const int buf = it & 1;
-        const uint32_t tag = (uint32_t)(it + 1) << 16;
-        if (valid && (peers & lanemask_lt()) == 0) wcnt[buf][w][d] = tag | (uint32_t)popc64(peers);
-        __syncthreads();
+        const uint32_t before = (uint32_t)popc64(peers & lanemask_lt());
         uint32_t r = 0;
-        if (valid) {
-            r = run[buf][d] + (uint32_t)popc64(peers & lanemask_lt());
-            for (int k = 0; k < w; ++k) {
-                const uint32_t c = wcnt[buf][k][d];
-                if ((c & 0xffff0000u) == tag) r += c & 0xffffu;
-            }
-        }
+        if (valid) r = wcnt[w][d] + before;
         rank[it] = r;
-        // digit thread: advance the running count for the next round
-        {
-            uint32_t add = 0;
-#pragma unroll
-            for (int k = 0; k < kWaves; ++k) {
-                const uint32_t c = wcnt[buf][k][tid];
-                if ((c & 0xffff0000u) == tag) add += c & 0xffffu;
-            }
-            run[buf ^ 1][tid] = run[buf][tid] + add;
-        }
+        // every lane has read the counters before the leaders advance them
+        __builtin_amdgcn_wave_barrier();
+        if (valid && before == 0) wcnt[w][d] += (uint32_t)popc64(peers);
+        __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    // block-local digit starts
+    // per digit (thread tid): start in the block and the counts of earlier waves
     {
+        uint32_t c[kWaves], sum = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) { c[k] = wcnt[k][tid]; sum += c[k]; }
         uint32_t tot;
-        const uint32_t ex = block_excl_scan<kThreads>(run[kItems & 1][tid], smem, &tot);
-        dstart[tid] = ex;
+        uint32_t start = block_excl_scan<kThreads>(sum, smem, &tot);
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) { wcnt[k][tid] = start; start += c[k]; }
     }
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
-        const int li = it * kThreads + tid;
+        const int li = w * kPerWave + it * 64 + lane;
         if (li < nvalid) {
             const uint32_t d = digit_of(key[it], shift, mask);
-            const uint32_t pos = dstart[d] + rank[it];
+            const uint32_t pos = wcnt[w][d] + rank[it];
             lkeys[pos] = key[it];
             lvals[pos] = val[it];
         }
     }
     __syncthreads();
+    // wcnt[0][d] is now the block-local start of digit d
+#pragma unroll 4
     for (int li = tid; li < nvalid; li += kThreads) {
         const uint32_t k = lkeys[li];
         const uint32_t d = digit_of(k, shift, mask);
-        const uint32_t out = gbase[d] + (uint32_t)li - dstart[d];
+        const uint32_t out = gbase[d] + (uint32_t)li - wcnt[0][d];
         keys_out[out] = k;
         vals_out[out] = lvals[li];
     }
