@@ -33,6 +33,10 @@ SEED_SCENE = 2
 SEED_CAMERAS = 3
 SEED_VIEW_SEQUENCE = 4
 SEED_INIT_PERTURB = 5
+SEED_BATCH_CAMERAS = 6
+
+# Resolutions of the batched multi-view launch: two views of each.
+BATCH_RESOLUTIONS = ((640, 480), (1245, 825), (1600, 1060), (980, 545))
 
 # Range of the degree-0 SH coefficient that spans colours [0, 1] once the
 # renderer adds its +0.5 offset: the DC basis constant is 1/(2*sqrt(pi)).
@@ -168,6 +172,16 @@ def hemisphere_cameras(seed: int, count: int, width: int, height: int,
     for a, e, r in zip(az, el, rad):
         c = r * np.array([math.cos(e) * math.cos(a), math.cos(e) * math.sin(a), math.sin(e)])
         cams.append(look_at_camera(c, width, height, fov_x_deg))
+    return cams
+
+
+def batched_cameras(seed: int = SEED_BATCH_CAMERAS) -> list[Camera]:
+    """Eight hemisphere views of mixed resolution for one batched launch:
+    two of each size in BATCH_RESOLUTIONS, poses drawn as in
+    hemisphere_cameras."""
+    cams = []
+    for k, (w, h) in enumerate(BATCH_RESOLUTIONS):
+        cams += hemisphere_cameras(seed * 100 + k, 2, w, h)
     return cams
 
 

@@ -1,0 +1,342 @@
+"""Parity at full size: the single-view configurations (1M Gaussians at
+1245x825, 3M at 1600x1060, the dense 6M cluster at 1600x1060) and the batched
+launch (2M Gaussians, eight views of four resolutions in one launch), run
+through the C ABI with 16x16 tiles as the benchmark runs them.
+
+The oracle cannot composite millions of pixels, so the checks use outputs it
+can compute one by one:
+* forward: sampled pixels (random, plus tile-border pixels), colour and final
+  transmittance to the forward tolerance; pixels whose colour moves when the
+  skip or termination threshold moves by 1e-5 relative, that see two
+  Gaussians whose depths lie within a few FP32 ulps (where FP32 and FP64
+  decisions can differ), or whose last blended Gaussian differs, are excluded
+  and counted;
+* backward: a cotangent that is nonzero only in a 32x32 pixel window (less
+  its decision-sensitive pixels). Only the Gaussians reaching the window get
+  a nonzero gradient, so the oracle's gradient of that window equals the full
+  gradient; every parameter group of all N Gaussians is compared, zeros
+  included.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import grad as G
+from oracle import render as R
+from paper_2603_08997_amd import scenes as S
+
+from .gpu_util import region, rel_max_err, rel_norm_err, require_gpu, say, sg, to_dev
+
+pytestmark = pytest.mark.gpu
+
+FWD_TOL = 1e-5
+GRAD_TOL = 1e-3
+DECISION_REL = 1e-5
+ORDER_ULPS = 8
+WIN = 32
+
+
+def _config(name):
+    if name == "n1M_1245x825":
+        return S.mixture_scene(S.SEED_SCENE, 1_000_000, 3), \
+            S.hemisphere_cameras(S.SEED_CAMERAS, 150, 1245, 825)[:1]
+    if name == "n3M_1600x1060":
+        return S.mixture_scene(S.SEED_SCENE, 3_000_000, 3), \
+            S.hemisphere_cameras(S.SEED_CAMERAS, 200, 1600, 1060)[:1]
+    if name == "dense6M_1600x1060":
+        return S.dense_cluster_scene(S.SEED_SCENE, 6_000_000, 3), \
+            S.hemisphere_cameras(S.SEED_CAMERAS, 1, 1600, 1060)
+    if name == "n2M_batched8":
+        return S.mixture_scene(S.SEED_SCENE, 2_000_000, 3), S.batched_cameras()
+    raise KeyError(name)
+
+
+CONFIGS = ["n1M_1245x825", "n3M_1600x1060", "dense6M_1600x1060", "n2M_batched8"]
+
+
+class FullRender:
+    """Forward of one configuration with a pair capacity sized by a probe
+    launch (the forward reports the pair count it needed)."""
+
+    def __init__(self, name):
+        m = sg()
+        self.m = m
+        self.scene, self.cams = _config(name)
+        self.n = self.scene.n
+        self.rp = m.RasterParams()
+        self.planes = to_dev(self.scene.to_planes())
+        self.px = sum(c.width * c.height for c in self.cams)
+        self.rgb = torch.zeros(3 * self.px, dtype=torch.float32, device="cuda")
+        probe = 1 << 16
+        ws = m.alloc_bytes(m.forward_workspace_size(self.rp, self.n, self.cams, probe)).zero_()
+        m.render_forward(self.planes, self.n, 3, self.cams, self.rp, ws, probe, self.rgb)
+        _, _, pairs = m.read_status(ws)
+        del ws
+        self.cap = int(pairs * 1.02) + 4096
+        self.ws = m.alloc_bytes(m.forward_workspace_size(self.rp, self.n, self.cams, self.cap))
+        self.ws.zero_()
+        self.L = m.get_workspace_layout(self.rp, self.n, self.cams, self.cap)
+        m.render_forward(self.planes, self.n, 3, self.cams, self.rp, self.ws, self.cap, self.rgb)
+        flags, self.visible, self.pairs = m.read_status(self.ws)
+        assert flags == 0, flags
+        cnt = m.read_counters(self.ws)
+        self.blended = cnt["blended"]
+        torch.cuda.synchronize()
+        self.rgb_np = self.rgb.cpu().numpy()
+        self.tf = region(self.ws, self.L.t_final, self.L.total_pixels, np.float32)
+        self.nl = region(self.ws, self.L.n_last, self.L.total_pixels, np.uint32)
+        self.pentry = region(self.ws, self.L.pair_entry, self.pairs, np.uint32)
+        self.ranges = region(self.ws, self.L.ranges, 2 * self.L.total_tiles,
+                             np.uint32).reshape(-1, 2)
+        # per entry: projected centre and overlap box (0 where not visible)
+        rec = region(self.ws, self.L.records, 12 * self.L.entries, np.float32).reshape(-1, 12)
+        vis = region(self.ws, self.L.tiles, self.L.entries, np.uint32) != 0
+        self.uv = rec[:, 0:2].copy()
+        self.ext = np.where(vis[:, None], rec[:, 6:8], 0.0).astype(np.int64)
+        del rec
+        say(f"  n={self.n} views={len(self.cams)} visible={self.visible} pairs={self.pairs} "
+            f"blended/px={self.blended / self.px:.1f}")
+
+    def view_offsets(self, v):
+        px_off = sum(c.width * c.height for c in self.cams[:v])
+        tile_off = sum(((c.width + 15) // 16) * ((c.height + 15) // 16) for c in self.cams[:v])
+        return px_off, tile_off
+
+    def gpu_pixels(self, v, xs, ys):
+        """Colour (3, k), final transmittance and last blended Gaussian index
+        (-1: none) of pixels (xs, ys) of view v."""
+        cam = self.cams[v]
+        px_off, tile_off = self.view_offsets(v)
+        pix = ys * cam.width + xs
+        plane = cam.width * cam.height
+        base = 3 * px_off
+        rgb = np.stack([self.rgb_np[base + c * plane + pix] for c in range(3)])
+        nl = self.nl[px_off + pix].astype(np.int64)
+        tiles = tile_off + (ys // 16) * ((cam.width + 15) // 16) + xs // 16
+        last = np.full(len(xs), -1, np.int64)
+        has = nl > 0
+        ent = self.pentry[self.ranges[tiles[has], 0].astype(np.int64) + nl[has] - 1]
+        last[has] = ent.astype(np.int64) - v * self.n
+        return rgb, self.tf[px_off + pix], last
+
+
+_proj = {}
+
+
+@pytest.fixture(scope="module", params=CONFIGS)
+def fr(request):
+    """One configuration at a time (pytest groups the tests by it)."""
+    require_gpu()
+    _proj.clear()
+    torch.cuda.empty_cache()
+    say(f"full-size {request.param}")
+    r = FullRender(request.param)
+    yield r
+    _proj.clear()
+    del r
+    torch.cuda.empty_cache()
+
+
+def _membership_flips(fr, v, pr, xs, ys):
+    """Pixels whose membership in some Gaussian's overlap box differs between
+    the GPU and the oracle. The box half-widths are integers (ceilings of the
+    3-sigma radius and of the alpha_min extent); where the FP32 and FP64
+    values fall on both sides of an integer the boxes differ by one pixel,
+    a difference the forward tolerance does not cover when the Gaussian is
+    opaque at the box edge."""
+    n = fr.n
+    ox = np.zeros((n, 2), np.int64)
+    ids = pr["ids"].numpy()
+    ox[ids] = np.asarray(pr["extent"]).reshape(-1, 2)
+    gx = fr.ext[v * n:(v + 1) * n]
+    diff = np.nonzero((gx != ox).any(1))[0]
+    out = np.zeros(len(xs), bool)
+    if len(diff) == 0:
+        return out, 0
+    g_uv = fr.uv[v * n + diff].astype(np.float64)
+    cx, cy = xs[:, None] + 0.5, ys[:, None] + 0.5
+    def member(ext):
+        return ((np.abs(cx - g_uv[None, :, 0]) <= ext[None, :, 0]) &
+                (np.abs(cy - g_uv[None, :, 1]) <= ext[None, :, 1]) & (ext[None, :, 0] > 0))
+    out = (member(gx[diff]) != member(ox[diff])).any(1)
+    return out, len(diff)
+
+
+def _order_sensitive(pr, xs, ys, scale):
+    """Pixels at which two consecutively blended Gaussians have depths closer
+    than ORDER_ULPS units in the last place of FP32 and swapping them would
+    move the colour by more than half the tolerance: the GPU's FP32 depth may
+    order such a pair the other way round than the oracle's FP64 depth."""
+    rp = R.RasterParams().as_f32()
+    u, v = pr["uv"][:, 0].numpy(), pr["uv"][:, 1].numpy()
+    a, b, c = (pr["conic"][:, k].numpy() for k in range(3))
+    o = pr["opacity"].numpy()
+    col = pr["rgb"].numpy()
+    d = pr["depth"].numpy()
+    ext = np.asarray(pr["extent"]).reshape(-1, 2)
+    out = np.zeros(len(xs), bool)
+    # candidates per 16x16 pixel block first, then per pixel
+    blocks = {}
+    for k, (x, y) in enumerate(zip(xs, ys)):
+        blocks.setdefault((x // 16, y // 16), []).append(k)
+    for (bx, by), ks in blocks.items():
+        x0, y0 = bx * 16 + 0.5, by * 16 + 0.5
+        cand = np.nonzero((u + ext[:, 0] >= x0) & (u - ext[:, 0] <= x0 + 15) &
+                          (v + ext[:, 1] >= y0) & (v - ext[:, 1] <= y0 + 15))[0]
+        for k in ks:
+            out[k] = _order_sensitive_pixel(xs[k] + 0.5, ys[k] + 0.5, cand, u, v, a, b, c, o,
+                                            col, d, ext, rp, scale)
+    return out
+
+
+def _order_sensitive_pixel(x, y, cand, u, v, a, b, c, o, col, d, ext, rp, scale):
+    dx, dy = x - u[cand], y - v[cand]
+    m = (np.abs(dx) <= ext[cand, 0]) & (np.abs(dy) <= ext[cand, 1])
+    i, dx, dy = cand[m], dx[m], dy[m]
+    p = -0.5 * (a[i] * dx ** 2 + c[i] * dy ** 2) - b[i] * dx * dy
+    al = np.minimum(o[i] * np.exp(p), rp.alpha_max)
+    keep = (p <= 0) & (al >= rp.alpha_min)
+    i, al = i[keep], al[keep]
+    order = np.argsort(d[i], kind="stable")
+    i, al = i[order], al[order]
+    t_after = np.cumprod(1.0 - al)
+    bl = t_after >= rp.t_min
+    i, al = i[bl], al[bl]
+    if len(i) < 2:
+        return False
+    T = np.concatenate([[1.0], np.cumprod(1.0 - al)[:-1]])
+    dd = d[i]
+    gap = np.diff(dd)
+    tol = ORDER_ULPS * np.spacing(dd[1:].astype(np.float32)).astype(np.float64)
+    effect = al[:-1] * al[1:] * T[:-1] * np.abs(col[i[:-1]] - col[i[1:]]).max(1)
+    return bool(((gap <= tol) & (effect > 0.5 * FWD_TOL * scale)).any())
+
+
+def _oracle_pixels(scene, cam, xs, ys, fr=None, v=0):
+    """Oracle colour, final transmittance and last blended Gaussian of the
+    given pixels (the projection of the view is computed once and kept), and
+    which pixels are decision-sensitive."""
+    key = (id(scene), id(cam))
+    if key not in _proj:
+        if len(_proj) > 1:
+            _proj.clear()
+        say(f"  oracle projection of {scene.n} Gaussians, {cam.width}x{cam.height}")
+        arrs = [torch.as_tensor(np.asarray(a, np.float64)) for a in
+                (scene.means, scene.log_scales, scene.quats, scene.opacity_logits, scene.sh)]
+        with torch.no_grad():
+            _proj[key] = R.project(*arrs, scene.sh_degree, cam, R.RasterParams())
+    pr = _proj[key]
+
+    def comp(rp):
+        with torch.no_grad():
+            return R.composite(pr["uv"], pr["conic"], pr["opacity"], pr["rgb"], pr["depth"],
+                               pr["extent"], pr["ids"], cam.width, cam.height, rp,
+                               px=xs, py=ys)
+
+    base = R.RasterParams()
+    out = comp(base)
+    rgb = out["rgb"].numpy()
+    # a pixel is decision-sensitive when moving the skip threshold or the
+    # termination threshold by DECISION_REL changes its colour by more than
+    # half the tolerance: FP32 and FP64 may then take different decisions
+    scale = max(np.abs(rgb).max(), 1e-30)
+    sens = np.zeros(len(xs), bool)
+    for f in (1.0 - DECISION_REL, 1.0 + DECISION_REL):
+        for rp in (R.RasterParams(alpha_min=base.alpha_min * f),
+                   R.RasterParams(t_min=base.t_min * f)):
+            d = np.abs(comp(rp)["rgb"].numpy() - rgb).max(0)
+            sens |= d > 0.5 * FWD_TOL * scale
+    osens = _order_sensitive(pr, xs, ys, scale)
+    if osens.any():
+        say(f"  {int(osens.sum())} pixels with a near depth tie")
+    sens |= osens
+    if fr is not None:
+        mf, ndiff = _membership_flips(fr, v, pr, xs, ys)
+        if ndiff:
+            say(f"  {ndiff} Gaussians with a different overlap box, {int(mf.sum())} pixels affected")
+        sens |= mf
+    return rgb, out["T_final"].numpy(), out["last"].numpy(), sens
+
+
+def _samples(cam, k, seed):
+    rng = np.random.default_rng(seed)
+    xs = rng.integers(0, cam.width, k)
+    ys = rng.integers(0, cam.height, k)
+    # pixels on both sides of tile borders and at the image edges
+    bx = np.array([15, 16, 31, 32, cam.width - 1, 0, (cam.width // 16) * 16 - 1])
+    by = np.array([16, 15, 32, 31, cam.height - 1, 0, (cam.height // 16) * 16 - 1])
+    bx = np.clip(bx, 0, cam.width - 1)
+    by = np.clip(by, 0, cam.height - 1)
+    return np.concatenate([xs, bx]), np.concatenate([ys, by])
+
+
+def test_fullsize_forward_sampled_pixels(fr):
+    k = 256 if len(fr.cams) == 1 else 64
+    flips = total = 0
+    for v, cam in enumerate(fr.cams):
+        xs, ys = _samples(cam, k, 100 + v)
+        g_rgb, g_t, g_last = fr.gpu_pixels(v, xs, ys)
+        o_rgb, o_t, o_last, sens = _oracle_pixels(fr.scene, cam, xs, ys, fr, v)
+        same = (g_last == o_last) & ~sens
+        flips += int((~same).sum())
+        total += len(xs)
+        assert rel_max_err(g_rgb[:, same], o_rgb[:, same]) <= FWD_TOL
+        # T_final lies in [0, 1]; on pixels the Gaussians saturate it is
+        # ~1e-4 and its relative error grows with the number of blended
+        # factors, so the tolerance is taken against the range of the tensor
+        err_t = np.abs(g_t[same] - o_t[same]).max()
+        assert err_t <= FWD_TOL * max(1.0, np.abs(o_t).max()), (v, err_t)
+    say(f"  {total} sampled pixels, {flips} decision-sensitive or with a different last "
+        f"blended Gaussian")
+    assert flips <= max(2, total // 50)
+
+
+def _window_pixels(fr, v):
+    """The pixels of a WIN x WIN window at the centre of view v, without the
+    decision-sensitive ones and those whose last blended Gaussian differs
+    between the GPU and the oracle: the cotangent is zero there, so a decision
+    that flips between FP32 and FP64 contributes nothing on either side."""
+    cam = fr.cams[v]
+    x0, y0 = cam.width // 2 - WIN // 2, cam.height // 2 - WIN // 2
+    ys, xs = np.meshgrid(np.arange(y0, y0 + WIN), np.arange(x0, x0 + WIN), indexing="ij")
+    xs, ys = xs.reshape(-1), ys.reshape(-1)
+    _, _, g_last = fr.gpu_pixels(v, xs, ys)
+    _, _, o_last, sens = _oracle_pixels(fr.scene, cam, xs, ys, fr, v)
+    keep = (g_last == o_last) & ~sens
+    say(f"  window of view {v}: {int((~keep).sum())} of {len(xs)} pixels excluded")
+    assert keep.mean() >= 0.9
+    return xs[keep], ys[keep]
+
+
+def test_fullsize_backward_window(fr):
+    views = [0] if len(fr.cams) == 1 else [1, 5]
+    dl = np.zeros(3 * fr.px, np.float32)
+    ref = None
+    for v in views:
+        cam = fr.cams[v]
+        xs, ys = _window_pixels(fr, v)
+        ct = np.random.default_rng(300 + v).normal(0.0, 1.0, (3, len(xs))).astype(np.float32)
+        px_off, _ = fr.view_offsets(v)
+        plane = cam.width * cam.height
+        for c in range(3):
+            dl[3 * px_off + c * plane + ys * cam.width + xs] = ct[c]
+        say(f"  oracle gradient of a {WIN}x{WIN} window of view {v}")
+        _, g = G.render_vjp(G.scene_dict(fr.scene), 3, cam, R.RasterParams(),
+                            ct.astype(np.float64), px=xs, py=ys)
+        ref = g if ref is None else {k: ref[k] + g[k] for k in g}
+    grads = torch.zeros_like(fr.planes)
+    fr.m.render_backward(fr.planes, fr.n, 3, fr.cams, fr.rp, fr.ws, fr.cap, to_dev(dl), None,
+                         grads)
+    torch.cuda.synchronize()
+    got = S.Scene.from_planes(grads.cpu().numpy(), fr.n, 3)
+    touched = int((np.abs(ref["means"]).sum(1) > 0).sum())
+    say(f"  window gradient reaches {touched} Gaussians")
+    assert touched > 0
+    pairs = [("means", got.means, ref["means"]), ("log_scales", got.log_scales, ref["log_scales"]),
+             ("quats", got.quats, ref["quats"]),
+             ("opacity", got.opacity_logits, ref["opacity_logits"]), ("sh", got.sh, ref["sh"])]
+    for k, a, b in pairs:
+        assert rel_norm_err(a, b) <= GRAD_TOL, (k, rel_norm_err(a, b))
+        assert rel_max_err(a, b) <= GRAD_TOL, (k, rel_max_err(a, b))
