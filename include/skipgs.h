@@ -114,7 +114,9 @@ void sgs_default_raster_params(sgs_raster_params* rp);
  * The workspace holds everything the backward needs (projected records, the
  * per-tile sorted lists, per-pixel final transmittance and last contributor).
  * It is valid for sgs_render_backward until it is reused; the backward must
- * see the same Gaussians, cameras and parameters.
+ * see the same Gaussians, cameras and parameters. The status word (sticky,
+ * see sgs_read_status) of a newly allocated workspace is undefined: clear it
+ * once with sgs_clear_status before the first forward.
  *
  * pair_capacity bounds the number of (tile, Gaussian) pairs of the whole
  * batch. If exceeded, the device sets SGS_STATUS_PAIR_OVERFLOW, records the

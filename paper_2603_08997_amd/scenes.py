@@ -249,10 +249,12 @@ def mixture_scene(seed: int, n: int, sh_degree: int = 3, log_scale_mean: float =
 
 
 def dense_cluster_scene(seed: int, n: int, sh_degree: int = 3, cluster_sigma: float = 0.35,
-                        log_scale_mean: float = -3.6, logit_mean: float = -1.0,
+                        log_scale_mean: float = -3.6, logit_mean: float = -0.45,
                         logit_std: float = 1.0) -> Scene:
     """All Gaussians in the two clusters of the mixture scene (no ground
-    plane): a dense scene with high depth complexity."""
+    plane): a dense scene with high depth complexity. The opacity-logit mean
+    is set so that 6M Gaussians seen from the hemisphere cameras at 1600x1060
+    blend about 60 Gaussians per pixel on average."""
     rng = np.random.default_rng(seed)
     means = _mixture_means(rng, n, cluster_sigma=cluster_sigma, weights=(0.0, 0.5, 0.5))
     log_scales = rng.normal(log_scale_mean, 0.5, (n, 3))

@@ -106,3 +106,40 @@ def test_loss_gradient_end_to_end_matches_central_differences():
             assert abs(fd - an) <= 1e-6 * max(np.abs(grads[grp]).max(), 1e-8) + 1e-9, (grp, idx, fd, an)
             checked += 1
     assert checked >= 25
+
+
+def test_dense_crop_gradient_matches_central_differences():
+    """The crop of the dense configuration (200 Gaussians, 64x64 window) with
+    the default thresholds: the analytic loss gradient against central
+    differences at points whose discrete decisions stay fixed."""
+    from .crops import dense_crop
+    crop, cam = dense_crop()
+    arrs = {k: np.asarray(v, np.float64) for k, v in G.scene_dict(crop).items()}
+    rp = R.RasterParams()
+    rng = np.random.default_rng(12)
+    ct = rng.normal(0, 1, (3, cam.width * cam.height))
+    _, grads = G.render_vjp(arrs, 3, cam, rp, ct)
+    base_val, base_out = _forward_value(arrs, 3, cam, rp, ct)
+    base_dec = _decisions(base_out)
+    assert base_out["n_blended"].numpy().mean() > 5
+    checked = 0
+    for grp in GROUPS:
+        a = arrs[grp]
+        for fi in rng.choice(a.size, size=min(a.size, 12), replace=False):
+            idx = np.unravel_index(fi, a.shape)
+            h = 1e-6 * max(1.0, abs(a[idx]))
+            vals, ok = [], True
+            for sgn in (1, -1):
+                b = {k: v.copy() for k, v in arrs.items()}
+                b[grp][idx] += sgn * h
+                val, out = _forward_value(b, 3, cam, rp, ct)
+                ok = ok and _decisions(out) == base_dec
+                vals.append(val)
+            if not ok:
+                continue
+            fd = (vals[0] - vals[1]) / (2 * h)
+            an = grads[grp][idx]
+            scale = max(1e-6, np.abs(grads[grp]).max())
+            assert abs(fd - an) <= 2e-6 * scale + 1e-6 * abs(an), (grp, idx, fd, an)
+            checked += 1
+    assert checked >= 40
