@@ -54,6 +54,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stage-events", action="store_true")
     ap.add_argument("--eval-views", type=int, default=200)
+    ap.add_argument("--workload", choices=["train", "batched"], default="train",
+                    help="train: gated vs full training (the headline); batched: forward + "
+                         "backward of 8 mixed-resolution views of 2M Gaussians, per-view "
+                         "launches vs one batched launch vs graph replay, per tile shape")
     return ap.parse_args()
 
 
@@ -122,12 +126,121 @@ def hbm_copy_probe(nbytes=1 << 30, reps=20):
     return gbs
 
 
+def run_batched(args):
+    """Forward + backward of eight views of four resolutions (two each of
+    640x480, 1245x825, 1600x1060, 980x545) of 2M Gaussians, gradients summed
+    over the views: eight single-view launches, one launch of all views, and
+    the replay of a captured graph of that launch, for each tile shape."""
+    from paper_2603_08997_amd import scenes as S
+    from paper_2603_08997_amd import skipgs as sk
+    n = 2_000_000
+    scene = S.mixture_scene(S.SEED_SCENE, n, 3)
+    cams = S.batched_cameras()
+    planes = torch.as_tensor(scene.to_planes()).cuda()
+    px = sum(c.width * c.height for c in cams)
+    dl = torch.randn(3 * px, device="cuda", generator=torch.Generator(device="cuda").manual_seed(7))
+    grads = torch.zeros_like(planes)
+    steps, warm = max(3, args.steps), max(1, args.warmup)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    results = {}
+    for tw, th in ((16, 16), (8, 8), (32, 8)):
+        rp = sk.RasterParams(tile_w=tw, tile_h=th)
+        # capacities: whole batch and each view, sized by one probe launch
+        def capacity(cs):
+            ws = sk.alloc_bytes(sk.forward_workspace_size(rp, n, cs, 1 << 16))
+            sk.clear_status(ws)
+            out = torch.empty(3 * sum(c.width * c.height for c in cs), device="cuda")
+            sk.render_forward(planes, n, 3, cs, rp, ws, 1 << 16, out)
+            return int(sk.read_status(ws)[2] * 1.02) + 4096
+        cap = capacity(cams)
+        ws = sk.alloc_bytes(sk.forward_workspace_size(rp, n, cams, cap))
+        sk.clear_status(ws)
+        rgb = torch.empty(3 * px, device="cuda")
+        per = []
+        off = 0
+        for c in cams:
+            k = 3 * c.width * c.height
+            cv = capacity([c])
+            w = sk.alloc_bytes(sk.forward_workspace_size(rp, n, [c], cv))
+            sk.clear_status(w)
+            per.append((c, cv, w, rgb[off:off + k], dl[off:off + k]))
+            off += k
+
+        def batched():
+            sk.render_forward(planes, n, 3, cams, rp, ws, cap, rgb)
+            sk.render_backward(planes, n, 3, cams, rp, ws, cap, dl, None, grads)
+
+        def per_view():
+            for c, cv, w, out, d in per:
+                sk.render_forward(planes, n, 3, [c], rp, w, cv, out)
+                sk.render_backward(planes, n, 3, [c], rp, w, cv, d, None, grads)
+
+        def timeit(fn):
+            for _ in range(warm):
+                fn()
+            a, b = ev(), ev()
+            torch.cuda.synchronize()
+            a.record()
+            for _ in range(steps):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            return a.elapsed_time(b) / steps
+
+        r = {"per_view_ms": timeit(per_view), "batched_ms": timeit(batched)}
+        # graph of the batched launch, replayed; the first replay's image must
+        # equal the eager one
+        grads.zero_()
+        batched()
+        torch.cuda.synchronize()
+        ref = rgb.clone()
+        cs = torch.cuda.Stream()
+        cs.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(cs):
+            batched()
+        torch.cuda.current_stream().wait_stream(cs)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=cs):
+            batched()
+        torch.cuda.synchronize()
+        for _ in range(3):
+            rgb.zero_()
+            g.replay()
+            torch.cuda.synchronize()
+            if not torch.equal(rgb, ref):
+                raise RuntimeError("graph replay differs from the eager launch")
+        r["graph_ms"] = timeit(g.replay)
+        flags = sk.read_status(ws)[0]
+        if flags:
+            raise RuntimeError(f"status flags {flags}")
+        r["pairs"] = cap
+        results[f"{tw}x{th}"] = r
+        log(f"tiles {tw}x{th}: per-view {r['per_view_ms']:.3f} ms, batched {r['batched_ms']:.3f} ms, "
+            f"graph {r['graph_ms']:.3f} ms")
+        del g, ws, per
+        torch.cuda.empty_cache()
+    best = min(results, key=lambda k: min(results[k]["batched_ms"], results[k]["graph_ms"]))
+    ms = min(results[best]["batched_ms"], results[best]["graph_ms"])
+    out = {"metric": "batched 8-view forward+backward throughput at 1 GPU", "value": 1000.0 / ms,
+           "unit": "batches/s", "n_gpus": 1, "steps": steps, "warmup": warm, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"forward+backward of 8 views (2x 640x480, 1245x825, 1600x1060, "
+                                  f"980x545) of {n} Gaussians SH3, one launch", "best_tiles": best},
+           "modes": results}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the sharding design is in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        torch.cuda.set_device(0)
+        return run_batched(args)
     from paper_2603_08997_amd import scenes as S
     from paper_2603_08997_amd import skipgs as sk
     from paper_2603_08997_amd.train import StageTimer, Trainer, measure_pairs, render_targets

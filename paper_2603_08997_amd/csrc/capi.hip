@@ -425,7 +425,9 @@ sgs_status sgs_read_status(const void* workspace, uint32_t* flags_out, int64_t* 
 
 sgs_status sgs_clear_status(void* workspace, void* stream) {
     if (!workspace) return fail(SGS_ERR_INVALID_ARG, "workspace is null");
-    SGS_HIP(hipMemsetAsync(workspace, 0, sizeof(uint32_t), static_cast<hipStream_t>(stream)),
+    // a kernel rather than a memset node, so that the call can be captured
+    SGS_HIP(sgs::fill_u32(static_cast<uint32_t*>(workspace), 1, 0u,
+                          static_cast<hipStream_t>(stream)),
             "clear status");
     return SGS_OK;
 }

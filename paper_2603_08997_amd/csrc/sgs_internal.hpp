@@ -101,6 +101,9 @@ hipError_t launch_project_backward(const float* planes, int64_t n, int64_t strid
                                    const Layout& L, char* ws, const int32_t* gate, float* grads,
                                    hipStream_t s);
 
+// p[0..n) = v on stream s (a kernel, so that callers can be captured).
+hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+
 // Stable LSD radix sort of (key, value) uint32 pairs over bits [0, bits).
 // n is read on the device from *n_dev; n_max bounds it for the grid size.
 // Returns the index (0/1) of the buffer holding the result.
