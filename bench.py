@@ -265,7 +265,12 @@ def main():
 
     results = {}
     for run in args.runs.split(","):
-        tr = Trainer(init, cams, targets, rp, gate, cap, gated=(run == "gated"))
+        if run not in ("gated", "full", "paper"):
+            raise SystemExit(f"unknown run {run!r} (gated, full, paper)")
+        # paper: the gate with the paper's own settings (decay 0.95, no
+        # tolerance, 500 warmup iterations, calibrated cumulative budget)
+        gp = sk.paper_gate(args.views) if run == "paper" else gate
+        tr = Trainer(init, cams, targets, rp, gp, cap, gated=(run != "full"))
         gslots = torch.zeros(args.warmup + args.steps, dtype=torch.int32, device=dev)
         for t in range(args.warmup):
             tr.iteration(int(seq[t]), gslots[t:t + 1])
@@ -384,6 +389,15 @@ def main():
         if gated.get("stage_ms_skipped") and full.get("stage_ms_all"):
             c = sum(gated["stage_ms_skipped"].values()) / sum(full["stage_ms_all"].values())
             out["skipped_iteration_cost"] = c
+    paper = results.get("paper")
+    if paper:
+        out["paper_iters_per_s"] = paper["iters_per_s"]
+        out["paper_skip_fraction"] = 1.0 - paper["backward_fraction"]
+        out["final_loss_paper"] = paper["final_mean_loss"]
+        if full:
+            out["paper_over_full"] = paper["iters_per_s"] / full["iters_per_s"]
+            out["final_loss_paper_rel_diff"] = (paper["final_mean_loss"] -
+                                                full["final_mean_loss"]) / full["final_mean_loss"]
     for k, r in results.items():
         out[f"stages_{k}"] = {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                               for kk, vv in r.get("stage_ms_executed", {}).items()}

@@ -286,6 +286,25 @@ def tile_rect(u, v, extent, tile_w, tile_h, tiles_x, tiles_y):
     return x0, x1, y0, y1
 
 
+def tile_contributes(u, v, a, b, c, o, rx, ry, tx, ty, tile_w, tile_h, width, height,
+                     rp: "RasterParams") -> bool:
+    """Whether a Gaussian can take part in the compositing of any pixel of
+    tile (tx, ty): some pixel centre p of the tile (inside the image) lies in
+    its overlap box and has P <= 0 and alpha' = min(alpha_max, o exp(P)) >=
+    alpha_min (Eq. 5 with the skip rule), by brute force over the tile's
+    pixels in FP64. A tile list may drop exactly the entries for which this
+    is false without changing any pixel."""
+    rp = rp.as_f32()
+    xs = np.arange(tx * tile_w, min((tx + 1) * tile_w, width)) + 0.5
+    ys = np.arange(ty * tile_h, min((ty + 1) * tile_h, height)) + 0.5
+    px, py = np.meshgrid(xs, ys)
+    dx, dy = px - float(u), py - float(v)
+    inbox = (np.abs(dx) <= rx) & (np.abs(dy) <= ry)
+    power = -0.5 * (a * dx * dx + c * dy * dy) - b * dx * dy
+    alpha = np.minimum(o * np.exp(np.minimum(power, 0.0)), rp.alpha_max)
+    return bool((inbox & (power <= 0) & (alpha >= rp.alpha_min)).any())
+
+
 def float32_bits(x) -> np.ndarray:
     return np.asarray(x, dtype=np.float32).view(np.uint32)
 

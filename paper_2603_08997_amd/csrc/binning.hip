@@ -134,6 +134,54 @@ __global__ void capacity_kernel(uint32_t* counters, int64_t capacity) {
     }
 }
 
+// Exact tile test of one (tile, Gaussian) pair: can alpha' = o exp(-q/2),
+// q = a dx^2 + 2 b dx dy + c dy^2, reach alpha_min at a pixel centre of the
+// tile inside the overlap box? The pixel-centre rectangle of the tile is
+// clipped to the box (widened by 1e-3 px). If the Gaussian's centre lies
+// outside it, the minimum of the convex q over the rectangle lies on an edge
+// that faces the centre (moving from any other boundary point towards the
+// centre enters the rectangle and lowers q), at the clamped stationary point
+// of that edge: at most one vertical and one horizontal edge to evaluate. The
+// pair is kept when that minimum, less a bound on its rounding error (8 ulp of
+// the sum of the terms' magnitudes), is within `lim` = 2 ln(o / alpha_min)
+// inflated by 1% + 0.01 (formed once per Gaussian): a culled pair cannot pass
+// the compositing kernels' skip test at any pixel of the tile, so images and
+// gradients are those of the uncut lists.
+__device__ __forceinline__ float reach_limit(float o, const RasterDev& rp) {
+    return rp.alpha_min > 0.f ? 2.f * logf(o / rp.alpha_min) * 1.01f + 0.01f : INFINITY;
+}
+
+__device__ __forceinline__ bool tile_reachable(float u, float v, float a, float b, float c,
+                                               float lim, float rx, float ry, int tx, int ty,
+                                               const RasterDev& rp) {
+    // relative to the centre; the box widened by 1e-3 px
+    const float m = 1e-3f;
+    const float bx = (float)(tx * rp.tile_w) - u, by = (float)(ty * rp.tile_h) - v;
+    const float x0 = fmaxf(bx + 0.5f, -rx - m), x1 = fminf(bx + ((float)rp.tile_w - 0.5f), rx + m);
+    const float y0 = fmaxf(by + 0.5f, -ry - m), y1 = fminf(by + ((float)rp.tile_h - 0.5f), ry + m);
+    if (x0 > x1 || y0 > y1) return false;   // no pixel centre of the tile in the box
+    const bool in_x = x0 <= 0.f && 0.f <= x1, in_y = y0 <= 0.f && 0.f <= y1;
+    if (in_x && in_y) return true;
+    if (lim == INFINITY) return true;
+    constexpr float kErr = 8.f * 5.96046448e-8f;
+    float best = INFINITY;
+    auto at = [&](float dx, float dy) {
+        const float bxy = b * dx * dy;
+        const float q = a * dx * dx + 2.f * bxy + c * dy * dy;
+        const float mag = a * dx * dx + 2.f * fabsf(bxy) + c * dy * dy;
+        best = fminf(best, q - kErr * mag);
+    };
+    if (!in_x) {   // the vertical edge facing the centre
+        const float ex = x0 > 0.f ? x0 : x1;
+        at(ex, fminf(fmaxf(-b * ex * __builtin_amdgcn_rcpf(c), y0), y1));
+    }
+    if (!in_y) {   // the horizontal edge facing the centre
+        const float ey = y0 > 0.f ? y0 : y1;
+        at(fminf(fmaxf(-b * ey * __builtin_amdgcn_rcpf(a), x0), x1), ey);
+    }
+    return best <= lim;
+}
+
 // Pair emission, load balanced over pairs: each workgroup writes a fixed
 // window of kEmitTile consecutive pairs. The Gaussians (in depth order) whose
 // pair ranges meet the window run from the one holding the window's first pair
@@ -141,9 +189,10 @@ __global__ void capacity_kernel(uint32_t* counters, int64_t capacity) {
 // scan); their tile rectangles are staged in LDS, a max-scan of their start
 // positions gives every window position its Gaussian, and every thread expands
 // its pairs to (tile, entry) with coalesced stores. Pair q of a Gaussian is
-// tile (x0 + q % w, y0 + q / w) of its rectangle, row-major.
+// tile (x0 + q % w, y0 + q / w) of its rectangle, row-major; pairs that fail
+// the exact tile test get the key kCulledTile.
 constexpr int kEmitThreads = 256;
-constexpr int kEmitItems = 8;
+constexpr int kEmitItems = 4;
 constexpr int kEmitTile = kEmitThreads * kEmitItems;
 static_assert(kEmitTile == kEmitWindow, "emission window size");
 // Gaussians meeting one window: at most one per pair plus the next window's first.
@@ -159,6 +208,9 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     __shared__ uint32_t s_base[kEmitMaxG];   // global tile of the rectangle's first tile
     __shared__ uint16_t s_w[kEmitMaxG];      // rectangle width in tiles
     __shared__ uint16_t s_tx[kEmitMaxG];     // tiles per row of the Gaussian's view
+    __shared__ uint16_t s_x0[kEmitMaxG];     // first tile column and row of the rectangle
+    __shared__ uint16_t s_y0[kEmitMaxG];
+    __shared__ float s_lim[kEmitMaxG];       // reach limit of the exact tile test
     __shared__ uint32_t s_own[kEmitTile];    // window position -> owning Gaussian
     __shared__ uint32_t s_scan[kEmitThreads / 64 + 1];
     const uint32_t P = counters[kPairsWritten];
@@ -191,13 +243,17 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
         s_base[j] = (uint32_t)(V.tile_offset + y0 * V.tiles_x + x0);
         s_w[j] = (uint16_t)(x1 - x0);
         s_tx[j] = (uint16_t)V.tiles_x;
+        s_x0[j] = (uint16_t)x0;
+        s_y0[j] = (uint16_t)y0;
+        s_lim[j] = reach_limit(r1.y, rp);
         // mark where this Gaussian's pairs start inside the window
         if (j > 0 && off - p0 < (uint32_t)kEmitTile) s_own[off - p0] = j;
     }
     __syncthreads();
     // owner of every window position = the last Gaussian starting at or
     // before it: inclusive max-scan of the start marks (thread t scans
-    // positions 8t .. 8t+7, then the block combines the per-thread maxima)
+    // positions kEmitItems t .. kEmitItems (t + 1) - 1, then the block
+    // combines the per-thread maxima)
     {
         uint32_t run[kEmitItems];
         uint32_t m = 0;
@@ -211,14 +267,36 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
         for (int i = 0; i < kEmitItems; ++i) s_own[tid * kEmitItems + i] = max(before, run[i]);
     }
     __syncthreads();
+    // gather every item's record first (one round of memory latency), then
+    // test and store
+    uint32_t own[kEmitItems];
+    float4 g0[kEmitItems], g1[kEmitItems];
+#pragma unroll
+    for (int it = 0; it < kEmitItems; ++it) {
+        const uint32_t p = p0 + (uint32_t)(it * kEmitThreads + tid);
+        own[it] = s_own[it * kEmitThreads + tid];
+        if (p <= p_last) {
+            const int64_t e = s_ent[own[it]];
+            g0[it] = rec[3 * e];
+            g1[it] = rec[3 * e + 1];
+        }
+    }
 #pragma unroll
     for (int it = 0; it < kEmitItems; ++it) {
         const uint32_t p = p0 + (uint32_t)(it * kEmitThreads + tid);
         if (p > p_last) break;
-        const uint32_t j = s_own[it * kEmitThreads + tid];
+        const uint32_t j = own[it];
         const uint32_t q = p - s_off[j];
         const uint32_t w = s_w[j];
-        ptile[p] = s_base[j] + (q / w) * s_tx[j] + (q % w);
+        // q / w and q % w through a float reciprocal, corrected to exact
+        uint32_t qy = (uint32_t)((float)q * __builtin_amdgcn_rcpf((float)w));
+        int32_t qx = (int32_t)(q - qy * w);
+        while (qx < 0) { --qy; qx += (int32_t)w; }
+        while (qx >= (int32_t)w) { ++qy; qx -= (int32_t)w; }
+        const bool keep = tile_reachable(g0[it].x, g0[it].y, g0[it].z, g0[it].w, g1[it].x,
+                                         s_lim[j], g1[it].z, g1[it].w, (int)s_x0[j] + qx,
+                                         (int)(s_y0[j] + qy), rp);
+        ptile[p] = keep ? s_base[j] + qy * s_tx[j] + (uint32_t)qx : kCulledTile;
         pentry[p] = s_ent[j];
     }
 }
@@ -231,7 +309,7 @@ __global__ void __launch_bounds__(256) ranges_kernel(const uint32_t* __restrict_
                                                      uint32_t* __restrict__ ranges) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total_tiles) return;
-    const uint32_t P = counters[kPairsWritten];
+    const uint32_t P = counters[kPairsKept];
     uint32_t lo = 0, hi = P;
     while (lo < hi) {  // first key >= t
         const uint32_t mid = (lo + hi) >> 1;
@@ -284,7 +362,7 @@ hipError_t launch_bin(const Views& views, const RasterDev& rp, int64_t n, const 
     hipError_t err;
 
     // visible entries -> (depth, entry), entry order; count -> counters[kVisible]
-    if ((err = fill_u32(counters + kVisible, kEvaluated + 2 - kVisible, 0u, s)) != hipSuccess)
+    if ((err = fill_u32(counters + kVisible, kPairsKept + 1 - kVisible, 0u, s)) != hipSuccess)
         return err;
     if (E > 0) {
         err = device_scan(VisibleSrc{tiles, E},
@@ -308,10 +386,11 @@ hipError_t launch_bin(const Views& views, const RasterDev& rp, int64_t n, const 
                                dim3(kEmitThreads), 0, s, dval[res], offsets, window_first, rec,
                                counters, n, views, rp, ptile[0], pentry[0]);
         if ((err = hipGetLastError()) != hipSuccess) return err;
-        // stable sort of the pairs by tile
+        // stable sort of the pairs by tile; the first pass drops culled pairs
+        // and counts the rest into counters[kPairsKept]
         int tres = 0;
         err = radix_sort(ptile, pentry, counters + kPairsWritten, L.capacity, L.tile_bits, hist,
-                         totals, s, &tres);
+                         totals, s, &tres, counters + kPairsKept);
         if (err != hipSuccess) return err;
     }
     if (L.total_tiles > 0)

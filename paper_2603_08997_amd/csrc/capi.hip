@@ -175,7 +175,8 @@ void make_layout(const Views& views, int64_t n, int64_t capacity, Layout* L) {
     L->capacity = capacity;
     L->scan_blocks = (L->entries + 2047) / 2048;
     L->sort_blocks = radix_blocks(std::max(L->entries, capacity));
-    int bits = 0;
+    // at least one pass: the first pass of the tile sort drops culled pairs
+    int bits = 1;
     while ((int64_t(1) << bits) < L->total_tiles) ++bits;
     L->tile_bits = bits;
     L->tile_passes = radix_passes(bits);

@@ -60,11 +60,16 @@ enum Counter : int {
     kPairsWritten = 3,  // min(pairs, capacity)
     kBlended = 4,       // uint64 at words 4-5: blended (pixel, Gaussian) pairs of the last rasterize
     kEvaluated = 6,     // uint64 at words 6-7: (pixel, list entry) pairs the forward examined
+    kPairsKept = 8,     // pairs left after the exact tile test (length of the sorted lists)
     kNumCounters = 16
 };
 
+// Tile key of an emitted pair whose Gaussian cannot reach alpha_min at any
+// pixel centre of the tile; the first pass of the tile sort drops such pairs.
+constexpr uint32_t kCulledTile = 0xffffffffu;
+
 // Pairs written by one workgroup of the emission kernel.
-constexpr int64_t kEmitWindow = 2048;
+constexpr int64_t kEmitWindow = 1024;
 
 struct Layout {
     int64_t entries, total_tiles, total_pixels, capacity;
@@ -108,8 +113,11 @@ hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 // n is read on the device from *n_dev; n_max bounds it for the grid size.
 // Returns the index (0/1) of the buffer holding the result.
 int radix_passes(int bits);
+// kept_dev (nullable): the first pass drops keys equal to kCulledTile and
+// writes the number of remaining pairs there; later passes sort that many.
 hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int64_t n_max,
-                      int bits, uint32_t* hist, uint32_t* totals, hipStream_t s, int* result);
+                      int bits, uint32_t* hist, uint32_t* totals, hipStream_t s, int* result,
+                      uint32_t* kept_dev = nullptr);
 int64_t radix_blocks(int64_t n_max);
 
 // Loss / gate / Adam

@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(kThreads) radix_hist_kernel(const uint32_t* __
                                                               const uint32_t* __restrict__ n_dev,
                                                               int shift, int bits,
                                                               uint32_t* __restrict__ hist,
-                                                              int nblocks) {
+                                                              int nblocks, bool skip_culled) {
     __shared__ uint32_t cnt[kWaves][kRadix];
     const int tid = threadIdx.x, w = tid / 64;
 #pragma unroll
@@ -60,13 +60,17 @@ __global__ void __launch_bounds__(kThreads) radix_hist_kernel(const uint32_t* __
             const int64_t j = (int64_t)(it * kThreads + tid) * 4;
             if (j + 3 < left) {
                 const uint4 q = k4[it * kThreads + tid];
-                atomicAdd(&cnt[w][digit_of(q.x, shift, mask)], 1u);
-                atomicAdd(&cnt[w][digit_of(q.y, shift, mask)], 1u);
-                atomicAdd(&cnt[w][digit_of(q.z, shift, mask)], 1u);
-                atomicAdd(&cnt[w][digit_of(q.w, shift, mask)], 1u);
+                const uint32_t kk[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (!(skip_culled && kk[c] == kCulledTile))
+                        atomicAdd(&cnt[w][digit_of(kk[c], shift, mask)], 1u);
             } else {
-                for (int64_t t = j; t < left && t < j + 4; ++t)
-                    atomicAdd(&cnt[w][digit_of(keys[base + t], shift, mask)], 1u);
+                for (int64_t t = j; t < left && t < j + 4; ++t) {
+                    const uint32_t k = keys[base + t];
+                    if (!(skip_culled && k == kCulledTile))
+                        atomicAdd(&cnt[w][digit_of(k, shift, mask)], 1u);
+                }
             }
         }
     }
@@ -107,7 +111,7 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
     const uint32_t* __restrict__ n_dev, int shift, int bits, const uint32_t* __restrict__ hist,
-    const uint32_t* __restrict__ totals, int nblocks) {
+    const uint32_t* __restrict__ totals, int nblocks, bool skip_culled) {
     __shared__ uint32_t lkeys[kTile];
     __shared__ uint32_t lvals[kTile];
     __shared__ uint32_t gbase[kRadix];          // global start of this block's digit run
@@ -140,12 +144,12 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
     for (int k = 0; k < kWaves; ++k) wcnt[k][tid] = 0;
     __syncthreads();
 
-    // wave-private stable ranking
+    // wave-private stable ranking (dropped keys take no position)
     uint32_t rank[kItems];
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
         const int li = w * kPerWave + it * 64 + lane;
-        const bool valid = li < nvalid;
+        const bool valid = li < nvalid && !(skip_culled && key[it] == kCulledTile);
         const uint32_t d = digit_of(key[it], shift, mask);
         const uint64_t peers = match_digit(d, valid, bits);
         const uint32_t before = (uint32_t)popc64(peers & lanemask_lt());
@@ -159,6 +163,7 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
     }
     __syncthreads();
     // per digit (thread tid): start in the block and the counts of earlier waves
+    int nkept;
     {
         uint32_t c[kWaves], sum = 0;
 #pragma unroll
@@ -167,12 +172,13 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
         uint32_t start = block_excl_scan<kThreads>(sum, smem, &tot);
 #pragma unroll
         for (int k = 0; k < kWaves; ++k) { wcnt[k][tid] = start; start += c[k]; }
+        nkept = (int)tot;
     }
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
         const int li = w * kPerWave + it * 64 + lane;
-        if (li < nvalid) {
+        if (li < nvalid && !(skip_culled && key[it] == kCulledTile)) {
             const uint32_t d = digit_of(key[it], shift, mask);
             const uint32_t pos = wcnt[w][d] + rank[it];
             lkeys[pos] = key[it];
@@ -182,13 +188,22 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
     __syncthreads();
     // wcnt[0][d] is now the block-local start of digit d
 #pragma unroll 4
-    for (int li = tid; li < nvalid; li += kThreads) {
+    for (int li = tid; li < nkept; li += kThreads) {
         const uint32_t k = lkeys[li];
         const uint32_t d = digit_of(k, shift, mask);
         const uint32_t out = gbase[d] + (uint32_t)li - wcnt[0][d];
         keys_out[out] = k;
         vals_out[out] = lvals[li];
     }
+}
+
+// *kept = sum of the digit totals (the keys the first pass kept).
+__global__ void __launch_bounds__(kRadix) radix_kept_kernel(const uint32_t* __restrict__ totals,
+                                                           int radix, uint32_t* __restrict__ kept) {
+    __shared__ uint32_t smem[kRadix / 64 + 1];
+    uint32_t tot;
+    block_excl_scan<kRadix>(threadIdx.x < (unsigned)radix ? totals[threadIdx.x] : 0u, smem, &tot);
+    if (threadIdx.x == 0) *kept = tot;
 }
 
 }  // namespace
@@ -209,22 +224,30 @@ static int pass_bits(int bits, int p, int* shift) {
 }
 
 hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int64_t n_max,
-                      int bits, uint32_t* hist, uint32_t* totals, hipStream_t s, int* result) {
+                      int bits, uint32_t* hist, uint32_t* totals, hipStream_t s, int* result,
+                      uint32_t* kept_dev) {
     const int passes = radix_passes(bits);
     const int nb = (int)radix_blocks(n_max);
     int cur = 0;
     for (int p = 0; p < passes; ++p) {
         int shift;
         const int pb = pass_bits(bits, p, &shift);
-        hipLaunchKernelGGL(radix_hist_kernel, dim3(nb), dim3(kThreads), 0, s, keys[cur], n_dev,
-                           shift, pb, hist, nb);
+        const bool skip = kept_dev != nullptr && p == 0;
+        const uint32_t* n_p = (kept_dev != nullptr && p > 0) ? kept_dev : n_dev;
+        hipLaunchKernelGGL(radix_hist_kernel, dim3(nb), dim3(kThreads), 0, s, keys[cur], n_p,
+                           shift, pb, hist, nb, skip);
         hipLaunchKernelGGL(radix_scan_kernel, dim3(kRadix), dim3(kScanThreads), 0, s, hist, nb,
                            totals);
+        if (skip)
+            hipLaunchKernelGGL(radix_kept_kernel, dim3(1), dim3(kRadix), 0, s, totals, 1 << pb,
+                               kept_dev);
         hipLaunchKernelGGL(radix_scatter_kernel, dim3(nb), dim3(kThreads), 0, s, keys[cur],
-                           vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_dev, shift, pb, hist, totals,
-                           nb);
+                           vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_p, shift, pb, hist, totals,
+                           nb, skip);
         cur ^= 1;
     }
+    if (kept_dev != nullptr && passes == 0)
+        return hipErrorInvalidValue;  // a kept count needs at least one pass
     *result = cur;
     return hipGetLastError();
 }

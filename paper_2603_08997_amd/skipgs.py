@@ -312,7 +312,8 @@ def read_counters(workspace, stream=None) -> dict:
     w = workspace[:64].cpu().numpy().view(np.uint32)
     u64 = lambda i: int(w[i]) | (int(w[i + 1]) << 32)
     return {"status": int(w[0]), "visible": int(w[1]), "pairs": int(w[2]),
-            "pairs_written": int(w[3]), "blended": u64(4), "evaluated": u64(6)}
+            "pairs_written": int(w[3]), "blended": u64(4), "evaluated": u64(6),
+            "pairs_kept": int(w[8])}
 
 
 def clear_status(workspace, stream=None):

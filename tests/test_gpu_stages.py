@@ -36,9 +36,10 @@ class Stage:
                        d["conic"], d["opacity"], d["rgb"])
         m.bin(cams, n, rp, self.ws, capacity)
         self.flags, self.vis, self.pairs = m.read_status(self.ws)
+        self.kept = m.read_counters(self.ws)["pairs_kept"]
 
     def lists(self):
-        P = self.pairs
+        P = self.kept
         tiles = region(self.ws, self.L.pair_tile, P, np.uint32)
         ents = region(self.ws, self.L.pair_entry, P, np.uint32)
         ranges = region(self.ws, self.L.ranges, 2 * self.L.total_tiles, np.uint32).reshape(-1, 2)
@@ -82,14 +83,44 @@ def test_binning_bit_exact(tile, ties):
     n = 1500
     recs, cat = _records(n, cams, 100 + int(ties * 10), max_radius=20, tie_fraction=ties)
     say(f"binning tile={tile} ties={ties} n={n}")
-    st = Stage(n, cams, m.RasterParams(tile_w=tw, tile_h=th), cat, 400_000)
+    rp = m.RasterParams(tile_w=tw, tile_h=th)
+    st = Stage(n, cams, rp, cat, 400_000)
     assert st.flags == 0
     keys, vals, ranges = _oracle_bins(recs, cams, n, tw, th)
     tiles, ents, granges = st.lists()
+    # the pair count the capacity must cover is that of the box lists
     assert st.pairs == len(keys)
-    assert np.array_equal(ents.astype(np.int64), vals)
-    assert np.array_equal(tiles.astype(np.int64), (keys >> np.uint64(32)).astype(np.int64))
-    assert np.array_equal(granges.astype(np.int64), ranges)
+    assert st.kept <= st.pairs and len(ents) == st.kept
+    # the GPU lists are the box lists less entries that fail the exact tile
+    # test: per tile, a subsequence of the oracle's list that keeps every
+    # entry able to contribute to a pixel of the tile, in the same order
+    orp = R.RasterParams(tile_w=tw, tile_h=th)
+    gtiles = (keys >> np.uint64(32)).astype(np.int64)
+    assert np.array_equal(tiles.astype(np.int64),
+                          np.repeat(np.arange(len(granges)), granges[:, 1] - granges[:, 0]))
+    toff, dropped, dropped_dead, dead = 0, 0, 0, 0
+    for v, (rec, cam) in enumerate(zip(recs, cams)):
+        tx_n = (cam.width + tw - 1) // tw
+        ty_n = (cam.height + th - 1) // th
+        for t in range(toff, toff + tx_n * ty_n):
+            lo, hi = ranges[t]
+            olist = vals[lo:hi]
+            glist = ents[granges[t][0]:granges[t][1]].astype(np.int64)
+            assert np.all(gtiles[lo:hi] == t)
+            keep = np.isin(olist, glist)
+            assert np.array_equal(olist[keep], glist)          # ordered subsequence
+            tx, ty = (t - toff) % tx_n, (t - toff) // tx_n
+            for e, kept in zip(olist, keep):
+                i = e - v * n
+                live = R.tile_contributes(rec["u"][i], rec["v"][i], *rec["conic"][i],
+                                          rec["opacity"][i], *rec["extent"][i], tx, ty, tw, th,
+                                          cam.width, cam.height, orp)
+                assert kept or not live, (t, e)
+                dead += int(not live)
+                dropped += int(not kept)
+        toff += tx_n * ty_n
+    say(f"  box pairs {len(vals)}, kept {len(ents)}, non-contributing {dead}, dropped {dropped}")
+    assert dropped >= 0.5 * dead
 
 
 def test_binning_empty_and_capacity_overflow():
@@ -132,26 +163,24 @@ def test_raster_forward_and_backward_match_oracle(tile):
     st = Stage(n, cams, m.RasterParams(tile_w=tw, tile_h=th, bg=bg), cat, 400_000)
     rgb, tf, nl = st.rasterize()
     orp = R.RasterParams(tile_w=tw, tile_h=th, bg=bg)
-    keys, vals, ranges = _oracle_bins(recs, cams, n, tw, th)
+    _, ents, granges = st.lists()
     rng = np.random.default_rng(5)
     dls, flips_total = [], 0
     for v, (rec, cam, img, T, NL) in enumerate(zip(recs, cams, split_views(rgb, cams, 3),
                                                    split_views(tf, cams), split_views(nl, cams))):
         out, _ = _oracle_composite(rec, cam, orp, n, v)
         ref_img = out["rgb"].detach().numpy()
-        # list positions of the oracle's last blended Gaussian in the oracle's lists
+        # the GPU's last blended Gaussian: entry at position n_last - 1 of the
+        # pixel's tile list
         px, py = R.pixel_grid(cam.width, cam.height)
         tiles_x = (cam.width + tw - 1) // tw
         toff = sum(((c.width + tw - 1) // tw) * ((c.height + th - 1) // th) for c in cams[:v])
-        pos = np.zeros(cam.width * cam.height, np.int64)
-        last = out["last"].numpy()
-        for k in range(len(pos)):
-            if last[k] < 0:
-                continue
-            t = toff + (py[k].item() // th) * tiles_x + px[k].item() // tw
-            s, e = ranges[t]
-            pos[k] = np.nonzero(vals[s:e] == last[k])[0][0] + 1
-        flips = pos != NL.astype(np.int64)
+        t = toff + (py.numpy() // th) * tiles_x + px.numpy() // tw
+        nlv = NL.astype(np.int64)
+        g_last = np.full(len(nlv), -1, np.int64)
+        has = nlv > 0
+        g_last[has] = ents[granges[t[has], 0].astype(np.int64) + nlv[has] - 1].astype(np.int64)
+        flips = g_last != out["last"].numpy()
         flips_total += int(flips.sum())
         ok = ~flips
         assert flips.mean() < 1e-3

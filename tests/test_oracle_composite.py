@@ -254,3 +254,45 @@ def test_overlap_box_contains_every_pixel_that_can_pass_alpha_min():
         assert not (passes & ~inbox).any(), i
         checked += 1
     assert checked > 100
+
+
+def test_dropping_non_contributing_entries_changes_no_pixel_of_the_tile():
+    """tile_contributes false => the Gaussian takes no part in any pixel of
+    the tile: compositing the tile's pixels without those Gaussians gives the
+    same result; and a Gaussian it calls contributing does get blended
+    somewhere in the tile (with thresholds that cannot stop compositing)."""
+    w, h, tw, th = 40, 29, 8, 8
+    rec = S.random_records(31, 300, w, h, max_radius=14)
+    rp = R.RasterParams(tile_w=tw, tile_h=th)
+    n = len(rec["u"])
+    uv = torch.tensor(np.stack([rec["u"], rec["v"]], 1), dtype=torch.float64)
+    con = torch.tensor(rec["conic"], dtype=torch.float64)
+    op = torch.tensor(rec["opacity"], dtype=torch.float64)
+    col = torch.tensor(rec["rgb"], dtype=torch.float64)
+    dep = torch.tensor(rec["depth"], dtype=torch.float64)
+    ext = torch.tensor(rec["extent"].astype(np.int64))
+    no_stop = R.RasterParams(tile_w=tw, tile_h=th, t_min=0.0)
+    dead_total = 0
+    for ty in range((h + th - 1) // th):
+        for tx in range((w + tw - 1) // tw):
+            xs = np.arange(tx * tw, min((tx + 1) * tw, w))
+            ys = np.arange(ty * th, min((ty + 1) * th, h))
+            px, py = [a.reshape(-1) for a in np.meshgrid(xs, ys)]
+            live = np.array([R.tile_contributes(rec["u"][i], rec["v"][i], *rec["conic"][i],
+                                                rec["opacity"][i], *rec["extent"][i], tx, ty,
+                                                tw, th, w, h, rp) for i in range(n)])
+            dead_total += int((~live).sum())
+            ids = torch.arange(n)
+            full = R.composite(uv, con, op, col, dep, ext, ids, w, h, rp, px=px, py=py)
+            k = torch.as_tensor(np.nonzero(live)[0])
+            part = R.composite(uv[k], con[k], op[k], col[k], dep[k], ext[k], ids[k], w, h, rp,
+                               px=px, py=py)
+            assert torch.equal(full["rgb"], part["rgb"])
+            assert torch.equal(full["last"], part["last"])
+            for i in k[:8].tolist():
+                # a live Gaussian alone (no termination) blends at some pixel
+                s1 = slice(i, i + 1)
+                one = R.composite(uv[s1], con[s1], op[s1], col[s1], dep[s1], ext[s1], ids[s1],
+                                  w, h, no_stop, px=px, py=py)
+                assert int(one["n_blended"].sum()) >= 1, (tx, ty, i)
+    assert dead_total > 0
