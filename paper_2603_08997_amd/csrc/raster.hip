@@ -25,17 +25,19 @@ namespace {
 constexpr int kLanes = 64;
 
 struct Splat {
-    float alpha;   // alpha' after the clamp
-    float ex;      // exp(P)
-    float dx, dy;  // pixel centre - mean
-    bool clamped;  // o exp(P) > alpha_max
+    float alpha;           // alpha' after the clamp
+    float ex;              // exp(P)
+    float dx, dy;          // pixel centre - mean
+    float dx2, dy2, dxy;   // dx^2, dy^2, dx dy
+    bool clamped;          // o exp(P) > alpha_max
 };
 
 // Overlap test, Gaussian falloff and alpha' of one (pixel, Gaussian) pair.
 // Forward and backward call this same function, so their skip decisions agree
 // bit for bit. Branch-free: every quantity is computed and the return value
-// says whether the Gaussian contributes. exp(P) is the hardware 2^x of
-// P log2(e) (about 2 ulp over the range where alpha' can reach alpha_min).
+// says whether the Gaussian contributes. P = -(a dx^2 + c dy^2)/2 - b dx dy
+// with explicit fused multiply-adds; exp(P) is the hardware 2^x of P log2(e)
+// (about 2 ulp over the range where alpha' can reach alpha_min).
 __device__ __forceinline__ bool splat_alpha(float px, float py, float u, float v, float rx,
                                             float ry, float o, float a, float b, float c,
                                             const RasterDev& rp, Splat& s) {
@@ -43,7 +45,10 @@ __device__ __forceinline__ bool splat_alpha(float px, float py, float u, float v
     const bool inbox = (px - rx <= u) & (u <= px + rx) & (py - ry <= v) & (v <= py + ry);
     s.dx = px - u;
     s.dy = py - v;
-    const float power = -0.5f * fmaf(a, s.dx * s.dx, c * (s.dy * s.dy)) - b * (s.dx * s.dy);
+    s.dx2 = s.dx * s.dx;
+    s.dy2 = s.dy * s.dy;
+    s.dxy = s.dx * s.dy;
+    const float power = fmaf(-0.5f, fmaf(a, s.dx2, c * s.dy2), -b * s.dxy);
     s.ex = __builtin_amdgcn_exp2f(power * 1.44269504088896341f);
     const float raw = o * s.ex;
     s.clamped = raw > rp.alpha_max;
@@ -171,8 +176,11 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
     }
 }
 
+// At most 72 VGPRs, so that 7 waves fit on each SIMD: the 6700 tiles of a
+// 1600x1060 view (16x16 tiles) then all run at once on the 1024 SIMDs of the
+// chip instead of leaving a second round for the last tiles.
 template <int TW, int TH>
-__global__ void __launch_bounds__(kLanes) raster_backward_kernel(
+__global__ void __launch_bounds__(kLanes, 7) raster_backward_kernel(
     Views views, RasterDev rp, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ pentry, const float4* __restrict__ rec,
     const float* __restrict__ t_final, const uint32_t* __restrict__ n_last,
@@ -237,8 +245,10 @@ __global__ void __launch_bounds__(kLanes) raster_backward_kernel(
         __syncthreads();
         for (int j = 0; j < cnt; ++j) {
             const uint32_t rel = b_end - 1u - (uint32_t)j - start;   // list position
-            float d_u = 0.f, d_v = 0.f, d_a = 0.f, d_b = 0.f, d_c = 0.f, d_o = 0.f;
-            float d_r = 0.f, d_g = 0.f, d_bl = 0.f;
+            // -0 is the additive identity for every float, so the first
+            // accumulation into each sum folds away
+            float d_u = -0.f, d_v = -0.f, d_a = -0.f, d_b = -0.f, d_c = -0.f, d_o = -0.f;
+            float d_r = -0.f, d_g = -0.f, d_bl = -0.f;
             bool contrib = false;
             const float4 P = s_pos[j];
             const float4 Q = s_con[j];
@@ -257,23 +267,27 @@ __global__ void __launch_bounds__(kLanes) raster_backward_kernel(
                     d_r = fmaf(G0[k], w, d_r);
                     d_g = fmaf(G1[k], w, d_g);
                     d_bl = fmaf(G2[k], w, d_bl);
-                    const float d_alpha = G0[k] * (col.x * Ti - S0[k] * inv_om) +
-                                          G1[k] * (col.y * Ti - S1[k] * inv_om) +
-                                          G2[k] * (col.z * Ti - S2[k] * inv_om);
+                    // dC/dalpha' = T_i c_i - S_i / (1 - alpha'_i), per channel
+                    const float d_alpha =
+                        fmaf(G0[k], fmaf(col.x, Ti, -S0[k] * inv_om),
+                             fmaf(G1[k], fmaf(col.y, Ti, -S1[k] * inv_om),
+                                  G2[k] * fmaf(col.z, Ti, -S2[k] * inv_om)));
                     S0[k] = fmaf(col.x, w, S0[k]);
                     S1[k] = fmaf(col.y, w, S1[k]);
                     S2[k] = fmaf(col.z, w, S2[k]);
                     T[k] = Ti;
                     // alpha' = o exp(P) unless clamped at alpha_max (then it
-                    // depends on neither o nor the geometry)
+                    // depends on neither o nor the geometry); dalpha'/dP = alpha'
                     const float dA = s.clamped ? 0.f : d_alpha;
                     const float dP = dA * s.alpha;
+                    const float hP = -0.5f * dP;
                     d_o = fmaf(dA, s.ex, d_o);
-                    d_a -= 0.5f * dP * s.dx * s.dx;
-                    d_b -= dP * s.dx * s.dy;
-                    d_c -= 0.5f * dP * s.dy * s.dy;
-                    d_u += dP * (Q.x * s.dx + Q.y * s.dy);
-                    d_v += dP * (Q.y * s.dx + Q.z * s.dy);
+                    d_a = fmaf(hP, s.dx2, d_a);
+                    d_b = fmaf(-dP, s.dxy, d_b);
+                    d_c = fmaf(hP, s.dy2, d_c);
+                    // dP/du = a dx + b dy, dP/dv = b dx + c dy
+                    d_u = fmaf(dP, fmaf(Q.x, s.dx, Q.y * s.dy), d_u);
+                    d_v = fmaf(dP, fmaf(Q.y, s.dx, Q.z * s.dy), d_v);
                     contrib = true;
                 }
             }
