@@ -29,6 +29,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per dispatch measured with rocprofv3 counters for the default
+# workload (written by paper_2603_08997_amd.profiling traffic); used only while
+# the sources still match the ones measured
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_train_3M_1600x1060.txt")
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 # FP32 operations per blended (pixel, Gaussian) pair in the compositing
 # kernels, counted from the arithmetic each pair performs (FMA = 2, exp = 1).
@@ -350,8 +354,14 @@ def main():
                           "frac": ach / c["peak"]}
         name = max(summary, key=lambda k: summary[k]["ms_per_iteration"])
         c, sm = cands[name], summary[name]
+        traffic = None
+        if (args.n, args.width, args.height) == (3_000_000, 1600, 1060):
+            from paper_2603_08997_amd.profiling import load_traffic
+            rec = load_traffic(TRAFFIC_FILE)
+            if rec is not None and name in rec["kernels"]:
+                traffic = rec["kernels"][name]["traffic_bytes"]
         roof = {"kernel": name, "bound": c["bound"], "achieved": sm["achieved"], "peak": c["peak"],
-                "unit": c["unit"], "frac": sm["frac"], "traffic": None,
+                "unit": c["unit"], "frac": sm["frac"], "traffic": traffic,
                 "avg_launch_ms": c["ms"], "blended_pairs_per_launch": blended,
                 "evaluated_pairs_per_launch": float(np.mean(evaluated)),
                 "tile_pairs_per_view": float(np.mean(pairs)), "visible_per_view": vis,

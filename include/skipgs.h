@@ -239,7 +239,10 @@ sgs_status sgs_photometric_loss(const float* rgb, const float* target, int32_t w
                                 int32_t height, float lambda, void* workspace,
                                 size_t workspace_bytes, float* d_loss, void* stream);
 
-/* dL/d rgb (planar [3][H][W]) of the loss above; predicated on d_gate. */
+/* dL/d rgb (planar [3][H][W]) of the loss above; predicated on d_gate. It
+ * reads per-pixel SSIM derivative maps that sgs_photometric_loss leaves in the
+ * workspace: call it after sgs_photometric_loss with the same rgb, target,
+ * size and workspace (the training step always does). */
 sgs_status sgs_photometric_loss_backward(const float* rgb, const float* target, int32_t width,
                                          int32_t height, float lambda, void* workspace,
                                          size_t workspace_bytes, const int32_t* d_gate,

@@ -37,12 +37,11 @@ struct CompactSink {  // visible entries -> (depth bits, entry), in entry order
         }
     }
 };
-struct PairCountSrc {  // tiles touched, in depth order
-    const uint32_t* tiles;
-    const uint32_t* sorted_entry;
+struct PairCountSrc {  // tiles touched, in depth order (gathered by the depth sort)
+    const uint32_t* tiles_sorted;
     const uint32_t* n_dev;
     __device__ int64_t count() const { return *n_dev; }
-    __device__ uint32_t operator()(int64_t k) const { return tiles[sorted_entry[k]]; }
+    __device__ uint32_t operator()(int64_t k) const { return tiles_sorted[k]; }
 };
 // Pair offset of every Gaussian in depth order, and for every emission window
 // (kEmitWindow consecutive pairs, windows 0 .. n_windows) the Gaussian whose
@@ -370,13 +369,16 @@ hipError_t launch_bin(const Views& views, const RasterDev& rp, int64_t n, const 
                                       dval[0]},
                           E, sums, counters + kVisible, s);
         if (err != hipSuccess) return err;
-        // stable sort by depth: ties keep ascending entry order
+        // stable sort by depth (ties keep ascending entry order); the last
+        // pass also gathers each entry's tile count into `offsets`, in depth
+        // order, for the scan below to read linearly and overwrite in place
         int res = 0;
-        err = radix_sort(dkey, dval, counters + kVisible, E, 32, hist, totals, s, &res);
+        err = radix_sort(dkey, dval, counters + kVisible, E, 32, hist, totals, s, &res, nullptr,
+                         tiles, offsets);
         if (err != hipSuccess) return err;
         // pair offsets in depth order; total -> counters[kPairs]
         const uint32_t n_windows = (uint32_t)((L.capacity + kEmitWindow - 1) / kEmitWindow);
-        err = device_scan(PairCountSrc{tiles, dval[res], counters + kVisible},
+        err = device_scan(PairCountSrc{offsets, counters + kVisible},
                           OffsetSink{offsets, window_first, n_windows}, E, sums,
                           counters + kPairs, s);
         if (err != hipSuccess) return err;

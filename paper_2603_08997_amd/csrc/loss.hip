@@ -11,7 +11,8 @@
 //
 // Backward: per pixel p the SSIM value S(p) depends on x through mu_x(p),
 // E[x^2](p) and E[xy](p); the map derivatives dS/dmu_x, dS/dE[x^2],
-// dS/dE[xy] are written once and filtered again (the window is symmetric):
+// dS/dE[xy] are written by the forward and filtered again by the backward
+// (the window is symmetric):
 //   dSSIM/dx(q) = F[dS/dmu_x](q) + 2 x(q) F[dS/dE[x^2]](q) + y(q) F[dS/dE[xy]](q).
 #include "sgs_internal.hpp"
 #include "sgs_device.hpp"
@@ -107,12 +108,12 @@ __device__ __forceinline__ void moments(const float (*X)[kE], const float (*Y)[k
 }
 
 // Forward tile: sums of |x - y| and of S over the tile's 3 x 256 values into
-// partials[2 blk]; with MAPS, instead writes dS/dmu_x, dS/dE[x^2], dS/dE[xy].
-template <bool MAPS>
+// partials[2 blk], and the maps dS/dmu_x, dS/dE[x^2], dS/dE[xy] the backward
+// filters (written on every forward, so that a backward needs no second pass
+// over the moments).
 __global__ void __launch_bounds__(kThreads) ssim_forward_kernel(
     const float* __restrict__ x, const float* __restrict__ y, int w, int h, Window W,
-    float* __restrict__ partials, float* __restrict__ maps, const int32_t* __restrict__ gate) {
-    if (MAPS && gate_closed(gate)) return;
+    float* __restrict__ partials, float* __restrict__ maps) {
     __shared__ float sx[3][kE][kE];
     __shared__ float sy[3][kE][kE];
     __shared__ float hb[5][kE][kT];
@@ -141,16 +142,13 @@ __global__ void __launch_bounds__(kThreads) ssim_forward_kernel(
             const float b = sy[ch][tid / kT + kR][tid % kT + kR];
             s_l1 += fabsf(a - b);
             s_ssim += S;
-            if (MAPS) {
-                const int64_t pix = (int64_t)oy * w + ox;
-                maps[(0 * 3 + ch) * plane + pix] =
-                    2.f * my * (A2 - A1) / D - 2.f * mx * S * (1.f / B1 - 1.f / B2);
-                maps[(1 * 3 + ch) * plane + pix] = -S / B2;
-                maps[(2 * 3 + ch) * plane + pix] = 2.f * A1 / D;
-            }
+            const int64_t pix = (int64_t)oy * w + ox;
+            maps[(0 * 3 + ch) * plane + pix] =
+                2.f * my * (A2 - A1) / D - 2.f * mx * S * (1.f / B1 - 1.f / B2);
+            maps[(1 * 3 + ch) * plane + pix] = -S / B2;
+            maps[(2 * 3 + ch) * plane + pix] = 2.f * A1 / D;
         }
     }
-    if (MAPS) return;
     // fixed-order workgroup sum
     s_l1 = wave_sum(s_l1);
     s_ssim = wave_sum(s_ssim);
@@ -258,8 +256,9 @@ hipError_t launch_loss_forward(const float* rgb, const float* target, int w, int
     const LossLayout L = loss_layout(w, h);
     const dim3 grid((unsigned)((w + kT - 1) / kT), (unsigned)((h + kT - 1) / kT));
     float* partials = reinterpret_cast<float*>(ws + L.partials);
-    hipLaunchKernelGGL(ssim_forward_kernel<false>, grid, dim3(kThreads), 0, s, rgb, target, w, h,
-                       make_window(), partials, (float*)nullptr, (const int32_t*)nullptr);
+    float* maps = reinterpret_cast<float*>(ws + L.maps);
+    hipLaunchKernelGGL(ssim_forward_kernel, grid, dim3(kThreads), 0, s, rgb, target, w, h,
+                       make_window(), partials, maps);
     hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(1024), 0, s, partials, L.blocks,
                        3.0 * (double)w * (double)h, lambda, d_loss);
     return hipGetLastError();
@@ -269,9 +268,7 @@ hipError_t launch_loss_backward(const float* rgb, const float* target, int w, in
                                 char* ws, const int32_t* gate, float* dl, hipStream_t s) {
     const LossLayout L = loss_layout(w, h);
     const dim3 grid((unsigned)((w + kT - 1) / kT), (unsigned)((h + kT - 1) / kT));
-    float* maps = reinterpret_cast<float*>(ws + L.maps);
-    hipLaunchKernelGGL(ssim_forward_kernel<true>, grid, dim3(kThreads), 0, s, rgb, target, w, h,
-                       make_window(), (float*)nullptr, maps, gate);
+    const float* maps = reinterpret_cast<const float*>(ws + L.maps);
     hipLaunchKernelGGL(ssim_backward_kernel, grid, dim3(kThreads), 0, s, rgb, target, w, h, lambda,
                        make_window(), maps, gate, dl);
     return hipGetLastError();

@@ -115,9 +115,12 @@ hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 int radix_passes(int bits);
 // kept_dev (nullable): the first pass drops keys equal to kCulledTile and
 // writes the number of remaining pairs there; later passes sort that many.
+// gather_dst (nullable): the last pass also writes gather_src[value] at each
+// sorted position.
 hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int64_t n_max,
                       int bits, uint32_t* hist, uint32_t* totals, hipStream_t s, int* result,
-                      uint32_t* kept_dev = nullptr);
+                      uint32_t* kept_dev = nullptr, const uint32_t* gather_src = nullptr,
+                      uint32_t* gather_dst = nullptr);
 int64_t radix_blocks(int64_t n_max);
 
 // Loss / gate / Adam

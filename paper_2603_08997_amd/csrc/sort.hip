@@ -111,7 +111,8 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
     const uint32_t* __restrict__ n_dev, int shift, int bits, const uint32_t* __restrict__ hist,
-    const uint32_t* __restrict__ totals, int nblocks, bool skip_culled) {
+    const uint32_t* __restrict__ totals, int nblocks, bool skip_culled,
+    const uint32_t* __restrict__ gather_src, uint32_t* __restrict__ gather_dst) {
     __shared__ uint32_t lkeys[kTile];
     __shared__ uint32_t lvals[kTile];
     __shared__ uint32_t gbase[kRadix];          // global start of this block's digit run
@@ -192,8 +193,10 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
         const uint32_t k = lkeys[li];
         const uint32_t d = digit_of(k, shift, mask);
         const uint32_t out = gbase[d] + (uint32_t)li - wcnt[0][d];
+        const uint32_t val = lvals[li];
         keys_out[out] = k;
-        vals_out[out] = lvals[li];
+        vals_out[out] = val;
+        if (gather_dst != nullptr) gather_dst[out] = gather_src[val];
     }
 }
 
@@ -225,7 +228,7 @@ static int pass_bits(int bits, int p, int* shift) {
 
 hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int64_t n_max,
                       int bits, uint32_t* hist, uint32_t* totals, hipStream_t s, int* result,
-                      uint32_t* kept_dev) {
+                      uint32_t* kept_dev, const uint32_t* gather_src, uint32_t* gather_dst) {
     const int passes = radix_passes(bits);
     const int nb = (int)radix_blocks(n_max);
     int cur = 0;
@@ -241,9 +244,10 @@ hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_de
         if (skip)
             hipLaunchKernelGGL(radix_kept_kernel, dim3(1), dim3(kRadix), 0, s, totals, 1 << pb,
                                kept_dev);
+        const bool last = p == passes - 1;
         hipLaunchKernelGGL(radix_scatter_kernel, dim3(nb), dim3(kThreads), 0, s, keys[cur],
                            vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_p, shift, pb, hist, totals,
-                           nb, skip);
+                           nb, skip, last ? gather_src : nullptr, last ? gather_dst : nullptr);
         cur ^= 1;
     }
     if (kept_dev != nullptr && passes == 0)
