@@ -3,15 +3,17 @@
 and the FP64 oracle timed on the host as a CPU reference.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py --workload batched     # 8 mixed-resolution views per launch
 
 Workload (defaults): 3,000,000 Gaussians (SH degree 3, ground-plane + two
 clusters), 200 views at 1600x1060 on a hemisphere of radius 4-5, 16x16 tiles,
 targets rendered from the ground-truth set, training from a perturbed copy,
 uniform view sampling, loss 0.8 L1 + 0.2 (1 - SSIM), gate with EMA decay 0.9,
 skip within 2% of the view's EMA, >= 50% backward per 100 iterations, Adam
-(means lr 1.6e-4). One step = one training iteration: forward render, loss,
-gate, and (when the gate opens) loss backward, render backward and Adam.
-Inputs are resident in HBM before the timed region starts.
+(means lr 1.6e-4); 10,000 timed iterations per run (gated, then full). One
+step = one training iteration: forward render, loss, gate, and (when the gate
+opens) loss backward, render backward and Adam. Inputs are resident in HBM
+before the timed region starts.
 """
 from __future__ import annotations
 
@@ -47,7 +49,7 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=3_000_000)
     ap.add_argument("--views", type=int, default=200)
