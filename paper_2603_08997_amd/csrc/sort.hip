@@ -21,6 +21,7 @@ constexpr int kTile = kThreads * kItems;  // keys per block
 constexpr int kRadix = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kScanThreads = 1024;
+constexpr int kHistCopies = 4;
 
 __device__ __forceinline__ uint32_t digit_of(uint32_t k, int shift, uint32_t mask) {
     return (k >> shift) & mask;
@@ -38,16 +39,18 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int bits
 }
 
 // Digit counts of one block's keys. Counting does not depend on order, so the
-// keys are read as uint4 and counted into per-wave LDS histograms.
+// keys are read as uint4 and counted into several LDS histograms.
 __global__ void __launch_bounds__(kThreads) radix_hist_kernel(const uint32_t* __restrict__ keys,
                                                               const uint32_t* __restrict__ n_dev,
                                                               int shift, int bits,
                                                               uint32_t* __restrict__ hist,
                                                               int nblocks, bool skip_culled) {
-    __shared__ uint32_t cnt[kWaves][kRadix];
-    const int tid = threadIdx.x, w = tid / 64;
+    // kHistCopies counters per digit, lane l counting into copy l % kHistCopies,
+    // so that fewer lanes of one atomic instruction hit the same address
+    __shared__ uint32_t cnt[kHistCopies][kRadix];
+    const int tid = threadIdx.x, w = tid % kHistCopies;
 #pragma unroll
-    for (int k = 0; k < kWaves; ++k) cnt[k][tid] = 0;
+    for (int k = 0; k < kHistCopies; ++k) cnt[k][tid] = 0;
     __syncthreads();
     const uint32_t n = *n_dev;
     const uint32_t mask = (1u << bits) - 1u;
@@ -55,30 +58,38 @@ __global__ void __launch_bounds__(kThreads) radix_hist_kernel(const uint32_t* __
     if (base < (int64_t)n) {
         const uint4* k4 = reinterpret_cast<const uint4*>(keys + base);
         const int64_t left = (int64_t)n - base;
+        // all loads first, then the counts
+        uint4 q[kItems / 4];
 #pragma unroll
         for (int it = 0; it < kItems / 4; ++it) {
             const int64_t j = (int64_t)(it * kThreads + tid) * 4;
             if (j + 3 < left) {
-                const uint4 q = k4[it * kThreads + tid];
-                const uint32_t kk[4] = {q.x, q.y, q.z, q.w};
+                q[it] = k4[it * kThreads + tid];
+            } else {
+                uint32_t kk[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
-                    if (!(skip_culled && kk[c] == kCulledTile))
-                        atomicAdd(&cnt[w][digit_of(kk[c], shift, mask)], 1u);
-            } else {
-                for (int64_t t = j; t < left && t < j + 4; ++t) {
-                    const uint32_t k = keys[base + t];
-                    if (!(skip_culled && k == kCulledTile))
-                        atomicAdd(&cnt[w][digit_of(k, shift, mask)], 1u);
-                }
+                    kk[c] = j + c < left ? keys[base + j + c] : kCulledTile;
+                q[it] = make_uint4(kk[0], kk[1], kk[2], kk[3]);
             }
+        }
+#pragma unroll
+        for (int it = 0; it < kItems / 4; ++it) {
+            const int64_t j = (int64_t)(it * kThreads + tid) * 4;
+            const uint32_t kk[4] = {q[it].x, q[it].y, q[it].z, q[it].w};
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (j + c < left && !(skip_culled && kk[c] == kCulledTile))
+                    atomicAdd(&cnt[w][digit_of(kk[c], shift, mask)], 1u);
         }
     }
     __syncthreads();
     uint32_t total = 0;
 #pragma unroll
-    for (int k = 0; k < kWaves; ++k) total += cnt[k][tid];
-    hist[(int64_t)tid * nblocks + blockIdx.x] = total;
+    for (int k = 0; k < kHistCopies; ++k) total += cnt[k][tid];
+    // only the rows of digits this pass can produce (each write is a separate
+    // cache line of the digit-major table)
+    if (tid < (1 << bits)) hist[(int64_t)tid * nblocks + blockIdx.x] = total;
 }
 
 // Exclusive scan of each digit row hist[d][0..nblocks) in place; totals[d] = row sum.
@@ -138,8 +149,9 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
     }
     {
         uint32_t tot;
-        const uint32_t ex = block_excl_scan<kThreads>(totals[tid], smem, &tot);
-        gbase[tid] = ex + hist[(int64_t)tid * nblocks + blockIdx.x];
+        const bool used = tid < (1 << bits);   // rows beyond 2^bits are not written
+        const uint32_t ex = block_excl_scan<kThreads>(used ? totals[tid] : 0u, smem, &tot);
+        gbase[tid] = ex + (used ? hist[(int64_t)tid * nblocks + blockIdx.x] : 0u);
     }
 #pragma unroll
     for (int k = 0; k < kWaves; ++k) wcnt[k][tid] = 0;
@@ -239,7 +251,8 @@ hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_de
         const uint32_t* n_p = (kept_dev != nullptr && p > 0) ? kept_dev : n_dev;
         hipLaunchKernelGGL(radix_hist_kernel, dim3(nb), dim3(kThreads), 0, s, keys[cur], n_p,
                            shift, pb, hist, nb, skip);
-        hipLaunchKernelGGL(radix_scan_kernel, dim3(kRadix), dim3(kScanThreads), 0, s, hist, nb,
+        // rows and totals of digits >= 2^pb are never read for a key of this pass
+        hipLaunchKernelGGL(radix_scan_kernel, dim3(1u << pb), dim3(kScanThreads), 0, s, hist, nb,
                            totals);
         if (skip)
             hipLaunchKernelGGL(radix_kept_kernel, dim3(1), dim3(kRadix), 0, s, totals, 1 << pb,
