@@ -215,14 +215,15 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     const uint32_t P = counters[kPairsWritten];
     const uint32_t total = counters[kPairs];
     const uint32_t nvis = counters[kVisible];
-    const uint32_t p0 = blockIdx.x * (uint32_t)kEmitTile;
+    const int win = blockIdx.x;
+    const uint32_t p0 = (uint32_t)win * (uint32_t)kEmitTile;
     if (p0 >= P) return;   // uniform across the workgroup
     const uint32_t p_last = min(p0 + (uint32_t)kEmitTile, P) - 1u;
     const int tid = threadIdx.x;
-    const uint32_t k0 = window_first[blockIdx.x];
+    const uint32_t k0 = window_first[win];
     // the next window's first Gaussian exists whenever pairs continue past
     // this window; otherwise the window ends with the last visible Gaussian
-    const uint32_t k1 = (uint64_t)p0 + kEmitTile < total ? window_first[blockIdx.x + 1]
+    const uint32_t k1 = (uint64_t)p0 + kEmitTile < total ? window_first[win + 1]
                                                           : nvis - 1u;
     const uint32_t cnt = k1 - k0 + 1u;
 #pragma unroll

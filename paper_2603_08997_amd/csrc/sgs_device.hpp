@@ -126,6 +126,19 @@ struct PlaneBuf {
     }
 };
 
+// Logical block index that gives each XCD a contiguous range of blocks. The
+// gfx950 dispatcher hands workgroups to its 8 XCDs round-robin (workgroup w to
+// XCD w % 8); with this mapping, blocks that write neighbouring addresses (the
+// columns of a digit-major histogram, adjacent digit runs of a radix scatter)
+// run on the same XCD, so partial cache lines merge in one L2 instead of being
+// written back by several. A bijection of [0, nblocks) whatever the dispatch.
+__device__ __forceinline__ int xcd_block(int wg, int nblocks) {
+    constexpr int kXcds = 8;
+    const int q = nblocks / kXcds, r = nblocks % kXcds;
+    const int x = wg % kXcds, k = wg / kXcds;
+    return x * q + min(x, r) + k;
+}
+
 __device__ __forceinline__ int floordiv(int a, int b) {
     const int q = a / b;
     return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;

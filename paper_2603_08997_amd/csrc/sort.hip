@@ -54,7 +54,10 @@ __global__ void __launch_bounds__(kThreads) radix_hist_kernel(const uint32_t* __
     __syncthreads();
     const uint32_t n = *n_dev;
     const uint32_t mask = (1u << bits) - 1u;
-    const int64_t base = (int64_t)blockIdx.x * kTile;
+    // the grid covers the capacity; the first ceil(n / kTile) workgroups work
+    const int active = (int)(((int64_t)n + kTile - 1) / kTile);
+    const int blk = (int)blockIdx.x < active ? xcd_block(blockIdx.x, active) : (int)blockIdx.x;
+    const int64_t base = (int64_t)blk * kTile;
     if (base < (int64_t)n) {
         const uint4* k4 = reinterpret_cast<const uint4*>(keys + base);
         const int64_t left = (int64_t)n - base;
@@ -89,7 +92,7 @@ __global__ void __launch_bounds__(kThreads) radix_hist_kernel(const uint32_t* __
     for (int k = 0; k < kHistCopies; ++k) total += cnt[k][tid];
     // only the rows of digits this pass can produce (each write is a separate
     // cache line of the digit-major table)
-    if (tid < (1 << bits)) hist[(int64_t)tid * nblocks + blockIdx.x] = total;
+    if (tid < (1 << bits)) hist[(int64_t)tid * nblocks + blk] = total;
 }
 
 // Exclusive scan of each digit row hist[d][0..nblocks) in place; totals[d] = row sum.
@@ -131,8 +134,10 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
     __shared__ uint32_t smem[kThreads / 64 + 1];
 
     const uint32_t n = *n_dev;
-    const int64_t base = (int64_t)blockIdx.x * kTile;
-    if (base >= (int64_t)n) return;  // uniform across the block
+    const int active = (int)(((int64_t)n + kTile - 1) / kTile);
+    if ((int)blockIdx.x >= active) return;  // uniform across the block
+    const int blk = xcd_block(blockIdx.x, active);
+    const int64_t base = (int64_t)blk * kTile;
     const int tid = threadIdx.x, w = tid / 64, lane = tid % 64;
     const uint32_t mask = (1u << bits) - 1u;
     const int nvalid = (int)min((int64_t)kTile, (int64_t)n - base);
@@ -151,7 +156,7 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
         uint32_t tot;
         const bool used = tid < (1 << bits);   // rows beyond 2^bits are not written
         const uint32_t ex = block_excl_scan<kThreads>(used ? totals[tid] : 0u, smem, &tot);
-        gbase[tid] = ex + (used ? hist[(int64_t)tid * nblocks + blockIdx.x] : 0u);
+        gbase[tid] = ex + (used ? hist[(int64_t)tid * nblocks + blk] : 0u);
     }
 #pragma unroll
     for (int k = 0; k < kWaves; ++k) wcnt[k][tid] = 0;
