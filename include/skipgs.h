@@ -91,7 +91,8 @@ typedef struct {
     float bg[3];             /* background colour, added with weight T_final        */
     float near_z;            /* camera depth <= near_z culls                        */
     float dilation;          /* Sigma2D += dilation * I (pixels^2)                  */
-    float alpha_min;         /* alpha' below this skips the Gaussian for the pixel  */
+    float alpha_min;         /* alpha' below this skips the Gaussian for the pixel; */
+                             /* 0 <= alpha_min <= alpha_max                         */
     float alpha_max;         /* alpha' = min(alpha_max, o exp(P))                   */
     float t_min;             /* stop before transmittance would fall below t_min   */
     float jac_clamp;         /* EWA Jacobian evaluated with tx/tz, ty/tz clamped to */

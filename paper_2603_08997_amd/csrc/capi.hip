@@ -44,7 +44,8 @@ sgs_status check_raster(const sgs_raster_params* rp) {
                     (rp->tile_w == 32 && rp->tile_h == 8);
     if (!ok) return fail(SGS_ERR_UNSUPPORTED, "tile shape %dx%d not in {16x16, 8x8, 32x8}",
                          rp->tile_w, rp->tile_h);
-    if (!(rp->alpha_max > 0.f && rp->alpha_max <= 1.f) || !(rp->alpha_min >= 0.f) ||
+    if (!(rp->alpha_max > 0.f && rp->alpha_max <= 1.f) ||
+        !(rp->alpha_min >= 0.f && rp->alpha_min <= rp->alpha_max) ||
         !(rp->t_min >= 0.f && rp->t_min < 1.f) || !(rp->near_z >= 0.f) || !(rp->dilation >= 0.f) ||
         !(rp->jac_clamp >= 0.f) || !std::isfinite(rp->bg[0]) || !std::isfinite(rp->bg[1]) ||
         !std::isfinite(rp->bg[2]))
@@ -165,6 +166,7 @@ RasterDev make_raster(const sgs_raster_params* rp) {
     r.alpha_min = rp->alpha_min;
     r.alpha_max = rp->alpha_max;
     r.t_min = rp->t_min;
+    r.log2_alpha_min = (float)std::log2((double)rp->alpha_min);
     return r;
 }
 

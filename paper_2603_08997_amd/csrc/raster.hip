@@ -1,20 +1,35 @@
 // Front-to-back compositing (paper Sec. 3, Eqs. 4-5) over the per-tile
 // depth-ordered lists, and its reverse-order adjoint.
 //
-// One wavefront (64 lanes) per tile; each lane owns TW*TH/64 pixels of the
-// tile (pixel k of lane l is tile-local index l + 64 k, so every per-pixel
-// load or store of the wave is a run of contiguous row segments). The tile's
-// list is staged through LDS 64 records at a time; every lane then walks the
-// batch with broadcast LDS reads, reusing each record for all its pixels.
+// One wavefront (64 lanes) per tile; lane l owns column l % TW of the tile
+// and the rows l / TW + k * 64 / TW, k < TW*TH/64 (pixel k of lane l is
+// tile-local index l + 64 k, so every per-pixel load or store of the wave is a
+// run of contiguous row segments). The tile's list is staged through LDS 64
+// records at a time; while staging, each lane turns one record into the
+// coefficients the inner loop needs. Every lane then walks the batch with
+// broadcast LDS reads.
+//
+// The exponent of Eq. 5 is evaluated in base 2 with the opacity folded in,
+// E = log2(o) + A dx^2 + B dx dy + C dy^2 (A = -a log2(e)/2, B = -b log2(e),
+// C = -c log2(e)/2), so that o exp(P) = 2^E. The part that depends on dx only
+// is formed once per lane and Gaussian (the lane's pixels share a column);
+// each pixel then costs two fused multiply-adds. A pixel takes part when it
+// lies in the overlap box (bit masks over the tile's columns and rows, formed
+// exactly in binary64 at staging), E >= log2(alpha_min) (alpha' >= alpha_min;
+// alpha_min <= alpha_max) and E <= log2(o) (P <= 0); only then is 2^E
+// evaluated. Forward and backward share these functions, so their skip
+// decisions agree bit for bit.
 //
 // The forward keeps, per pixel, only the final transmittance and the list
 // position of the last blended Gaussian. The backward walks the list again
 // from that position towards the front, recovering T_i = T_{i+1} / (1 -
-// alpha'_i) and the colour accumulated behind each Gaussian, so no per-pixel
-// blend list is stored. A Gaussian's gradient is summed over the lane's
-// pixels in registers, then over the 64 lanes with one DPP reduction, and one
-// lane issues the 9 hardware float atomics of that (tile, Gaussian) pair;
-// Gaussians that touch no pixel of the tile skip both.
+// alpha'_i) and, per pixel, G.S = sum over channels of dL/dC times the colour
+// accumulated behind the Gaussian, so no per-pixel blend list is stored. A
+// Gaussian's gradient is gathered per lane as moments of dL/dP over its
+// pixels, combined over the 64 lanes with DPP reductions, and one lane turns
+// them into the 9 parameter gradients and issues the hardware float atomics
+// of that (tile, Gaussian) pair; Gaussians that touch no pixel of the tile
+// skip both.
 #include "sgs_internal.hpp"
 #include "sgs_device.hpp"
 
@@ -23,37 +38,55 @@ namespace sgs {
 namespace {
 
 constexpr int kLanes = 64;
+constexpr float kNegHalfLog2e = -0.721347520444481703680f;  // -log2(e) / 2
+constexpr float kNegLog2e = -1.44269504088896340736f;       // -log2(e)
 
-struct Splat {
-    float alpha;           // alpha' after the clamp
-    float ex;              // exp(P)
-    float dx, dy;          // pixel centre - mean
-    float dx2, dy2, dxy;   // dx^2, dy^2, dx dy
-    bool clamped;          // o exp(P) > alpha_max
+// Bit q set iff the pixel origin + q (centre origin + q + 0.5) of an n-pixel
+// tile span lies in the overlap box |p - centre| <= r. In binary64 every
+// step is exact for float inputs, so this is the box test of the reals.
+__device__ __forceinline__ uint32_t box_mask(float centre, float r, int origin, int n) {
+    const double lo = ceil((double)centre - (double)r - 0.5) - (double)origin;
+    const double hi = floor((double)centre + (double)r - 0.5) - (double)origin;
+    const double l = fmax(lo, 0.0), h = fmin(hi, (double)(n - 1));
+    if (!(l <= h)) return 0u;
+    return (0xffffffffu >> (31 - (int)h)) & (0xffffffffu << (int)l);
+}
+
+// Staged record of one list entry for one tile: geo = (u, v, A, B), aux = (C,
+// log2 o, column mask bits, row mask bits).
+__device__ __forceinline__ void stage_entry(const float4& r0, const float4& r1, int x0, int y0,
+                                            int tw, int th, float4& geo, float4& aux) {
+    geo = make_float4(r0.x, r0.y, r0.z * kNegHalfLog2e, r0.w * kNegLog2e);
+    aux = make_float4(r1.x * kNegHalfLog2e, __builtin_amdgcn_logf(r1.y),
+                      __uint_as_float(box_mask(r0.x, r1.z, x0, tw)),
+                      __uint_as_float(box_mask(r0.y, r1.w, y0, th)));
+}
+
+// Per lane and Gaussian: the dx-only part of E and the box bits of the
+// lane's pixels (bit RS*k for pixel k).
+struct LaneTerms {
+    float dx, bx, base;
+    uint32_t m;
 };
 
-// Overlap test, Gaussian falloff and alpha' of one (pixel, Gaussian) pair.
-// Forward and backward call this same function, so their skip decisions agree
-// bit for bit. Branch-free: every quantity is computed and the return value
-// says whether the Gaussian contributes. P = -(a dx^2 + c dy^2)/2 - b dx dy
-// with explicit fused multiply-adds; exp(P) is the hardware 2^x of P log2(e)
-// (about 2 ulp over the range where alpha' can reach alpha_min).
-__device__ __forceinline__ bool splat_alpha(float px, float py, float u, float v, float rx,
-                                            float ry, float o, float a, float b, float c,
-                                            const RasterDev& rp, Splat& s) {
-    // overlap box |p - mean| <= (rx, ry); p +- r is exact for half-integer p, integer r
-    const bool inbox = (px - rx <= u) & (u <= px + rx) & (py - ry <= v) & (v <= py + ry);
-    s.dx = px - u;
-    s.dy = py - v;
-    s.dx2 = s.dx * s.dx;
-    s.dy2 = s.dy * s.dy;
-    s.dxy = s.dx * s.dy;
-    const float power = fmaf(-0.5f, fmaf(a, s.dx2, c * s.dy2), -b * s.dxy);
-    s.ex = __builtin_amdgcn_exp2f(power * 1.44269504088896341f);
-    const float raw = o * s.ex;
-    s.clamped = raw > rp.alpha_max;
-    s.alpha = s.clamped ? rp.alpha_max : raw;
-    return inbox & (power <= 0.f) & (s.alpha >= rp.alpha_min);
+__device__ __forceinline__ LaneTerms lane_terms(const float4& geo, const float4& aux, float px,
+                                                int col, int row0) {
+    LaneTerms t;
+    t.dx = px - geo.x;
+    t.base = fmaf(geo.z * t.dx, t.dx, aux.y);
+    t.bx = geo.w * t.dx;
+    const uint32_t inx = (__float_as_uint(aux.z) >> col) & 1u;
+    t.m = inx ? (__float_as_uint(aux.w) >> row0) : 0u;
+    return t;
+}
+
+// E at the pixel row offset dy = py - v.
+__device__ __forceinline__ float exponent2(const LaneTerms& t, const float4& aux, float dy) {
+    return fmaf(dy, fmaf(aux.x, dy, t.bx), t.base);
+}
+
+__device__ __forceinline__ bool takes_part(bool in_box, float e, const float4& aux, float lmin) {
+    return in_box & (e >= lmin) & (e <= aux.y);
 }
 
 __device__ __forceinline__ int view_of_tile(const Views& views, int tile) {
@@ -81,8 +114,9 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
     float* __restrict__ out_rgb, float* __restrict__ t_final, uint32_t* __restrict__ n_last,
     uint32_t* __restrict__ counters) {
     constexpr int PIX = TW * TH / kLanes;
-    __shared__ float4 s_pos[kLanes];   // u, v, rx, ry
-    __shared__ float4 s_con[kLanes];   // a, b, c, opacity
+    constexpr int RS = kLanes / TW;   // row step between a lane's pixels
+    __shared__ float4 s_geo[kLanes];
+    __shared__ float4 s_aux[kLanes];
     __shared__ float4 s_col[kLanes];   // r, g, b, -
 
     const int tile = blockIdx.x;
@@ -90,76 +124,74 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
     const int local = tile - V.tile_offset;
     const int tx = local % V.tiles_x, ty = local / V.tiles_x;
     const int tid = threadIdx.x;
+    const int col = tid % TW, row0 = tid / TW;
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+    const float lmin = rp.log2_alpha_min, amax = rp.alpha_max, tmin = rp.t_min;
 
-    float px[PIX], py[PIX], T[PIX], C0[PIX], C1[PIX], C2[PIX];
+    const float px = (float)(tx * TW + col) + 0.5f;
+    float py[PIX], T[PIX], C0[PIX], C1[PIX], C2[PIX];
     uint32_t last[PIX];
-    bool done[PIX], inside[PIX];
-    bool lane_done = true;
+    uint32_t live = 0;   // bit RS*k: pixel k is in the view and has not stopped
 #pragma unroll
     for (int k = 0; k < PIX; ++k) {
-        const int li = tid + kLanes * k;
-        const int x = tx * TW + li % TW, y = ty * TH + li / TW;
-        inside[k] = x < V.width && y < V.height;
-        px[k] = (float)x + 0.5f;
+        const int y = ty * TH + row0 + RS * k;
         py[k] = (float)y + 0.5f;
         T[k] = 1.f;
         C0[k] = C1[k] = C2[k] = 0.f;
         last[k] = 0;
-        done[k] = !inside[k];
-        lane_done = lane_done && done[k];
+        if (tx * TW + col < V.width && y < V.height) live |= 1u << (RS * k);
     }
     uint32_t n_blend = 0, n_eval = 0;
     for (uint32_t b0 = start; b0 < end; b0 += kLanes) {
-        if (ballot(!lane_done) == 0) break;
+        if (ballot(live != 0u) == 0) break;
         __syncthreads();
         const uint32_t idx = b0 + tid;
         if (idx < end) {
             const int64_t e = pentry[idx];
-            const float4 r0 = rec[3 * e], r1 = rec[3 * e + 1], r2 = rec[3 * e + 2];
-            s_pos[tid] = make_float4(r0.x, r0.y, r1.z, r1.w);
-            s_con[tid] = make_float4(r0.z, r0.w, r1.x, r1.y);
-            s_col[tid] = r2;
+            const float4 r0 = rec[3 * e], r1 = rec[3 * e + 1];
+            stage_entry(r0, r1, tx * TW, ty * TH, TW, TH, s_geo[tid], s_aux[tid]);
+            s_col[tid] = rec[3 * e + 2];
         }
         __syncthreads();
         const int cnt = (int)min((uint32_t)kLanes, end - b0);
-        for (int j = 0; j < cnt && !lane_done; ++j) {
-            const float4 P = s_pos[j];
-            const float4 Q = s_con[j];
-            lane_done = true;
+        for (int j = 0; j < cnt && live != 0u; ++j) {
+            const float4 G = s_geo[j];
+            const float4 X = s_aux[j];
+            const LaneTerms L = lane_terms(G, X, px, col, row0);
+            const uint32_t m = L.m & live;
             const uint32_t pos = b0 + (uint32_t)j + 1u - start;
+            n_eval += (uint32_t)__builtin_popcount(live);
 #pragma unroll
             for (int k = 0; k < PIX; ++k) {
-                n_eval += done[k] ? 0u : 1u;
-                Splat s;
-                const bool hit =
-                    !done[k] & splat_alpha(px[k], py[k], P.x, P.y, P.z, P.w, Q.w, Q.x, Q.y, Q.z, rp, s);
-                if (hit) {
+                const float e = exponent2(L, X, py[k] - G.y);
+                if (takes_part(((m >> (RS * k)) & 1u) != 0u, e, X, lmin)) {
                     // a pixel whose transmittance would fall below t_min stops
                     // before this Gaussian; otherwise the Gaussian is blended
-                    const float test = T[k] * (1.f - s.alpha);
-                    const bool stop = test < rp.t_min;
-                    const float4 col = s_col[j];
-                    const float w = stop ? 0.f : s.alpha * T[k];
-                    C0[k] = fmaf(col.x, w, C0[k]);
-                    C1[k] = fmaf(col.y, w, C1[k]);
-                    C2[k] = fmaf(col.z, w, C2[k]);
-                    T[k] = stop ? T[k] : test;
+                    const float alpha = fminf(__builtin_amdgcn_exp2f(e), amax);
+                    const float w = alpha * T[k];
+                    const float tn = T[k] - w;
+                    const bool stop = tn < tmin;
+                    const float4 c = s_col[j];
+                    const float wv = stop ? 0.f : w;
+                    C0[k] = fmaf(c.x, wv, C0[k]);
+                    C1[k] = fmaf(c.y, wv, C1[k]);
+                    C2[k] = fmaf(c.z, wv, C2[k]);
+                    T[k] = stop ? T[k] : tn;
                     last[k] = stop ? last[k] : pos;
                     n_blend += stop ? 0u : 1u;
-                    done[k] = stop;
+                    live &= stop ? ~(1u << (RS * k)) : ~0u;
                 }
-                lane_done = lane_done & done[k];
             }
         }
     }
     const int64_t plane = (int64_t)V.width * V.height;
     float* img = out_rgb + 3 * V.px_offset;
+    const int x = tx * TW + col;
 #pragma unroll
     for (int k = 0; k < PIX; ++k) {
-        if (!inside[k]) continue;
-        const int li = tid + kLanes * k;
-        const int64_t pix = (int64_t)(ty * TH + li / TW) * V.width + (tx * TW + li % TW);
+        const int y = ty * TH + row0 + RS * k;
+        if (x >= V.width || y >= V.height) continue;
+        const int64_t pix = (int64_t)y * V.width + x;
         img[pix] = fmaf(T[k], rp.bg[0], C0[k]);
         img[plane + pix] = fmaf(T[k], rp.bg[1], C1[k]);
         img[2 * plane + pix] = fmaf(T[k], rp.bg[2], C2[k]);
@@ -179,6 +211,14 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
 // At most 72 VGPRs, so that 7 waves fit on each SIMD: the 6700 tiles of a
 // 1600x1060 view (16x16 tiles) then all run at once on the 1024 SIMDs of the
 // chip instead of leaving a second round for the last tiles.
+//
+// Gradient of one (tile, Gaussian) pair from per-lane moments of dL/dP over
+// the lane's pixels (dP = dL/dP, dy per pixel, dx per lane): with
+// P = -(a dx^2 + c dy^2)/2 - b dx dy, dx = px - u, dy = py - v,
+//   dL/du = a M1 + b M2,  dL/dv = b M1 + c M2,  dL/da = -M3/2,
+//   dL/db = -M4,  dL/dc = -M5/2,  dL/do = M6 / o  (unclamped alpha' = o e^P),
+// M1 = sum dP dx, M2 = sum dP dy, M3 = sum dP dx^2, M4 = sum dP dx dy,
+// M5 = sum dP dy^2, M6 = sum dP.
 template <int TW, int TH>
 __global__ void __launch_bounds__(kLanes, 7) raster_backward_kernel(
     Views views, RasterDev rp, const uint32_t* __restrict__ ranges,
@@ -187,9 +227,11 @@ __global__ void __launch_bounds__(kLanes, 7) raster_backward_kernel(
     const float* __restrict__ dl_drgb, const int32_t* __restrict__ gate,
     float* __restrict__ accum) {
     constexpr int PIX = TW * TH / kLanes;
-    __shared__ float4 s_pos[kLanes];   // u, v, rx, ry
-    __shared__ float4 s_con[kLanes];   // a, b, c, opacity
+    constexpr int RS = kLanes / TW;
+    __shared__ float4 s_geo[kLanes];
+    __shared__ float4 s_aux[kLanes];
     __shared__ float4 s_col[kLanes];   // r, g, b, entry (bits)
+    __shared__ float4 s_con[kLanes];   // a, b, c, 1 / o
     if (gate_closed(gate)) return;
 
     const int tile = blockIdx.x;
@@ -197,18 +239,20 @@ __global__ void __launch_bounds__(kLanes, 7) raster_backward_kernel(
     const int local = tile - V.tile_offset;
     const int tx = local % V.tiles_x, ty = local / V.tiles_x;
     const int tid = threadIdx.x;
+    const int col = tid % TW, row0 = tid / TW;
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+    const float lmin = rp.log2_alpha_min, amax = rp.alpha_max;
 
     const int64_t plane = (int64_t)V.width * V.height;
     const float* dl = dl_drgb + 3 * V.px_offset;
-    float px[PIX], py[PIX], T[PIX], G0[PIX], G1[PIX], G2[PIX], S0[PIX], S1[PIX], S2[PIX];
+    const int x = tx * TW + col;
+    const float px = (float)x + 0.5f;
+    float py[PIX], T[PIX], G0[PIX], G1[PIX], G2[PIX], GS[PIX];
     uint32_t last[PIX];
     uint32_t my_max = 0;
 #pragma unroll
     for (int k = 0; k < PIX; ++k) {
-        const int li = tid + kLanes * k;
-        const int x = tx * TW + li % TW, y = ty * TH + li / TW;
-        px[k] = (float)x + 0.5f;
+        const int y = ty * TH + row0 + RS * k;
         py[k] = (float)y + 0.5f;
         T[k] = 1.f;
         G0[k] = G1[k] = G2[k] = 0.f;
@@ -221,10 +265,8 @@ __global__ void __launch_bounds__(kLanes, 7) raster_backward_kernel(
             T[k] = t_final[V.px_offset + pix];
             last[k] = n_last[V.px_offset + pix];
         }
-        // colour composited behind the current Gaussian, background included
-        S0[k] = rp.bg[0] * T[k];
-        S1[k] = rp.bg[1] * T[k];
-        S2[k] = rp.bg[2] * T[k];
+        // dL/dC . (colour composited behind the current Gaussian), background included
+        GS[k] = fmaf(G0[k], rp.bg[0], fmaf(G1[k], rp.bg[1], G2[k] * rp.bg[2])) * T[k];
         my_max = max(my_max, last[k]);
     }
     const uint32_t stop = start + min(wave_max_u32(my_max), end - start);
@@ -238,77 +280,76 @@ __global__ void __launch_bounds__(kLanes, 7) raster_backward_kernel(
             const uint32_t e = pentry[idx];
             const float4 r0 = rec[3 * (int64_t)e], r1 = rec[3 * (int64_t)e + 1],
                          r2 = rec[3 * (int64_t)e + 2];
-            s_pos[tid] = make_float4(r0.x, r0.y, r1.z, r1.w);
-            s_con[tid] = make_float4(r0.z, r0.w, r1.x, r1.y);
+            stage_entry(r0, r1, tx * TW, ty * TH, TW, TH, s_geo[tid], s_aux[tid]);
             s_col[tid] = make_float4(r2.x, r2.y, r2.z, __uint_as_float(e));
+            // 1/o capped at FLT_MAX: an opacity that underflowed to 0 can only
+            // take part with alpha' = 0 (alpha_min = 0), where M6 = 0
+            s_con[tid] = make_float4(r0.z, r0.w, r1.x, fminf(1.f / r1.y, 3.402823466e38f));
         }
         __syncthreads();
         for (int j = 0; j < cnt; ++j) {
             const uint32_t rel = b_end - 1u - (uint32_t)j - start;   // list position
+            const float4 G = s_geo[j];
+            const float4 X = s_aux[j];
+            const LaneTerms L = lane_terms(G, X, px, col, row0);
             // -0 is the additive identity for every float, so the first
             // accumulation into each sum folds away
-            float d_u = -0.f, d_v = -0.f, d_a = -0.f, d_b = -0.f, d_c = -0.f, d_o = -0.f;
-            float d_r = -0.f, d_g = -0.f, d_bl = -0.f;
+            float sdp = -0.f, sdy = -0.f, sdy2 = -0.f, d_r = -0.f, d_g = -0.f, d_bl = -0.f;
             bool contrib = false;
-            const float4 P = s_pos[j];
-            const float4 Q = s_con[j];
 #pragma unroll
             for (int k = 0; k < PIX; ++k) {
-                Splat s;
-                const bool hit = (rel < last[k]) &
-                                 splat_alpha(px[k], py[k], P.x, P.y, P.z, P.w, Q.w, Q.x, Q.y, Q.z, rp, s);
-                if (hit) {
-                    const float4 col = s_col[j];
+                const float dy = py[k] - G.y;
+                const float e = exponent2(L, X, dy);
+                if ((rel < last[k]) & takes_part(((L.m >> (RS * k)) & 1u) != 0u, e, X, lmin)) {
+                    const float raw = __builtin_amdgcn_exp2f(e);
+                    const bool clamped = raw > amax;
+                    const float alpha = clamped ? amax : raw;
                     // 1 - alpha' >= 1 - alpha_max > 0: one hardware reciprocal
                     // (1 ulp) serves the transmittance recovery and dC/dalpha'
-                    const float inv_om = __builtin_amdgcn_rcpf(1.f - s.alpha);
+                    const float inv_om = __builtin_amdgcn_rcpf(1.f - alpha);
                     const float Ti = T[k] * inv_om;
-                    const float w = s.alpha * Ti;
+                    const float w = alpha * Ti;
+                    const float4 c = s_col[j];
                     d_r = fmaf(G0[k], w, d_r);
                     d_g = fmaf(G1[k], w, d_g);
                     d_bl = fmaf(G2[k], w, d_bl);
-                    // dC/dalpha' = T_i c_i - S_i / (1 - alpha'_i), per channel
-                    const float d_alpha =
-                        fmaf(G0[k], fmaf(col.x, Ti, -S0[k] * inv_om),
-                             fmaf(G1[k], fmaf(col.y, Ti, -S1[k] * inv_om),
-                                  G2[k] * fmaf(col.z, Ti, -S2[k] * inv_om)));
-                    S0[k] = fmaf(col.x, w, S0[k]);
-                    S1[k] = fmaf(col.y, w, S1[k]);
-                    S2[k] = fmaf(col.z, w, S2[k]);
+                    // dL/dalpha' = T_i (dL/dC . c_i) - (dL/dC . S_i) / (1 - alpha'_i)
+                    const float gc = fmaf(G0[k], c.x, fmaf(G1[k], c.y, G2[k] * c.z));
+                    const float d_alpha = fmaf(Ti, gc, -(inv_om * GS[k]));
+                    GS[k] = fmaf(w, gc, GS[k]);
                     T[k] = Ti;
                     // alpha' = o exp(P) unless clamped at alpha_max (then it
                     // depends on neither o nor the geometry); dalpha'/dP = alpha'
-                    const float dA = s.clamped ? 0.f : d_alpha;
-                    const float dP = dA * s.alpha;
-                    const float hP = -0.5f * dP;
-                    d_o = fmaf(dA, s.ex, d_o);
-                    d_a = fmaf(hP, s.dx2, d_a);
-                    d_b = fmaf(-dP, s.dxy, d_b);
-                    d_c = fmaf(hP, s.dy2, d_c);
-                    // dP/du = a dx + b dy, dP/dv = b dx + c dy
-                    d_u = fmaf(dP, fmaf(Q.x, s.dx, Q.y * s.dy), d_u);
-                    d_v = fmaf(dP, fmaf(Q.y, s.dx, Q.z * s.dy), d_v);
+                    const float dP = clamped ? 0.f : d_alpha * alpha;
+                    sdp += dP;
+                    const float t = dP * dy;
+                    sdy += t;
+                    sdy2 = fmaf(t, dy, sdy2);
                     contrib = true;
                 }
             }
             if (ballot(contrib) == 0) continue;
-            d_u = wave_sum_to_lane63(d_u);
-            d_v = wave_sum_to_lane63(d_v);
-            d_a = wave_sum_to_lane63(d_a);
-            d_b = wave_sum_to_lane63(d_b);
-            d_c = wave_sum_to_lane63(d_c);
-            d_o = wave_sum_to_lane63(d_o);
+            float m1 = L.dx * sdp;
+            float m3 = L.dx * m1;
+            float m4 = L.dx * sdy;
+            m1 = wave_sum_to_lane63(m1);
+            const float m2 = wave_sum_to_lane63(sdy);
+            m3 = wave_sum_to_lane63(m3);
+            m4 = wave_sum_to_lane63(m4);
+            const float m5 = wave_sum_to_lane63(sdy2);
+            const float m6 = wave_sum_to_lane63(sdp);
             d_r = wave_sum_to_lane63(d_r);
             d_g = wave_sum_to_lane63(d_g);
             d_bl = wave_sum_to_lane63(d_bl);
             if (tid == 63) {
+                const float4 Q = s_con[j];
                 float* acc = accum + (int64_t)kAccumFloats * __float_as_uint(s_col[j].w);
-                unsafeAtomicAdd(acc + 0, d_u);
-                unsafeAtomicAdd(acc + 1, d_v);
-                unsafeAtomicAdd(acc + 2, d_a);
-                unsafeAtomicAdd(acc + 3, d_b);
-                unsafeAtomicAdd(acc + 4, d_c);
-                unsafeAtomicAdd(acc + 5, d_o);
+                unsafeAtomicAdd(acc + 0, fmaf(Q.x, m1, Q.y * m2));
+                unsafeAtomicAdd(acc + 1, fmaf(Q.y, m1, Q.z * m2));
+                unsafeAtomicAdd(acc + 2, -0.5f * m3);
+                unsafeAtomicAdd(acc + 3, -m4);
+                unsafeAtomicAdd(acc + 4, -0.5f * m5);
+                unsafeAtomicAdd(acc + 5, Q.w * m6);
                 unsafeAtomicAdd(acc + 6, d_r);
                 unsafeAtomicAdd(acc + 7, d_g);
                 unsafeAtomicAdd(acc + 8, d_bl);

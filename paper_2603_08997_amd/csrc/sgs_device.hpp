@@ -20,16 +20,20 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 __device__ __forceinline__ int popc64(uint64_t m) { return __popcll(m); }
 
-// Sum over the 64 lanes of a wave, result valid in lane 63. DPP steps:
-// xor 1, xor 2 (quad permutes), rotate 4 and 8 within rows of 16, then the
-// row broadcasts of lane 15 and lane 31 (gfx9 wave64).
+// Sum over the 64 lanes of a wave, result valid in lane 63 only. DPP steps:
+// xor 1, xor 2 (quad permutes), rotate 4 and 8 within rows of 16 (every lane
+// then holds its row's sum), then lane 15 of each row added into the next
+// row and lane 31 into rows 2 and 3 (gfx9 wave64 row broadcasts). The
+// broadcasts run on every row, so rows 0-2 end with partial or repeated sums,
+// but lane 63 receives R3 + R2 and then R1 + R0 from lane 31; with full row
+// masks each step is one fused add.
 __device__ __forceinline__ float wave_sum_to_lane63(float v) {
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xb1, 0xf, 0xf, false));
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4e, 0xf, 0xf, false));
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xf, 0xf, false));
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, false));
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xa, 0xf, false));
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xc, 0xf, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xf, 0xf, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xf, 0xf, false));
     return v;
 }
 

@@ -39,6 +39,7 @@ struct RasterDev {
     int32_t tile_w, tile_h;
     float bg[3];
     float near_z, dilation, alpha_min, alpha_max, t_min;
+    float log2_alpha_min;  // log2(alpha_min), rounded from binary64 (-inf for 0)
 };
 
 // Adam constants: beta and 1 - beta formed in binary64, then rounded.
