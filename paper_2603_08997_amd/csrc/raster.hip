@@ -89,6 +89,10 @@ __device__ __forceinline__ bool takes_part(bool in_box, float e, const float4& a
     return in_box & (e >= lmin) & (e <= aux.y);
 }
 
+__device__ __forceinline__ float lane63(float v) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 __device__ __forceinline__ int view_of_tile(const Views& views, int tile) {
     int vi = 0;
     while (vi + 1 < views.n && tile >= views.v[vi + 1].tile_offset) ++vi;
@@ -341,19 +345,23 @@ __global__ void __launch_bounds__(kLanes, 7) raster_backward_kernel(
             d_r = wave_sum_to_lane63(d_r);
             d_g = wave_sum_to_lane63(d_g);
             d_bl = wave_sum_to_lane63(d_bl);
-            if (tid == 63) {
-                const float4 Q = s_con[j];
-                float* acc = accum + (int64_t)kAccumFloats * __float_as_uint(s_col[j].w);
-                unsafeAtomicAdd(acc + 0, fmaf(Q.x, m1, Q.y * m2));
-                unsafeAtomicAdd(acc + 1, fmaf(Q.y, m1, Q.z * m2));
-                unsafeAtomicAdd(acc + 2, -0.5f * m3);
-                unsafeAtomicAdd(acc + 3, -m4);
-                unsafeAtomicAdd(acc + 4, -0.5f * m5);
-                unsafeAtomicAdd(acc + 5, Q.w * m6);
-                unsafeAtomicAdd(acc + 6, d_r);
-                unsafeAtomicAdd(acc + 7, d_g);
-                unsafeAtomicAdd(acc + 8, d_bl);
-            }
+            // the sums live in lane 63; lane k < 9 adds gradient k, so the
+            // pair's 9 atomics go out as one instruction over contiguous floats
+            const float M1 = lane63(m1), M2 = lane63(m2), M3 = lane63(m3), M4 = lane63(m4);
+            const float M5 = lane63(m5), M6 = lane63(m6);
+            const float R = lane63(d_r), Gr = lane63(d_g), Bl = lane63(d_bl);
+            const float4 Q = s_con[j];
+            float g = Bl;
+            g = tid == 7 ? Gr : g;
+            g = tid == 6 ? R : g;
+            g = tid == 5 ? Q.w * M6 : g;
+            g = tid == 4 ? -0.5f * M5 : g;
+            g = tid == 3 ? -M4 : g;
+            g = tid == 2 ? -0.5f * M3 : g;
+            g = tid == 1 ? fmaf(Q.y, M1, Q.z * M2) : g;
+            g = tid == 0 ? fmaf(Q.x, M1, Q.y * M2) : g;
+            if (tid < 9)
+                unsafeAtomicAdd(accum + (int64_t)kAccumFloats * __float_as_uint(s_col[j].w) + tid, g);
         }
         b_end = b0;
     }
