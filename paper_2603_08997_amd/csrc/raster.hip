@@ -89,8 +89,53 @@ __device__ __forceinline__ bool takes_part(bool in_box, float e, const float4& a
     return in_box & (e >= lmin) & (e <= aux.y);
 }
 
-__device__ __forceinline__ float lane63(float v) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+template <int kCtrl>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xf, 0xf, false));
+}
+
+// One exchange step of the reduce-scatter: lanes with `hi` set keep b and
+// send a, the others keep a and send b; the kept value adds what the partner
+// lane (the DPP source, which differs in that bit) sent, the sum of the same
+// value over both lanes.
+template <int kCtrl>
+__device__ __forceinline__ float rs_step(float a, float b, bool hi) {
+    const float keep = hi ? b : a, send = hi ? a : b;
+    return keep + dpp_f<kCtrl>(send);
+}
+
+// x + x of the lane 16 (permlane16 swap) or 32 (permlane32 swap) apart.
+__device__ __forceinline__ float xrow16(float x) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false,
+                                                    false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float xrow32(float x) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false,
+                                                    false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Sums of x[0..8] over the 64 lanes of a (fully active) wave. Returns, in
+// lane l, the total of x[l % 8]; *t8 gets the total of x[8] in every lane.
+// Bits 0, 1, 2 of the lane pick, in three halving exchanges (xor 1, xor 2,
+// rotate by 4 within the row), which of the eight values the lane keeps; a
+// rotate by 8 completes the row sums and two permlane swaps add the rows.
+__device__ __forceinline__ float wave_sum9_scatter(const float (&x)[9], int lane, float* t8) {
+    const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
+    float y[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) y[k] = rs_step<0xb1>(x[2 * k], x[2 * k + 1], b0);   // xor 1
+    float s = x[8] + dpp_f<0xb1>(x[8]);
+    const float z0 = rs_step<0x4e>(y[0], y[1], b1), z1 = rs_step<0x4e>(y[2], y[3], b1);  // xor 2
+    s += dpp_f<0x4e>(s);
+    float w = rs_step<0x124>(z0, z1, b2);   // row rotate 4: the source lane differs in bit 2
+    s += dpp_f<0x124>(s);
+    w += dpp_f<0x128>(w);                   // row rotate 8: same bits 0-2, the other half-row
+    s += dpp_f<0x128>(s);
+    w = xrow32(xrow16(w));
+    *t8 = xrow32(xrow16(s));
+    return w;
 }
 
 __device__ __forceinline__ int view_of_tile(const Views& views, int tile) {
@@ -333,35 +378,27 @@ __global__ void __launch_bounds__(kLanes, 7) raster_backward_kernel(
                 }
             }
             if (ballot(contrib) == 0) continue;
-            float m1 = L.dx * sdp;
-            float m3 = L.dx * m1;
-            float m4 = L.dx * sdy;
-            m1 = wave_sum_to_lane63(m1);
-            const float m2 = wave_sum_to_lane63(sdy);
-            m3 = wave_sum_to_lane63(m3);
-            m4 = wave_sum_to_lane63(m4);
-            const float m5 = wave_sum_to_lane63(sdy2);
-            const float m6 = wave_sum_to_lane63(sdp);
-            d_r = wave_sum_to_lane63(d_r);
-            d_g = wave_sum_to_lane63(d_g);
-            d_bl = wave_sum_to_lane63(d_bl);
-            // the sums live in lane 63; lane k < 9 adds gradient k, so the
-            // pair's 9 atomics go out as one instruction over contiguous floats
-            const float M1 = lane63(m1), M2 = lane63(m2), M3 = lane63(m3), M4 = lane63(m4);
-            const float M5 = lane63(m5), M6 = lane63(m6);
-            const float R = lane63(d_r), Gr = lane63(d_g), Bl = lane63(d_bl);
+            // per-lane parameter gradients (the moments scaled by the
+            // Gaussian's a, b, c, 1/o), summed over the wave reduce-scatter
+            // style: lane k < 8 ends with the total of gradient k, every lane
+            // with the total of gradient 8; one atomic instruction adds all 9
             const float4 Q = s_con[j];
-            float g = Bl;
-            g = tid == 7 ? Gr : g;
-            g = tid == 6 ? R : g;
-            g = tid == 5 ? Q.w * M6 : g;
-            g = tid == 4 ? -0.5f * M5 : g;
-            g = tid == 3 ? -M4 : g;
-            g = tid == 2 ? -0.5f * M3 : g;
-            g = tid == 1 ? fmaf(Q.y, M1, Q.z * M2) : g;
-            g = tid == 0 ? fmaf(Q.x, M1, Q.y * M2) : g;
+            const float m1 = L.dx * sdp;
+            float x[9];
+            x[0] = fmaf(Q.x, m1, Q.y * sdy);   // dL/du
+            x[1] = fmaf(Q.y, m1, Q.z * sdy);   // dL/dv
+            x[2] = (-0.5f * L.dx) * m1;        // dL/da
+            x[3] = -(L.dx * sdy);              // dL/db
+            x[4] = -0.5f * sdy2;               // dL/dc
+            x[5] = Q.w * sdp;                  // dL/do
+            x[6] = d_r;
+            x[7] = d_g;
+            x[8] = d_bl;
+            float t8;
+            const float t = wave_sum9_scatter(x, tid, &t8);
             if (tid < 9)
-                unsafeAtomicAdd(accum + (int64_t)kAccumFloats * __float_as_uint(s_col[j].w) + tid, g);
+                unsafeAtomicAdd(accum + (int64_t)kAccumFloats * __float_as_uint(s_col[j].w) + tid,
+                                tid == 8 ? t8 : t);
         }
         b_end = b0;
     }
