@@ -326,6 +326,34 @@ __global__ void __launch_bounds__(256) ranges_kernel(const uint32_t* __restrict_
     ranges[2 * t + 1] = empty ? 0u : lo;
 }
 
+// Counting sort of the tiles by cost >> shift, largest first, in one
+// workgroup: bucket counts in LDS, their exclusive scan, then every tile takes
+// the next slot of its bucket.
+constexpr int kOrderThreads = 1024;
+__global__ void __launch_bounds__(kOrderThreads) order_tiles_kernel(
+    const uint32_t* __restrict__ cost, int64_t tiles, int shift, uint32_t* __restrict__ order,
+    const int32_t* __restrict__ gate) {
+    if (gate != nullptr && gate_closed(gate)) return;
+    __shared__ uint32_t slot[kOrderThreads];
+    __shared__ uint32_t smem[kOrderThreads / 64 + 1];
+    const int tid = threadIdx.x;
+    auto bucket = [&](int64_t t) {
+        return (uint32_t)(kOrderThreads - 1) - min(cost[t] >> shift, (uint32_t)(kOrderThreads - 1));
+    };
+    slot[tid] = 0;
+    __syncthreads();
+    for (int64_t t = tid; t < tiles; t += kOrderThreads) atomicAdd(&slot[bucket(t)], 1u);
+    __syncthreads();
+    const uint32_t c = slot[tid];
+    uint32_t tot;
+    const uint32_t first = block_excl_scan<kOrderThreads>(c, smem, &tot);
+    __syncthreads();
+    slot[tid] = first;
+    __syncthreads();
+    for (int64_t t = tid; t < tiles; t += kOrderThreads)
+        order[atomicAdd(&slot[bucket(t)], 1u)] = (uint32_t)t;
+}
+
 __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -399,6 +427,14 @@ hipError_t launch_bin(const Views& views, const RasterDev& rp, int64_t n, const 
     if (L.total_tiles > 0)
         hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((L.total_tiles + 255) / 256)), dim3(256),
                            0, s, ptile[L.tile_result], counters, L.total_tiles, ranges);
+    return hipGetLastError();
+}
+
+hipError_t launch_order_tiles(const uint32_t* cost, int64_t tiles, int shift, uint32_t* order,
+                              const int32_t* gate, hipStream_t s) {
+    if (tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(order_tiles_kernel, dim3(1), dim3(kOrderThreads), 0, s, cost, tiles, shift,
+                       order, gate);
     return hipGetLastError();
 }
 

@@ -209,6 +209,8 @@ void make_layout(const Views& views, int64_t n, int64_t capacity, Layout* L) {
     L->sort_hist = take(sizeof(uint32_t) * 256 * (size_t)L->sort_blocks);
     L->sort_totals = take(sizeof(uint32_t) * 256);
     L->ranges = take(sizeof(uint32_t) * 2 * (size_t)L->total_tiles);
+    L->tile_cost = take(sizeof(uint32_t) * (size_t)L->total_tiles);
+    L->tile_order = take(sizeof(uint32_t) * (size_t)L->total_tiles);
     L->t_final = take(sizeof(float) * (size_t)L->total_pixels);
     L->n_last = take(sizeof(uint32_t) * (size_t)L->total_pixels);
     L->total = off;

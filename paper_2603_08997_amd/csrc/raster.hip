@@ -30,6 +30,12 @@
 // them into the 9 parameter gradients and issues the hardware float atomics
 // of that (tile, Gaussian) pair; Gaussians that touch no pixel of the tile
 // skip both.
+//
+// All tiles of a launch are resident at once, so a launch lasts as long as
+// its busiest SIMD. The forward records each tile's work for the backward
+// (the longest prefix of the list any pixel blends), and the backward takes
+// the tiles in decreasing order of it: consecutive workgroups land on
+// different SIMDs, so every SIMD gets a mix of long and short tiles.
 #include "sgs_internal.hpp"
 #include "sgs_device.hpp"
 
@@ -161,7 +167,7 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
     Views views, RasterDev rp, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ pentry, const float4* __restrict__ rec,
     float* __restrict__ out_rgb, float* __restrict__ t_final, uint32_t* __restrict__ n_last,
-    uint32_t* __restrict__ counters) {
+    uint32_t* __restrict__ counters, uint32_t* __restrict__ tile_cost) {
     constexpr int PIX = TW * TH / kLanes;
     constexpr int RS = kLanes / TW;   // row step between a lane's pixels
     __shared__ float4 s_geo[kLanes];
@@ -203,9 +209,15 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
         }
         __syncthreads();
         const int cnt = (int)min((uint32_t)kLanes, end - b0);
+        // the next entry's LDS reads are issued before the current entry is
+        // processed, so a wave running alone does not wait on them
+        float4 Gn = s_geo[0], Xn = s_aux[0], Cn = s_col[0];
         for (int j = 0; j < cnt && live != 0u; ++j) {
-            const float4 G = s_geo[j];
-            const float4 X = s_aux[j];
+            const float4 G = Gn, X = Xn, c = Cn;
+            const int jn = min(j + 1, cnt - 1);
+            Gn = s_geo[jn];
+            Xn = s_aux[jn];
+            Cn = s_col[jn];
             const LaneTerms L = lane_terms(G, X, px, col, row0);
             const uint32_t m = L.m & live;
             const uint32_t pos = b0 + (uint32_t)j + 1u - start;
@@ -220,7 +232,6 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
                     const float w = alpha * T[k];
                     const float tn = T[k] - w;
                     const bool stop = tn < tmin;
-                    const float4 c = s_col[j];
                     const float wv = stop ? 0.f : w;
                     C0[k] = fmaf(c.x, wv, C0[k]);
                     C1[k] = fmaf(c.y, wv, C1[k]);
@@ -247,9 +258,16 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
         t_final[V.px_offset + pix] = T[k];
         n_last[V.px_offset + pix] = last[k];
     }
+    // the backward walks every pixel's list up to its last blended Gaussian:
+    // the tile's longest such prefix is its work
+    uint32_t my_last = 0;
+#pragma unroll
+    for (int k = 0; k < PIX; ++k) my_last = max(my_last, last[k]);
+    const uint32_t tile_last = wave_max_u32(my_last);
     // work counters: one 64-bit atomic each per tile
     const uint32_t nb = wave_add_u32(n_blend), ne = wave_add_u32(n_eval);
     if (tid == 0) {
+        tile_cost[tile] = tile_last;
         atomicAdd(reinterpret_cast<unsigned long long*>(counters + kBlended),
                   (unsigned long long)nb);
         atomicAdd(reinterpret_cast<unsigned long long*>(counters + kEvaluated),
@@ -274,7 +292,7 @@ __global__ void __launch_bounds__(kLanes, 7) raster_backward_kernel(
     const uint32_t* __restrict__ pentry, const float4* __restrict__ rec,
     const float* __restrict__ t_final, const uint32_t* __restrict__ n_last,
     const float* __restrict__ dl_drgb, const int32_t* __restrict__ gate,
-    float* __restrict__ accum) {
+    float* __restrict__ accum, const uint32_t* __restrict__ order, int total_tiles) {
     constexpr int PIX = TW * TH / kLanes;
     constexpr int RS = kLanes / TW;
     __shared__ float4 s_geo[kLanes];
@@ -283,7 +301,8 @@ __global__ void __launch_bounds__(kLanes, 7) raster_backward_kernel(
     __shared__ float4 s_con[kLanes];   // a, b, c, 1 / o
     if (gate_closed(gate)) return;
 
-    const int tile = blockIdx.x;
+    const int tile = (int)order[blockIdx.x];
+    if (tile >= total_tiles) return;   // order is a permutation of the tiles
     const ViewDev& V = views.v[view_of_tile(views, tile)];
     const int local = tile - V.tile_offset;
     const int tx = local % V.tiles_x, ty = local / V.tiles_x;
@@ -421,16 +440,17 @@ hipError_t launch_rasterize(const Views& views, const RasterDev& rp, const Layou
     float* tf = reinterpret_cast<float*>(ws + L.t_final);
     uint32_t* nl = reinterpret_cast<uint32_t*>(ws + L.n_last);
     uint32_t* cnt = reinterpret_cast<uint32_t*>(ws + L.counters);
+    uint32_t* cost = reinterpret_cast<uint32_t*>(ws + L.tile_cost);
     const dim3 grid((unsigned)L.total_tiles), block(kLanes);
     if (rp.tile_w == 16 && rp.tile_h == 16)
         hipLaunchKernelGGL((raster_forward_kernel<16, 16>), grid, block, 0, s, views, rp, ranges,
-                           pentry, rec, out_rgb, tf, nl, cnt);
+                           pentry, rec, out_rgb, tf, nl, cnt, cost);
     else if (rp.tile_w == 8 && rp.tile_h == 8)
         hipLaunchKernelGGL((raster_forward_kernel<8, 8>), grid, block, 0, s, views, rp, ranges,
-                           pentry, rec, out_rgb, tf, nl, cnt);
+                           pentry, rec, out_rgb, tf, nl, cnt, cost);
     else
         hipLaunchKernelGGL((raster_forward_kernel<32, 8>), grid, block, 0, s, views, rp, ranges,
-                           pentry, rec, out_rgb, tf, nl, cnt);
+                           pentry, rec, out_rgb, tf, nl, cnt, cost);
     return hipGetLastError();
 }
 
@@ -448,16 +468,24 @@ hipError_t launch_rasterize_backward(const Views& views, const RasterDev& rp, co
     const float4* rec = reinterpret_cast<const float4*>(ws + L.records);
     const float* tf = reinterpret_cast<const float*>(ws + L.t_final);
     const uint32_t* nl = reinterpret_cast<const uint32_t*>(ws + L.n_last);
+    // the tiles in order of the forward's measured work, largest first, so
+    // that every SIMD gets a mix of long and short tiles
+    uint32_t* order = reinterpret_cast<uint32_t*>(ws + L.tile_order);
+    if (hipError_t err = launch_order_tiles(reinterpret_cast<const uint32_t*>(ws + L.tile_cost),
+                                            L.total_tiles, 0, order, gate, s);
+        err != hipSuccess)
+        return err;
+    const int tiles = (int)L.total_tiles;
     const dim3 grid((unsigned)L.total_tiles), block(kLanes);
     if (rp.tile_w == 16 && rp.tile_h == 16)
         hipLaunchKernelGGL((raster_backward_kernel<16, 16>), grid, block, 0, s, views, rp, ranges,
-                           pentry, rec, tf, nl, dl_drgb, gate, acc);
+                           pentry, rec, tf, nl, dl_drgb, gate, acc, order, tiles);
     else if (rp.tile_w == 8 && rp.tile_h == 8)
         hipLaunchKernelGGL((raster_backward_kernel<8, 8>), grid, block, 0, s, views, rp, ranges,
-                           pentry, rec, tf, nl, dl_drgb, gate, acc);
+                           pentry, rec, tf, nl, dl_drgb, gate, acc, order, tiles);
     else
         hipLaunchKernelGGL((raster_backward_kernel<32, 8>), grid, block, 0, s, views, rp, ranges,
-                           pentry, rec, tf, nl, dl_drgb, gate, acc);
+                           pentry, rec, tf, nl, dl_drgb, gate, acc, order, tiles);
     return hipGetLastError();
 }
 

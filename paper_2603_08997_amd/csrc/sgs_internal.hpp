@@ -78,7 +78,8 @@ struct Layout {
     int tile_bits, tile_passes, tile_result;  // result buffer index (0/1) of the tile sort
     size_t records, tiles, depth, dkey[2], dval[2], offsets, window_first, scan_sums, pair_tile[2],
         pair_entry[2],
-        sort_hist, sort_totals, ranges, t_final, n_last, accum, counters, total;
+        sort_hist, sort_totals, ranges, tile_cost, tile_order, t_final, n_last, accum, counters,
+        total;
 };
 
 bool make_views(const sgs_camera* cams, int n_views, const sgs_raster_params* rp, Views* out,
@@ -109,6 +110,10 @@ hipError_t launch_project_backward(const float* planes, int64_t n, int64_t strid
 
 // p[0..n) = v on stream s (a kernel, so that callers can be captured).
 hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+// order = the tiles sorted by cost >> shift, largest first (ties in any
+// order); a permutation of [0, tiles). Skipped when the gate is closed.
+hipError_t launch_order_tiles(const uint32_t* cost, int64_t tiles, int shift, uint32_t* order,
+                              const int32_t* gate, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) uint32 pairs over bits [0, bits).
 // n is read on the device from *n_dev; n_max bounds it for the grid size.
