@@ -210,7 +210,8 @@ sgs_status sgs_project_backward(const sgs_gaussians* g, const sgs_camera* cams, 
  * records:    float32 [entries][12]  u v a b | c o rx ry | r g b clamp-mask(bits)
  * tiles:      uint32  [entries]      tiles touched (0 = not visible)
  * depth:      float32 [entries]      camera depth (the sort key) of visible entries
- * pair_tile:  uint32  [pair_capacity] sorted global tile index per pair
+ * pair_tile:  uint16 or uint32 (pair_tile_bytes: 2 when total_tiles < 65535)
+ *             [pair_capacity] sorted global tile index per pair
  * pair_entry: uint32  [pair_capacity] entry index per pair (sorted with tiles)
  * ranges:     uint32  [total_tiles][2] [start, end) into the pair arrays
  * t_final:    float32 [total_pixels]  final transmittance per pixel
@@ -220,6 +221,7 @@ sgs_status sgs_project_backward(const sgs_gaussians* g, const sgs_camera* cams, 
 typedef struct {
     size_t records, tiles, depth, pair_tile, pair_entry, ranges, t_final, n_last, accum, counters;
     int64_t entries, total_tiles, total_pixels;
+    int32_t pair_tile_bytes;  /* 2 or 4 */
 } sgs_workspace_layout;
 
 sgs_status sgs_get_workspace_layout(const sgs_raster_params* rp, int64_t n, const sgs_camera* cams,

@@ -189,7 +189,8 @@ __device__ __forceinline__ bool tile_reachable(float u, float v, float a, float 
 // positions gives every window position its Gaussian, and every thread expands
 // its pairs to (tile, entry) with coalesced stores. Pair q of a Gaussian is
 // tile (x0 + q % w, y0 + q / w) of its rectangle, row-major; pairs that fail
-// the exact tile test get the key kCulledTile.
+// the exact tile test get the all-ones key (kCulledTile, or kCulledTile16
+// when the batch keeps uint16 tile keys).
 constexpr int kEmitThreads = 256;
 constexpr int kEmitItems = 4;
 constexpr int kEmitTile = kEmitThreads * kEmitItems;
@@ -197,11 +198,12 @@ static_assert(kEmitTile == kEmitWindow, "emission window size");
 // Gaussians meeting one window: at most one per pair plus the next window's first.
 constexpr int kEmitMaxG = kEmitTile + 1;
 
+template <typename K>
 __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     const uint32_t* __restrict__ sorted_entry, const uint32_t* __restrict__ offsets,
     const uint32_t* __restrict__ window_first, const float4* __restrict__ rec,
     const uint32_t* __restrict__ counters, int64_t n, Views views, RasterDev rp,
-    uint32_t* __restrict__ ptile, uint32_t* __restrict__ pentry) {
+    K* __restrict__ ptile, uint32_t* __restrict__ pentry) {
     __shared__ uint32_t s_off[kEmitMaxG];
     __shared__ uint32_t s_ent[kEmitMaxG];
     __shared__ uint32_t s_base[kEmitMaxG];   // global tile of the rectangle's first tile
@@ -296,14 +298,15 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
         const bool keep = tile_reachable(g0[it].x, g0[it].y, g0[it].z, g0[it].w, g1[it].x,
                                          s_lim[j], g1[it].z, g1[it].w, (int)s_x0[j] + qx,
                                          (int)(s_y0[j] + qy), rp);
-        ptile[p] = keep ? s_base[j] + qy * s_tx[j] + (uint32_t)qx : kCulledTile;
+        ptile[p] = keep ? (K)(s_base[j] + qy * s_tx[j] + (uint32_t)qx) : (K)~(K)0;
         pentry[p] = s_ent[j];
     }
 }
 
 // [start, end) of every tile by binary search in the sorted tile keys
 // (empty tiles: [0, 0)).
-__global__ void __launch_bounds__(256) ranges_kernel(const uint32_t* __restrict__ ptile,
+template <typename K>
+__global__ void __launch_bounds__(256) ranges_kernel(const K* __restrict__ ptile,
                                                      const uint32_t* __restrict__ counters,
                                                      int64_t total_tiles,
                                                      uint32_t* __restrict__ ranges) {
@@ -384,6 +387,9 @@ hipError_t launch_bin(const Views& views, const RasterDev& rp, int64_t n, const 
     uint32_t* totals = reinterpret_cast<uint32_t*>(ws + L.sort_totals);
     uint32_t* ptile[2] = {reinterpret_cast<uint32_t*>(ws + L.pair_tile[0]),
                           reinterpret_cast<uint32_t*>(ws + L.pair_tile[1])};
+    uint16_t* ptile16[2] = {reinterpret_cast<uint16_t*>(ws + L.pair_tile[0]),
+                            reinterpret_cast<uint16_t*>(ws + L.pair_tile[1])};
+    const bool key16 = L.tile_key_bytes == 2;
     uint32_t* pentry[2] = {reinterpret_cast<uint32_t*>(ws + L.pair_entry[0]),
                            reinterpret_cast<uint32_t*>(ws + L.pair_entry[1])};
     uint32_t* ranges = reinterpret_cast<uint32_t*>(ws + L.ranges);
@@ -412,21 +418,32 @@ hipError_t launch_bin(const Views& views, const RasterDev& rp, int64_t n, const 
                           counters + kPairs, s);
         if (err != hipSuccess) return err;
         hipLaunchKernelGGL(capacity_kernel, dim3(1), dim3(1), 0, s, counters, L.capacity);
-        if (L.capacity > 0)
-            hipLaunchKernelGGL(emit_kernel, dim3((unsigned)((L.capacity + kEmitTile - 1) / kEmitTile)),
-                               dim3(kEmitThreads), 0, s, dval[res], offsets, window_first, rec,
-                               counters, n, views, rp, ptile[0], pentry[0]);
+        const dim3 egrid((unsigned)((L.capacity + kEmitTile - 1) / kEmitTile));
+        if (L.capacity > 0 && key16)
+            hipLaunchKernelGGL(emit_kernel<uint16_t>, egrid, dim3(kEmitThreads), 0, s, dval[res],
+                               offsets, window_first, rec, counters, n, views, rp, ptile16[0],
+                               pentry[0]);
+        else if (L.capacity > 0)
+            hipLaunchKernelGGL(emit_kernel<uint32_t>, egrid, dim3(kEmitThreads), 0, s, dval[res],
+                               offsets, window_first, rec, counters, n, views, rp, ptile[0],
+                               pentry[0]);
         if ((err = hipGetLastError()) != hipSuccess) return err;
         // stable sort of the pairs by tile; the first pass drops culled pairs
         // and counts the rest into counters[kPairsKept]
         int tres = 0;
-        err = radix_sort(ptile, pentry, counters + kPairsWritten, L.capacity, L.tile_bits, hist,
-                         totals, s, &tres, counters + kPairsKept);
+        err = key16 ? radix_sort(ptile16, pentry, counters + kPairsWritten, L.capacity, L.tile_bits,
+                                 hist, totals, s, &tres, counters + kPairsKept)
+                    : radix_sort(ptile, pentry, counters + kPairsWritten, L.capacity, L.tile_bits,
+                                 hist, totals, s, &tres, counters + kPairsKept);
         if (err != hipSuccess) return err;
     }
-    if (L.total_tiles > 0)
-        hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((L.total_tiles + 255) / 256)), dim3(256),
-                           0, s, ptile[L.tile_result], counters, L.total_tiles, ranges);
+    const dim3 rgrid((unsigned)((L.total_tiles + 255) / 256));
+    if (L.total_tiles > 0 && key16)
+        hipLaunchKernelGGL(ranges_kernel<uint16_t>, rgrid, dim3(256), 0, s, ptile16[L.tile_result],
+                           counters, L.total_tiles, ranges);
+    else if (L.total_tiles > 0)
+        hipLaunchKernelGGL(ranges_kernel<uint32_t>, rgrid, dim3(256), 0, s, ptile[L.tile_result],
+                           counters, L.total_tiles, ranges);
     return hipGetLastError();
 }
 

@@ -183,6 +183,7 @@ void make_layout(const Views& views, int64_t n, int64_t capacity, Layout* L) {
     L->tile_bits = bits;
     L->tile_passes = radix_passes(bits);
     L->tile_result = L->tile_passes & 1;
+    L->tile_key_bytes = L->total_tiles < kMaxTiles16 ? 2 : 4;
     const int64_t E = L->entries;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -202,8 +203,8 @@ void make_layout(const Views& views, int64_t n, int64_t capacity, Layout* L) {
     L->offsets = take(sizeof(uint32_t) * (size_t)E);
     L->window_first = take(sizeof(uint32_t) * (size_t)((capacity + kEmitWindow - 1) / kEmitWindow + 1));
     L->scan_sums = take(sizeof(uint32_t) * (size_t)(L->scan_blocks + 1));
-    L->pair_tile[0] = take(sizeof(uint32_t) * (size_t)capacity);
-    L->pair_tile[1] = take(sizeof(uint32_t) * (size_t)capacity);
+    L->pair_tile[0] = take((size_t)L->tile_key_bytes * (size_t)capacity);
+    L->pair_tile[1] = take((size_t)L->tile_key_bytes * (size_t)capacity);
     L->pair_entry[0] = take(sizeof(uint32_t) * (size_t)capacity);
     L->pair_entry[1] = take(sizeof(uint32_t) * (size_t)capacity);
     L->sort_hist = take(sizeof(uint32_t) * 256 * (size_t)L->sort_blocks);
@@ -262,6 +263,7 @@ sgs_status sgs_get_workspace_layout(const sgs_raster_params* rp, int64_t n, cons
     out->tiles = L.tiles;
     out->depth = L.depth;
     out->pair_tile = L.pair_tile[L.tile_result];
+    out->pair_tile_bytes = L.tile_key_bytes;
     out->pair_entry = L.pair_entry[L.tile_result];
     out->ranges = L.ranges;
     out->t_final = L.t_final;

@@ -67,7 +67,10 @@ enum Counter : int {
 
 // Tile key of an emitted pair whose Gaussian cannot reach alpha_min at any
 // pixel centre of the tile; the first pass of the tile sort drops such pairs.
+// Batches of fewer than 65535 tiles keep tile keys in uint16 (kCulledTile16).
 constexpr uint32_t kCulledTile = 0xffffffffu;
+constexpr uint16_t kCulledTile16 = 0xffffu;
+constexpr int64_t kMaxTiles16 = 0xffff;
 
 // Pairs written by one workgroup of the emission kernel.
 constexpr int64_t kEmitWindow = 1024;
@@ -76,6 +79,7 @@ struct Layout {
     int64_t entries, total_tiles, total_pixels, capacity;
     int64_t scan_blocks, sort_blocks;
     int tile_bits, tile_passes, tile_result;  // result buffer index (0/1) of the tile sort
+    int tile_key_bytes;                        // 2 (total_tiles < kMaxTiles16) or 4
     size_t records, tiles, depth, dkey[2], dval[2], offsets, window_first, scan_sums, pair_tile[2],
         pair_entry[2],
         sort_hist, sort_totals, ranges, tile_cost, tile_order, t_final, n_last, accum, counters,
@@ -119,11 +123,13 @@ hipError_t launch_order_tiles(const uint32_t* cost, int64_t tiles, int shift, ui
 // n is read on the device from *n_dev; n_max bounds it for the grid size.
 // Returns the index (0/1) of the buffer holding the result.
 int radix_passes(int bits);
-// kept_dev (nullable): the first pass drops keys equal to kCulledTile and
-// writes the number of remaining pairs there; later passes sort that many.
+// K is uint32_t or uint16_t. kept_dev (nullable): the first pass drops keys
+// with all bits set (kCulledTile, or kCulledTile16 for uint16 keys) and writes
+// the number of remaining pairs there; later passes sort that many.
 // gather_dst (nullable): the last pass also writes gather_src[value] at each
 // sorted position.
-hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int64_t n_max,
+template <typename K>
+hipError_t radix_sort(K* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int64_t n_max,
                       int bits, uint32_t* hist, uint32_t* totals, hipStream_t s, int* result,
                       uint32_t* kept_dev = nullptr, const uint32_t* gather_src = nullptr,
                       uint32_t* gather_dst = nullptr);

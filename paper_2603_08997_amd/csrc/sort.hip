@@ -1,5 +1,7 @@
-// Stable least-significant-digit radix sort of (uint32 key, uint32 value)
-// pairs, 8-bit digits, reduce-then-scan:
+// Stable least-significant-digit radix sort of (key, uint32 value) pairs,
+// keys uint32 or uint16 (tile keys of batches with fewer than 65535 tiles,
+// which halves the key traffic and the LDS a scatter block needs), digits of
+// at most 8 bits, reduce-then-scan:
 //   hist:    per-block digit counts, stored digit-major [256][blocks];
 //   scan:    one block per digit row scans the row and records its total;
 //   scatter: each block ranks its keys stably (each wave ranks a contiguous
@@ -38,13 +40,22 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int bits
     return peers;
 }
 
+// Culled-pair sentinel of a key type (all bits set).
+template <typename K>
+__device__ __forceinline__ constexpr uint32_t culled_key() {
+    return (uint32_t)(K)~(K)0;
+}
+
 // Digit counts of one block's keys. Counting does not depend on order, so the
-// keys are read as uint4 and counted into several LDS histograms.
-__global__ void __launch_bounds__(kThreads) radix_hist_kernel(const uint32_t* __restrict__ keys,
+// keys are read as uint4 (4 or 8 keys) and counted into several LDS histograms.
+template <typename K>
+__global__ void __launch_bounds__(kThreads) radix_hist_kernel(const K* __restrict__ keys,
                                                               const uint32_t* __restrict__ n_dev,
                                                               int shift, int bits,
                                                               uint32_t* __restrict__ hist,
                                                               int nblocks, bool skip_culled) {
+    constexpr int VEC = 16 / (int)sizeof(K);
+    static_assert(kItems % VEC == 0, "keys per thread");
     // kHistCopies counters per digit, lane l counting into copy l % kHistCopies,
     // so that fewer lanes of one atomic instruction hit the same address
     __shared__ uint32_t cnt[kHistCopies][kRadix];
@@ -62,28 +73,31 @@ __global__ void __launch_bounds__(kThreads) radix_hist_kernel(const uint32_t* __
         const uint4* k4 = reinterpret_cast<const uint4*>(keys + base);
         const int64_t left = (int64_t)n - base;
         // all loads first, then the counts
-        uint4 q[kItems / 4];
+        uint4 q[kItems / VEC];
 #pragma unroll
-        for (int it = 0; it < kItems / 4; ++it) {
-            const int64_t j = (int64_t)(it * kThreads + tid) * 4;
-            if (j + 3 < left) {
+        for (int it = 0; it < kItems / VEC; ++it) {
+            const int64_t j = (int64_t)(it * kThreads + tid) * VEC;
+            if (j + VEC - 1 < left) {
                 q[it] = k4[it * kThreads + tid];
             } else {
-                uint32_t kk[4];
+                K kk[VEC];
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    kk[c] = j + c < left ? keys[base + j + c] : kCulledTile;
-                q[it] = make_uint4(kk[0], kk[1], kk[2], kk[3]);
+                for (int c = 0; c < VEC; ++c)
+                    kk[c] = j + c < left ? keys[base + j + c] : (K)culled_key<K>();
+                __builtin_memcpy(&q[it], kk, sizeof(q[it]));
             }
         }
 #pragma unroll
-        for (int it = 0; it < kItems / 4; ++it) {
-            const int64_t j = (int64_t)(it * kThreads + tid) * 4;
-            const uint32_t kk[4] = {q[it].x, q[it].y, q[it].z, q[it].w};
+        for (int it = 0; it < kItems / VEC; ++it) {
+            const int64_t j = (int64_t)(it * kThreads + tid) * VEC;
+            K kk[VEC];
+            __builtin_memcpy(kk, &q[it], sizeof(q[it]));
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                if (j + c < left && !(skip_culled && kk[c] == kCulledTile))
-                    atomicAdd(&cnt[w][digit_of(kk[c], shift, mask)], 1u);
+            for (int c = 0; c < VEC; ++c) {
+                const uint32_t k = kk[c];
+                if (j + c < left && !(skip_culled && k == culled_key<K>()))
+                    atomicAdd(&cnt[w][digit_of(k, shift, mask)], 1u);
+            }
         }
     }
     __syncthreads();
@@ -95,19 +109,37 @@ __global__ void __launch_bounds__(kThreads) radix_hist_kernel(const uint32_t* __
     if (tid < (1 << bits)) hist[(int64_t)tid * nblocks + blk] = total;
 }
 
-// Exclusive scan of each digit row hist[d][0..nblocks) in place; totals[d] = row sum.
+// Exclusive scan of each digit row hist[d][0..nblocks) in place; totals[d] =
+// row sum. Each thread takes a run of up to kScanItems consecutive entries
+// (kept in registers), so a row of up to kScanThreads * kScanItems entries
+// needs one block scan; longer rows go in chunks of that size.
+constexpr int kScanItems = 16;
 __global__ void __launch_bounds__(kScanThreads) radix_scan_kernel(uint32_t* __restrict__ hist,
                                                                   int nblocks,
                                                                   uint32_t* __restrict__ totals) {
     __shared__ uint32_t smem[kScanThreads / 64 + 1];
     uint32_t* row = hist + (int64_t)blockIdx.x * nblocks;
+    const int per = min(kScanItems, (nblocks + kScanThreads - 1) / kScanThreads);
+    const int chunk = per * kScanThreads;
     uint32_t carry = 0;
-    for (int base = 0; base < nblocks; base += kScanThreads) {
-        const int i = base + threadIdx.x;
-        const uint32_t v = i < nblocks ? row[i] : 0u;
+    for (int base = 0; base < nblocks; base += chunk) {
+        const int first = base + (int)threadIdx.x * per;
+        uint32_t v[kScanItems];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            const int i = first + k;
+            v[k] = (k < per && i < nblocks) ? row[i] : 0u;
+            sum += v[k];
+        }
         uint32_t tot;
-        const uint32_t ex = block_excl_scan<kScanThreads>(v, smem, &tot);
-        if (i < nblocks) row[i] = carry + ex;
+        uint32_t run = carry + block_excl_scan<kScanThreads>(sum, smem, &tot);
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            const int i = first + k;
+            if (k < per && i < nblocks) row[i] = run;
+            run += v[k];
+        }
         carry += tot;
     }
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
@@ -121,13 +153,14 @@ __global__ void __launch_bounds__(kScanThreads) radix_scan_kernel(uint32_t* __re
 // count. One barrier later, the digit's start in the block plus the counts of
 // the earlier waves give every key its block-local position; keys are sorted
 // into LDS and written out in digit runs.
+template <typename K>
 __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
-    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
-    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+    const K* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+    K* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
     const uint32_t* __restrict__ n_dev, int shift, int bits, const uint32_t* __restrict__ hist,
     const uint32_t* __restrict__ totals, int nblocks, bool skip_culled,
     const uint32_t* __restrict__ gather_src, uint32_t* __restrict__ gather_dst) {
-    __shared__ uint32_t lkeys[kTile];
+    __shared__ K lkeys[kTile];
     __shared__ uint32_t lvals[kTile];
     __shared__ uint32_t gbase[kRadix];          // global start of this block's digit run
     __shared__ uint32_t wcnt[kWaves][kRadix];   // keys of each digit per wave
@@ -149,7 +182,7 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
     for (int it = 0; it < kItems; ++it) {
         const int li = w * kPerWave + it * 64 + lane;
         const bool valid = li < nvalid;
-        key[it] = valid ? keys_in[base + li] : 0xffffffffu;
+        key[it] = valid ? (uint32_t)keys_in[base + li] : culled_key<K>();
         val[it] = valid ? vals_in[base + li] : 0u;
     }
     {
@@ -167,7 +200,7 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
         const int li = w * kPerWave + it * 64 + lane;
-        const bool valid = li < nvalid && !(skip_culled && key[it] == kCulledTile);
+        const bool valid = li < nvalid && !(skip_culled && key[it] == culled_key<K>());
         const uint32_t d = digit_of(key[it], shift, mask);
         const uint64_t peers = match_digit(d, valid, bits);
         const uint32_t before = (uint32_t)popc64(peers & lanemask_lt());
@@ -196,10 +229,10 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
         const int li = w * kPerWave + it * 64 + lane;
-        if (li < nvalid && !(skip_culled && key[it] == kCulledTile)) {
+        if (li < nvalid && !(skip_culled && key[it] == culled_key<K>())) {
             const uint32_t d = digit_of(key[it], shift, mask);
             const uint32_t pos = wcnt[w][d] + rank[it];
-            lkeys[pos] = key[it];
+            lkeys[pos] = (K)key[it];
             lvals[pos] = val[it];
         }
     }
@@ -207,7 +240,7 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
     // wcnt[0][d] is now the block-local start of digit d
 #pragma unroll 4
     for (int li = tid; li < nkept; li += kThreads) {
-        const uint32_t k = lkeys[li];
+        const K k = lkeys[li];
         const uint32_t d = digit_of(k, shift, mask);
         const uint32_t out = gbase[d] + (uint32_t)li - wcnt[0][d];
         const uint32_t val = lvals[li];
@@ -243,7 +276,8 @@ static int pass_bits(int bits, int p, int* shift) {
     return base + (p < extra ? 1 : 0);
 }
 
-hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int64_t n_max,
+template <typename K>
+hipError_t radix_sort(K* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int64_t n_max,
                       int bits, uint32_t* hist, uint32_t* totals, hipStream_t s, int* result,
                       uint32_t* kept_dev, const uint32_t* gather_src, uint32_t* gather_dst) {
     const int passes = radix_passes(bits);
@@ -254,7 +288,7 @@ hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_de
         const int pb = pass_bits(bits, p, &shift);
         const bool skip = kept_dev != nullptr && p == 0;
         const uint32_t* n_p = (kept_dev != nullptr && p > 0) ? kept_dev : n_dev;
-        hipLaunchKernelGGL(radix_hist_kernel, dim3(nb), dim3(kThreads), 0, s, keys[cur], n_p,
+        hipLaunchKernelGGL(radix_hist_kernel<K>, dim3(nb), dim3(kThreads), 0, s, keys[cur], n_p,
                            shift, pb, hist, nb, skip);
         // rows and totals of digits >= 2^pb are never read for a key of this pass
         hipLaunchKernelGGL(radix_scan_kernel, dim3(1u << pb), dim3(kScanThreads), 0, s, hist, nb,
@@ -263,7 +297,7 @@ hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_de
             hipLaunchKernelGGL(radix_kept_kernel, dim3(1), dim3(kRadix), 0, s, totals, 1 << pb,
                                kept_dev);
         const bool last = p == passes - 1;
-        hipLaunchKernelGGL(radix_scatter_kernel, dim3(nb), dim3(kThreads), 0, s, keys[cur],
+        hipLaunchKernelGGL(radix_scatter_kernel<K>, dim3(nb), dim3(kThreads), 0, s, keys[cur],
                            vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_p, shift, pb, hist, totals,
                            nb, skip, last ? gather_src : nullptr, last ? gather_dst : nullptr);
         cur ^= 1;
@@ -273,5 +307,12 @@ hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_de
     *result = cur;
     return hipGetLastError();
 }
+
+template hipError_t radix_sort<uint32_t>(uint32_t* keys[2], uint32_t* vals[2], const uint32_t*,
+                                         int64_t, int, uint32_t*, uint32_t*, hipStream_t, int*,
+                                         uint32_t*, const uint32_t*, uint32_t*);
+template hipError_t radix_sort<uint16_t>(uint16_t* keys[2], uint32_t* vals[2], const uint32_t*,
+                                         int64_t, int, uint32_t*, uint32_t*, hipStream_t, int*,
+                                         uint32_t*, const uint32_t*, uint32_t*);
 
 }  // namespace sgs

@@ -51,7 +51,8 @@ class WorkspaceLayoutC(C.Structure):
     _fields_ = [(k, C.c_size_t) for k in ("records", "tiles", "depth", "pair_tile", "pair_entry",
                                             "ranges", "t_final", "n_last", "accum",
                                             "counters")] + \
-               [("entries", C.c_int64), ("total_tiles", C.c_int64), ("total_pixels", C.c_int64)]
+               [("entries", C.c_int64), ("total_tiles", C.c_int64), ("total_pixels", C.c_int64),
+                ("pair_tile_bytes", C.c_int32)]
 
 
 class GateParamsC(C.Structure):

@@ -57,7 +57,7 @@ def test_workspace_size_and_bad_tile_shape():
     sg = _lib()
     cams = [_cam()]
     nbytes = sg.forward_workspace_size(sg.RasterParams(), 1000, cams, 50_000)
-    assert nbytes > 50_000 * 16
+    assert nbytes > 50_000 * 12   # two (uint16 tile, uint32 entry) pair buffers
     with pytest.raises(sg.SkipGSError) as e:
         sg.forward_workspace_size(sg.RasterParams(tile_w=12, tile_h=12), 1000, cams, 10)
     assert e.value.status == 2 and "tile shape" in str(e.value)
@@ -122,8 +122,9 @@ def test_layout_regions_fit_and_do_not_overlap():
     assert L.entries == 1000
     assert L.total_tiles == 8 * 6 + 5 * 3
     assert L.total_pixels == 64 * 48 + 40 * 24
+    assert L.pair_tile_bytes == 2   # fewer than 65535 tiles: uint16 tile keys
     regions = sorted([(L.records, 48 * 1000), (L.tiles, 4 * 1000), (L.depth, 4 * 1000),
-                      (L.pair_tile, 4 * 30_000),
+                      (L.pair_tile, L.pair_tile_bytes * 30_000),
                       (L.pair_entry, 4 * 30_000), (L.ranges, 8 * L.total_tiles),
                       (L.t_final, 4 * L.total_pixels), (L.n_last, 4 * L.total_pixels),
                       (L.accum, 48 * 1000), (L.counters, 64)])

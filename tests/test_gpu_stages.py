@@ -40,7 +40,8 @@ class Stage:
 
     def lists(self):
         P = self.kept
-        tiles = region(self.ws, self.L.pair_tile, P, np.uint32)
+        kt = np.uint16 if self.L.pair_tile_bytes == 2 else np.uint32
+        tiles = region(self.ws, self.L.pair_tile, P, kt).astype(np.uint32)
         ents = region(self.ws, self.L.pair_entry, P, np.uint32)
         ranges = region(self.ws, self.L.ranges, 2 * self.L.total_tiles, np.uint32).reshape(-1, 2)
         return tiles, ents, ranges
@@ -77,12 +78,24 @@ def _oracle_bins(recs, cams, n, tw, th):
 @pytest.mark.parametrize("ties", [0.0, 0.4])
 def test_binning_bit_exact(tile, ties):
     require_gpu()
+    st = _check_binning(_views(), tile, ties, 1500, 100 + int(ties * 10))
+    assert st.L.pair_tile_bytes == 2   # few tiles: uint16 tile keys
+
+
+def test_binning_bit_exact_wide_tile_keys():
+    """79,800 tiles (three 1600x1060 views, 8x8 tiles): uint32 tile keys."""
+    require_gpu()
+    cams = [S.look_at_camera(p, 1600, 1060) for p in ((3.0, 1.0, 1.0), (0.5, -3.0, 2.0),
+                                                        (-2.0, 2.0, 1.5))]
+    st = _check_binning(cams, (8, 8), 0.2, 1500, 131)
+    assert st.L.pair_tile_bytes == 4
+
+
+def _check_binning(cams, tile, ties, n, seed):
     m = sg()
     tw, th = tile
-    cams = _views()
-    n = 1500
-    recs, cat = _records(n, cams, 100 + int(ties * 10), max_radius=20, tie_fraction=ties)
-    say(f"binning tile={tile} ties={ties} n={n}")
+    recs, cat = _records(n, cams, seed, max_radius=20, tie_fraction=ties)
+    say(f"binning tile={tile} ties={ties} n={n} views={len(cams)}")
     rp = m.RasterParams(tile_w=tw, tile_h=th)
     st = Stage(n, cams, rp, cat, 400_000)
     assert st.flags == 0
@@ -121,6 +134,7 @@ def test_binning_bit_exact(tile, ties):
         toff += tx_n * ty_n
     say(f"  box pairs {len(vals)}, kept {len(ents)}, non-contributing {dead}, dropped {dropped}")
     assert dropped >= 0.5 * dead
+    return st
 
 
 def test_binning_empty_and_capacity_overflow():
