@@ -8,6 +8,8 @@
 // stable sort keeps the depth order inside each tile, so the lists are the
 // same as those of the 64-bit sort while the long pair array is sorted on
 // ceil(log2(tiles)) bits instead of 32 + that many.
+#include <algorithm>
+
 #include "sgs_internal.hpp"
 #include "sgs_device.hpp"
 
@@ -59,9 +61,13 @@ struct OffsetSink {
     }
 };
 
+// Block sums of the scan input. Block 0 also zeroes `clear[0..nclear)` (the
+// counters a binning pass accumulates into), saving a launch.
 template <class Src>
-__global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(Src src, uint32_t* sums) {
+__global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(Src src, uint32_t* sums,
+                                                                   uint32_t* clear, int nclear) {
     __shared__ uint32_t smem[kScanThreads / 64 + 1];
+    if (blockIdx.x == 0 && (int)threadIdx.x < nclear) clear[threadIdx.x] = 0u;
     const int64_t n = src.count();
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t s = 0;
@@ -73,25 +79,18 @@ __global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(Src src, uint
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-// Exclusive scan of the block sums in place (one block); *total = grand total.
-__global__ void __launch_bounds__(1024) scan_sums_kernel(uint32_t* sums, int nb, uint32_t* total) {
-    __shared__ uint32_t smem[1024 / 64 + 1];
-    uint32_t carry = 0;
-    for (int base = 0; base < nb; base += 1024) {
-        const int i = base + threadIdx.x;
-        const uint32_t v = i < nb ? sums[i] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan<1024>(v, smem, &tot);
-        if (i < nb) sums[i] = carry + ex;
-        carry += tot;
-    }
-    if (threadIdx.x == 0) *total = carry;
-}
-
+// Second and last kernel of the scan: every block adds up the sums of the
+// blocks before it (a few thousand L2-resident words), scans its own tile and
+// feeds the sink; the last block writes the grand total.
 template <class Src, class Sink>
 __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(Src src, Sink sink,
-                                                                 const uint32_t* sums) {
+                                                                 const uint32_t* sums,
+                                                                 uint32_t* total) {
     __shared__ uint32_t smem[kScanThreads / 64 + 1];
+    uint32_t before = 0;
+    for (int i = threadIdx.x; i < (int)blockIdx.x; i += kScanThreads) before += sums[i];
+    uint32_t prefix;
+    block_excl_scan<kScanThreads>(before, smem, &prefix);
     const int64_t n = src.count();
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
@@ -102,35 +101,25 @@ __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(Src src, Sink s
         s += v[j];
     }
     uint32_t tot;
-    uint32_t pos = block_excl_scan<kScanThreads>(s, smem, &tot) + sums[blockIdx.x];
+    uint32_t pos = block_excl_scan<kScanThreads>(s, smem, &tot) + prefix;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
         if (base + j < n) sink(base + j, v[j], pos);
         pos += v[j];
     }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = prefix + tot;
 }
 
 template <class Src, class Sink>
 hipError_t device_scan(Src src, Sink sink, int64_t n_max, uint32_t* sums, uint32_t* total,
-                       hipStream_t s) {
+                       hipStream_t s, uint32_t* clear = nullptr, int nclear = 0) {
     const int nb = (int)((n_max + kScanTile - 1) / kScanTile);
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(scan_reduce_kernel<Src>, dim3(nb), dim3(kScanThreads), 0, s, src, sums);
-    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, s, sums, nb, total);
+    hipLaunchKernelGGL(scan_reduce_kernel<Src>, dim3(nb), dim3(kScanThreads), 0, s, src, sums, clear,
+                       nclear);
     hipLaunchKernelGGL((scan_down_kernel<Src, Sink>), dim3(nb), dim3(kScanThreads), 0, s, src,
-                       sink, sums);
+                       sink, sums, total);
     return hipGetLastError();
-}
-
-// pairs = counters[kPairs]; written = min(pairs, capacity); flag overflow.
-__global__ void capacity_kernel(uint32_t* counters, int64_t capacity) {
-    const uint32_t p = counters[kPairs];
-    if ((int64_t)p > capacity) {
-        counters[kStatus] |= SGS_STATUS_PAIR_OVERFLOW;
-        counters[kPairsWritten] = (uint32_t)capacity;
-    } else {
-        counters[kPairsWritten] = p;
-    }
 }
 
 // Exact tile test of one (tile, Gaussian) pair: can alpha' = o exp(-q/2),
@@ -202,8 +191,8 @@ template <typename K>
 __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     const uint32_t* __restrict__ sorted_entry, const uint32_t* __restrict__ offsets,
     const uint32_t* __restrict__ window_first, const float4* __restrict__ rec,
-    const uint32_t* __restrict__ counters, int64_t n, Views views, RasterDev rp,
-    K* __restrict__ ptile, uint32_t* __restrict__ pentry) {
+    uint32_t* __restrict__ counters, int64_t n, Views views, RasterDev rp,
+    int64_t capacity, K* __restrict__ ptile, uint32_t* __restrict__ pentry) {
     __shared__ uint32_t s_off[kEmitMaxG];
     __shared__ uint32_t s_ent[kEmitMaxG];
     __shared__ uint32_t s_base[kEmitMaxG];   // global tile of the rectangle's first tile
@@ -214,8 +203,14 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     __shared__ float s_lim[kEmitMaxG];       // reach limit of the exact tile test
     __shared__ uint32_t s_own[kEmitTile];    // window position -> owning Gaussian
     __shared__ uint32_t s_scan[kEmitThreads / 64 + 1];
-    const uint32_t P = counters[kPairsWritten];
+    // pairs written = min(pairs needed, capacity); block 0 records it and
+    // flags an overflow (the tile sort reads the count after this kernel)
     const uint32_t total = counters[kPairs];
+    const uint32_t P = (int64_t)total > capacity ? (uint32_t)capacity : total;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        counters[kPairsWritten] = P;
+        if ((int64_t)total > capacity) counters[kStatus] |= SGS_STATUS_PAIR_OVERFLOW;
+    }
     const uint32_t nvis = counters[kVisible];
     const int win = blockIdx.x;
     const uint32_t p0 = (uint32_t)win * (uint32_t)kEmitTile;
@@ -396,13 +391,16 @@ hipError_t launch_bin(const Views& views, const RasterDev& rp, int64_t n, const 
     hipError_t err;
 
     // visible entries -> (depth, entry), entry order; count -> counters[kVisible]
-    if ((err = fill_u32(counters + kVisible, kPairsKept + 1 - kVisible, 0u, s)) != hipSuccess)
+    // (the first scan kernel also clears the counters binning and compositing
+    // accumulate into)
+    if (E == 0 && (err = fill_u32(counters + kVisible, kPairsKept + 1 - kVisible, 0u, s)) != hipSuccess)
         return err;
     if (E > 0) {
         err = device_scan(VisibleSrc{tiles, E},
                           CompactSink{reinterpret_cast<const uint32_t*>(ws + L.depth), dkey[0],
                                       dval[0]},
-                          E, sums, counters + kVisible, s);
+                          E, sums, counters + kVisible, s, counters + kVisible,
+                          kPairsKept + 1 - kVisible);
         if (err != hipSuccess) return err;
         // stable sort by depth (ties keep ascending entry order); the last
         // pass also gathers each entry's tile count into `offsets`, in depth
@@ -417,16 +415,16 @@ hipError_t launch_bin(const Views& views, const RasterDev& rp, int64_t n, const 
                           OffsetSink{offsets, window_first, n_windows}, E, sums,
                           counters + kPairs, s);
         if (err != hipSuccess) return err;
-        hipLaunchKernelGGL(capacity_kernel, dim3(1), dim3(1), 0, s, counters, L.capacity);
-        const dim3 egrid((unsigned)((L.capacity + kEmitTile - 1) / kEmitTile));
-        if (L.capacity > 0 && key16)
+        // at least one workgroup: block 0 also records the written pair count
+        const dim3 egrid((unsigned)std::max<int64_t>(1, (L.capacity + kEmitTile - 1) / kEmitTile));
+        if (key16)
             hipLaunchKernelGGL(emit_kernel<uint16_t>, egrid, dim3(kEmitThreads), 0, s, dval[res],
-                               offsets, window_first, rec, counters, n, views, rp, ptile16[0],
-                               pentry[0]);
-        else if (L.capacity > 0)
+                               offsets, window_first, rec, counters, n, views, rp, L.capacity,
+                               ptile16[0], pentry[0]);
+        else
             hipLaunchKernelGGL(emit_kernel<uint32_t>, egrid, dim3(kEmitThreads), 0, s, dval[res],
-                               offsets, window_first, rec, counters, n, views, rp, ptile[0],
-                               pentry[0]);
+                               offsets, window_first, rec, counters, n, views, rp, L.capacity,
+                               ptile[0], pentry[0]);
         if ((err = hipGetLastError()) != hipSuccess) return err;
         // stable sort of the pairs by tile; the first pass drops culled pairs
         // and counts the rest into counters[kPairsKept]

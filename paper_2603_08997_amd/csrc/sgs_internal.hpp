@@ -123,9 +123,10 @@ hipError_t launch_order_tiles(const uint32_t* cost, int64_t tiles, int shift, ui
 // n is read on the device from *n_dev; n_max bounds it for the grid size.
 // Returns the index (0/1) of the buffer holding the result.
 int radix_passes(int bits);
-// K is uint32_t or uint16_t. kept_dev (nullable): the first pass drops keys
-// with all bits set (kCulledTile, or kCulledTile16 for uint16 keys) and writes
-// the number of remaining pairs there; later passes sort that many.
+// K is uint32_t or uint16_t. kept_dev (nullable, must hold 0): the first
+// pass drops keys with all bits set (kCulledTile, or kCulledTile16 for uint16
+// keys) and adds the number of remaining pairs there; later passes sort that
+// many.
 // gather_dst (nullable): the last pass also writes gather_src[value] at each
 // sorted position.
 template <typename K>

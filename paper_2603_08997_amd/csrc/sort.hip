@@ -116,7 +116,8 @@ __global__ void __launch_bounds__(kThreads) radix_hist_kernel(const K* __restric
 constexpr int kScanItems = 16;
 __global__ void __launch_bounds__(kScanThreads) radix_scan_kernel(uint32_t* __restrict__ hist,
                                                                   int nblocks,
-                                                                  uint32_t* __restrict__ totals) {
+                                                                  uint32_t* __restrict__ totals,
+                                                                  uint32_t* __restrict__ kept) {
     __shared__ uint32_t smem[kScanThreads / 64 + 1];
     uint32_t* row = hist + (int64_t)blockIdx.x * nblocks;
     const int per = min(kScanItems, (nblocks + kScanThreads - 1) / kScanThreads);
@@ -142,7 +143,11 @@ __global__ void __launch_bounds__(kScanThreads) radix_scan_kernel(uint32_t* __re
         }
         carry += tot;
     }
-    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+    if (threadIdx.x == 0) {
+        totals[blockIdx.x] = carry;
+        // the first tile-sort pass: the kept pairs are the sum of the rows
+        if (kept != nullptr) atomicAdd(kept, carry);
+    }
 }
 
 // Scatter of one block's kTile keys. Wave w owns the contiguous key range
@@ -250,15 +255,6 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
     }
 }
 
-// *kept = sum of the digit totals (the keys the first pass kept).
-__global__ void __launch_bounds__(kRadix) radix_kept_kernel(const uint32_t* __restrict__ totals,
-                                                           int radix, uint32_t* __restrict__ kept) {
-    __shared__ uint32_t smem[kRadix / 64 + 1];
-    uint32_t tot;
-    block_excl_scan<kRadix>(threadIdx.x < (unsigned)radix ? totals[threadIdx.x] : 0u, smem, &tot);
-    if (threadIdx.x == 0) *kept = tot;
-}
-
 }  // namespace
 
 int64_t radix_blocks(int64_t n_max) { return n_max <= 0 ? 1 : (n_max + kTile - 1) / kTile; }
@@ -292,10 +288,7 @@ hipError_t radix_sort(K* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int6
                            shift, pb, hist, nb, skip);
         // rows and totals of digits >= 2^pb are never read for a key of this pass
         hipLaunchKernelGGL(radix_scan_kernel, dim3(1u << pb), dim3(kScanThreads), 0, s, hist, nb,
-                           totals);
-        if (skip)
-            hipLaunchKernelGGL(radix_kept_kernel, dim3(1), dim3(kRadix), 0, s, totals, 1 << pb,
-                               kept_dev);
+                           totals, skip ? kept_dev : nullptr);
         const bool last = p == passes - 1;
         hipLaunchKernelGGL(radix_scatter_kernel<K>, dim3(nb), dim3(kThreads), 0, s, keys[cur],
                            vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_p, shift, pb, hist, totals,
