@@ -57,21 +57,29 @@ def _rows(path):
         return list(csv.DictReader(fh))
 
 
-def kernels_table(d: str, iterations: int = 40, marker: str = "project_kernel") -> str:
+def kernels_table(d: str, iterations: int = 40, marker: str = "project_kernel",
+                  require: str = "raster_backward") -> str:
     """Markdown table: time per iteration of each kernel over the last
-    `iterations` iterations of the trace (an iteration starts at each launch
-    of `marker`), then rocprofv3's own per-kernel statistics."""
+    `iterations` iterations of the trace that launch `require` (an iteration
+    starts at each launch of `marker`; iterations without `require`, such as
+    evaluation renders, are left out), then rocprofv3's own per-kernel
+    statistics."""
     trace = sorted(_rows(os.path.join(d, "run_kernel_trace.csv")),
                    key=lambda r: int(r["Start_Timestamp"]))
     names = [short_name(r["Kernel_Name"]) for r in trace]
-    starts = [i for i, n in enumerate(names) if n.startswith(marker)]
-    if len(starts) < iterations + 2:
+    starts = [i for i, n in enumerate(names) if n.startswith(marker)] + [len(trace)]
+    spans = [(a, b) for a, b in zip(starts, starts[1:])
+             if any(names[i].startswith(require) for i in range(a, b))]
+    if len(spans) < iterations:
         raise SystemExit("trace too short for the requested iterations")
-    a, b = starts[-2 - iterations], starts[-2]
+    spans = spans[-iterations:]
     agg = collections.defaultdict(list)
-    for r, n in zip(trace[a:b], names[a:b]):
-        agg[n].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
-    wall = (int(trace[b - 1]["End_Timestamp"]) - int(trace[a]["Start_Timestamp"])) / 1e3
+    wall = 0.0
+    for a, b in spans:
+        for r, n in zip(trace[a:b], names[a:b]):
+            agg[n].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        last = max(i for i in range(a, b) if not names[i].startswith("__amd"))
+        wall += (int(trace[last]["End_Timestamp"]) - int(trace[a]["Start_Timestamp"])) / 1e3
     out = ["| kernel | us/iter | launches/iter | us/launch |", "|---|---|---|---|"]
     tot = 0.0
     for n, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
@@ -80,11 +88,11 @@ def kernels_table(d: str, iterations: int = 40, marker: str = "project_kernel") 
         if per >= 1.0:
             out.append(f"| `{n}` | {per:.1f} | {len(v) / iterations:.1f} | {sum(v) / len(v):.1f} |")
     out.append(f"| **sum of kernel time** | {tot:.1f} | | |")
-    out.append(f"| **wall time per iteration (first to last kernel)** | "
+    out.append(f"| **first kernel start to last kernel end, per iteration** | "
                f"{wall / iterations:.1f} | | |")
-    stats = _rows(os.path.join(d, "run_kernel_stats.csv"))
     out += ["", "rocprofv3 statistics over the whole run (all dispatches, setup included):", "",
             "| kernel | calls | average us | min us | max us |", "|---|---|---|---|---|"]
+    stats = _rows(os.path.join(d, "run_kernel_stats.csv"))
     for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:16]:
         out.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | "
                    f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
