@@ -18,6 +18,7 @@ before the timed region starts.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -56,7 +57,8 @@ def parse():
     ap.add_argument("--width", type=int, default=1600)
     ap.add_argument("--height", type=int, default=1060)
     ap.add_argument("--gate", choices=["windowed", "paper"], default="windowed")
-    ap.add_argument("--runs", default="gated,full")
+    ap.add_argument("--runs", default="gated,full",
+                    help="comma list of gated, full, paper, paper_nobudget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stage-events", action="store_true")
     ap.add_argument("--eval-views", type=int, default=200)
@@ -271,11 +273,18 @@ def main():
 
     results = {}
     for run in args.runs.split(","):
-        if run not in ("gated", "full", "paper"):
-            raise SystemExit(f"unknown run {run!r} (gated, full, paper)")
+        if run not in ("gated", "full", "paper", "paper_nobudget"):
+            raise SystemExit(f"unknown run {run!r} (gated, full, paper, paper_nobudget)")
         # paper: the gate with the paper's own settings (decay 0.95, no
-        # tolerance, 500 warmup iterations, calibrated cumulative budget)
-        gp = sk.paper_gate(args.views) if run == "paper" else gate
+        # tolerance, 500 warmup iterations, calibrated cumulative budget);
+        # paper_nobudget: the same without the minimum-backward budget (the
+        # "w/o budget" row of the paper's ablation, Table 4)
+        if run == "paper":
+            gp = sk.paper_gate(args.views)
+        elif run == "paper_nobudget":
+            gp = dataclasses.replace(sk.paper_gate(args.views), budget=False)
+        else:
+            gp = gate
         tr = Trainer(init, cams, targets, rp, gp, cap, gated=(run != "full"))
         gslots = torch.zeros(args.warmup + args.steps, dtype=torch.int32, device=dev)
         for t in range(args.warmup):
@@ -401,15 +410,17 @@ def main():
         if gated.get("stage_ms_skipped") and full.get("stage_ms_all"):
             c = sum(gated["stage_ms_skipped"].values()) / sum(full["stage_ms_all"].values())
             out["skipped_iteration_cost"] = c
-    paper = results.get("paper")
-    if paper:
-        out["paper_iters_per_s"] = paper["iters_per_s"]
-        out["paper_skip_fraction"] = 1.0 - paper["backward_fraction"]
-        out["final_loss_paper"] = paper["final_mean_loss"]
+    for name in ("paper", "paper_nobudget"):
+        r = results.get(name)
+        if not r:
+            continue
+        out[f"{name}_iters_per_s"] = r["iters_per_s"]
+        out[f"{name}_skip_fraction"] = 1.0 - r["backward_fraction"]
+        out[f"final_loss_{name}"] = r["final_mean_loss"]
         if full:
-            out["paper_over_full"] = paper["iters_per_s"] / full["iters_per_s"]
-            out["final_loss_paper_rel_diff"] = (paper["final_mean_loss"] -
-                                                full["final_mean_loss"]) / full["final_mean_loss"]
+            out[f"{name}_over_full"] = r["iters_per_s"] / full["iters_per_s"]
+            out[f"final_loss_{name}_rel_diff"] = (r["final_mean_loss"] -
+                                                  full["final_mean_loss"]) / full["final_mean_loss"]
     for k, r in results.items():
         out[f"stages_{k}"] = {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                               for kk, vv in r.get("stage_ms_executed", {}).items()}
