@@ -46,17 +46,19 @@ struct PairCountSrc {  // tiles touched, in depth order (gathered by the depth s
     __device__ uint32_t operator()(int64_t k) const { return tiles_sorted[k]; }
 };
 // Pair offset of every Gaussian in depth order, and for every emission window
-// (kEmitWindow consecutive pairs, windows 0 .. n_windows) the Gaussian whose
-// pair range holds the window's first pair.
+// (kEmitWindow consecutive emission units, windows 0 .. n_windows) the
+// Gaussian whose units hold the window's first unit. Gaussian k owns units
+// [pos + kEmitHead k, pos + kEmitHead (k + 1) + v).
 struct OffsetSink {
     uint32_t* offsets;
     uint32_t* window_first;
     uint32_t n_windows;
     __device__ void operator()(int64_t k, uint32_t v, uint32_t pos) const {
         offsets[k] = pos;
-        const uint32_t end = pos + v;
-        for (uint32_t w = (pos + (uint32_t)kEmitWindow - 1u) / (uint32_t)kEmitWindow;
-             w <= n_windows && (uint64_t)w * kEmitWindow < end; ++w)
+        const uint64_t first = (uint64_t)pos + (uint64_t)kEmitHead * (uint64_t)k;
+        const uint64_t end = first + (uint64_t)kEmitHead + v;
+        for (uint64_t w = (first + kEmitWindow - 1) / kEmitWindow;
+             w <= n_windows && w * kEmitWindow < end; ++w)
             window_first[w] = (uint32_t)k;
     }
 };
@@ -170,13 +172,16 @@ __device__ __forceinline__ bool tile_reachable(float u, float v, float a, float 
     return best <= lim;
 }
 
-// Pair emission, load balanced over pairs: each workgroup writes a fixed
-// window of kEmitTile consecutive pairs. The Gaussians (in depth order) whose
-// pair ranges meet the window run from the one holding the window's first pair
-// to the one holding the next window's first pair (both recorded by the offset
-// scan); their tile rectangles are staged in LDS, a max-scan of their start
-// positions gives every window position its Gaussian, and every thread expands
-// its pairs to (tile, entry) with coalesced stores. Pair q of a Gaussian is
+// Pair emission, load balanced over emission units (a few header units per
+// Gaussian, then one per pair): each workgroup takes a fixed window of
+// kEmitTile consecutive units. The Gaussians (in depth order) whose units meet
+// the window run from the one holding the window's first unit to the one
+// holding the next window's first unit (both recorded by the offset scan); the
+// header units bound their number, and so the LDS a workgroup needs (more
+// workgroups in flight hide the dependent loads of each). Their tile
+// rectangles are staged in LDS, a max-scan of their start positions gives
+// every window position its Gaussian, and every thread expands its pairs to
+// (tile, entry) with coalesced stores. Pair q of a Gaussian is
 // tile (x0 + q % w, y0 + q / w) of its rectangle, row-major; pairs that fail
 // the exact tile test get the all-ones key (kCulledTile, or kCulledTile16
 // when the batch keeps uint16 tile keys).
@@ -184,8 +189,8 @@ constexpr int kEmitThreads = 256;
 constexpr int kEmitItems = 4;
 constexpr int kEmitTile = kEmitThreads * kEmitItems;
 static_assert(kEmitTile == kEmitWindow, "emission window size");
-// Gaussians meeting one window: at most one per pair plus the next window's first.
-constexpr int kEmitMaxG = kEmitTile + 1;
+// Gaussians meeting one window: each owns at least kEmitHead + 1 units.
+constexpr int kEmitMaxG = kEmitTile / (kEmitHead + 1) + 2;
 
 template <typename K>
 __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
@@ -213,16 +218,16 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     }
     const uint32_t nvis = counters[kVisible];
     const int win = blockIdx.x;
-    const uint32_t p0 = (uint32_t)win * (uint32_t)kEmitTile;
-    if (p0 >= P) return;   // uniform across the workgroup
-    const uint32_t p_last = min(p0 + (uint32_t)kEmitTile, P) - 1u;
+    const uint64_t c0 = (uint64_t)win * kEmitTile;   // first unit of the window
+    const uint64_t units = (uint64_t)total + (uint64_t)kEmitHead * nvis;
+    if (c0 >= units) return;   // uniform across the workgroup
     const int tid = threadIdx.x;
     const uint32_t k0 = window_first[win];
-    // the next window's first Gaussian exists whenever pairs continue past
+    // the next window's first Gaussian exists whenever units continue past
     // this window; otherwise the window ends with the last visible Gaussian
-    const uint32_t k1 = (uint64_t)p0 + kEmitTile < total ? window_first[win + 1]
-                                                          : nvis - 1u;
+    const uint32_t k1 = c0 + kEmitTile < units ? window_first[win + 1] : nvis - 1u;
     const uint32_t cnt = k1 - k0 + 1u;
+    if (k1 < k0 || cnt > (uint32_t)kEmitMaxG) return;   // cannot happen: the header bound
 #pragma unroll
     for (int it = 0; it < kEmitItems; ++it) s_own[it * kEmitThreads + tid] = 0u;
     __syncthreads();
@@ -243,8 +248,9 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
         s_x0[j] = (uint16_t)x0;
         s_y0[j] = (uint16_t)y0;
         s_lim[j] = reach_limit(r1.y, rp);
-        // mark where this Gaussian's pairs start inside the window
-        if (j > 0 && off - p0 < (uint32_t)kEmitTile) s_own[off - p0] = j;
+        // mark where this Gaussian's units start inside the window
+        const uint64_t first = (uint64_t)off + (uint64_t)kEmitHead * k;
+        if (j > 0 && first - c0 < (uint64_t)kEmitTile) s_own[first - c0] = j;
     }
     __syncthreads();
     // owner of every window position = the last Gaussian starting at or
@@ -265,25 +271,33 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     }
     __syncthreads();
     // gather every item's record first (one round of memory latency), then
-    // test and store
-    uint32_t own[kEmitItems];
+    // test and store; header units and units past the written pairs do nothing
+    uint32_t own[kEmitItems], qq[kEmitItems], pp[kEmitItems];
+    bool pair[kEmitItems];
     float4 g0[kEmitItems], g1[kEmitItems];
 #pragma unroll
     for (int it = 0; it < kEmitItems; ++it) {
-        const uint32_t p = p0 + (uint32_t)(it * kEmitThreads + tid);
-        own[it] = s_own[it * kEmitThreads + tid];
-        if (p <= p_last) {
-            const int64_t e = s_ent[own[it]];
+        const uint64_t c = c0 + (uint64_t)(it * kEmitThreads + tid);
+        const uint32_t j = s_own[it * kEmitThreads + tid];
+        const uint64_t first = (uint64_t)s_off[j] + (uint64_t)kEmitHead * (k0 + j);
+        const bool is_pair = c < units && c >= first + (uint64_t)kEmitHead;
+        const uint32_t q = is_pair ? (uint32_t)(c - first - (uint64_t)kEmitHead) : 0u;
+        const uint32_t p = s_off[j] + q;
+        own[it] = j;
+        qq[it] = q;
+        pp[it] = p;
+        pair[it] = is_pair && p < P;
+        if (pair[it]) {
+            const int64_t e = s_ent[j];
             g0[it] = rec[3 * e];
             g1[it] = rec[3 * e + 1];
         }
     }
 #pragma unroll
     for (int it = 0; it < kEmitItems; ++it) {
-        const uint32_t p = p0 + (uint32_t)(it * kEmitThreads + tid);
-        if (p > p_last) break;
+        if (!pair[it]) continue;
         const uint32_t j = own[it];
-        const uint32_t q = p - s_off[j];
+        const uint32_t q = qq[it], p = pp[it];
         const uint32_t w = s_w[j];
         // q / w and q % w through a float reciprocal, corrected to exact
         uint32_t qy = (uint32_t)((float)q * __builtin_amdgcn_rcpf((float)w));
@@ -410,13 +424,13 @@ hipError_t launch_bin(const Views& views, const RasterDev& rp, int64_t n, const 
                          tiles, offsets);
         if (err != hipSuccess) return err;
         // pair offsets in depth order; total -> counters[kPairs]
-        const uint32_t n_windows = (uint32_t)((L.capacity + kEmitWindow - 1) / kEmitWindow);
+        const uint32_t n_windows = (uint32_t)emit_windows(E, L.capacity);
         err = device_scan(PairCountSrc{offsets, counters + kVisible},
                           OffsetSink{offsets, window_first, n_windows}, E, sums,
                           counters + kPairs, s);
         if (err != hipSuccess) return err;
         // at least one workgroup: block 0 also records the written pair count
-        const dim3 egrid((unsigned)std::max<int64_t>(1, (L.capacity + kEmitTile - 1) / kEmitTile));
+        const dim3 egrid((unsigned)std::max<int64_t>(1, emit_windows(E, L.capacity)));
         if (key16)
             hipLaunchKernelGGL(emit_kernel<uint16_t>, egrid, dim3(kEmitThreads), 0, s, dval[res],
                                offsets, window_first, rec, counters, n, views, rp, L.capacity,

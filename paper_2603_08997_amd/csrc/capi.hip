@@ -201,7 +201,7 @@ void make_layout(const Views& views, int64_t n, int64_t capacity, Layout* L) {
     L->dval[0] = take(sizeof(uint32_t) * (size_t)E);
     L->dval[1] = take(sizeof(uint32_t) * (size_t)E);
     L->offsets = take(sizeof(uint32_t) * (size_t)E);
-    L->window_first = take(sizeof(uint32_t) * (size_t)((capacity + kEmitWindow - 1) / kEmitWindow + 1));
+    L->window_first = take(sizeof(uint32_t) * (size_t)(emit_windows(E, capacity) + 1));
     L->scan_sums = take(sizeof(uint32_t) * (size_t)(L->scan_blocks + 1));
     L->pair_tile[0] = take((size_t)L->tile_key_bytes * (size_t)capacity);
     L->pair_tile[1] = take((size_t)L->tile_key_bytes * (size_t)capacity);

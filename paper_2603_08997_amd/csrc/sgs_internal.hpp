@@ -72,8 +72,16 @@ constexpr uint32_t kCulledTile = 0xffffffffu;
 constexpr uint16_t kCulledTile16 = 0xffffu;
 constexpr int64_t kMaxTiles16 = 0xffff;
 
-// Pairs written by one workgroup of the emission kernel.
+// Emission units: each visible Gaussian (in depth order) owns kEmitHead
+// header units followed by one unit per pair; a workgroup of the emission
+// kernel covers a window of kEmitWindow consecutive units, so it meets at
+// most kEmitWindow / (kEmitHead + 1) + 2 Gaussians.
 constexpr int64_t kEmitWindow = 1024;
+constexpr int64_t kEmitHead = 2;
+// Windows of an emission over `entries` entries and `capacity` pairs.
+constexpr int64_t emit_windows(int64_t entries, int64_t capacity) {
+    return (capacity + kEmitHead * entries + kEmitWindow - 1) / kEmitWindow;
+}
 
 struct Layout {
     int64_t entries, total_tiles, total_pixels, capacity;
