@@ -212,6 +212,9 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
         // the next entry's LDS reads are issued before the current entry is
         // processed, so a wave running alone does not wait on them
         float4 Gn = s_geo[0], Xn = s_aux[0], Cn = s_col[0];
+        // unrolled twice: the prefetched records alternate between two
+        // register sets instead of being copied at the end of every step
+#pragma unroll 2
         for (int j = 0; j < cnt && live != 0u; ++j) {
             const float4 G = Gn, X = Xn, c = Cn;
             const int jn = min(j + 1, cnt - 1);
