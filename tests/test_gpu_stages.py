@@ -167,16 +167,27 @@ def _oracle_composite(rec, cam, rp, n, view, leaf=False):
 @pytest.mark.parametrize("tile", TILES)
 def test_raster_forward_and_backward_match_oracle(tile):
     require_gpu()
+    _check_raster(tile)
+
+
+def test_raster_nondefault_params_match_oracle():
+    """alpha_min = 0 (no skip threshold: log2 alpha_min = -inf, no exact tile
+    culling), alpha_max = 0.9 and t_min = 1e-3."""
+    require_gpu()
+    _check_raster((16, 16), alpha_min=0.0, alpha_max=0.9, t_min=1e-3)
+
+
+def _check_raster(tile, **params):
     m = sg()
     tw, th = tile
     cams = _views()
     n = 900
     recs, cat = _records(n, cams, 300, max_radius=14)
     bg = (0.2, 0.4, 0.6)
-    say(f"raster tile={tile} n={n}")
-    st = Stage(n, cams, m.RasterParams(tile_w=tw, tile_h=th, bg=bg), cat, 400_000)
+    say(f"raster tile={tile} n={n} {params}")
+    st = Stage(n, cams, m.RasterParams(tile_w=tw, tile_h=th, bg=bg, **params), cat, 400_000)
     rgb, tf, nl = st.rasterize()
-    orp = R.RasterParams(tile_w=tw, tile_h=th, bg=bg)
+    orp = R.RasterParams(tile_w=tw, tile_h=th, bg=bg, **params)
     _, ents, granges = st.lists()
     rng = np.random.default_rng(5)
     dls, flips_total = [], 0
