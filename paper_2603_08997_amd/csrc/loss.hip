@@ -214,18 +214,24 @@ __global__ void __launch_bounds__(kThreads) ssim_backward_kernel(
                               ? maps[(f * 3 + ch) * plane + (int64_t)gy * w + gx] : 0.f;
         }
         __syncthreads();
-        for (int i = tid; i < kE * kT; i += kThreads) {
-            const int r = i / kT, c = i % kT;
-            float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+        // horizontal pass: two neighbouring outputs per thread share 10 of
+        // their 12 inputs (kE rows x kT / 2 pairs: one round of the workgroup)
+        for (int i = tid; i < kE * (kT / 2); i += kThreads) {
+            const int r = i / (kT / 2), c = 2 * (i % (kT / 2));
 #pragma unroll
-            for (int k = 0; k < 11; ++k) {
-                s0 = fmaf(W.g[k], sm[0][r][c + k], s0);
-                s1 = fmaf(W.g[k], sm[1][r][c + k], s1);
-                s2 = fmaf(W.g[k], sm[2][r][c + k], s2);
+            for (int f = 0; f < 3; ++f) {
+                float v[12];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) v[k] = sm[f][r][c + k];
+                float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+                for (int k = 0; k < 11; ++k) {
+                    s0 = fmaf(W.g[k], v[k], s0);
+                    s1 = fmaf(W.g[k], v[k + 1], s1);
+                }
+                hb[f][r][c] = s0;
+                hb[f][r][c + 1] = s1;
             }
-            hb[0][r][c] = s0;
-            hb[1][r][c] = s1;
-            hb[2][r][c] = s2;
         }
         __syncthreads();
         const int r = tid / kT, c = tid % kT;
