@@ -50,8 +50,11 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 10000 iterations of the training workload, "
+                         "20 batches of the batched one)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps first (default: 20 iterations, 2 batches)")
     ap.add_argument("--n", type=int, default=3_000_000)
     ap.add_argument("--views", type=int, default=200)
     ap.add_argument("--width", type=int, default=1600)
@@ -148,7 +151,8 @@ def run_batched(args):
     px = sum(c.width * c.height for c in cams)
     dl = torch.randn(3 * px, device="cuda", generator=torch.Generator(device="cuda").manual_seed(7))
     grads = torch.zeros_like(planes)
-    steps, warm = max(3, args.steps), max(1, args.warmup)
+    steps = max(3, args.steps if args.steps is not None else 20)
+    warm = max(1, args.warmup if args.warmup is not None else 2)
     ev = lambda: torch.cuda.Event(enable_timing=True)
     results = {}
     for tw, th in ((16, 16), (8, 8), (32, 8)):
@@ -195,6 +199,7 @@ def run_batched(args):
             torch.cuda.synchronize()
             return a.elapsed_time(b) / steps
 
+        log(f"tiles {tw}x{th}: capacity {cap} pairs; timing {steps} steps per mode")
         r = {"per_view_ms": timeit(per_view), "batched_ms": timeit(batched)}
         # graph of the batched launch, replayed; the first replay's image must
         # equal the eager one
@@ -249,6 +254,10 @@ def main():
     if args.workload == "batched":
         torch.cuda.set_device(0)
         return run_batched(args)
+    if args.steps is None:
+        args.steps = 10000
+    if args.warmup is None:
+        args.warmup = 20
     from paper_2603_08997_amd import scenes as S
     from paper_2603_08997_amd import skipgs as sk
     from paper_2603_08997_amd.train import StageTimer, Trainer, measure_pairs, render_targets
