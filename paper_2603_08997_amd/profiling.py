@@ -141,6 +141,43 @@ def traffic(fetch_dir: str, write_dir: str, copy_bytes: int) -> dict:
     return out
 
 
+def issue(pmc_dir: str, trace_dir: str | None, simds: int, clock_ghz: float) -> dict:
+    """VALU issue utilisation per kernel from a counter run (SQ_INSTS_VALU ...):
+    sum of VALU instructions x 4 cycles (a wave64 instruction on a 16-lane SIMD)
+    / sum of (duration x clock x SIMDs). Durations are the counter run's own
+    dispatch timestamps, or, with `trace_dir`, those of a kernel trace of the
+    same command (the k-th launch of each kernel in both)."""
+    counts = collections.defaultdict(list)
+    durs = collections.defaultdict(list)
+    seen = set()
+    for r in sorted(_rows(os.path.join(pmc_dir, "run_counter_collection.csv")),
+                    key=lambda r: int(r["Dispatch_Id"])):
+        name = short_name(r["Kernel_Name"])
+        counts[(name, r["Counter_Name"])].append(float(r["Counter_Value"]))
+        if trace_dir is None and r["Dispatch_Id"] not in seen:
+            seen.add(r["Dispatch_Id"])
+            durs[name].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+    if trace_dir is not None:
+        for r in sorted(_rows(os.path.join(trace_dir, "run_kernel_trace.csv")),
+                        key=lambda r: int(r["Start_Timestamp"])):
+            durs[short_name(r["Kernel_Name"])].append(
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+    out = {}
+    for (name, ctr), vals in counts.items():
+        if ctr != "SQ_INSTS_VALU" or name not in durs:
+            continue
+        k = min(len(vals), len(durs[name]))
+        busy = sum(durs[name][:k]) * clock_ghz * 1e9 * simds
+        rec = {"dispatches": k, "valu_instructions_per_dispatch": sum(vals[:k]) / k,
+               "seconds_per_dispatch": sum(durs[name][:k]) / k,
+               "valu_issue_utilisation": sum(vals[:k]) * 4 / busy}
+        for other in ("SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM"):
+            if (name, other) in counts:
+                rec[other.lower() + "_per_dispatch"] = sum(counts[(name, other)][:k]) / k
+        out[name] = rec
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -157,7 +194,29 @@ def main(argv=None):
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--command", required=True)
     t.add_argument("--out", required=True)
+    i = sub.add_parser("issue")
+    i.add_argument("pmc_dir")
+    i.add_argument("--trace-dir", default=None)
+    i.add_argument("--simds", type=int, default=1024)
+    i.add_argument("--clock-ghz", type=float, default=2.4)
+    i.add_argument("--command", required=True)
+    i.add_argument("--out", required=True)
     a = ap.parse_args(argv)
+    if a.cmd == "issue":
+        res = issue(a.pmc_dir, a.trace_dir, a.simds, a.clock_ghz)
+        lines = [f"{k}: {v['valu_issue_utilisation']:.1%} VALU issue over {v['dispatches']} "
+                 f"dispatches ({v['valu_instructions_per_dispatch'] / 1e6:.1f}M VALU "
+                 f"instructions, {v['seconds_per_dispatch'] * 1e6:.1f} us each)"
+                 for k, v in sorted(res.items())]
+        text = ("VALU issue utilisation (rocprofv3 SQ_INSTS_VALU per dispatch over the "
+                "dispatch's duration; wave64 VALU = 4 cycles on a 16-lane SIMD, "
+                f"{a.simds} SIMDs at {a.clock_ghz} GHz)\n\n" + "\n".join(lines) +
+                "\n\nCommand (repository root, one MI355X):\n\n    " + a.command + "\n\n" +
+                f"Source digest: `{source_digest()}`\n\n" + json.dumps(res, indent=1) + "\n")
+        with open(a.out, "w") as fh:
+            fh.write(text)
+        print(text)
+        return
     if a.cmd == "kernels":
         body = kernels_table(a.dir, a.iterations)
         text = (f"# {a.title}\n\n{a.about}\n\nCommand (repository root, one MI355X):\n\n"
