@@ -362,6 +362,10 @@ __global__ void __launch_bounds__(kLanes, 7) raster_backward_kernel(
             const uint32_t rel = b_end - 1u - (uint32_t)j - start;   // list position
             const float4 G = s_geo[j];
             const float4 X = s_aux[j];
+            // read once per Gaussian with the coefficients (the compiler would
+            // otherwise re-read it inside each pixel's branch)
+            const float4 c = s_col[j];
+            asm volatile("" ::"v"(c.x), "v"(c.y), "v"(c.z));
             const LaneTerms L = lane_terms(G, X, px, col, row0);
             // -0 is the additive identity for every float, so the first
             // accumulation into each sum folds away
@@ -374,13 +378,12 @@ __global__ void __launch_bounds__(kLanes, 7) raster_backward_kernel(
                 if ((rel < last[k]) & takes_part(((L.m >> (RS * k)) & 1u) != 0u, e, X, lmin)) {
                     const float raw = __builtin_amdgcn_exp2f(e);
                     const bool clamped = raw > amax;
-                    const float alpha = clamped ? amax : raw;
+                    const float alpha = fminf(raw, amax);
                     // 1 - alpha' >= 1 - alpha_max > 0: one hardware reciprocal
                     // (1 ulp) serves the transmittance recovery and dC/dalpha'
                     const float inv_om = __builtin_amdgcn_rcpf(1.f - alpha);
                     const float Ti = T[k] * inv_om;
                     const float w = alpha * Ti;
-                    const float4 c = s_col[j];
                     d_r = fmaf(G0[k], w, d_r);
                     d_g = fmaf(G1[k], w, d_g);
                     d_bl = fmaf(G2[k], w, d_bl);
