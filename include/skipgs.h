@@ -109,7 +109,7 @@ void sgs_default_raster_params(sgs_raster_params* rp);
  * one batch of launches: projection of every (view, Gaussian) entry, a
  * depth-ordered tile binning of all views together, and compositing of every
  * tile of every view. Each pixel composites, front to back in (depth,
- * Gaussian index) order, the Gaussians whose cut-off square contains the pixel
+ * Gaussian index) order, the Gaussians whose overlap box contains the pixel
  * centre (C(p) = sum c_i alpha'_i T_i + bg T_final).
  *
  * The workspace holds everything the backward needs (projected records, the
@@ -181,8 +181,9 @@ sgs_status sgs_load_records(const sgs_camera* cams, int32_t n_views, int64_t n,
                             const float* depth, const int32_t* extent, const float* conic,
                             const float* opacity, const float* rgb, void* stream);
 
-/* Tile binning: depth-ordered, per-tile lists of every visible entry,
- * ties in depth broken by ascending entry index. */
+/* Tile binning: depth-ordered, per-tile lists of the visible entries whose
+ * overlap box reaches the tile and that can reach alpha_min at one of its pixel
+ * centres, ties in depth broken by ascending entry index. */
 sgs_status sgs_bin(const sgs_camera* cams, int32_t n_views, int64_t n, const sgs_raster_params* rp,
                    void* workspace, size_t workspace_bytes, int64_t pair_capacity, void* stream);
 
@@ -217,7 +218,8 @@ sgs_status sgs_project_backward(const sgs_gaussians* g, const sgs_camera* cams, 
  * t_final:    float32 [total_pixels]  final transmittance per pixel
  * n_last:     uint32  [total_pixels]  1 + list position of the last blended pair (0: none)
  * accum:      float32 [entries][12]   du dv da db | dc do dr dg | db 0 0 0
- * counters:   uint32  [8]             status, visible, pairs, ... */
+ * counters:   uint32  [16]            status, visible, pairs needed, pairs written,
+ *                                     blended (u64), examined (u64), pairs kept, ... */
 typedef struct {
     size_t records, tiles, depth, pair_tile, pair_entry, ranges, t_final, n_last, accum, counters;
     int64_t entries, total_tiles, total_pixels;

@@ -1,13 +1,15 @@
 // Tile binning: the depth-ordered per-tile lists of the tile-based rasteriser.
 //
-// The lists must hold, for every tile, the visible entries whose cut-off
-// square reaches the tile, in ascending (depth, entry) order. Instead of one
+// The lists must hold, for every tile, the visible entries whose overlap box
+// reaches the tile and that can reach alpha_min at one of its pixel centres
+// (the exact tile test below), in ascending (depth, entry) order. Instead of one
 // radix sort over 64-bit (tile << 32 | depth) keys, the stage sorts the
 // visible entries once by depth (a short array), emits their (tile, entry)
 // pairs in that order, and then sorts the pairs stably by tile alone. A
 // stable sort keeps the depth order inside each tile, so the lists are the
 // same as those of the 64-bit sort while the long pair array is sorted on
-// ceil(log2(tiles)) bits instead of 32 + that many.
+// ceil(log2(tiles)) bits instead of 32 + that many (uint16 keys when a batch
+// has fewer than 65535 tiles).
 #include <algorithm>
 
 #include "sgs_internal.hpp"

@@ -26,10 +26,10 @@
 // alpha'_i) and, per pixel, G.S = sum over channels of dL/dC times the colour
 // accumulated behind the Gaussian, so no per-pixel blend list is stored. A
 // Gaussian's gradient is gathered per lane as moments of dL/dP over its
-// pixels, combined over the 64 lanes with DPP reductions, and one lane turns
-// them into the 9 parameter gradients and issues the hardware float atomics
-// of that (tile, Gaussian) pair; Gaussians that touch no pixel of the tile
-// skip both.
+// pixels, turned into the 9 parameter gradients per lane, summed over the 64
+// lanes reduce-scatter style (lane k ends with gradient k), and added with one
+// hardware float atomic instruction over 9 lanes for that (tile, Gaussian)
+// pair; Gaussians that touch no pixel of the tile skip both.
 //
 // All tiles of a launch are resident at once, so a launch lasts as long as
 // its busiest SIMD. The forward records each tile's work for the backward

@@ -127,7 +127,7 @@ hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_order_tiles(const uint32_t* cost, int64_t tiles, int shift, uint32_t* order,
                               const int32_t* gate, hipStream_t s);
 
-// Stable LSD radix sort of (key, value) uint32 pairs over bits [0, bits).
+// Stable LSD radix sort of (key, uint32 value) pairs over key bits [0, bits).
 // n is read on the device from *n_dev; n_max bounds it for the grid size.
 // Returns the index (0/1) of the buffer holding the result.
 int radix_passes(int bits);
