@@ -32,7 +32,8 @@ thresholds unstated; the readings used here (fixed in ``RasterParams``) are:
   alpha' < alpha_min skips the Gaussian for that pixel; compositing stops
   before a Gaussian that would take the transmittance below t_min;
 * background colour bg is added with weight T_final;
-* depth order ties are broken by ascending Gaussian index.
+* the depth order is that of the float32 camera depth; ties (equal float32
+  depths) are broken by ascending Gaussian index.
 """
 from __future__ import annotations
 
@@ -353,8 +354,11 @@ def bin_and_sort(u32, v32, depth32, extent, ids, width, height, tile_w, tile_h,
 # Compositing (Eqs. 4-5)
 # ---------------------------------------------------------------------------
 def depth_order(depth: torch.Tensor, ids: torch.Tensor) -> torch.Tensor:
-    """Permutation sorting by (depth, Gaussian index) ascending."""
-    d = depth.detach().numpy()
+    """Permutation sorting by (depth rounded to float32, Gaussian index)
+    ascending: the renderer's depth key is the float32 camera depth, so two
+    Gaussians whose depths round to the same float32 value count as tied and
+    keep ascending index order."""
+    d = np.asarray(depth.detach().numpy(), dtype=np.float32)
     i = ids.numpy() if isinstance(ids, torch.Tensor) else np.asarray(ids)
     return torch.as_tensor(np.lexsort((i, d)), dtype=torch.int64)
 
@@ -461,18 +465,4 @@ def render(means, log_scales, quats, opacity_logits, sh, sh_degree, cam, rp: Ras
     out = composite(pr["uv"], pr["conic"], pr["opacity"], pr["rgb"], pr["depth"], pr["extent"],
                     pr["ids"], cam.width, cam.height, rp, px=px, py=py)
     out["proj"] = pr
-    return out
-
-
-def list_position(last_gid: np.ndarray, px: np.ndarray, py: np.ndarray, vals: np.ndarray,
-                  ranges: np.ndarray, tile_w: int, tile_h: int, tiles_x: int) -> np.ndarray:
-    """1 + the position of Gaussian ``last_gid`` in its pixel's tile list (0 if -1)."""
-    out = np.zeros(len(last_gid), dtype=np.int64)
-    for k, (g, x, y) in enumerate(zip(last_gid, px, py)):
-        if g < 0:
-            continue
-        t = (y // tile_h) * tiles_x + (x // tile_w)
-        s, e = ranges[t]
-        where = np.nonzero(vals[s:e] == g)[0]
-        out[k] = where[0] + 1
     return out

@@ -134,6 +134,28 @@ def test_equal_depth_ties_break_by_index():
     assert out["last"].item() == 7
 
 
+def test_depths_equal_in_float32_tie_and_break_by_index():
+    """The depth key is the float32 camera depth: Gaussian 3 lies 5e-9 behind
+    Gaussian 7 in binary64, but both depths round to the same float32 value,
+    so they tie and the lower index (3, green) is composited first."""
+    assert np.float32(2.0 + 5e-9) == np.float32(2.0) and 2.0 + 5e-9 > 2.0
+    uv = torch.tensor([[3.5, 3.5], [3.5, 3.5]], dtype=DT)
+    conic = torch.tensor([[0.5, 0.0, 0.5]] * 2, dtype=DT)
+    o = torch.tensor([0.5, 0.5], dtype=DT)
+    rgb = torch.tensor([[1.0, 0, 0], [0, 1.0, 0]], dtype=DT)
+    depth = torch.tensor([2.0, 2.0 + 5e-9], dtype=DT)
+    out = R.composite(uv, conic, o, rgb, depth, torch.tensor([[3, 3], [3, 3]]),
+                      torch.tensor([7, 3]), 8, 8, R.RasterParams(), px=[3], py=[3])
+    assert np.allclose(out["rgb"][:, 0].numpy(), [0.25, 0.5, 0.0], atol=1e-15)
+    assert out["last"].item() == 7
+    # one float32 step apart, the nearer one is in front whatever the index
+    depth = torch.tensor([float(np.nextafter(np.float32(2.0), np.float32(3.0))), 2.0], dtype=DT)
+    out = R.composite(uv, conic, o, rgb, depth, torch.tensor([[3, 3], [3, 3]]),
+                      torch.tensor([3, 7]), 8, 8, R.RasterParams(), px=[3], py=[3])
+    assert np.allclose(out["rgb"][:, 0].numpy(), [0.25, 0.5, 0.0], atol=1e-15)
+    assert out["last"].item() == 3
+
+
 def test_single_isotropic_splat_closed_form():
     """One isotropic Gaussian on the optical axis at depth d: its screen
     covariance is ((f s / d)^2 + h) I, so alpha'(p) = o exp(-|p - c|^2 / (2 sigma^2))

@@ -143,3 +143,59 @@ def test_dense_crop_gradient_matches_central_differences():
             assert abs(fd - an) <= 2e-6 * scale + 1e-6 * abs(an), (grp, idx, fd, an)
             checked += 1
     assert checked >= 40
+
+
+def test_gradient_beyond_the_jacobian_clamp_matches_central_differences():
+    """Large Gaussians whose centres lie beyond the Jacobian clamp (tx/tz or
+    ty/tz past +-1.3 half-extents over the focal length) with thresholds on:
+    the analytic gradient (zero through the clamped coordinates) against
+    central differences of the forward, at decision-stable points, for every
+    parameter group."""
+    cam = S.look_at_camera((0.5, -4.0, 1.5), 40, 30)
+    Rc, t = cam.R.astype(np.float64), cam.t.astype(np.float64)
+    C = -Rc.T @ t
+    fr = [(1.613, 0.217), (-1.907, -0.389), (0.291, 1.823), (-0.517, -2.093), (1.541, 1.487),
+          (0.109, 0.123)]
+    means = np.array([C + (2.6 + 0.13 * k) * (Rc[2] + a * (cam.width / 2.0) / cam.fx * Rc[0]
+                                              + b * (cam.height / 2.0) / cam.fy * Rc[1])
+                      for k, (a, b) in enumerate(fr)])
+    n = len(means)
+    rng = np.random.default_rng(41)
+    arrs = dict(means=means, log_scales=rng.normal(np.log(0.5), 0.1, (n, 3)),
+                quats=rng.normal(size=(n, 4)), opacity_logits=rng.normal(0.5, 0.3, n),
+                sh=np.concatenate([rng.uniform(-1.0, 1.0, (n, 1, 3)),
+                                   rng.normal(0, 0.3, (n, 3, 3))], 1))
+    rp = R.RasterParams()
+    # the clamp is active for all but the last Gaussian
+    tc = means @ Rc.T + t
+    lim_x = 1.3 * (cam.width / 2.0) / cam.fx
+    lim_y = 1.3 * (cam.height / 2.0) / cam.fy
+    beyond = (np.abs(tc[:, 0] / tc[:, 2]) > lim_x) | (np.abs(tc[:, 1] / tc[:, 2]) > lim_y)
+    assert beyond.tolist() == [True] * (n - 1) + [False]
+    ct = rng.normal(0, 1, (3, cam.width * cam.height))
+    _, grads = G.render_vjp(arrs, 1, cam, rp, ct)
+    _, base_out = _forward_value(arrs, 1, cam, rp, ct)
+    assert base_out["proj"]["ids"].tolist() == list(range(n))
+    base_dec = _decisions(base_out)
+    checked = clamped_means = 0
+    for grp in GROUPS:
+        a = arrs[grp]
+        for fi in range(a.size):
+            idx = np.unravel_index(fi, a.shape)
+            h = 1e-6 * max(1.0, abs(a[idx]))
+            vals, ok = [], True
+            for sgn in (1, -1):
+                b = {k: v.copy() for k, v in arrs.items()}
+                b[grp][idx] += sgn * h
+                val, out = _forward_value(b, 1, cam, rp, ct)
+                ok = ok and _decisions(out) == base_dec
+                vals.append(val)
+            if not ok:
+                continue
+            fd = (vals[0] - vals[1]) / (2 * h)
+            an = grads[grp][idx]
+            scale = max(1e-6, np.abs(grads[grp]).max())
+            assert abs(fd - an) <= 2e-6 * scale + 1e-6 * abs(an), (grp, idx, fd, an)
+            checked += 1
+            clamped_means += int(grp == "means" and beyond[idx[0]])
+    assert checked >= 60 and clamped_means >= 10, (checked, clamped_means)

@@ -190,3 +190,114 @@ def test_opacity_is_sigmoid_of_logit():
     pr = R.project(g["means"], g["log_scales"], g["quats"], g["opacity_logits"], g["sh"], 0, cam,
                    R.RasterParams())
     assert pr["opacity"].item() == pytest.approx(1 / (1 + math.exp(-0.7)), abs=1e-15)
+
+
+def _sigma2d_by_hand(cam, mean, ls, quat, lim_x, lim_y, h):
+    """Sigma2D of the EWA step written out independently of the oracle: the
+    covariance from scipy's rotation, the camera-space point, the Jacobian of
+    the pinhole map with tx/tz and ty/tz clamped to +-lim, then J W Sigma W^T
+    J^T + h I (W the world-to-camera rotation)."""
+    Rc, t = cam.R.astype(np.float64), cam.t.astype(np.float64)
+    rot = Rotation.from_quat(np.asarray(quat, np.float64)[[1, 2, 3, 0]]).as_matrix()
+    sig = rot @ np.diag(np.exp(2 * np.asarray(ls, np.float64))) @ rot.T
+    tx, ty, tz = Rc @ mean + t
+    xr = min(max(tx / tz, -lim_x), lim_x)
+    yr = min(max(ty / tz, -lim_y), lim_y)
+    J = np.array([[cam.fx / tz, 0.0, -cam.fx * xr / tz],
+                  [0.0, cam.fy / tz, -cam.fy * yr / tz]])
+    s2 = J @ Rc @ sig @ Rc.T @ J.T
+    uv = (cam.fx * tx / tz + cam.cx, cam.fy * ty / tz + cam.cy)
+    return np.array([s2[0, 0] + h, s2[0, 1], s2[1, 1] + h]), uv, (tx / tz, ty / tz)
+
+
+def _beyond_clamp_gaussians(cam, frac_x, frac_y, depth=3.0):
+    """Large Gaussians whose centres sit at tx/tz = frac_x * half-width / fx
+    (and likewise in y): beyond the Jacobian clamp for |frac| > 1.3 while
+    their 3-sigma boxes still reach into the image."""
+    Rc, t = cam.R.astype(np.float64), cam.t.astype(np.float64)
+    C = -Rc.T @ t
+    out = []
+    for fx_, fy_ in zip(frac_x, frac_y):
+        xr = fx_ * (cam.width / 2.0) / cam.fx
+        yr = fy_ * (cam.height / 2.0) / cam.fy
+        out.append(C + depth * (Rc[2] + xr * Rc[0] + yr * Rc[1]))
+    return np.array(out)
+
+
+def test_jacobian_clamp_beyond_the_limit_matches_hand_built_jacobian():
+    """Gaussians outside +-1.3 half-extents: Sigma2D equals J W Sigma W^T J^T
+    + h I with J evaluated at the clamped tx/tz, ty/tz (the centre u, v stays
+    the unclamped pinhole projection); with the clamp off the same Gaussians
+    give the unclamped Jacobian, and the two differ."""
+    cam = S.look_at_camera((0.5, -4.0, 1.5), 96, 64)
+    fracs_x = [1.6, -2.0, 1.8, 0.2, -1.45]
+    fracs_y = [0.1, 1.9, -1.7, -2.2, 1.5]
+    means = _beyond_clamp_gaussians(cam, fracs_x, fracs_y)
+    rng = np.random.default_rng(21)
+    n = len(means)
+    ls = rng.normal(np.log(0.55), 0.1, (n, 3))
+    quat = rng.normal(size=(n, 4))
+    lim_x = R.f32(1.3) * (cam.width / 2.0) / float(cam.fx)
+    lim_y = R.f32(1.3) * (cam.height / 2.0) / float(cam.fy)
+    h = R.f32(0.3)
+    for clamp, lims in ((1.3, (lim_x, lim_y)), (0.0, (np.inf, np.inf))):
+        pr = R.project(means, ls, quat, np.zeros(n), np.zeros((n, 1, 3)), 0, cam,
+                       R.RasterParams(jac_clamp=clamp))
+        assert pr["ids"].tolist() == list(range(n)), "every test Gaussian must be visible"
+        for k in range(n):
+            exp_cov, exp_uv, ratios = _sigma2d_by_hand(cam, means[k], ls[k], quat[k], *lims, h)
+            got = pr["cov2d"][k].detach().numpy()
+            assert np.allclose(got, exp_cov, rtol=1e-9, atol=0), (clamp, k, got, exp_cov)
+            assert np.allclose(pr["uv"][k].detach().numpy(), exp_uv, rtol=1e-12)
+            if clamp > 0:
+                beyond = abs(ratios[0]) > lim_x or abs(ratios[1]) > lim_y
+                assert beyond or abs(fracs_x[k]) <= 1.3
+    # the clamp changes the covariance of every Gaussian beyond it
+    c_on = R.project(means, ls, quat, np.zeros(n), np.zeros((n, 1, 3)), 0, cam,
+                     R.RasterParams())["cov2d"].detach().numpy()
+    c_off = R.project(means, ls, quat, np.zeros(n), np.zeros((n, 1, 3)), 0, cam,
+                      R.RasterParams(jac_clamp=0.0))["cov2d"].detach().numpy()
+    differs = np.abs(c_on - c_off).max(1) > 1e-6 * np.abs(c_off).max(1)
+    assert differs.tolist() == [True] * n
+
+
+def test_sh_degree_one_colour_follows_the_view_direction():
+    """Degree-1 closed form: with only the three l = 1 coefficients set, the
+    colour is 0.5 + f_1 Y_1(d) + f_2 Y_2(d) + f_3 Y_3(d), d the unit vector
+    from the camera centre to the Gaussian, Y_1 = -c y, Y_2 = c z, Y_3 = -c x,
+    c = sqrt(3 / (4 pi)). A Gaussian straight to the camera's right and one
+    straight ahead, and off-axis ones in general directions."""
+    cam = S.look_at_camera((2.0, -3.0, 1.0), 96, 64)
+    Rc, t = cam.R.astype(np.float64), cam.t.astype(np.float64)
+    C = -Rc.T @ t
+    c1 = math.sqrt(3.0 / (4.0 * math.pi))
+    rng = np.random.default_rng(31)
+    offs = [(0.0, 0.0), (0.25, 0.0), (-0.2, 0.15), (0.1, -0.2), (0.3, 0.2)]
+    means = np.array([C + 3.0 * (Rc[2] + a * Rc[0] + b * Rc[1]) for a, b in offs])
+    n = len(means)
+    sh = np.zeros((n, 4, 3))
+    sh[:, 1:4, :] = rng.normal(0.0, 0.3, (n, 3, 3))
+    pr = R.project(means, np.full((n, 3), np.log(0.05)), np.tile([1.0, 0, 0, 0], (n, 1)),
+                   np.zeros(n), sh, 1, cam, R.RasterParams())
+    assert pr["ids"].tolist() == list(range(n))
+    got = pr["rgb_raw"].detach().numpy()
+    for k in range(n):
+        d = means[k] - C
+        d /= np.linalg.norm(d)
+        expect = 0.5 + sh[k, 1] * (-c1 * d[1]) + sh[k, 2] * (c1 * d[2]) + sh[k, 3] * (-c1 * d[0])
+        assert np.allclose(got[k], expect, rtol=0, atol=1e-14), (k, got[k], expect)
+    # one coefficient on the x-type basis function, for the Gaussian whose
+    # direction has the largest world-x component: the colour moves from 0.5
+    # against the sign of that component (a reversed direction would move it
+    # the other way)
+    dirs = means - C
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    k = int(np.argmax(np.abs(dirs[:, 0])))
+    assert abs(dirs[k, 0]) > 0.3
+    sh1 = np.zeros((1, 4, 3))
+    sh1[0, 3, :] = 1.0
+    pr1 = R.project(means[k:k + 1], np.full((1, 3), np.log(0.05)), np.array([[1.0, 0, 0, 0]]),
+                    np.zeros(1), sh1, 1, cam, R.RasterParams())
+    col = pr1["rgb_raw"][0].detach().numpy()
+    assert np.allclose(col, 0.5 - c1 * dirs[k, 0], atol=1e-14)
+    assert (np.sign(col - 0.5) == -np.sign(dirs[k, 0])).all()
