@@ -22,6 +22,9 @@
  *    non-null and *d_gate == 0 at execution time, every kernel of the call
  *    returns without touching memory. This is how a skipped backward costs no
  *    host synchronisation.
+ *  - Versioned structs: the parameter structs start with `struct_size`, which
+ *    the caller sets to sizeof(the struct) as compiled against this header;
+ *    a call that sees another value returns SGS_ERR_INVALID_ARG.
  *
  * Gaussian parameter layout (float32, planar, [F][stride], F = 11 + 3 (D+1)^2):
  *   planes 0-2 mean xyz | 3-5 log-scale xyz | 6-9 quaternion wxyz (any norm)
@@ -54,6 +57,7 @@ typedef enum {
 /* Device status word bits (sgs_read_status). */
 #define SGS_STATUS_PAIR_OVERFLOW 0x1u  /* more tile/Gaussian pairs than pair_capacity */
 #define SGS_STATUS_NONFINITE_LOSS 0x2u /* the gate saw a non-finite loss              */
+#define SGS_STATUS_BAD_VIEW 0x4u       /* the gate read a view index out of range     */
 
 #define SGS_MAX_VIEWS 16
 #define SGS_MAX_PLANES 59
@@ -67,6 +71,7 @@ int32_t sgs_version(void);
  * Inputs
  * ------------------------------------------------------------------------- */
 typedef struct {
+    uint32_t struct_size; /* sizeof(sgs_gaussians)                             */
     float* data;        /* device, [F][stride] float32, planes as above        */
     int64_t n;          /* number of Gaussians, >= 0                           */
     int64_t stride;     /* plane stride in elements, >= n, multiple of 64, < 2^29 */
@@ -84,10 +89,18 @@ typedef struct {
 } sgs_camera;
 
 /* Rasteriser readings of points the paper leaves open (Sec. 3 gives only the
- * equations). Defaults: 16x16 tiles, black background, near 0.2, dilation 0.3,
- * alpha_min 1/255, alpha_max 0.99, t_min 1e-4, jac_clamp 1.3. */
+ * equations), and the launch shape. Defaults: 16x16 tiles, super-tiles of 8x8
+ * tiles, batches of 64 list entries, black background, near 0.2, dilation
+ * 0.3, alpha_min 1/255, alpha_max 0.99, t_min 1e-4, jac_clamp 1.3. The tile
+ * shape, super-tile edge and batch change how the work is laid out, never the
+ * image or the gradients. */
 typedef struct {
+    uint32_t struct_size;    /* sizeof(sgs_raster_params)                           */
     int32_t tile_w, tile_h;  /* 8x8, 16x16 or 32x8                                  */
+    int32_t super_tile;      /* binning granularity: squares of super_tile tiles,   */
+                             /* 1..64 (0: 8)                                        */
+    int32_t lds_batch;       /* list entries per compositing batch staged in LDS:   */
+                             /* 32, 64, 128 or 256 (0: 64)                          */
     float bg[3];             /* background colour, added with weight T_final        */
     float near_z;            /* camera depth <= near_z culls                        */
     float dilation;          /* Sigma2D += dilation * I (pixels^2)                  */
@@ -99,7 +112,7 @@ typedef struct {
                              /* +-jac_clamp * half-extent / focal; 0 disables       */
 } sgs_raster_params;
 
-/* Fills *rp with the defaults above. */
+/* Fills *rp with the defaults above (struct_size included). */
 void sgs_default_raster_params(sgs_raster_params* rp);
 
 /* ---------------------------------------------------------------------------
@@ -107,21 +120,30 @@ void sgs_default_raster_params(sgs_raster_params* rp);
  *
  * One call renders n_views (1..SGS_MAX_VIEWS) views of the same Gaussians in
  * one batch of launches: projection of every (view, Gaussian) entry, a
- * depth-ordered tile binning of all views together, and compositing of every
- * tile of every view. Each pixel composites, front to back in (depth,
+ * depth-ordered binning of all views together, and compositing of every tile
+ * of every view. Each pixel composites, front to back in (float32 depth,
  * Gaussian index) order, the Gaussians whose overlap box contains the pixel
  * centre (C(p) = sum c_i alpha'_i T_i + bg T_final).
  *
+ * Binning works on super-tiles (squares of super_tile tiles): their
+ * depth-ordered lists are sorted once, and the compositing of each tile walks
+ * its super-tile's list, keeps the entries that can reach alpha_min on the
+ * tile (its own depth-ordered list), and stops when every pixel has
+ * terminated. The part of each tile list it composites is recorded, in chunks
+ * of lds_batch entries, for the backward.
+ *
  * The workspace holds everything the backward needs (projected records, the
- * per-tile sorted lists, per-pixel final transmittance and last contributor).
+ * recorded tile lists, per-pixel final transmittance and last contributor).
  * It is valid for sgs_render_backward until it is reused; the backward must
  * see the same Gaussians, cameras and parameters. The status word (sticky,
  * see sgs_read_status) of a newly allocated workspace is undefined: clear it
  * once with sgs_clear_status before the first forward.
  *
- * pair_capacity bounds the number of (tile, Gaussian) pairs of the whole
- * batch. If exceeded, the device sets SGS_STATUS_PAIR_OVERFLOW, records the
- * required count (sgs_read_status) and the image is incomplete.
+ * pair_capacity bounds both the (super-tile, Gaussian) pairs of the batch and
+ * the tile-list entries the compositing records. If either is exceeded, the
+ * device sets SGS_STATUS_PAIR_OVERFLOW and records the required capacity
+ * (sgs_read_status); with too few pairs the image is incomplete, with too
+ * little list storage the image is right but the backward is not.
  * ------------------------------------------------------------------------- */
 sgs_status sgs_forward_workspace_size(const sgs_raster_params* rp, int64_t n,
                                       const sgs_camera* cams /* host */, int32_t n_views,
@@ -135,8 +157,9 @@ sgs_status sgs_render_forward(const sgs_gaussians* g /* host struct */,
                               void* stream);
 
 /* Synchronises `stream`, then reads the workspace's device status word, the
- * number of visible (view, Gaussian) entries and of (tile, Gaussian) pairs of
- * the last forward. Any output pointer may be NULL. */
+ * number of visible (view, Gaussian) entries and the pair capacity the last
+ * forward needed (the larger of its super-tile pairs and its recorded list
+ * entries). Any output pointer may be NULL. */
 sgs_status sgs_read_status(const void* workspace, uint32_t* flags_out, int64_t* visible_out,
                            int64_t* pairs_out, void* stream);
 
@@ -181,13 +204,15 @@ sgs_status sgs_load_records(const sgs_camera* cams, int32_t n_views, int64_t n,
                             const float* depth, const int32_t* extent, const float* conic,
                             const float* opacity, const float* rgb, void* stream);
 
-/* Tile binning: depth-ordered, per-tile lists of the visible entries whose
- * overlap box reaches the tile and that can reach alpha_min at one of its pixel
- * centres, ties in depth broken by ascending entry index. */
+/* Binning: depth-ordered, per-super-tile lists of the visible entries whose
+ * overlap box reaches the super-tile and that can reach alpha_min at one of
+ * its pixel centres, ties in depth broken by ascending entry index. Also
+ * clears the counters the compositing forward accumulates into: every
+ * sgs_rasterize follows an sgs_bin. */
 sgs_status sgs_bin(const sgs_camera* cams, int32_t n_views, int64_t n, const sgs_raster_params* rp,
                    void* workspace, size_t workspace_bytes, int64_t pair_capacity, void* stream);
 
-/* Compositing forward of every tile (Eqs. 4-5). */
+/* Compositing forward of every tile (Eqs. 4-5); records the tile lists. */
 sgs_status sgs_rasterize(const sgs_camera* cams, int32_t n_views, int64_t n,
                          const sgs_raster_params* rp, void* workspace, size_t workspace_bytes,
                          int64_t pair_capacity, float* out_rgb, void* stream);
@@ -209,21 +234,29 @@ sgs_status sgs_project_backward(const sgs_gaussians* g, const sgs_camera* cams, 
 
 /* Byte offsets of the workspace regions, for inspection (host struct).
  * records:    float32 [entries][12]  u v a b | c o rx ry | r g b clamp-mask(bits)
- * tiles:      uint32  [entries]      tiles touched (0 = not visible)
+ * tiles:      uint32  [entries]      super-tiles touched (0 = not visible)
  * depth:      float32 [entries]      camera depth (the sort key) of visible entries
- * pair_tile:  uint16 or uint32 (pair_tile_bytes: 2 when total_tiles < 65535)
- *             [pair_capacity] sorted global tile index per pair
- * pair_entry: uint32  [pair_capacity] entry index per pair (sorted with tiles)
- * ranges:     uint32  [total_tiles][2] [start, end) into the pair arrays
+ * sup_key:    uint16 or uint32 (key_bytes: 2 when total_supers < 65535)
+ *             [pair_capacity] sorted global super-tile index per pair
+ * sup_entry:  uint32  [pair_capacity] entry index per pair (sorted with the keys)
+ * sup_ranges: uint32  [total_supers][2] [start, end) into the pair arrays
+ * chunks:     uint32  [chunk_capacity][batch] recorded tile-list entries
+ * links:      uint32  [chunk_capacity][2] previous chunk of the tile (all ones:
+ *                                     none), (chunk ordinal << 9) | entries
+ * tile_head:  uint32  [total_tiles]   chunk holding the tile's last blended position
  * t_final:    float32 [total_pixels]  final transmittance per pixel
- * n_last:     uint32  [total_pixels]  1 + list position of the last blended pair (0: none)
+ * n_last:     uint32  [total_pixels]  1 + list position of the last blended entry (0: none)
  * accum:      float32 [entries][12]   du dv da db | dc do dr dg | db 0 0 0
  * counters:   uint32  [16]            status, visible, pairs needed, pairs written,
- *                                     blended (u64), examined (u64), pairs kept, ... */
+ *                                     blended (u64), examined (u64), pairs kept,
+ *                                     chunks, listed entries, walked entries */
 typedef struct {
-    size_t records, tiles, depth, pair_tile, pair_entry, ranges, t_final, n_last, accum, counters;
-    int64_t entries, total_tiles, total_pixels;
-    int32_t pair_tile_bytes;  /* 2 or 4 */
+    size_t records, tiles, depth, sup_key, sup_entry, sup_ranges, chunks, links, tile_head,
+        t_final, n_last, accum, counters;
+    int64_t entries, total_tiles, total_pixels, total_supers, chunk_capacity;
+    int32_t key_bytes;   /* 2 or 4 */
+    int32_t batch;       /* entries per chunk (lds_batch) */
+    int32_t super_tile;  /* super-tile edge in tiles */
 } sgs_workspace_layout;
 
 sgs_status sgs_get_workspace_layout(const sgs_raster_params* rp, int64_t n, const sgs_camera* cams,
@@ -254,19 +287,24 @@ sgs_status sgs_photometric_loss_backward(const float* rgb, const float* target, 
                                          float* dl_drgb, void* stream);
 
 /* ---------------------------------------------------------------------------
- * SkipGS backward gate (Algorithm 1, Eqs. 7-13), one update per iteration,
- * executed on the device by a single thread in binary64.
- *   s = L / (EMA_v + eps) if view v has an EMA, else +inf          (Eq. 8)
- *   proposal g = 1[s > 1 + delta]                                   (Eq. 9)
- *   rho = b / max(t - 1, 1) (or over the current tumbling window)  (Eq. 10)
- *   t <= warmup: record the proposal when v had an EMA, force g = 1
- *   t  > warmup: calibrate rho_min once (Eqs. 12-13); force g = 1 if
- *                rho < rho_min and budget != 0                      (Eq. 11)
- *   g = 1: b += 1; always: EMA_v <- beta EMA_v + (1 - beta) L      (Eq. 7)
- * The first observation of a view sets its EMA to L. A non-finite loss leaves
- * the EMA alone, gives g = 0 and sets SGS_STATUS_NONFINITE_LOSS in the state.
+ * SkipGS backward gate (Sec. 4: Algorithm 1, Eqs. 7-13), one update per
+ * post-densification iteration, executed on the device by a single thread in
+ * binary64. It scores the iteration's loss against the view's loss EMA
+ * (Eq. 8), proposes the backward pass when the score exceeds 1 + delta
+ * (Eq. 9; delta = 0 is the paper's test), and overrides a skip when the
+ * fraction of iterations that ran the backward falls below the budget floor
+ * (Eqs. 10-11), a floor calibrated once from the warmup (Eqs. 12-13). The
+ * EMA moves on every iteration (Eq. 7).
+ * Readings where the paper is silent: the first observation of a view sets
+ * its EMA to the loss (and runs the backward); only views that already had an
+ * EMA count towards the warmup statistic, and with none the floor stays at
+ * rho_lo; `window` > 0 takes the ratio over tumbling windows aligned at
+ * t = 1, window + 1, ...; `budget` = 0 drops the override (the "w/o budget"
+ * ablation of Table 4). A non-finite loss leaves the EMA alone, gives g = 0
+ * and sets SGS_STATUS_NONFINITE_LOSS in the state's flags.
  * ------------------------------------------------------------------------- */
 typedef struct {
+    uint32_t struct_size; /* sizeof(sgs_gate_params)                              */
     double beta;       /* EMA decay (paper: 0.95)                               */
     double eps;        /* stability constant (1e-8)                             */
     double delta;      /* threshold offset: backward iff s > 1 + delta (0)      */
@@ -288,8 +326,13 @@ typedef struct {
 sgs_status sgs_gate_state_size(const sgs_gate_params* p, size_t* bytes_out);
 /* Resets the state (no EMA, t = b = 0, rho_min = rho_lo). */
 sgs_status sgs_gate_init(const sgs_gate_params* p, void* d_state, void* stream);
-/* One iteration: reads *d_loss (device float), writes *d_gate (device int32). */
-sgs_status sgs_gate_update(const sgs_gate_params* p, void* d_state, int32_t view,
+/* One iteration: reads the view index *d_view (device int32) and the loss
+ * *d_loss (device float), writes *d_gate (device int32). A view index outside
+ * [0, n_views) is not an iteration: the state is left as it was apart from
+ * SGS_STATUS_BAD_VIEW in its flags, and *d_gate = 0. Everything stays on the
+ * device, so a training iteration can be captured once and replayed over a
+ * device-side view sequence. */
+sgs_status sgs_gate_update(const sgs_gate_params* p, void* d_state, const int32_t* d_view,
                            const float* d_loss, int32_t* d_gate, void* stream);
 /* Synchronises `stream`; copies the header and, if non-null, the per-view
  * EMA (host double[n_views]) and has-EMA flags (host uint8[n_views]). */
@@ -298,15 +341,22 @@ sgs_status sgs_gate_read(const sgs_gate_params* p, const void* d_state,
                          void* stream);
 
 /* ---------------------------------------------------------------------------
- * Adam (the update applied when the backward runs), per element of the
- * [n_planes][stride] parameter array, one learning rate per plane:
+ * Adam (Kingma & Ba, with bias correction): the optimiser the 3DGS parameters
+ * are trained with (Sec. 3) and the standard update SkipGS applies whenever
+ * the gate runs the backward (Sec. 4, Algorithm 1; Sec. 5.1), per element of
+ * the [n_planes][stride] parameter array, one learning rate per plane:
  *   k <- k + 1; m <- b1 m + (1-b1) g; v <- b2 v + (1-b2) g^2;
  *   p <- p - lr (m / (1 - b1^k)) / (sqrt(v / (1 - b2^k)) + eps); g <- 0.
  * Predicated on d_gate; *d_step (device int32) is the executed-step count k.
  * ------------------------------------------------------------------------- */
 typedef struct {
+    uint32_t struct_size;      /* sizeof(sgs_adam_params)                       */
     double beta1, beta2, eps;  /* 1 - beta is formed in binary64 before rounding */
     float lr[SGS_MAX_PLANES];  /* per plane; planes beyond n_planes ignored     */
+    int32_t visible_only;      /* fused step only: 1 updates only the Gaussians  */
+                               /* visible in a view of the batch (the others    */
+                               /* keep parameters and moments; the step count k */
+                               /* is the shared executed-step count); 0: dense  */
 } sgs_adam_params;
 
 sgs_status sgs_adam_step(const sgs_adam_params* p, float* params, float* grads, float* m,
@@ -335,6 +385,46 @@ sgs_status sgs_render_backward_adam(const sgs_gaussians* g, const sgs_camera* ca
                                     const float* dl_drgb, const sgs_adam_params* adam, float* m,
                                     float* v, int32_t* d_step, const int32_t* d_gate,
                                     void* stream);
+
+/* ---------------------------------------------------------------------------
+ * One post-densification training iteration (Sec. 4, Algorithm 1) with the
+ * view chosen on the device, so that an iteration can be captured once (HIP
+ * graph) and replayed over a device-side view sequence.
+ *
+ * A camera table holds n_cams cameras of one resolution, prepared for the
+ * device. sgs_camera_table_init validates them on the host and copies the
+ * table to device memory; it synchronises `stream` (set-up, not for capture).
+ * ------------------------------------------------------------------------- */
+sgs_status sgs_camera_table_size(int32_t n_cams, size_t* bytes_out);
+sgs_status sgs_camera_table_init(const sgs_camera* cams /* host, n_cams */, int32_t n_cams,
+                                 const sgs_raster_params* rp, void* d_table, size_t table_bytes,
+                                 void* stream);
+
+/* *d_view = d_sequence[*d_iter % sequence_len]; *d_iter += 1 (device int64).
+ * The first launch of a captured iteration, so that each replay takes the
+ * next view of the sequence. */
+sgs_status sgs_view_sequence_next(const int32_t* d_sequence, int64_t sequence_len,
+                                  int64_t* d_iter, int32_t* d_view, void* stream);
+
+/* One iteration for view v = *d_view of the table (all cameras of the table
+ * share cams[0]'s size; cams is the host array the table was built from):
+ * render view v (sgs_render_forward), the loss against targets[v] (planar
+ * [n_cams][3][H][W]) into *d_loss, the gate decision into *d_gate
+ * (sgs_gate_update; with gate_state NULL the backward always runs: *d_gate =
+ * 1), and, predicated on *d_gate, the loss backward into dl_drgb, the
+ * compositing backward and the fused projection backward + Adam step
+ * (sgs_render_backward_adam). No host synchronisation; rgb and dl_drgb are
+ * [3][H][W] device buffers; the view index is clamped into the table for the
+ * render and the loss (the gate flags an out-of-range index). */
+sgs_status sgs_train_iteration(const sgs_gaussians* g, const sgs_camera* cams /* host */,
+                               const void* d_table, int32_t n_cams, const int32_t* d_view,
+                               const sgs_raster_params* rp, void* workspace,
+                               size_t workspace_bytes, int64_t pair_capacity,
+                               const float* targets, float lambda, void* loss_workspace,
+                               size_t loss_workspace_bytes, float* rgb, float* dl_drgb,
+                               float* d_loss, const sgs_gate_params* gp, void* gate_state,
+                               int32_t* d_gate, const sgs_adam_params* adam, float* m, float* v,
+                               int32_t* d_step, void* stream);
 
 #ifdef __cplusplus
 }

@@ -1,23 +1,28 @@
 """Oracle SkipGS backward gate (plain Python floats = IEEE binary64). Test
 infrastructure only.
 
-Algorithm 1 of the paper, one call per post-densification iteration t
-(t = 1 at the first iteration after densification stops, Sec. 4):
+Sec. 4 of the paper (Algorithm 1; Eqs. 7-13) gates the backward pass of each
+post-densification iteration t (t = 1 at the first iteration after
+densification stops). Here the gate is split into what it observes, what it
+decides and how its state moves:
 
-1. deviation score s = L / (EMA_v + eps) if view v has an EMA, else +inf (Eq. 8);
-2. skip test g = 1[s > 1] (Eq. 9);
-3. cumulative backward ratio before this iteration rho = b / max(t - 1, 1) (Eq. 10);
-4. warmup (t <= W): record g for calibration when the view already had an EMA,
-   then force g = 1;
-5. after warmup: at t = W + 1 calibrate once rho_min = rho_lo + (1 - rho_lo) rho_hat_W
-   (Eqs. 12-13); if rho < rho_min force g = 1 (Eq. 11);
-6. if g = 1 the backward and optimiser step run and b += 1;
-7. EMA_v <- beta EMA_v + (1 - beta) L, unconditionally (Eq. 7).
+* observation: the per-view deviation score of Eq. 8 against the EMA held
+  before this iteration, and the backward ratio of Eq. 10 over the
+  iterations before this one;
+* decision (``decide``): a pure function of the score's proposal (Eq. 9),
+  the phase (warmup or gated) and the budget test of Eq. 11 against the
+  current floor;
+* state: the warmup statistic and the one-time calibration of the floor
+  (Eqs. 12-13), the backward count, and the EMA of Eq. 7, which moves on
+  every iteration whatever the decision.
 
 Readings where the paper is silent:
-* the first observation of a view sets its EMA to that loss;
+* the first observation of a view sets its EMA to that loss (the view is
+  then backpropagated, its score being undefined);
 * ``delta`` generalises the threshold of Eq. 9 to s > 1 + delta (delta = 0 is the
   paper; delta = 0.02 reads "skip when within 2% of the EMA" one-sidedly);
+* the warmup statistic counts only views that already had an EMA;
+* with no such view in the warmup the floor stays at rho_lo;
 * ``window`` > 0 replaces the cumulative ratio by one over tumbling windows of
   that many iterations aligned at t = 1, window + 1, ...; the count and the
   iteration index restart at each window start;
@@ -28,7 +33,7 @@ Readings where the paper is silent:
 from __future__ import annotations
 
 import math
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 
 import numpy as np
 
@@ -63,13 +68,13 @@ def windowed_preset(n_views: int) -> GateParams:
 class GateState:
     ema: list
     has_ema: list
-    t: int = 0
-    b: int = 0
-    t_w: int = 0
+    t: int = 0              # iterations seen
+    b: int = 0              # backward passes run
+    t_w: int = 0            # iterations and backward passes in the current window
     b_w: int = 0
-    warm_hits: int = 0
-    warm_count: int = 0
-    rho_min: float = 0.5
+    warm_hits: int = 0      # warmup statistic: proposals to backpropagate ...
+    warm_count: int = 0     # ... out of the warmup iterations that had a score
+    rho_min: float = 0.5    # current budget floor
     calibrated: bool = False
     nonfinite: bool = False
 
@@ -87,57 +92,86 @@ class GateResult:
     rho: float
 
 
-def step(p: GateParams, st: GateState, view: int, loss) -> GateResult:
-    """One iteration of Algorithm 1; mutates ``st``."""
-    L = float(np.float32(loss))
+# --- observation -----------------------------------------------------------
+def deviation_score(p: GateParams, st: GateState, view: int, L: float) -> float:
+    """Eq. 8 against the EMA before this iteration; +inf for a view with no EMA."""
+    if not st.has_ema[view]:
+        return math.inf
+    return L / (st.ema[view] + p.eps)
+
+
+def backward_ratio(p: GateParams, st: GateState) -> float:
+    """Eq. 10 over the iterations before the current one (of the current
+    window when ``window`` > 0). Called after the clock has advanced."""
+    if p.window > 0:
+        return st.b_w / max(st.t_w - 1, 1)
+    return st.b / max(st.t - 1, 1)
+
+
+# --- decision --------------------------------------------------------------
+def decide(proposal: int, in_warmup: bool, budget: bool, rho: float, rho_min: float) -> int:
+    """g of one iteration: the warmup always backpropagates; afterwards the
+    proposal of Eq. 9 stands unless the budget floor is enforced and the
+    ratio is below it (Eq. 11)."""
+    if in_warmup:
+        return 1
+    if budget and rho < rho_min:
+        return 1
+    return proposal
+
+
+# --- state -----------------------------------------------------------------
+def advance_clock(p: GateParams, st: GateState):
     st.t += 1
-    t = st.t
-    if p.window > 0 and (t - 1) % p.window == 0:
-        st.t_w = 0
-        st.b_w = 0
+    if p.window > 0 and (st.t - 1) % p.window == 0:
+        st.t_w, st.b_w = 0, 0
     st.t_w += 1
 
-    if not math.isfinite(L):
-        st.nonfinite = True
-        return GateResult(0, 0, 0, math.nan, math.nan)
 
-    had = st.has_ema[view]
-    if had:
-        s = L / (st.ema[view] + p.eps)
-        g = 1 if s > 1.0 + p.delta else 0
-    else:
-        s = math.inf
-        g = 1
-    proposed = g
+def calibrate_floor(p: GateParams, st: GateState):
+    """Eqs. 12-13, once, at the first iteration after the warmup."""
+    if st.calibrated or not p.calibrate or p.warmup <= 0:
+        return
+    if st.warm_count > 0:
+        st.rho_min = p.rho_lo + (1.0 - p.rho_lo) * (st.warm_hits / st.warm_count)
+    st.calibrated = True
 
-    if p.window > 0:
-        rho = st.b_w / max(st.t_w - 1, 1)
-    else:
-        rho = st.b / max(t - 1, 1)
 
-    if t <= p.warmup:
-        if had:
-            st.warm_count += 1
-            st.warm_hits += g
-        g = 1
-    else:
-        if p.calibrate and p.warmup > 0 and not st.calibrated:
-            if st.warm_count > 0:
-                rho_hat = st.warm_hits / st.warm_count
-                st.rho_min = p.rho_lo + (1.0 - p.rho_lo) * rho_hat
-            st.calibrated = True
-        if p.budget and rho < st.rho_min:
-            g = 1
+def account(st: GateState, g: int):
+    st.b += g
+    st.b_w += g
 
-    if g:
-        st.b += 1
-        st.b_w += 1
-    if had:
+
+def update_ema(p: GateParams, st: GateState, view: int, L: float):
+    """Eq. 7 (the first observation initialises the EMA)."""
+    if st.has_ema[view]:
         st.ema[view] = p.beta * st.ema[view] + (1.0 - p.beta) * L
     else:
         st.ema[view] = L
         st.has_ema[view] = True
-    return GateResult(g, proposed, int(g and not proposed), s, rho)
+
+
+def step(p: GateParams, st: GateState, view: int, loss) -> GateResult:
+    """One post-densification iteration of the gate; mutates ``st``."""
+    L = float(np.float32(loss))
+    advance_clock(p, st)
+    if not math.isfinite(L):
+        st.nonfinite = True
+        return GateResult(0, 0, 0, math.nan, math.nan)
+    s = deviation_score(p, st, view, L)
+    proposal = 1 if s > 1.0 + p.delta else 0       # +inf always proposes
+    rho = backward_ratio(p, st)
+    in_warmup = st.t <= p.warmup
+    if in_warmup:
+        if st.has_ema[view]:
+            st.warm_count += 1
+            st.warm_hits += proposal
+    else:
+        calibrate_floor(p, st)
+    g = decide(proposal, in_warmup, p.budget, rho, st.rho_min)
+    account(st, g)
+    update_ema(p, st, view, L)
+    return GateResult(g, proposal, int(g == 1 and proposal == 0), s, rho)
 
 
 def run(p: GateParams, views, losses) -> tuple[GateState, list]:

@@ -287,23 +287,29 @@ def tile_rect(u, v, extent, tile_w, tile_h, tiles_x, tiles_y):
     return x0, x1, y0, y1
 
 
-def tile_contributes(u, v, a, b, c, o, rx, ry, tx, ty, tile_w, tile_h, width, height,
-                     rp: "RasterParams") -> bool:
+def rect_contributes(u, v, a, b, c, o, rx, ry, x0, x1, y0, y1, rp: "RasterParams") -> bool:
     """Whether a Gaussian can take part in the compositing of any pixel of
-    tile (tx, ty): some pixel centre p of the tile (inside the image) lies in
-    its overlap box and has P <= 0 and alpha' = min(alpha_max, o exp(P)) >=
-    alpha_min (Eq. 5 with the skip rule), by brute force over the tile's
-    pixels in FP64. A tile list may drop exactly the entries for which this
-    is false without changing any pixel."""
+    the pixel rectangle [x0, x1) x [y0, y1): some pixel centre p lies in its
+    overlap box and has P <= 0 and alpha' = min(alpha_max, o exp(P)) >=
+    alpha_min (Eq. 5 with the skip rule), by brute force over the pixels in
+    FP64. A list may drop exactly the entries for which this is false without
+    changing any of those pixels."""
     rp = rp.as_f32()
-    xs = np.arange(tx * tile_w, min((tx + 1) * tile_w, width)) + 0.5
-    ys = np.arange(ty * tile_h, min((ty + 1) * tile_h, height)) + 0.5
+    xs = np.arange(x0, x1) + 0.5
+    ys = np.arange(y0, y1) + 0.5
     px, py = np.meshgrid(xs, ys)
     dx, dy = px - float(u), py - float(v)
     inbox = (np.abs(dx) <= rx) & (np.abs(dy) <= ry)
     power = -0.5 * (a * dx * dx + c * dy * dy) - b * dx * dy
     alpha = np.minimum(o * np.exp(np.minimum(power, 0.0)), rp.alpha_max)
     return bool((inbox & (power <= 0) & (alpha >= rp.alpha_min)).any())
+
+
+def tile_contributes(u, v, a, b, c, o, rx, ry, tx, ty, tile_w, tile_h, width, height,
+                     rp: "RasterParams") -> bool:
+    """rect_contributes on the pixels of tile (tx, ty) inside the image."""
+    return rect_contributes(u, v, a, b, c, o, rx, ry, tx * tile_w, min((tx + 1) * tile_w, width),
+                            ty * tile_h, min((ty + 1) * tile_h, height), rp)
 
 
 def float32_bits(x) -> np.ndarray:
@@ -348,6 +354,48 @@ def bin_and_sort(u32, v32, depth32, extent, ids, width, height, tile_w, tile_h,
             ranges[t, 0] = i
         ranges[t, 1] = i + 1
     return keys, vals, ranges
+
+
+def super_tile_lists(u32, v32, depth32, extent, ids, width, height, tile_w, tile_h, super_tile,
+                     super_offset: int = 0):
+    """Depth-ordered lists at the granularity of super-tiles (squares of
+    ``super_tile`` x ``super_tile`` tiles): the list of super-tile s holds
+    every visible Gaussian whose tile rectangle meets s, in (float32 depth,
+    index) order. A tile's own list is the ordered subsequence of its
+    super-tile's list whose rectangles contain the tile.
+    Returns (super index int64 per list entry, values int64, ranges
+    (supers, 2) int64 [start, end)), the entries sorted by super-tile."""
+    u32 = np.asarray(u32, dtype=np.float32)
+    v32 = np.asarray(v32, dtype=np.float32)
+    dbits = float32_bits(depth32).astype(np.uint64)
+    extent = np.asarray(extent, dtype=np.int64).reshape(-1, 2)
+    ids = np.asarray(ids, dtype=np.int64)
+    tx_n = (width + tile_w - 1) // tile_w
+    ty_n = (height + tile_h - 1) // tile_h
+    sx_n = (tx_n + super_tile - 1) // super_tile
+    sy_n = (ty_n + super_tile - 1) // super_tile
+    x0, x1, y0, y1 = (a.numpy() for a in tile_rect(u32.astype(np.float64), v32.astype(np.float64),
+                                                     extent, tile_w, tile_h, tx_n, ty_n))
+    keys, vals = [], []
+    for k in range(len(ids)):
+        if x1[k] <= x0[k] or y1[k] <= y0[k]:
+            continue
+        for sy in range(y0[k] // super_tile, (y1[k] - 1) // super_tile + 1):
+            for sx in range(x0[k] // super_tile, (x1[k] - 1) // super_tile + 1):
+                sup = super_offset + sy * sx_n + sx
+                keys.append((np.uint64(sup) << np.uint64(32)) | dbits[k])
+                vals.append(ids[k])
+    keys = np.asarray(keys, dtype=np.uint64)
+    vals = np.asarray(vals, dtype=np.int64)
+    order = np.argsort(keys, kind="stable")
+    keys, vals = keys[order], vals[order]
+    sups = (keys >> np.uint64(32)).astype(np.int64)
+    ranges = np.zeros((sx_n * sy_n, 2), dtype=np.int64)
+    for i, t in enumerate(sups - super_offset):
+        if i == 0 or sups[i - 1] - super_offset != t:
+            ranges[t, 0] = i
+        ranges[t, 1] = i + 1
+    return sups, vals, ranges
 
 
 # ---------------------------------------------------------------------------

@@ -1,15 +1,20 @@
-// Tile binning: the depth-ordered per-tile lists of the tile-based rasteriser.
+// Binning: the depth-ordered lists the tile-based rasteriser composites.
 //
-// The lists must hold, for every tile, the visible entries whose overlap box
-// reaches the tile and that can reach alpha_min at one of its pixel centres
-// (the exact tile test below), in ascending (depth, entry) order. Instead of one
-// radix sort over 64-bit (tile << 32 | depth) keys, the stage sorts the
-// visible entries once by depth (a short array), emits their (tile, entry)
-// pairs in that order, and then sorts the pairs stably by tile alone. A
-// stable sort keeps the depth order inside each tile, so the lists are the
-// same as those of the 64-bit sort while the long pair array is sorted on
-// ceil(log2(tiles)) bits instead of 32 + that many (uint16 keys when a batch
-// has fewer than 65535 tiles).
+// The lists are built at the granularity of super-tiles (squares of S x S
+// tiles): a super-tile's list holds, in ascending (depth, entry) order, the
+// visible entries whose overlap box reaches it and that can reach alpha_min
+// at one of its pixel centres. The compositing forward walks its tile's
+// super-tile list and keeps the entries that pass the same test on the tile
+// alone, which is the tile's own list in the same order, and stops when every
+// pixel of the tile has terminated; the tile lists are therefore never sorted
+// as a whole, and only the prefix a tile actually composites is ever formed.
+//
+// The stage sorts the visible entries once by depth (a short array), emits
+// their (super-tile, entry) pairs in that order, and sorts the pairs stably
+// by super-tile alone: stability keeps the depth order inside each
+// super-tile, as a sort of 64-bit (super-tile << 32 | depth) keys would, on
+// ceil(log2(super-tiles)) bits (uint16 keys when a batch has fewer than
+// 65535 super-tiles).
 #include <algorithm>
 
 #include "sgs_internal.hpp"
@@ -24,6 +29,10 @@ constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
 // ---- sources and sinks of the two device-wide scans ----
+// The scans add in uint32 with saturation at 2^32 - 1 (saturating addition is
+// associative, so the block and grand totals are the saturated true sums): a
+// batch whose pair count does not fit ends with the all-ones total, which no
+// capacity (< 2^31) reaches, and every offset past the overflow saturates.
 struct VisibleSrc {  // 1 for every visible entry
     const uint32_t* tiles;
     int64_t n;
@@ -41,16 +50,17 @@ struct CompactSink {  // visible entries -> (depth bits, entry), in entry order
         }
     }
 };
-struct PairCountSrc {  // tiles touched, in depth order (gathered by the depth sort)
-    const uint32_t* tiles_sorted;
+struct PairCountSrc {  // super-tiles touched, in depth order (gathered by the depth sort)
+    const uint32_t* counts_sorted;
     const uint32_t* n_dev;
     __device__ int64_t count() const { return *n_dev; }
-    __device__ uint32_t operator()(int64_t k) const { return tiles_sorted[k]; }
+    __device__ uint32_t operator()(int64_t k) const { return counts_sorted[k]; }
 };
 // Pair offset of every Gaussian in depth order, and for every emission window
 // (kEmitWindow consecutive emission units, windows 0 .. n_windows) the
 // Gaussian whose units hold the window's first unit. Gaussian k owns units
-// [pos + kEmitHead k, pos + kEmitHead (k + 1) + v).
+// [pos + kEmitHead k, pos + kEmitHead (k + 1) + v). A saturated offset lies
+// beyond every window.
 struct OffsetSink {
     uint32_t* offsets;
     uint32_t* window_first;
@@ -65,6 +75,49 @@ struct OffsetSink {
     }
 };
 
+__device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
+    const uint32_t c = a + b;
+    return c < a ? 0xffffffffu : c;
+}
+
+// Inclusive saturating prefix sum over the lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_sat_scan(uint32_t v) {
+    const int l = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(v, d, 64);
+        if (l >= d) v = sat_add(v, o);
+    }
+    return v;
+}
+
+// Exclusive saturating scan over a block of NT threads; *total = block sum.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_sat_scan(uint32_t v, uint32_t* smem,
+                                                        uint32_t* total) {
+    constexpr int NW = NT / 64;
+    const int w = threadIdx.x / 64;
+    const int l = __lane_id();
+    const uint32_t inc = wave_incl_sat_scan(v);
+    if (l == 63) smem[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        const uint32_t x = (l < NW) ? smem[l] : 0u;
+        const uint32_t xi = wave_incl_sat_scan(x);
+        const uint32_t ex = __shfl_up(xi, 1, 64);
+        if (l < NW) smem[l] = l == 0 ? 0u : ex;
+        if (l == NW - 1) smem[NW] = xi;
+    }
+    __syncthreads();
+    // exclusive prefix of this thread = block prefix of its wave + the wave's
+    // exclusive prefix (lane l - 1's inclusive value)
+    const uint32_t wex = __shfl_up(inc, 1, 64);
+    const uint32_t r = sat_add(smem[w], l == 0 ? 0u : wex);
+    *total = smem[NW];
+    __syncthreads();
+    return r;
+}
+
 // Block sums of the scan input. Block 0 also zeroes `clear[0..nclear)` (the
 // counters a binning pass accumulates into), saving a launch.
 template <class Src>
@@ -77,9 +130,9 @@ __global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(Src src, uint
     uint32_t s = 0;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j)
-        if (base + j < n) s += src(base + j);
+        if (base + j < n) s = sat_add(s, src(base + j));
     uint32_t tot;
-    block_excl_scan<kScanThreads>(s, smem, &tot);
+    block_excl_sat_scan<kScanThreads>(s, smem, &tot);
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
@@ -92,9 +145,9 @@ __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(Src src, Sink s
                                                                  uint32_t* total) {
     __shared__ uint32_t smem[kScanThreads / 64 + 1];
     uint32_t before = 0;
-    for (int i = threadIdx.x; i < (int)blockIdx.x; i += kScanThreads) before += sums[i];
+    for (int i = threadIdx.x; i < (int)blockIdx.x; i += kScanThreads) before = sat_add(before, sums[i]);
     uint32_t prefix;
-    block_excl_scan<kScanThreads>(before, smem, &prefix);
+    block_excl_sat_scan<kScanThreads>(before, smem, &prefix);
     const int64_t n = src.count();
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
@@ -102,16 +155,16 @@ __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(Src src, Sink s
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
         v[j] = (base + j < n) ? src(base + j) : 0u;
-        s += v[j];
+        s = sat_add(s, v[j]);
     }
     uint32_t tot;
-    uint32_t pos = block_excl_scan<kScanThreads>(s, smem, &tot) + prefix;
+    uint32_t pos = sat_add(block_excl_sat_scan<kScanThreads>(s, smem, &tot), prefix);
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
         if (base + j < n) sink(base + j, v[j], pos);
-        pos += v[j];
+        pos = sat_add(pos, v[j]);
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = prefix + tot;
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = sat_add(prefix, tot);
 }
 
 template <class Src, class Sink>
@@ -126,52 +179,13 @@ hipError_t device_scan(Src src, Sink sink, int64_t n_max, uint32_t* sums, uint32
     return hipGetLastError();
 }
 
-// Exact tile test of one (tile, Gaussian) pair: can alpha' = o exp(-q/2),
-// q = a dx^2 + 2 b dx dy + c dy^2, reach alpha_min at a pixel centre of the
-// tile inside the overlap box? The pixel-centre rectangle of the tile is
-// clipped to the box (widened by 1e-3 px). If the Gaussian's centre lies
-// outside it, the minimum of the convex q over the rectangle lies on an edge
-// that faces the centre (moving from any other boundary point towards the
-// centre enters the rectangle and lowers q), at the clamped stationary point
-// of that edge: at most one vertical and one horizontal edge to evaluate. The
-// pair is kept when that minimum, less a bound on its rounding error (8 ulp of
-// the sum of the terms' magnitudes), is within `lim` = 2 ln(o / alpha_min)
-// inflated by 1% + 0.01 (formed once per Gaussian): a culled pair cannot pass
-// the compositing kernels' skip test at any pixel of the tile, so images and
-// gradients are those of the uncut lists.
-__device__ __forceinline__ float reach_limit(float o, const RasterDev& rp) {
-    return rp.alpha_min > 0.f ? 2.f * logf(o / rp.alpha_min) * 1.01f + 0.01f : INFINITY;
-}
-
-__device__ __forceinline__ bool tile_reachable(float u, float v, float a, float b, float c,
-                                               float lim, float rx, float ry, int tx, int ty,
-                                               const RasterDev& rp) {
-    // relative to the centre; the box widened by 1e-3 px
-    const float m = 1e-3f;
-    const float bx = (float)(tx * rp.tile_w) - u, by = (float)(ty * rp.tile_h) - v;
-    const float x0 = fmaxf(bx + 0.5f, -rx - m), x1 = fminf(bx + ((float)rp.tile_w - 0.5f), rx + m);
-    const float y0 = fmaxf(by + 0.5f, -ry - m), y1 = fminf(by + ((float)rp.tile_h - 0.5f), ry + m);
-    if (x0 > x1 || y0 > y1) return false;   // no pixel centre of the tile in the box
-    const bool in_x = x0 <= 0.f && 0.f <= x1, in_y = y0 <= 0.f && 0.f <= y1;
-    if (in_x && in_y) return true;
-    if (lim == INFINITY) return true;
-    constexpr float kErr = 8.f * 5.96046448e-8f;
-    float best = INFINITY;
-    auto at = [&](float dx, float dy) {
-        const float bxy = b * dx * dy;
-        const float q = a * dx * dx + 2.f * bxy + c * dy * dy;
-        const float mag = a * dx * dx + 2.f * fabsf(bxy) + c * dy * dy;
-        best = fminf(best, q - kErr * mag);
-    };
-    if (!in_x) {   // the vertical edge facing the centre
-        const float ex = x0 > 0.f ? x0 : x1;
-        at(ex, fminf(fmaxf(-b * ex * __builtin_amdgcn_rcpf(c), y0), y1));
-    }
-    if (!in_y) {   // the horizontal edge facing the centre
-        const float ey = y0 > 0.f ? y0 : y1;
-        at(fminf(fmaxf(-b * ey * __builtin_amdgcn_rcpf(a), x0), x1), ey);
-    }
-    return best <= lim;
+// Reach limit of a super-tile: the tile test's limit (reach_limit) widened by
+// 1e-3 (1 + lim), more than twice the rounding bound of either evaluation, so
+// that an entry the compositing forward's tile test keeps on any tile of the
+// super-tile is never dropped from the super-tile's list (the minimum over
+// the super-tile's pixels is at most the minimum over one tile's).
+__device__ __forceinline__ float super_limit(float lim) {
+    return lim == INFINITY ? lim : lim + 1e-3f * (1.f + fabsf(lim));
 }
 
 // Pair emission, load balanced over emission units (a few header units per
@@ -180,13 +194,14 @@ __device__ __forceinline__ bool tile_reachable(float u, float v, float a, float 
 // the window run from the one holding the window's first unit to the one
 // holding the next window's first unit (both recorded by the offset scan); the
 // header units bound their number, and so the LDS a workgroup needs (more
-// workgroups in flight hide the dependent loads of each). Their tile
+// workgroups in flight hide the dependent loads of each). Their super-tile
 // rectangles are staged in LDS, a max-scan of their start positions gives
 // every window position its Gaussian, and every thread expands its pairs to
-// (tile, entry) with coalesced stores. Pair q of a Gaussian is
-// tile (x0 + q % w, y0 + q / w) of its rectangle, row-major; pairs that fail
-// the exact tile test get the all-ones key (kCulledTile, or kCulledTile16
-// when the batch keeps uint16 tile keys).
+// (super-tile, entry) with coalesced stores. Pair q of a Gaussian is
+// super-tile (x0 + q % w, y0 + q / w) of its rectangle, row-major; with
+// alpha_min > 0, pairs whose Gaussian cannot reach alpha_min on the
+// super-tile's pixels in the image get the all-ones key (kCulledTile, or
+// kCulledTile16 when the batch keeps uint16 keys).
 constexpr int kEmitThreads = 256;
 constexpr int kEmitItems = 4;
 constexpr int kEmitTile = kEmitThreads * kEmitItems;
@@ -198,16 +213,18 @@ template <typename K>
 __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     const uint32_t* __restrict__ sorted_entry, const uint32_t* __restrict__ offsets,
     const uint32_t* __restrict__ window_first, const float4* __restrict__ rec,
-    uint32_t* __restrict__ counters, int64_t n, Views views, RasterDev rp,
+    uint32_t* __restrict__ counters, int64_t n, const Views* __restrict__ views, RasterDev rp,
     int64_t capacity, K* __restrict__ ptile, uint32_t* __restrict__ pentry) {
     __shared__ uint32_t s_off[kEmitMaxG];
     __shared__ uint32_t s_ent[kEmitMaxG];
-    __shared__ uint32_t s_base[kEmitMaxG];   // global tile of the rectangle's first tile
-    __shared__ uint16_t s_w[kEmitMaxG];      // rectangle width in tiles
-    __shared__ uint16_t s_tx[kEmitMaxG];     // tiles per row of the Gaussian's view
-    __shared__ uint16_t s_x0[kEmitMaxG];     // first tile column and row of the rectangle
+    __shared__ uint32_t s_base[kEmitMaxG];   // global super-tile of the rectangle's first one
+    __shared__ uint16_t s_w[kEmitMaxG];      // rectangle width in super-tiles
+    __shared__ uint16_t s_tx[kEmitMaxG];     // super-tiles per row of the Gaussian's view
+    __shared__ uint16_t s_x0[kEmitMaxG];     // first super-tile column and row of the rectangle
     __shared__ uint16_t s_y0[kEmitMaxG];
-    __shared__ float s_lim[kEmitMaxG];       // reach limit of the exact tile test
+    __shared__ uint16_t s_iw[kEmitMaxG];     // image size of the Gaussian's view
+    __shared__ uint16_t s_ih[kEmitMaxG];
+    __shared__ float s_lim[kEmitMaxG];       // reach limit on a super-tile
     __shared__ uint32_t s_own[kEmitTile];    // window position -> owning Gaussian
     __shared__ uint32_t s_scan[kEmitThreads / 64 + 1];
     // pairs written = min(pairs needed, capacity); block 0 records it and
@@ -236,20 +253,23 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     for (uint32_t j = tid; j < cnt; j += kEmitThreads) {
         const uint32_t k = k0 + j;
         const uint32_t e = sorted_entry[k];
-        const ViewDev& V = views.v[(int)(e / n)];
+        const ViewDev& V = views->v[(int)(e / n)];
         const float4 r0 = rec[3 * (int64_t)e], r1 = rec[3 * (int64_t)e + 1];
-        int x0, x1, y0, y1;
+        int x0, x1, y0, y1, sx0, sx1, sy0, sy1;
         tile_rect(r0.x, r0.y, (int)r1.z, (int)r1.w, rp.tile_w, rp.tile_h, V.tiles_x, V.tiles_y,
                   &x0, &x1, &y0, &y1);
+        super_rect(x0, x1, y0, y1, rp.super_tile, &sx0, &sx1, &sy0, &sy1);
         const uint32_t off = offsets[k];
         s_off[j] = off;
         s_ent[j] = e;
-        s_base[j] = (uint32_t)(V.tile_offset + y0 * V.tiles_x + x0);
-        s_w[j] = (uint16_t)(x1 - x0);
-        s_tx[j] = (uint16_t)V.tiles_x;
-        s_x0[j] = (uint16_t)x0;
-        s_y0[j] = (uint16_t)y0;
-        s_lim[j] = reach_limit(r1.y, rp);
+        s_base[j] = (uint32_t)(V.sup_offset + sy0 * V.sup_x + sx0);
+        s_w[j] = (uint16_t)(sx1 - sx0);
+        s_tx[j] = (uint16_t)V.sup_x;
+        s_x0[j] = (uint16_t)sx0;
+        s_y0[j] = (uint16_t)sy0;
+        s_iw[j] = (uint16_t)V.width;
+        s_ih[j] = (uint16_t)V.height;
+        s_lim[j] = super_limit(reach_limit(r1.y, rp));
         // mark where this Gaussian's units start inside the window
         const uint64_t first = (uint64_t)off + (uint64_t)kEmitHead * k;
         if (j > 0 && first - c0 < (uint64_t)kEmitTile) s_own[first - c0] = j;
@@ -306,16 +326,20 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
         int32_t qx = (int32_t)(q - qy * w);
         while (qx < 0) { --qy; qx += (int32_t)w; }
         while (qx >= (int32_t)w) { ++qy; qx -= (int32_t)w; }
-        const bool keep = tile_reachable(g0[it].x, g0[it].y, g0[it].z, g0[it].w, g1[it].x,
-                                         s_lim[j], g1[it].z, g1[it].w, (int)s_x0[j] + qx,
-                                         (int)(s_y0[j] + qy), rp);
+        // the super-tile's pixels inside the image
+        const int sw = rp.super_tile * rp.tile_w, sh = rp.super_tile * rp.tile_h;
+        const int px0 = ((int)s_x0[j] + qx) * sw, py0 = ((int)s_y0[j] + (int)qy) * sh;
+        const bool keep = s_lim[j] == INFINITY ||
+                          rect_reachable(g0[it].x, g0[it].y, g0[it].z, g0[it].w, g1[it].x,
+                                         s_lim[j], g1[it].z, g1[it].w, px0, py0,
+                                         min(sw, (int)s_iw[j] - px0), min(sh, (int)s_ih[j] - py0));
         ptile[p] = keep ? (K)(s_base[j] + qy * s_tx[j] + (uint32_t)qx) : (K)~(K)0;
         pentry[p] = s_ent[j];
     }
 }
 
-// [start, end) of every tile by binary search in the sorted tile keys
-// (empty tiles: [0, 0)).
+// [start, end) of every super-tile by binary search in the sorted keys
+// (empty super-tiles: [0, 0)).
 template <typename K>
 __global__ void __launch_bounds__(256) ranges_kernel(const K* __restrict__ ptile,
                                                      const uint32_t* __restrict__ counters,
@@ -368,6 +392,26 @@ __global__ void __launch_bounds__(kOrderThreads) order_tiles_kernel(
         order[atomicAdd(&slot[bucket(t)], 1u)] = (uint32_t)t;
 }
 
+// The call's view table into the workspace, word by word: the views passed
+// by value or, with a camera table, its entry *d_view (clamped into range) as
+// view 0 of a one-view batch (table entries are stored for that position).
+__global__ void __launch_bounds__(64) store_views_kernel(Views v, const ViewDev* __restrict__ table,
+                                                         int n_table,
+                                                         const int32_t* __restrict__ d_view,
+                                                         Views* __restrict__ dst) {
+    static_assert(sizeof(Views) % 4 == 0 && sizeof(ViewDev) % 4 == 0, "word copy");
+    constexpr int kWords = (int)(sizeof(Views) / 4), kViewWords = (int)(sizeof(ViewDev) / 4);
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&v);
+    const uint32_t* sel = nullptr;
+    if (table != nullptr) {
+        const int i = min(max(*d_view, 0), n_table - 1);
+        sel = reinterpret_cast<const uint32_t*>(table + i);
+    }
+    uint32_t* out = reinterpret_cast<uint32_t*>(dst);
+    for (int w = threadIdx.x; w < kWords; w += 64)
+        out[w] = (sel != nullptr && w < kViewWords) ? sel[w] : src[w];
+}
+
 __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -375,15 +419,22 @@ __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
 
 }  // namespace
 
+hipError_t launch_store_views(const Views& views, const ViewDev* table, int n_table,
+                              const int32_t* d_view, Views* dst, hipStream_t s) {
+    hipLaunchKernelGGL(store_views_kernel, dim3(1), dim3(64), 0, s, views, table, n_table, d_view,
+                       dst);
+    return hipGetLastError();
+}
+
 hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 
-hipError_t launch_bin(const Views& views, const RasterDev& rp, int64_t n, const Layout& L,
-                      char* ws, hipStream_t s) {
+hipError_t launch_bin(const RasterDev& rp, int64_t n, const Layout& L, char* ws, hipStream_t s) {
     const int64_t E = L.entries;
+    const Views* views = reinterpret_cast<const Views*>(ws + L.views);
     uint32_t* counters = reinterpret_cast<uint32_t*>(ws + L.counters);
     uint32_t* tiles = reinterpret_cast<uint32_t*>(ws + L.tiles);
     const float4* rec = reinterpret_cast<const float4*>(ws + L.records);
@@ -396,31 +447,30 @@ hipError_t launch_bin(const Views& views, const RasterDev& rp, int64_t n, const 
     uint32_t* sums = reinterpret_cast<uint32_t*>(ws + L.scan_sums);
     uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.sort_hist);
     uint32_t* totals = reinterpret_cast<uint32_t*>(ws + L.sort_totals);
-    uint32_t* ptile[2] = {reinterpret_cast<uint32_t*>(ws + L.pair_tile[0]),
-                          reinterpret_cast<uint32_t*>(ws + L.pair_tile[1])};
-    uint16_t* ptile16[2] = {reinterpret_cast<uint16_t*>(ws + L.pair_tile[0]),
-                            reinterpret_cast<uint16_t*>(ws + L.pair_tile[1])};
-    const bool key16 = L.tile_key_bytes == 2;
+    uint32_t* pkey[2] = {reinterpret_cast<uint32_t*>(ws + L.pair_key[0]),
+                         reinterpret_cast<uint32_t*>(ws + L.pair_key[1])};
+    uint16_t* pkey16[2] = {reinterpret_cast<uint16_t*>(ws + L.pair_key[0]),
+                           reinterpret_cast<uint16_t*>(ws + L.pair_key[1])};
+    const bool key16 = L.key_bytes == 2;
     uint32_t* pentry[2] = {reinterpret_cast<uint32_t*>(ws + L.pair_entry[0]),
                            reinterpret_cast<uint32_t*>(ws + L.pair_entry[1])};
-    uint32_t* ranges = reinterpret_cast<uint32_t*>(ws + L.ranges);
+    uint32_t* ranges = reinterpret_cast<uint32_t*>(ws + L.sup_ranges);
     hipError_t err;
+    // counters this stage and the compositing forward accumulate into
+    constexpr int kClear = kWalked + 1 - kVisible;
 
     // visible entries -> (depth, entry), entry order; count -> counters[kVisible]
-    // (the first scan kernel also clears the counters binning and compositing
-    // accumulate into)
-    if (E == 0 && (err = fill_u32(counters + kVisible, kPairsKept + 1 - kVisible, 0u, s)) != hipSuccess)
-        return err;
+    // (the first scan kernel also clears the counters)
+    if (E == 0 && (err = fill_u32(counters + kVisible, kClear, 0u, s)) != hipSuccess) return err;
     if (E > 0) {
         err = device_scan(VisibleSrc{tiles, E},
                           CompactSink{reinterpret_cast<const uint32_t*>(ws + L.depth), dkey[0],
                                       dval[0]},
-                          E, sums, counters + kVisible, s, counters + kVisible,
-                          kPairsKept + 1 - kVisible);
+                          E, sums, counters + kVisible, s, counters + kVisible, kClear);
         if (err != hipSuccess) return err;
         // stable sort by depth (ties keep ascending entry order); the last
-        // pass also gathers each entry's tile count into `offsets`, in depth
-        // order, for the scan below to read linearly and overwrite in place
+        // pass also gathers each entry's super-tile count into `offsets`, in
+        // depth order, for the scan below to read linearly and overwrite in place
         int res = 0;
         err = radix_sort(dkey, dval, counters + kVisible, E, 32, hist, totals, s, &res, nullptr,
                          tiles, offsets);
@@ -436,28 +486,28 @@ hipError_t launch_bin(const Views& views, const RasterDev& rp, int64_t n, const 
         if (key16)
             hipLaunchKernelGGL(emit_kernel<uint16_t>, egrid, dim3(kEmitThreads), 0, s, dval[res],
                                offsets, window_first, rec, counters, n, views, rp, L.capacity,
-                               ptile16[0], pentry[0]);
+                               pkey16[0], pentry[0]);
         else
             hipLaunchKernelGGL(emit_kernel<uint32_t>, egrid, dim3(kEmitThreads), 0, s, dval[res],
                                offsets, window_first, rec, counters, n, views, rp, L.capacity,
-                               ptile[0], pentry[0]);
+                               pkey[0], pentry[0]);
         if ((err = hipGetLastError()) != hipSuccess) return err;
-        // stable sort of the pairs by tile; the first pass drops culled pairs
-        // and counts the rest into counters[kPairsKept]
-        int tres = 0;
-        err = key16 ? radix_sort(ptile16, pentry, counters + kPairsWritten, L.capacity, L.tile_bits,
-                                 hist, totals, s, &tres, counters + kPairsKept)
-                    : radix_sort(ptile, pentry, counters + kPairsWritten, L.capacity, L.tile_bits,
-                                 hist, totals, s, &tres, counters + kPairsKept);
+        // stable sort of the pairs by super-tile; the first pass drops culled
+        // pairs and counts the rest into counters[kPairsKept]
+        int kres = 0;
+        err = key16 ? radix_sort(pkey16, pentry, counters + kPairsWritten, L.capacity, L.key_bits,
+                                 hist, totals, s, &kres, counters + kPairsKept)
+                    : radix_sort(pkey, pentry, counters + kPairsWritten, L.capacity, L.key_bits,
+                                 hist, totals, s, &kres, counters + kPairsKept);
         if (err != hipSuccess) return err;
     }
-    const dim3 rgrid((unsigned)((L.total_tiles + 255) / 256));
-    if (L.total_tiles > 0 && key16)
-        hipLaunchKernelGGL(ranges_kernel<uint16_t>, rgrid, dim3(256), 0, s, ptile16[L.tile_result],
-                           counters, L.total_tiles, ranges);
-    else if (L.total_tiles > 0)
-        hipLaunchKernelGGL(ranges_kernel<uint32_t>, rgrid, dim3(256), 0, s, ptile[L.tile_result],
-                           counters, L.total_tiles, ranges);
+    const dim3 rgrid((unsigned)((L.total_supers + 255) / 256));
+    if (L.total_supers > 0 && key16)
+        hipLaunchKernelGGL(ranges_kernel<uint16_t>, rgrid, dim3(256), 0, s, pkey16[L.key_result],
+                           counters, L.total_supers, ranges);
+    else if (L.total_supers > 0)
+        hipLaunchKernelGGL(ranges_kernel<uint32_t>, rgrid, dim3(256), 0, s, pkey[L.key_result],
+                           counters, L.total_supers, ranges);
     return hipGetLastError();
 }
 

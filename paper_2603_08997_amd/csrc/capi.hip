@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "sgs_internal.hpp"
 
@@ -40,10 +41,20 @@ bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) %
 
 sgs_status check_raster(const sgs_raster_params* rp) {
     if (!rp) return fail(SGS_ERR_INVALID_ARG, "raster params are null");
+    if (rp->struct_size != sizeof(sgs_raster_params))
+        return fail(SGS_ERR_INVALID_ARG, "raster params struct_size %u, expected %zu",
+                    rp->struct_size, sizeof(sgs_raster_params));
     const bool ok = (rp->tile_w == 16 && rp->tile_h == 16) || (rp->tile_w == 8 && rp->tile_h == 8) ||
                     (rp->tile_w == 32 && rp->tile_h == 8);
     if (!ok) return fail(SGS_ERR_UNSUPPORTED, "tile shape %dx%d not in {16x16, 8x8, 32x8}",
                          rp->tile_w, rp->tile_h);
+    if (rp->super_tile < 0 || rp->super_tile > 64)
+        return fail(SGS_ERR_UNSUPPORTED, "super_tile %d not in [1, 64] (0: default)",
+                    rp->super_tile);
+    if (rp->lds_batch != 0 && rp->lds_batch != 32 && rp->lds_batch != 64 &&
+        rp->lds_batch != 128 && rp->lds_batch != 256)
+        return fail(SGS_ERR_UNSUPPORTED, "lds_batch %d not in {32, 64, 128, 256} (0: default)",
+                    rp->lds_batch);
     if (!(rp->alpha_max > 0.f && rp->alpha_max <= 1.f) ||
         !(rp->alpha_min >= 0.f && rp->alpha_min <= rp->alpha_max) ||
         !(rp->t_min >= 0.f && rp->t_min < 1.f) || !(rp->near_z >= 0.f) || !(rp->dilation >= 0.f) ||
@@ -74,7 +85,9 @@ sgs_status prepare(const sgs_raster_params* rp, int64_t n, const sgs_camera* cam
     const char* err = nullptr;
     if (!sgs::make_views(cams, n_views, rp, &P->views, &err)) return fail(SGS_ERR_INVALID_ARG, "%s", err);
     P->rd = sgs::make_raster(rp);
-    sgs::make_layout(P->views, n, capacity, &P->L);
+    sgs::make_layout(P->views, P->rd, n, capacity, &P->L);
+    if (P->L.chunk_capacity > (int64_t)0xfffffffe)
+        return fail(SGS_ERR_INVALID_ARG, "pair_capacity too large for the list storage");
     return SGS_OK;
 }
 
@@ -88,6 +101,9 @@ sgs_status check_ws(const Prepared& P, const void* ws, size_t bytes) {
 
 sgs_status check_gaussians(const sgs_gaussians* g) {
     if (!g) return fail(SGS_ERR_INVALID_ARG, "gaussians are null");
+    if (g->struct_size != sizeof(sgs_gaussians))
+        return fail(SGS_ERR_INVALID_ARG, "gaussians struct_size %u, expected %zu", g->struct_size,
+                    sizeof(sgs_gaussians));
     if (g->n < 0) return fail(SGS_ERR_INVALID_ARG, "n < 0");
     if (g->sh_degree < 0 || g->sh_degree > 3)
         return fail(SGS_ERR_INVALID_ARG, "sh_degree %d not in [0, 3]", g->sh_degree);
@@ -108,7 +124,7 @@ bool make_views(const sgs_camera* cams, int n_views, const sgs_raster_params* rp
                 const char** err) {
     std::memset(out, 0, sizeof(*out));
     out->n = n_views;
-    int64_t tiles = 0, pixels = 0;
+    int64_t tiles = 0, supers = 0, pixels = 0;
     for (int v = 0; v < n_views; ++v) {
         const sgs_camera& c = cams[v];
         if (c.width <= 0 || c.height <= 0 || c.width > 32768 || c.height > 32768) {
@@ -144,7 +160,12 @@ bool make_views(const sgs_camera* cams, int n_views, const sgs_raster_params* rp
         d.tiles_y = (c.height + rp->tile_h - 1) / rp->tile_h;
         d.tile_offset = (int32_t)tiles;
         d.px_offset = pixels;
+        const int S = rp->super_tile > 0 ? rp->super_tile : kDefaultSuperTile;
+        d.sup_x = (d.tiles_x + S - 1) / S;
+        d.sup_y = (d.tiles_y + S - 1) / S;
+        d.sup_offset = (int32_t)supers;
         tiles += (int64_t)d.tiles_x * d.tiles_y;
+        supers += (int64_t)d.sup_x * d.sup_y;
         pixels += (int64_t)c.width * c.height;
     }
     if (tiles > (1 << 24)) {
@@ -152,6 +173,7 @@ bool make_views(const sgs_camera* cams, int n_views, const sgs_raster_params* rp
         return false;
     }
     out->total_tiles = (int32_t)tiles;
+    out->total_supers = (int32_t)supers;
     out->total_pixels = pixels;
     return true;
 }
@@ -160,6 +182,8 @@ RasterDev make_raster(const sgs_raster_params* rp) {
     RasterDev r;
     r.tile_w = rp->tile_w;
     r.tile_h = rp->tile_h;
+    r.super_tile = rp->super_tile > 0 ? rp->super_tile : kDefaultSuperTile;
+    r.batch = rp->lds_batch > 0 ? rp->lds_batch : kDefaultBatch;
     for (int k = 0; k < 3; ++k) r.bg[k] = rp->bg[k];
     r.near_z = rp->near_z;
     r.dilation = rp->dilation;
@@ -170,20 +194,24 @@ RasterDev make_raster(const sgs_raster_params* rp) {
     return r;
 }
 
-void make_layout(const Views& views, int64_t n, int64_t capacity, Layout* L) {
+void make_layout(const Views& views, const RasterDev& rp, int64_t n, int64_t capacity, Layout* L) {
+    L->n_views = views.n;
     L->entries = n * views.n;
     L->total_tiles = views.total_tiles;
+    L->total_supers = views.total_supers;
     L->total_pixels = views.total_pixels;
     L->capacity = capacity;
+    L->batch = rp.batch;
+    L->chunk_capacity = list_chunks(capacity, L->total_tiles, rp.batch);
     L->scan_blocks = (L->entries + 2047) / 2048;
     L->sort_blocks = radix_blocks(std::max(L->entries, capacity));
-    // at least one pass: the first pass of the tile sort drops culled pairs
+    // at least one pass: the first pass of the super-tile sort drops culled pairs
     int bits = 1;
-    while ((int64_t(1) << bits) < L->total_tiles) ++bits;
-    L->tile_bits = bits;
-    L->tile_passes = radix_passes(bits);
-    L->tile_result = L->tile_passes & 1;
-    L->tile_key_bytes = L->total_tiles < kMaxTiles16 ? 2 : 4;
+    while ((int64_t(1) << bits) < L->total_supers) ++bits;
+    L->key_bits = bits;
+    L->key_passes = radix_passes(bits);
+    L->key_result = L->key_passes & 1;
+    L->key_bytes = L->total_supers < kMaxTiles16 ? 2 : 4;
     const int64_t E = L->entries;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -192,6 +220,7 @@ void make_layout(const Views& views, int64_t n, int64_t capacity, Layout* L) {
         return o;
     };
     L->counters = take(sizeof(uint32_t) * kNumCounters);
+    L->views = take(sizeof(Views));
     L->records = take(sizeof(float) * kRecordFloats * (size_t)E);
     L->accum = take(sizeof(float) * kAccumFloats * (size_t)E);
     L->tiles = take(sizeof(uint32_t) * (size_t)E);
@@ -203,13 +232,16 @@ void make_layout(const Views& views, int64_t n, int64_t capacity, Layout* L) {
     L->offsets = take(sizeof(uint32_t) * (size_t)E);
     L->window_first = take(sizeof(uint32_t) * (size_t)(emit_windows(E, capacity) + 1));
     L->scan_sums = take(sizeof(uint32_t) * (size_t)(L->scan_blocks + 1));
-    L->pair_tile[0] = take((size_t)L->tile_key_bytes * (size_t)capacity);
-    L->pair_tile[1] = take((size_t)L->tile_key_bytes * (size_t)capacity);
+    L->pair_key[0] = take((size_t)L->key_bytes * (size_t)capacity);
+    L->pair_key[1] = take((size_t)L->key_bytes * (size_t)capacity);
     L->pair_entry[0] = take(sizeof(uint32_t) * (size_t)capacity);
     L->pair_entry[1] = take(sizeof(uint32_t) * (size_t)capacity);
     L->sort_hist = take(sizeof(uint32_t) * 256 * (size_t)L->sort_blocks);
     L->sort_totals = take(sizeof(uint32_t) * 256);
-    L->ranges = take(sizeof(uint32_t) * 2 * (size_t)L->total_tiles);
+    L->sup_ranges = take(sizeof(uint32_t) * 2 * (size_t)L->total_supers);
+    L->chunks = take(sizeof(uint32_t) * (size_t)rp.batch * (size_t)L->chunk_capacity);
+    L->links = take(sizeof(uint32_t) * 2 * (size_t)L->chunk_capacity);
+    L->tile_head = take(sizeof(uint32_t) * (size_t)L->total_tiles);
     L->tile_cost = take(sizeof(uint32_t) * (size_t)L->total_tiles);
     L->tile_order = take(sizeof(uint32_t) * (size_t)L->total_tiles);
     L->t_final = take(sizeof(float) * (size_t)L->total_pixels);
@@ -229,8 +261,11 @@ int32_t sgs_version(void) { return 100; }
 
 void sgs_default_raster_params(sgs_raster_params* rp) {
     if (!rp) return;
+    rp->struct_size = sizeof(sgs_raster_params);
     rp->tile_w = 16;
     rp->tile_h = 16;
+    rp->super_tile = sgs::kDefaultSuperTile;
+    rp->lds_batch = sgs::kDefaultBatch;
     rp->bg[0] = rp->bg[1] = rp->bg[2] = 0.f;
     rp->near_z = 0.2f;
     rp->dilation = 0.3f;
@@ -262,10 +297,12 @@ sgs_status sgs_get_workspace_layout(const sgs_raster_params* rp, int64_t n, cons
     out->records = L.records;
     out->tiles = L.tiles;
     out->depth = L.depth;
-    out->pair_tile = L.pair_tile[L.tile_result];
-    out->pair_tile_bytes = L.tile_key_bytes;
-    out->pair_entry = L.pair_entry[L.tile_result];
-    out->ranges = L.ranges;
+    out->sup_key = L.pair_key[L.key_result];
+    out->sup_entry = L.pair_entry[L.key_result];
+    out->sup_ranges = L.sup_ranges;
+    out->chunks = L.chunks;
+    out->links = L.links;
+    out->tile_head = L.tile_head;
     out->t_final = L.t_final;
     out->n_last = L.n_last;
     out->accum = L.accum;
@@ -273,23 +310,45 @@ sgs_status sgs_get_workspace_layout(const sgs_raster_params* rp, int64_t n, cons
     out->entries = L.entries;
     out->total_tiles = L.total_tiles;
     out->total_pixels = L.total_pixels;
+    out->total_supers = L.total_supers;
+    out->chunk_capacity = L.chunk_capacity;
+    out->key_bytes = L.key_bytes;
+    out->batch = L.batch;
+    out->super_tile = P.rd.super_tile;
     return SGS_OK;
 }
+
+namespace {
+
+// Validated arguments of a render-path call and the call's view table stored
+// into its workspace (the first launch of every call).
+sgs_status begin_call(const sgs_raster_params* rp, int64_t n, const sgs_camera* cams,
+                      int32_t n_views, void* workspace, size_t workspace_bytes,
+                      int64_t pair_capacity, hipStream_t s, Prepared* P) {
+    sgs_status st = prepare(rp, n, cams, n_views, pair_capacity, P);
+    if (st != SGS_OK) return st;
+    if ((st = check_ws(*P, workspace, workspace_bytes)) != SGS_OK) return st;
+    char* ws = static_cast<char*>(workspace);
+    SGS_HIP(sgs::launch_store_views(P->views, nullptr, 0, nullptr,
+                                    reinterpret_cast<sgs::Views*>(ws + P->L.views), s),
+            "store views");
+    return SGS_OK;
+}
+
+}  // namespace
 
 sgs_status sgs_project(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_views,
                        const sgs_raster_params* rp, void* workspace, size_t workspace_bytes,
                        int64_t pair_capacity, void* stream) {
     sgs_status st = check_gaussians(g);
     if (st != SGS_OK) return st;
-    Prepared P;
-    if ((st = prepare(rp, g->n, cams, n_views, pair_capacity, &P)) != SGS_OK) return st;
-    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
-    char* ws = static_cast<char*>(workspace);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    SGS_HIP(sgs::launch_project(g->data, g->n, g->stride, g->sh_degree, P.views, P.rd,
-                                reinterpret_cast<float*>(ws + P.L.records),
-                                reinterpret_cast<uint32_t*>(ws + P.L.tiles),
-                                reinterpret_cast<uint32_t*>(ws + P.L.depth), s),
+    Prepared P;
+    if ((st = begin_call(rp, g->n, cams, n_views, workspace, workspace_bytes, pair_capacity, s,
+                         &P)) != SGS_OK)
+        return st;
+    SGS_HIP(sgs::launch_project(g->data, g->n, g->stride, g->sh_degree, P.rd, P.L,
+                                static_cast<char*>(workspace), s),
             "project");
     return SGS_OK;
 }
@@ -302,41 +361,37 @@ sgs_status sgs_load_records(const sgs_camera* cams, int32_t n_views, int64_t n,
     Prepared P;
     sgs_status st = prepare(rp, n, cams, n_views, pair_capacity, &P);
     if (st != SGS_OK) return st;
-    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
     if (P.L.entries > 0 && (!u || !v || !depth || !extent || !conic || !opacity || !rgb))
         return fail(SGS_ERR_INVALID_ARG, "record arrays are null");
-    char* ws = static_cast<char*>(workspace);
-    SGS_HIP(sgs::launch_load_records(P.L.entries, u, v, depth, extent, conic, opacity, rgb, n,
-                                     P.views, P.rd, reinterpret_cast<float*>(ws + P.L.records),
-                                     reinterpret_cast<uint32_t*>(ws + P.L.tiles),
-                                     reinterpret_cast<uint32_t*>(ws + P.L.depth),
-                                     static_cast<hipStream_t>(stream)),
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = begin_call(rp, n, cams, n_views, workspace, workspace_bytes, pair_capacity, s, &P)) !=
+        SGS_OK)
+        return st;
+    SGS_HIP(sgs::launch_load_records(u, v, depth, extent, conic, opacity, rgb, n, P.rd, P.L,
+                                     static_cast<char*>(workspace), s),
             "load_records");
     return SGS_OK;
 }
 
 sgs_status sgs_bin(const sgs_camera* cams, int32_t n_views, int64_t n, const sgs_raster_params* rp,
                    void* workspace, size_t workspace_bytes, int64_t pair_capacity, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
     Prepared P;
-    sgs_status st = prepare(rp, n, cams, n_views, pair_capacity, &P);
+    sgs_status st = begin_call(rp, n, cams, n_views, workspace, workspace_bytes, pair_capacity, s, &P);
     if (st != SGS_OK) return st;
-    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
-    SGS_HIP(sgs::launch_bin(P.views, P.rd, n, P.L, static_cast<char*>(workspace),
-                            static_cast<hipStream_t>(stream)),
-            "bin");
+    SGS_HIP(sgs::launch_bin(P.rd, n, P.L, static_cast<char*>(workspace), s), "bin");
     return SGS_OK;
 }
 
 sgs_status sgs_rasterize(const sgs_camera* cams, int32_t n_views, int64_t n,
                          const sgs_raster_params* rp, void* workspace, size_t workspace_bytes,
                          int64_t pair_capacity, float* out_rgb, void* stream) {
-    Prepared P;
-    sgs_status st = prepare(rp, n, cams, n_views, pair_capacity, &P);
-    if (st != SGS_OK) return st;
-    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
     if (!out_rgb) return fail(SGS_ERR_INVALID_ARG, "out_rgb is null");
-    SGS_HIP(sgs::launch_rasterize(P.views, P.rd, P.L, static_cast<char*>(workspace), out_rgb,
-                                  static_cast<hipStream_t>(stream)),
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Prepared P;
+    sgs_status st = begin_call(rp, n, cams, n_views, workspace, workspace_bytes, pair_capacity, s, &P);
+    if (st != SGS_OK) return st;
+    SGS_HIP(sgs::launch_rasterize(P.rd, P.L, static_cast<char*>(workspace), out_rgb, s),
             "rasterize");
     return SGS_OK;
 }
@@ -346,19 +401,17 @@ sgs_status sgs_render_forward(const sgs_gaussians* g, const sgs_camera* cams, in
                               int64_t pair_capacity, float* out_rgb, void* stream) {
     sgs_status st = check_gaussians(g);
     if (st != SGS_OK) return st;
-    Prepared P;
-    if ((st = prepare(rp, g->n, cams, n_views, pair_capacity, &P)) != SGS_OK) return st;
-    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
     if (!out_rgb) return fail(SGS_ERR_INVALID_ARG, "out_rgb is null");
-    char* ws = static_cast<char*>(workspace);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    SGS_HIP(sgs::launch_project(g->data, g->n, g->stride, g->sh_degree, P.views, P.rd,
-                                reinterpret_cast<float*>(ws + P.L.records),
-                                reinterpret_cast<uint32_t*>(ws + P.L.tiles),
-                                reinterpret_cast<uint32_t*>(ws + P.L.depth), s),
+    Prepared P;
+    if ((st = begin_call(rp, g->n, cams, n_views, workspace, workspace_bytes, pair_capacity, s,
+                         &P)) != SGS_OK)
+        return st;
+    char* ws = static_cast<char*>(workspace);
+    SGS_HIP(sgs::launch_project(g->data, g->n, g->stride, g->sh_degree, P.rd, P.L, ws, s),
             "project");
-    SGS_HIP(sgs::launch_bin(P.views, P.rd, g->n, P.L, ws, s), "bin");
-    SGS_HIP(sgs::launch_rasterize(P.views, P.rd, P.L, ws, out_rgb, s), "rasterize");
+    SGS_HIP(sgs::launch_bin(P.rd, g->n, P.L, ws, s), "bin");
+    SGS_HIP(sgs::launch_rasterize(P.rd, P.L, ws, out_rgb, s), "rasterize");
     return SGS_OK;
 }
 
@@ -366,13 +419,13 @@ sgs_status sgs_rasterize_backward(const sgs_camera* cams, int32_t n_views, int64
                                   const sgs_raster_params* rp, void* workspace,
                                   size_t workspace_bytes, int64_t pair_capacity,
                                   const float* dl_drgb, const int32_t* d_gate, void* stream) {
-    Prepared P;
-    sgs_status st = prepare(rp, n, cams, n_views, pair_capacity, &P);
-    if (st != SGS_OK) return st;
-    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
     if (!dl_drgb) return fail(SGS_ERR_INVALID_ARG, "dl_drgb is null");
-    SGS_HIP(sgs::launch_rasterize_backward(P.views, P.rd, P.L, static_cast<char*>(workspace),
-                                           dl_drgb, d_gate, static_cast<hipStream_t>(stream)),
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Prepared P;
+    sgs_status st = begin_call(rp, n, cams, n_views, workspace, workspace_bytes, pair_capacity, s, &P);
+    if (st != SGS_OK) return st;
+    SGS_HIP(sgs::launch_rasterize_backward(P.rd, P.L, static_cast<char*>(workspace), dl_drgb,
+                                           d_gate, s),
             "rasterize_backward");
     return SGS_OK;
 }
@@ -383,13 +436,14 @@ sgs_status sgs_project_backward(const sgs_gaussians* g, const sgs_camera* cams, 
                                 const int32_t* d_gate, float* grads, void* stream) {
     sgs_status st = check_gaussians(g);
     if (st != SGS_OK) return st;
-    Prepared P;
-    if ((st = prepare(rp, g->n, cams, n_views, pair_capacity, &P)) != SGS_OK) return st;
-    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
     if (!grads || !aligned(grads, 16)) return fail(SGS_ERR_INVALID_ARG, "grads null or unaligned");
-    SGS_HIP(sgs::launch_project_backward(g->data, g->n, g->stride, g->sh_degree, P.views, P.rd, P.L,
-                                         static_cast<char*>(workspace), d_gate, grads,
-                                         static_cast<hipStream_t>(stream)),
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Prepared P;
+    if ((st = begin_call(rp, g->n, cams, n_views, workspace, workspace_bytes, pair_capacity, s,
+                         &P)) != SGS_OK)
+        return st;
+    SGS_HIP(sgs::launch_project_backward(g->data, g->n, g->stride, g->sh_degree, P.rd, P.L,
+                                         static_cast<char*>(workspace), d_gate, grads, s),
             "project_backward");
     return SGS_OK;
 }
@@ -401,17 +455,18 @@ sgs_status sgs_render_backward(const sgs_gaussians* g, const sgs_camera* cams, i
                                void* stream) {
     sgs_status st = check_gaussians(g);
     if (st != SGS_OK) return st;
-    Prepared P;
-    if ((st = prepare(rp, g->n, cams, n_views, pair_capacity, &P)) != SGS_OK) return st;
-    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
     if (!dl_drgb) return fail(SGS_ERR_INVALID_ARG, "dl_drgb is null");
     if (!grads || !aligned(grads, 16)) return fail(SGS_ERR_INVALID_ARG, "grads null or unaligned");
-    char* ws = static_cast<char*>(workspace);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    SGS_HIP(sgs::launch_rasterize_backward(P.views, P.rd, P.L, ws, dl_drgb, d_gate, s),
+    Prepared P;
+    if ((st = begin_call(rp, g->n, cams, n_views, workspace, workspace_bytes, pair_capacity, s,
+                         &P)) != SGS_OK)
+        return st;
+    char* ws = static_cast<char*>(workspace);
+    SGS_HIP(sgs::launch_rasterize_backward(P.rd, P.L, ws, dl_drgb, d_gate, s),
             "rasterize_backward");
-    SGS_HIP(sgs::launch_project_backward(g->data, g->n, g->stride, g->sh_degree, P.views, P.rd, P.L,
-                                         ws, d_gate, grads, s),
+    SGS_HIP(sgs::launch_project_backward(g->data, g->n, g->stride, g->sh_degree, P.rd, P.L, ws,
+                                         d_gate, grads, s),
             "project_backward");
     return SGS_OK;
 }
@@ -426,7 +481,7 @@ sgs_status sgs_read_status(const void* workspace, uint32_t* flags_out, int64_t* 
     SGS_HIP(hipMemcpy(c, workspace, sizeof(c), hipMemcpyDeviceToHost), "read counters");
     if (flags_out) *flags_out = c[sgs::kStatus];
     if (visible_out) *visible_out = c[sgs::kVisible];
-    if (pairs_out) *pairs_out = c[sgs::kPairs];
+    if (pairs_out) *pairs_out = std::max(c[sgs::kPairs], c[sgs::kListed]);
     return SGS_OK;
 }
 
@@ -457,7 +512,7 @@ sgs_status sgs_photometric_loss(const float* rgb, const float* target, int32_t w
     if (!(lambda >= 0.f && lambda <= 1.f)) return fail(SGS_ERR_INVALID_ARG, "lambda not in [0, 1]");
     if (workspace_bytes < sgs::loss_workspace_bytes(width, height))
         return fail(SGS_ERR_CAPACITY, "loss workspace too small");
-    SGS_HIP(sgs::launch_loss_forward(rgb, target, width, height, lambda,
+    SGS_HIP(sgs::launch_loss_forward(rgb, sgs::TargetRef{target, nullptr, 1}, width, height, lambda,
                                      static_cast<char*>(workspace), d_loss,
                                      static_cast<hipStream_t>(stream)),
             "loss");
@@ -475,7 +530,7 @@ sgs_status sgs_photometric_loss_backward(const float* rgb, const float* target, 
     if (!(lambda >= 0.f && lambda <= 1.f)) return fail(SGS_ERR_INVALID_ARG, "lambda not in [0, 1]");
     if (workspace_bytes < sgs::loss_workspace_bytes(width, height))
         return fail(SGS_ERR_CAPACITY, "loss workspace too small");
-    SGS_HIP(sgs::launch_loss_backward(rgb, target, width, height, lambda,
+    SGS_HIP(sgs::launch_loss_backward(rgb, sgs::TargetRef{target, nullptr, 1}, width, height, lambda,
                                       static_cast<char*>(workspace), d_gate, dl_drgb,
                                       static_cast<hipStream_t>(stream)),
             "loss backward");
@@ -484,6 +539,9 @@ sgs_status sgs_photometric_loss_backward(const float* rgb, const float* target, 
 
 static sgs_status check_gate(const sgs_gate_params* p) {
     if (!p) return fail(SGS_ERR_INVALID_ARG, "gate params are null");
+    if (p->struct_size != sizeof(sgs_gate_params))
+        return fail(SGS_ERR_INVALID_ARG, "gate params struct_size %u, expected %zu", p->struct_size,
+                    sizeof(sgs_gate_params));
     if (p->n_views < 1) return fail(SGS_ERR_INVALID_ARG, "n_views < 1");
     if (!(p->beta > 0.0 && p->beta < 1.0)) return fail(SGS_ERR_INVALID_ARG, "beta not in (0, 1)");
     if (!(p->eps >= 0.0) || !std::isfinite(p->delta) || !(p->rho_lo >= 0.0 && p->rho_lo <= 1.0))
@@ -508,14 +566,15 @@ sgs_status sgs_gate_init(const sgs_gate_params* p, void* d_state, void* stream) 
     return SGS_OK;
 }
 
-sgs_status sgs_gate_update(const sgs_gate_params* p, void* d_state, int32_t view,
+sgs_status sgs_gate_update(const sgs_gate_params* p, void* d_state, const int32_t* d_view,
                            const float* d_loss, int32_t* d_gate, void* stream) {
     sgs_status st = check_gate(p);
     if (st != SGS_OK) return st;
-    if (!d_state || !d_loss || !d_gate) return fail(SGS_ERR_INVALID_ARG, "null pointer argument");
-    if (view < 0 || view >= p->n_views)
-        return fail(SGS_ERR_INVALID_ARG, "view %d not in [0, %d)", view, p->n_views);
-    SGS_HIP(sgs::launch_gate_update(p, d_state, view, d_loss, d_gate, static_cast<hipStream_t>(stream)),
+    if (!d_state || !d_view || !d_loss || !d_gate)
+        return fail(SGS_ERR_INVALID_ARG, "null pointer argument");
+    if (!aligned(d_state, 8)) return fail(SGS_ERR_INVALID_ARG, "gate state not 8-byte aligned");
+    SGS_HIP(sgs::launch_gate_update(p, d_state, d_view, d_loss, d_gate,
+                                    static_cast<hipStream_t>(stream)),
             "gate update");
     return SGS_OK;
 }
@@ -555,6 +614,8 @@ sgs_status sgs_adam_step(const sgs_adam_params* p, float* params, float* grads, 
     if (!aligned(params, 16) || !aligned(grads, 16) || !aligned(m, 16) || !aligned(v, 16))
         return fail(SGS_ERR_INVALID_ARG, "arrays must be 16-byte aligned");
     if ((st = check_adam(p)) != SGS_OK) return st;
+    if (p->visible_only)
+        return fail(SGS_ERR_UNSUPPORTED, "visible_only needs the fused projection backward step");
     SGS_HIP(sgs::launch_adam(p, params, grads, m, v, n, stride, n_planes, d_step, d_gate,
                              static_cast<hipStream_t>(stream)),
             "adam");
@@ -563,8 +624,11 @@ sgs_status sgs_adam_step(const sgs_adam_params* p, float* params, float* grads, 
 
 static sgs_status check_adam(const sgs_adam_params* p) {
     if (!p) return fail(SGS_ERR_INVALID_ARG, "adam params are null");
+    if (p->struct_size != sizeof(sgs_adam_params))
+        return fail(SGS_ERR_INVALID_ARG, "adam params struct_size %u, expected %zu", p->struct_size,
+                    sizeof(sgs_adam_params));
     if (!(p->beta1 >= 0.0 && p->beta1 < 1.0) || !(p->beta2 >= 0.0 && p->beta2 < 1.0) ||
-        !(p->eps >= 0.0))
+        !(p->eps >= 0.0) || (p->visible_only != 0 && p->visible_only != 1))
         return fail(SGS_ERR_INVALID_ARG, "Adam constants out of range");
     return SGS_OK;
 }
@@ -578,13 +642,15 @@ sgs_status sgs_project_backward_adam(const sgs_gaussians* g, const sgs_camera* c
     sgs_status st = check_gaussians(g);
     if (st != SGS_OK) return st;
     if ((st = check_adam(adam)) != SGS_OK) return st;
-    Prepared P;
-    if ((st = prepare(rp, g->n, cams, n_views, pair_capacity, &P)) != SGS_OK) return st;
-    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
     if (!m || !v || !d_step) return fail(SGS_ERR_INVALID_ARG, "m, v or step is null");
-    SGS_HIP(sgs::launch_project_backward_adam(g->data, g->n, g->stride, g->sh_degree, P.views,
-                                              P.rd, P.L, static_cast<char*>(workspace), adam, m, v,
-                                              d_step, d_gate, static_cast<hipStream_t>(stream)),
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Prepared P;
+    if ((st = begin_call(rp, g->n, cams, n_views, workspace, workspace_bytes, pair_capacity, s,
+                         &P)) != SGS_OK)
+        return st;
+    SGS_HIP(sgs::launch_project_backward_adam(g->data, g->n, g->stride, g->sh_degree, P.rd, P.L,
+                                              static_cast<char*>(workspace), adam,
+                                              adam->visible_only != 0, m, v, d_step, d_gate, s),
             "project_backward_adam");
     return SGS_OK;
 }
@@ -598,17 +664,120 @@ sgs_status sgs_render_backward_adam(const sgs_gaussians* g, const sgs_camera* ca
     sgs_status st = check_gaussians(g);
     if (st != SGS_OK) return st;
     if ((st = check_adam(adam)) != SGS_OK) return st;
-    Prepared P;
-    if ((st = prepare(rp, g->n, cams, n_views, pair_capacity, &P)) != SGS_OK) return st;
-    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
     if (!dl_drgb) return fail(SGS_ERR_INVALID_ARG, "dl_drgb is null");
     if (!m || !v || !d_step) return fail(SGS_ERR_INVALID_ARG, "m, v or step is null");
-    char* ws = static_cast<char*>(workspace);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    SGS_HIP(sgs::launch_rasterize_backward(P.views, P.rd, P.L, ws, dl_drgb, d_gate, s),
+    Prepared P;
+    if ((st = begin_call(rp, g->n, cams, n_views, workspace, workspace_bytes, pair_capacity, s,
+                         &P)) != SGS_OK)
+        return st;
+    char* ws = static_cast<char*>(workspace);
+    SGS_HIP(sgs::launch_rasterize_backward(P.rd, P.L, ws, dl_drgb, d_gate, s),
             "rasterize_backward");
-    SGS_HIP(sgs::launch_project_backward_adam(g->data, g->n, g->stride, g->sh_degree, P.views,
-                                              P.rd, P.L, ws, adam, m, v, d_step, d_gate, s),
+    SGS_HIP(sgs::launch_project_backward_adam(g->data, g->n, g->stride, g->sh_degree, P.rd, P.L,
+                                              ws, adam, adam->visible_only != 0, m, v, d_step,
+                                              d_gate, s),
+            "project_backward_adam");
+    return SGS_OK;
+}
+
+sgs_status sgs_camera_table_size(int32_t n_cams, size_t* bytes_out) {
+    if (!bytes_out) return fail(SGS_ERR_INVALID_ARG, "bytes_out is null");
+    if (n_cams < 1) return fail(SGS_ERR_INVALID_ARG, "n_cams < 1");
+    *bytes_out = sizeof(sgs::ViewDev) * (size_t)n_cams;
+    return SGS_OK;
+}
+
+sgs_status sgs_camera_table_init(const sgs_camera* cams, int32_t n_cams,
+                                 const sgs_raster_params* rp, void* d_table, size_t table_bytes,
+                                 void* stream) {
+    sgs_status st = check_raster(rp);
+    if (st != SGS_OK) return st;
+    if (!cams || n_cams < 1) return fail(SGS_ERR_INVALID_ARG, "no cameras");
+    if (!d_table || !aligned(d_table, 16)) return fail(SGS_ERR_INVALID_ARG, "table null or unaligned");
+    if (table_bytes < sizeof(sgs::ViewDev) * (size_t)n_cams)
+        return fail(SGS_ERR_CAPACITY, "camera table has %zu bytes, needs %zu", table_bytes,
+                    sizeof(sgs::ViewDev) * (size_t)n_cams);
+    std::vector<sgs::ViewDev> host((size_t)n_cams);
+    for (int32_t i = 0; i < n_cams; ++i) {
+        if (cams[i].width != cams[0].width || cams[i].height != cams[0].height)
+            return fail(SGS_ERR_INVALID_ARG, "camera %d is %dx%d, camera 0 is %dx%d", i,
+                        cams[i].width, cams[i].height, cams[0].width, cams[0].height);
+        sgs::Views one;
+        const char* err = nullptr;
+        if (!sgs::make_views(cams + i, 1, rp, &one, &err))
+            return fail(SGS_ERR_INVALID_ARG, "camera %d: %s", i, err);
+        host[(size_t)i] = one.v[0];
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SGS_HIP(hipMemcpyAsync(d_table, host.data(), sizeof(sgs::ViewDev) * (size_t)n_cams,
+                           hipMemcpyHostToDevice, s),
+            "copy camera table");
+    SGS_HIP(hipStreamSynchronize(s), "stream sync");
+    return SGS_OK;
+}
+
+sgs_status sgs_view_sequence_next(const int32_t* d_sequence, int64_t sequence_len,
+                                  int64_t* d_iter, int32_t* d_view, void* stream) {
+    if (!d_sequence || !d_iter || !d_view) return fail(SGS_ERR_INVALID_ARG, "null pointer argument");
+    if (sequence_len < 1) return fail(SGS_ERR_INVALID_ARG, "sequence_len < 1");
+    if (!aligned(d_iter, 8)) return fail(SGS_ERR_INVALID_ARG, "d_iter not 8-byte aligned");
+    SGS_HIP(sgs::launch_sequence_next(d_sequence, sequence_len, d_iter, d_view,
+                                      static_cast<hipStream_t>(stream)),
+            "view sequence");
+    return SGS_OK;
+}
+
+sgs_status sgs_train_iteration(const sgs_gaussians* g, const sgs_camera* cams,
+                               const void* d_table, int32_t n_cams, const int32_t* d_view,
+                               const sgs_raster_params* rp, void* workspace,
+                               size_t workspace_bytes, int64_t pair_capacity,
+                               const float* targets, float lambda, void* loss_workspace,
+                               size_t loss_workspace_bytes, float* rgb, float* dl_drgb,
+                               float* d_loss, const sgs_gate_params* gp, void* gate_state,
+                               int32_t* d_gate, const sgs_adam_params* adam, float* m, float* v,
+                               int32_t* d_step, void* stream) {
+    sgs_status st = check_gaussians(g);
+    if (st != SGS_OK) return st;
+    if ((st = check_adam(adam)) != SGS_OK) return st;
+    if (!d_table || !aligned(d_table, 16) || !d_view || n_cams < 1)
+        return fail(SGS_ERR_INVALID_ARG, "camera table, view index or n_cams missing");
+    if (!targets || !rgb || !dl_drgb || !d_loss || !d_gate || !m || !v || !d_step ||
+        !loss_workspace)
+        return fail(SGS_ERR_INVALID_ARG, "null pointer argument");
+    if (!(lambda >= 0.f && lambda <= 1.f)) return fail(SGS_ERR_INVALID_ARG, "lambda not in [0, 1]");
+    if (gate_state != nullptr) {
+        if ((st = check_gate(gp)) != SGS_OK) return st;
+        if (!aligned(gate_state, 8)) return fail(SGS_ERR_INVALID_ARG, "gate state not 8-byte aligned");
+    }
+    Prepared P;
+    if ((st = prepare(rp, g->n, cams, 1, pair_capacity, &P)) != SGS_OK) return st;
+    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
+    const int w = cams[0].width, h = cams[0].height;
+    if (loss_workspace_bytes < sgs::loss_workspace_bytes(w, h))
+        return fail(SGS_ERR_CAPACITY, "loss workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* ws = static_cast<char*>(workspace);
+    char* lws = static_cast<char*>(loss_workspace);
+    const sgs::TargetRef tgt{targets, d_view, n_cams};
+    SGS_HIP(sgs::launch_store_views(P.views, static_cast<const sgs::ViewDev*>(d_table), n_cams,
+                                    d_view, reinterpret_cast<sgs::Views*>(ws + P.L.views), s),
+            "select view");
+    SGS_HIP(sgs::launch_project(g->data, g->n, g->stride, g->sh_degree, P.rd, P.L, ws, s),
+            "project");
+    SGS_HIP(sgs::launch_bin(P.rd, g->n, P.L, ws, s), "bin");
+    SGS_HIP(sgs::launch_rasterize(P.rd, P.L, ws, rgb, s), "rasterize");
+    SGS_HIP(sgs::launch_loss_forward(rgb, tgt, w, h, lambda, lws, d_loss, s), "loss");
+    if (gate_state != nullptr)
+        SGS_HIP(sgs::launch_gate_update(gp, gate_state, d_view, d_loss, d_gate, s), "gate");
+    else
+        SGS_HIP(sgs::fill_u32(reinterpret_cast<uint32_t*>(d_gate), 1, 1u, s), "open gate");
+    SGS_HIP(sgs::launch_loss_backward(rgb, tgt, w, h, lambda, lws, d_gate, dl_drgb, s),
+            "loss backward");
+    SGS_HIP(sgs::launch_rasterize_backward(P.rd, P.L, ws, dl_drgb, d_gate, s), "rasterize_backward");
+    SGS_HIP(sgs::launch_project_backward_adam(g->data, g->n, g->stride, g->sh_degree, P.rd, P.L, ws,
+                                              adam, adam->visible_only != 0, m, v, d_step, d_gate,
+                                              s),
             "project_backward_adam");
     return SGS_OK;
 }

@@ -60,6 +60,14 @@ LossLayout loss_layout(int w, int h) {
     return L;
 }
 
+// The reference image of a call: the given one, or image *d_view (clamped)
+// of an array of n_targets images of 3 H W floats.
+__device__ __forceinline__ const float* target_of(const TargetRef& t, int64_t image_floats) {
+    if (t.d_view == nullptr) return t.base;
+    const int i = min(max(*t.d_view, 0), t.n_targets - 1);
+    return t.base + (int64_t)i * image_floats;
+}
+
 // Stages field f of channels 0..2 of an image (plane stride `plane`) around
 // the tile into dst[ch][26][26], zero outside the image.
 __device__ __forceinline__ void stage3(const float* __restrict__ img, int64_t plane, int w, int h,
@@ -112,7 +120,7 @@ __device__ __forceinline__ void moments(const float (*X)[kE], const float (*Y)[k
 // filters (written on every forward, so that a backward needs no second pass
 // over the moments).
 __global__ void __launch_bounds__(kThreads) ssim_forward_kernel(
-    const float* __restrict__ x, const float* __restrict__ y, int w, int h, Window W,
+    const float* __restrict__ x, TargetRef target, int w, int h, Window W,
     float* __restrict__ partials, float* __restrict__ maps) {
     __shared__ float sx[3][kE][kE];
     __shared__ float sy[3][kE][kE];
@@ -124,6 +132,7 @@ __global__ void __launch_bounds__(kThreads) ssim_forward_kernel(
     const int ox = bx * kT + tid % kT, oy = by * kT + tid / kT;
     const bool inside = ox < w && oy < h;
     const int64_t plane = (int64_t)w * h;
+    const float* __restrict__ y = target_of(target, 3 * plane);
     stage3(x, plane, w, h, x0, y0, sx);
     stage3(y, plane, w, h, x0, y0, sy);
     __syncthreads();
@@ -192,7 +201,7 @@ __global__ void __launch_bounds__(1024) loss_reduce_kernel(const float* __restri
 }
 
 __global__ void __launch_bounds__(kThreads) ssim_backward_kernel(
-    const float* __restrict__ x, const float* __restrict__ y, int w, int h, float lambda,
+    const float* __restrict__ x, TargetRef target, int w, int h, float lambda,
     Window W, const float* __restrict__ maps, const int32_t* __restrict__ gate,
     float* __restrict__ dl) {
     if (gate_closed(gate)) return;
@@ -204,6 +213,7 @@ __global__ void __launch_bounds__(kThreads) ssim_backward_kernel(
     const int ox = bx * kT + tid % kT, oy = by * kT + tid / kT;
     const bool inside = ox < w && oy < h;
     const int64_t plane = (int64_t)w * h;
+    const float* __restrict__ y = target_of(target, 3 * plane);
     const float inv = 1.f / (3.f * (float)w * (float)h);
     for (int ch = 0; ch < 3; ++ch) {
         for (int i = tid; i < 3 * kE * kE; i += kThreads) {
@@ -257,7 +267,7 @@ __global__ void __launch_bounds__(kThreads) ssim_backward_kernel(
 
 size_t loss_workspace_bytes(int w, int h) { return loss_layout(w, h).total; }
 
-hipError_t launch_loss_forward(const float* rgb, const float* target, int w, int h, float lambda,
+hipError_t launch_loss_forward(const float* rgb, TargetRef target, int w, int h, float lambda,
                                char* ws, float* d_loss, hipStream_t s) {
     const LossLayout L = loss_layout(w, h);
     const dim3 grid((unsigned)((w + kT - 1) / kT), (unsigned)((h + kT - 1) / kT));
@@ -270,7 +280,7 @@ hipError_t launch_loss_forward(const float* rgb, const float* target, int w, int
     return hipGetLastError();
 }
 
-hipError_t launch_loss_backward(const float* rgb, const float* target, int w, int h, float lambda,
+hipError_t launch_loss_backward(const float* rgb, TargetRef target, int w, int h, float lambda,
                                 char* ws, const int32_t* gate, float* dl, hipStream_t s) {
     const LossLayout L = loss_layout(w, h);
     const dim3 grid((unsigned)((w + kT - 1) / kT), (unsigned)((h + kT - 1) / kT));

@@ -140,7 +140,7 @@ __device__ __forceinline__ bool compute_geometry(const float mu[3], const float 
     return true;
 }
 
-__device__ __forceinline__ int find_view(const Views& views, int64_t e, int64_t n, int64_t* i) {
+__device__ __forceinline__ int find_view(int64_t e, int64_t n, int64_t* i) {
     const int v = (int)(e / n);
     *i = e - (int64_t)v * n;
     return v;
@@ -148,16 +148,16 @@ __device__ __forceinline__ int find_view(const Views& views, int64_t e, int64_t 
 
 template <int sh_degree>
 __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ planes, int64_t n,
-                                                      int64_t stride, Views views,
+                                                      int64_t stride, const Views* __restrict__ views,
                                                       RasterDev rp, float4* __restrict__ rec,
                                                       uint32_t* __restrict__ tiles,
                                                       uint32_t* __restrict__ dkey) {
-    const int64_t entries = n * views.n;
+    const int64_t entries = n * views->n;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= entries) return;
     int64_t i;
-    const int vi = find_view(views, e, n, &i);
-    const ViewDev& V = views.v[vi];
+    const int vi = find_view(e, n, &i);
+    const ViewDev& V = views->v[vi];
     const PlaneBuf P{const_cast<float*>(planes), stride};
     const uint32_t off = (uint32_t)i * 4u;
     float mu[3], ls[3], q[4];
@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
             tile_rect(u, v, (int)ex, (int)ey, rp.tile_w, rp.tile_h, V.tiles_x, V.tiles_y, &x0, &x1,
                       &y0, &y1);
             if (x1 > x0 && y1 > y0) {
-                ntiles = (uint32_t)((x1 - x0) * (y1 - y0));
+                ntiles = super_count(x0, x1, y0, y1, rp.super_tile);
                 const uint32_t mask = (col[0] >= 0.f ? 1u : 0u) | (col[1] >= 0.f ? 2u : 0u) |
                                       (col[2] >= 0.f ? 4u : 0u);
                 r0 = make_float4(u, v, ca, cb);
@@ -235,12 +235,13 @@ __global__ void __launch_bounds__(256) load_records_kernel(
     int64_t entries, int64_t n, const float* __restrict__ u, const float* __restrict__ v,
     const float* __restrict__ depth, const int32_t* __restrict__ extent,
     const float* __restrict__ conic, const float* __restrict__ opacity,
-    const float* __restrict__ rgb, Views views, RasterDev rp, float4* __restrict__ rec,
+    const float* __restrict__ rgb, const Views* __restrict__ views, RasterDev rp,
+    float4* __restrict__ rec,
     uint32_t* __restrict__ tiles, uint32_t* __restrict__ dkey) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= entries) return;
     int64_t i;
-    const ViewDev& V = views.v[find_view(views, e, n, &i)];
+    const ViewDev& V = views->v[find_view(e, n, &i)];
     const int rx = extent[2 * e], ry = extent[2 * e + 1];
     uint32_t ntiles = 0;
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
@@ -250,7 +251,7 @@ __global__ void __launch_bounds__(256) load_records_kernel(
         tile_rect(u[e], v[e], rx, ry, rp.tile_w, rp.tile_h, V.tiles_x, V.tiles_y, &x0, &x1, &y0,
                   &y1);
         if (x1 > x0 && y1 > y0) {
-            ntiles = (uint32_t)((x1 - x0) * (y1 - y0));
+            ntiles = super_count(x0, x1, y0, y1, rp.super_tile);
             r0 = make_float4(u[e], v[e], conic[3 * e], conic[3 * e + 1]);
             r1 = make_float4(conic[3 * e + 2], opacity[e], (float)rx, (float)ry);
             r2 = make_float4(rgb[3 * e], rgb[3 * e + 1], rgb[3 * e + 2], __uint_as_float(7u));
@@ -436,9 +437,10 @@ __device__ __forceinline__ void sh_coef_grad(const ViewSH& o, float* g_sh) {
 // view; otherwise: gradient ADDED to grads, visible Gaussians only) runs over
 // the planes in batches whose moment (or gradient) loads are issued one batch
 // ahead, so that each thread keeps several memory requests in flight.
-template <int sh_degree, bool kFused, bool kMulti>
+template <int sh_degree, bool kFused, bool kMulti, bool kSparse = false>
 __device__ __forceinline__ void gaussian_backward(float* __restrict__ planes, int64_t n,
-                                                  int64_t stride, int64_t i, const Views& views,
+                                                  int64_t stride, int64_t i,
+                                                  const Views* __restrict__ views,
                                                   const RasterDev& rp,
                                                   const float4* __restrict__ rec,
                                                   const uint32_t* __restrict__ tiles,
@@ -469,20 +471,22 @@ __device__ __forceinline__ void gaussian_backward(float* __restrict__ planes, in
     }
     bool any = false;
     ViewSH one;
-    for (int vi = 0; vi < views.n; ++vi) {
+    for (int vi = 0; vi < views->n; ++vi) {
         const int64_t e = (int64_t)vi * n + i;
         if (tiles[e] == 0) continue;
         const float4 a0 = acc[3 * e], a1 = acc[3 * e + 1];
-        if (geom_grads(mu, ls, q, p[10], views.v[vi], rp, a0, a1, g, g + 3, g + 6, g + 10)) {
+        if (geom_grads(mu, ls, q, p[10], views->v[vi], rp, a0, a1, g, g + 3, g + 6, g + 10)) {
             any = true;
             ViewSH o;
-            view_sh(mu, views.v[vi], a1, acc[3 * e + 2], rec[3 * e + 2], o);
+            view_sh(mu, views->v[vi], a1, acc[3 * e + 2], rec[3 * e + 2], o);
             sh_mean_grad<sh_degree>(o, f, g);
             if constexpr (kMulti) sh_coef_grad<sh_degree>(o, g_sh);
             else one = o;
         }
     }
-    if (!kFused && !any) return;
+    // without a visible entry: nothing to add (gradient accumulation), or,
+    // for the visible-only (sparse) Adam step, nothing to update
+    if ((!kFused || kSparse) && !any) return;
     float Y[16];
     if constexpr (!kMulti) {
         if (any) sh_eval(sh_degree, one.d[0], one.d[1], one.d[2], Y);
@@ -538,7 +542,8 @@ __device__ __forceinline__ void gaussian_backward(float* __restrict__ planes, in
 // Adjoint of the projection: one thread per Gaussian, gradient ADDED to grads.
 template <int sh_degree, bool kMulti>
 __global__ void __launch_bounds__(kBackwardThreads) project_backward_kernel(
-    const float* __restrict__ planes, int64_t n, int64_t stride, Views views, RasterDev rp,
+    const float* __restrict__ planes, int64_t n, int64_t stride, const Views* __restrict__ views,
+    RasterDev rp,
     const float4* __restrict__ rec, const uint32_t* __restrict__ tiles,
     const float4* __restrict__ acc, const int32_t* __restrict__ gate, float* __restrict__ grads) {
     if (gate_closed(gate)) return;
@@ -549,14 +554,14 @@ __global__ void __launch_bounds__(kBackwardThreads) project_backward_kernel(
                                                 nullptr, nullptr);
 }
 
-// Adjoint of the projection fused with the Adam step: every Gaussian (visible
-// or not, as in dense Adam) gets its gradient computed in registers and its
-// parameters, first and second moments updated in place; no gradient array
-// is written or read.
-template <int sh_degree, bool kMulti>
+// Adjoint of the projection fused with the Adam step: every Gaussian (dense
+// Adam: visible or not) or only the Gaussians visible in a view of the batch
+// (kSparse) gets its gradient computed in registers and its parameters, first
+// and second moments updated in place; no gradient array is written or read.
+template <int sh_degree, bool kMulti, bool kSparse>
 __global__ void __launch_bounds__(kBackwardThreads) project_backward_adam_kernel(
-    float* __restrict__ planes, int64_t n, int64_t stride, Views views, RasterDev rp,
-    const float4* __restrict__ rec, const uint32_t* __restrict__ tiles,
+    float* __restrict__ planes, int64_t n, int64_t stride, const Views* __restrict__ views,
+    RasterDev rp, const float4* __restrict__ rec, const uint32_t* __restrict__ tiles,
     const float4* __restrict__ acc, AdamDev ad, float* __restrict__ m, float* __restrict__ v,
     const int32_t* __restrict__ step, const int32_t* __restrict__ gate) {
     if (gate_closed(gate)) return;
@@ -566,40 +571,49 @@ __global__ void __launch_bounds__(kBackwardThreads) project_backward_adam_kernel
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const AdamStep as = s_as;
-    gaussian_backward<sh_degree, true, kMulti>(planes, n, stride, i, views, rp, rec, tiles, acc,
-                                               nullptr, &ad, &as, m, v);
+    gaussian_backward<sh_degree, true, kMulti, kSparse>(planes, n, stride, i, views, rp, rec,
+                                                        tiles, acc, nullptr, &ad, &as, m, v);
 }
 
 }  // namespace
 
 hipError_t launch_project(const float* planes, int64_t n, int64_t stride, int sh_degree,
-                          const Views& views, const RasterDev& rp, float* records,
-                          uint32_t* tiles, uint32_t* dkey, hipStream_t s) {
-    const int64_t entries = n * views.n;
+                          const RasterDev& rp, const Layout& L, char* ws, hipStream_t s) {
+    const int64_t entries = L.entries;
     if (entries == 0) return hipSuccess;
     const int nt = 256;
     const int64_t nb = (entries + nt - 1) / nt;
-    float4* rec = reinterpret_cast<float4*>(records);
+    const Views* views = reinterpret_cast<const Views*>(ws + L.views);
+    float4* rec = reinterpret_cast<float4*>(ws + L.records);
+    uint32_t* tiles = reinterpret_cast<uint32_t*>(ws + L.tiles);
+    uint32_t* dkey = reinterpret_cast<uint32_t*>(ws + L.depth);
+#define SGS_PK(D)                                                                          \
+    hipLaunchKernelGGL(project_kernel<D>, dim3((unsigned)nb), dim3(nt), 0, s, planes, n, stride, \
+                       views, rp, rec, tiles, dkey)
     switch (sh_degree) {
-        case 0: hipLaunchKernelGGL(project_kernel<0>, dim3((unsigned)nb), dim3(nt), 0, s, planes, n, stride, views, rp, rec, tiles, dkey); break;
-        case 1: hipLaunchKernelGGL(project_kernel<1>, dim3((unsigned)nb), dim3(nt), 0, s, planes, n, stride, views, rp, rec, tiles, dkey); break;
-        case 2: hipLaunchKernelGGL(project_kernel<2>, dim3((unsigned)nb), dim3(nt), 0, s, planes, n, stride, views, rp, rec, tiles, dkey); break;
-        default: hipLaunchKernelGGL(project_kernel<3>, dim3((unsigned)nb), dim3(nt), 0, s, planes, n, stride, views, rp, rec, tiles, dkey); break;
+        case 0: SGS_PK(0); break;
+        case 1: SGS_PK(1); break;
+        case 2: SGS_PK(2); break;
+        default: SGS_PK(3); break;
     }
+#undef SGS_PK
     return hipGetLastError();
 }
 
-hipError_t launch_load_records(int64_t entries, const float* u, const float* v,
-                               const float* depth, const int32_t* extent, const float* conic,
-                               const float* opacity, const float* rgb, int64_t n,
-                               const Views& views, const RasterDev& rp, float* records,
-                               uint32_t* tiles, uint32_t* dkey, hipStream_t s) {
+hipError_t launch_load_records(const float* u, const float* v, const float* depth,
+                               const int32_t* extent, const float* conic, const float* opacity,
+                               const float* rgb, int64_t n, const RasterDev& rp, const Layout& L,
+                               char* ws, hipStream_t s) {
+    const int64_t entries = L.entries;
     if (entries == 0) return hipSuccess;
     const int nt = 256;
     const int64_t nb = (entries + nt - 1) / nt;
     hipLaunchKernelGGL(load_records_kernel, dim3((unsigned)nb), dim3(nt), 0, s, entries, n, u, v,
-                       depth, extent, conic, opacity, rgb, views, rp,
-                       reinterpret_cast<float4*>(records), tiles, dkey);
+                       depth, extent, conic, opacity, rgb,
+                       reinterpret_cast<const Views*>(ws + L.views), rp,
+                       reinterpret_cast<float4*>(ws + L.records),
+                       reinterpret_cast<uint32_t*>(ws + L.tiles),
+                       reinterpret_cast<uint32_t*>(ws + L.depth));
     return hipGetLastError();
 }
 
@@ -612,40 +626,45 @@ hipError_t launch_load_records(int64_t entries, const float* u, const float* v,
     }
 
 hipError_t launch_project_backward(const float* planes, int64_t n, int64_t stride,
-                                   int sh_degree, const Views& views, const RasterDev& rp,
-                                   const Layout& L, char* ws, const int32_t* gate, float* grads,
-                                   hipStream_t s) {
+                                   int sh_degree, const RasterDev& rp, const Layout& L, char* ws,
+                                   const int32_t* gate, float* grads, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const int nt = kBackwardThreads;
     const int64_t nb = (n + nt - 1) / nt;
+    const Views* views = reinterpret_cast<const Views*>(ws + L.views);
     const float4* rec = reinterpret_cast<const float4*>(ws + L.records);
     const uint32_t* tl = reinterpret_cast<const uint32_t*>(ws + L.tiles);
     const float4* acc = reinterpret_cast<const float4*>(ws + L.accum);
 #define SGS_PB(D, M)                                                                              \
     hipLaunchKernelGGL((project_backward_kernel<D, M>), dim3((unsigned)nb), dim3(nt), 0, s, planes, \
                        n, stride, views, rp, rec, tl, acc, gate, grads)
-    SGS_DISPATCH_DEG(SGS_PB, views.n > 1)
+    SGS_DISPATCH_DEG(SGS_PB, L.n_views > 1)
 #undef SGS_PB
     return hipGetLastError();
 }
 
 hipError_t launch_project_backward_adam(float* planes, int64_t n, int64_t stride, int sh_degree,
-                                        const Views& views, const RasterDev& rp, const Layout& L,
-                                        char* ws, const sgs_adam_params* prm, float* m, float* v,
-                                        int32_t* step, const int32_t* gate, hipStream_t s) {
+                                        const RasterDev& rp, const Layout& L, char* ws,
+                                        const sgs_adam_params* prm, bool sparse, float* m,
+                                        float* v, int32_t* step, const int32_t* gate,
+                                        hipStream_t s) {
     hipError_t err = launch_adam_count(step, gate, s);
     if (err != hipSuccess || n == 0) return err;
     const AdamDev ad = make_adam(prm);
     const int nt = kBackwardThreads;
     const int64_t nb = (n + nt - 1) / nt;
+    const Views* views = reinterpret_cast<const Views*>(ws + L.views);
     const float4* rec = reinterpret_cast<const float4*>(ws + L.records);
     const uint32_t* tl = reinterpret_cast<const uint32_t*>(ws + L.tiles);
     const float4* acc = reinterpret_cast<const float4*>(ws + L.accum);
-#define SGS_PBA(D, M)                                                                         \
-    hipLaunchKernelGGL((project_backward_adam_kernel<D, M>), dim3((unsigned)nb), dim3(nt), 0, s, \
-                       planes, n, stride, views, rp, rec, tl, acc, ad, m, v, step, gate)
-    SGS_DISPATCH_DEG(SGS_PBA, views.n > 1)
+#define SGS_PBA_S(D, M, SP)                                                                     \
+    hipLaunchKernelGGL((project_backward_adam_kernel<D, M, SP>), dim3((unsigned)nb), dim3(nt), 0, \
+                       s, planes, n, stride, views, rp, rec, tl, acc, ad, m, v, step, gate)
+#define SGS_PBA(D, M) \
+    if (sparse) SGS_PBA_S(D, M, true); else SGS_PBA_S(D, M, false)
+    SGS_DISPATCH_DEG(SGS_PBA, L.n_views > 1)
 #undef SGS_PBA
+#undef SGS_PBA_S
     return hipGetLastError();
 }
 

@@ -144,9 +144,9 @@ __device__ __forceinline__ float wave_sum9_scatter(const float (&x)[9], int lane
     return w;
 }
 
-__device__ __forceinline__ int view_of_tile(const Views& views, int tile) {
+__device__ __forceinline__ int view_of_tile(const Views* views, int tile) {
     int vi = 0;
-    while (vi + 1 < views.n && tile >= views.v[vi + 1].tile_offset) ++vi;
+    while (vi + 1 < views->n && tile >= views->v[vi + 1].tile_offset) ++vi;
     return vi;
 }
 
@@ -162,53 +162,116 @@ __device__ __forceinline__ uint32_t wave_add_u32(uint32_t v) {
     return v;
 }
 
-template <int TW, int TH>
+// Forward of one tile. The wave walks its super-tile's list 64 entries at a
+// time; every lane tests one entry against the tile (the tile lies in the
+// entry's tile rectangle and, with alpha_min > 0, the entry passes the reach
+// test on the tile's pixels), and the entries that pass are appended, staged,
+// to a queue in LDS in list order: the queue receives the tile's own list. Each time the queue
+// holds B entries (or the list ends) the batch is composited, and recorded as
+// the tile's next list chunk of B entry indices (chunk storage handed out by
+// an atomic counter; each chunk links to the tile's previous one). The walk
+// stops when every pixel of the tile has terminated, so only the part of the
+// list the tile composites is formed.
+template <int TW, int TH, int B>
 __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
-    Views views, RasterDev rp, const uint32_t* __restrict__ ranges,
-    const uint32_t* __restrict__ pentry, const float4* __restrict__ rec,
+    const Views* __restrict__ views, RasterDev rp, const uint32_t* __restrict__ sup_ranges,
+    const uint32_t* __restrict__ sentry, const float4* __restrict__ rec,
     float* __restrict__ out_rgb, float* __restrict__ t_final, uint32_t* __restrict__ n_last,
-    uint32_t* __restrict__ counters, uint32_t* __restrict__ tile_cost) {
+    uint32_t* __restrict__ counters, uint32_t* __restrict__ tile_cost,
+    uint32_t* __restrict__ chunks, uint2* __restrict__ links, uint32_t* __restrict__ tile_head,
+    uint32_t chunk_capacity, uint32_t pair_capacity, uint32_t entries) {
     constexpr int PIX = TW * TH / kLanes;
     constexpr int RS = kLanes / TW;   // row step between a lane's pixels
-    __shared__ float4 s_geo[kLanes];
-    __shared__ float4 s_aux[kLanes];
-    __shared__ float4 s_col[kLanes];   // r, g, b, -
+    constexpr int Q = B + kLanes;     // queue: one batch plus one walk step
+    static_assert(B % 32 == 0 && B >= 32 && B <= 256, "batch size");
+    __shared__ float4 s_geo[Q];
+    __shared__ float4 s_aux[Q];
+    __shared__ float4 s_col[Q];   // r, g, b, -
+    __shared__ uint32_t s_ent[Q];
 
     const int tile = blockIdx.x;
-    const ViewDev& V = views.v[view_of_tile(views, tile)];
+    const ViewDev& V = views->v[view_of_tile(views, tile)];
     const int local = tile - V.tile_offset;
     const int tx = local % V.tiles_x, ty = local / V.tiles_x;
     const int tid = threadIdx.x;
     const int col = tid % TW, row0 = tid / TW;
-    const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+    const int sup = V.sup_offset + (ty / rp.super_tile) * V.sup_x + tx / rp.super_tile;
+    // (bounded by the pair storage, whatever the workspace holds)
+    const uint32_t w_end = min(sup_ranges[2 * sup + 1], pair_capacity);
+    uint32_t w = sup_ranges[2 * sup];
     const float lmin = rp.log2_alpha_min, amax = rp.alpha_max, tmin = rp.t_min;
+    const int px0 = tx * TW, py0 = ty * TH;
 
-    const float px = (float)(tx * TW + col) + 0.5f;
+    const float px = (float)(px0 + col) + 0.5f;
     float py[PIX], T[PIX], C0[PIX], C1[PIX], C2[PIX];
     uint32_t last[PIX];
     uint32_t live = 0;   // bit RS*k: pixel k is in the view and has not stopped
 #pragma unroll
     for (int k = 0; k < PIX; ++k) {
-        const int y = ty * TH + row0 + RS * k;
+        const int y = py0 + row0 + RS * k;
         py[k] = (float)y + 0.5f;
         T[k] = 1.f;
         C0[k] = C1[k] = C2[k] = 0.f;
         last[k] = 0;
-        if (tx * TW + col < V.width && y < V.height) live |= 1u << (RS * k);
+        if (px0 + col < V.width && y < V.height) live |= 1u << (RS * k);
     }
     uint32_t n_blend = 0, n_eval = 0;
-    for (uint32_t b0 = start; b0 < end; b0 += kLanes) {
+    // wave-uniform: queued entries, list positions composited, entries
+    // walked, the previous chunk, the chunk of the latest blend, chunk ordinal
+    uint32_t qn = 0, listed = 0, walked = 0, prev = kNoChunk, head = kNoChunk, ordinal = 0;
+    bool overflow = false;
+    for (;;) {
         if (ballot(live != 0u) == 0) break;
-        __syncthreads();
-        const uint32_t idx = b0 + tid;
-        if (idx < end) {
-            const int64_t e = pentry[idx];
-            const float4 r0 = rec[3 * e], r1 = rec[3 * e + 1];
-            stage_entry(r0, r1, tx * TW, ty * TH, TW, TH, s_geo[tid], s_aux[tid]);
-            s_col[tid] = rec[3 * e + 2];
+        // fill the queue from the super-tile list
+        while (qn < (uint32_t)B && w < w_end) {
+            const uint32_t idx = w + (uint32_t)tid;
+            bool pass = false;
+            uint32_t e = 0;
+            float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
+            if (idx < w_end) e = sentry[idx];
+            if (idx < w_end && e < entries) {
+                r0 = rec[3 * (int64_t)e];
+                r1 = rec[3 * (int64_t)e + 1];
+                // the tile lies in the entry's tile rectangle and, with a skip
+                // threshold, the entry can reach alpha_min on the tile's pixels
+                int x0, x1, y0, y1;
+                tile_rect(r0.x, r0.y, (int)r1.z, (int)r1.w, TW, TH, V.tiles_x, V.tiles_y, &x0,
+                          &x1, &y0, &y1);
+                pass = x0 <= tx && tx < x1 && y0 <= ty && ty < y1;
+                const float lim = reach_limit(r1.y, rp);
+                if (pass && lim != INFINITY)
+                    pass = rect_reachable(r0.x, r0.y, r0.z, r0.w, r1.x, lim, r1.z, r1.w, px0, py0,
+                                          min(TW, V.width - px0), min(TH, V.height - py0));
+            }
+            const uint64_t m = ballot(pass);
+            if (pass) {
+                const uint32_t slot = qn + (uint32_t)popc64(m & lanemask_lt());
+                stage_entry(r0, r1, px0, py0, TW, TH, s_geo[slot], s_aux[slot]);
+                s_col[slot] = rec[3 * (int64_t)e + 2];
+                s_ent[slot] = e;
+            }
+            qn += (uint32_t)popc64(m);
+            walked += min((uint32_t)kLanes, w_end - w);
+            w += kLanes;
         }
+        if (qn == 0) break;
         __syncthreads();
-        const int cnt = (int)min((uint32_t)kLanes, end - b0);
+        const int cnt = (int)min(qn, (uint32_t)B);
+        // the batch becomes the tile's next list chunk
+        uint32_t chunk = kNoChunk;
+        if (!overflow) {
+            uint32_t c = 0;
+            if (tid == 0) c = atomicAdd(&counters[kChunks], 1u);
+            c = (uint32_t)__shfl((int)c, 0, kLanes);
+            if (c < chunk_capacity) chunk = c;
+            else overflow = true;
+        }
+        if (chunk != kNoChunk) {
+            for (int j = tid; j < cnt; j += kLanes) chunks[(int64_t)chunk * B + j] = s_ent[j];
+            if (tid == 0) links[chunk] = make_uint2(prev, (ordinal << 9) | (uint32_t)cnt);
+            prev = chunk;
+        }
+        bool blended = false;
         // the next entry's LDS reads are issued before the current entry is
         // processed, so a wave running alone does not wait on them
         float4 Gn = s_geo[0], Xn = s_aux[0], Cn = s_col[0];
@@ -223,7 +286,7 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
             Cn = s_col[jn];
             const LaneTerms L = lane_terms(G, X, px, col, row0);
             const uint32_t m = L.m & live;
-            const uint32_t pos = b0 + (uint32_t)j + 1u - start;
+            const uint32_t pos = listed + (uint32_t)j + 1u;
             n_eval += (uint32_t)__builtin_popcount(live);
 #pragma unroll
             for (int k = 0; k < PIX; ++k) {
@@ -242,17 +305,41 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
                     T[k] = stop ? T[k] : tn;
                     last[k] = stop ? last[k] : pos;
                     n_blend += stop ? 0u : 1u;
+                    blended |= !stop;
                     live &= stop ? ~(1u << (RS * k)) : ~0u;
                 }
             }
         }
+        if (ballot(blended) != 0) head = chunk;
+        listed += (uint32_t)cnt;
+        ordinal += 1;
+        // the entries past the batch move to the front of the queue (fewer
+        // than one walk step)
+        const int rem = (int)qn - cnt;
+        float4 g = make_float4(0.f, 0.f, 0.f, 0.f), a = g, cc = g;
+        uint32_t en = 0;
+        if (tid < rem) {
+            g = s_geo[cnt + tid];
+            a = s_aux[cnt + tid];
+            cc = s_col[cnt + tid];
+            en = s_ent[cnt + tid];
+        }
+        __syncthreads();
+        if (tid < rem) {
+            s_geo[tid] = g;
+            s_aux[tid] = a;
+            s_col[tid] = cc;
+            s_ent[tid] = en;
+        }
+        __syncthreads();
+        qn = (uint32_t)rem;
     }
     const int64_t plane = (int64_t)V.width * V.height;
     float* img = out_rgb + 3 * V.px_offset;
-    const int x = tx * TW + col;
+    const int x = px0 + col;
 #pragma unroll
     for (int k = 0; k < PIX; ++k) {
-        const int y = ty * TH + row0 + RS * k;
+        const int y = py0 + row0 + RS * k;
         if (x >= V.width || y >= V.height) continue;
         const int64_t pix = (int64_t)y * V.width + x;
         img[pix] = fmaf(T[k], rp.bg[0], C0[k]);
@@ -267,10 +354,15 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
 #pragma unroll
     for (int k = 0; k < PIX; ++k) my_last = max(my_last, last[k]);
     const uint32_t tile_last = wave_max_u32(my_last);
-    // work counters: one 64-bit atomic each per tile
+    // work counters: one atomic each per tile
     const uint32_t nb = wave_add_u32(n_blend), ne = wave_add_u32(n_eval);
     if (tid == 0) {
         tile_cost[tile] = tile_last;
+        // a tile whose list did not fit the chunk storage has no usable list
+        tile_head[tile] = overflow ? kNoChunk : head;
+        if (overflow) atomicOr(&counters[kStatus], SGS_STATUS_PAIR_OVERFLOW);
+        atomicAdd(&counters[kListed], listed);
+        atomicAdd(&counters[kWalked], walked);
         atomicAdd(reinterpret_cast<unsigned long long*>(counters + kBlended),
                   (unsigned long long)nb);
         atomicAdd(reinterpret_cast<unsigned long long*>(counters + kEvaluated),
@@ -278,9 +370,9 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
     }
 }
 
-// At most 72 VGPRs, so that 7 waves fit on each SIMD: the 6700 tiles of a
-// 1600x1060 view (16x16 tiles) then all run at once on the 1024 SIMDs of the
-// chip instead of leaving a second round for the last tiles.
+// At most 72 VGPRs (batches of 64), so that 7 waves fit on each SIMD: the
+// 6700 tiles of a 1600x1060 view (16x16 tiles) then all run at once on the
+// 1024 SIMDs of the chip instead of leaving a second round for the last tiles.
 //
 // Gradient of one (tile, Gaussian) pair from per-lane moments of dL/dP over
 // the lane's pixels (dP = dL/dP, dy per pixel, dx per lane): with
@@ -289,29 +381,32 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
 //   dL/db = -M4,  dL/dc = -M5/2,  dL/do = M6 / o  (unclamped alpha' = o e^P),
 // M1 = sum dP dx, M2 = sum dP dy, M3 = sum dP dx^2, M4 = sum dP dx dy,
 // M5 = sum dP dy^2, M6 = sum dP.
-template <int TW, int TH>
-__global__ void __launch_bounds__(kLanes, 7) raster_backward_kernel(
-    Views views, RasterDev rp, const uint32_t* __restrict__ ranges,
-    const uint32_t* __restrict__ pentry, const float4* __restrict__ rec,
-    const float* __restrict__ t_final, const uint32_t* __restrict__ n_last,
-    const float* __restrict__ dl_drgb, const int32_t* __restrict__ gate,
-    float* __restrict__ accum, const uint32_t* __restrict__ order, int total_tiles) {
+// Waves per SIMD the LDS of a batch allows (64 B per staged entry).
+constexpr int backward_waves(int batch) { return batch <= 64 ? 7 : (batch == 128 ? 5 : 3); }
+
+template <int TW, int TH, int B>
+__global__ void __launch_bounds__(kLanes, backward_waves(B)) raster_backward_kernel(
+    const Views* __restrict__ views, RasterDev rp, const uint32_t* __restrict__ chunks,
+    const uint2* __restrict__ links, const uint32_t* __restrict__ tile_head,
+    const float4* __restrict__ rec, const float* __restrict__ t_final,
+    const uint32_t* __restrict__ n_last, const float* __restrict__ dl_drgb,
+    const int32_t* __restrict__ gate, float* __restrict__ accum, const uint32_t* __restrict__ order,
+    int total_tiles, uint32_t chunk_capacity, uint32_t entries) {
     constexpr int PIX = TW * TH / kLanes;
     constexpr int RS = kLanes / TW;
-    __shared__ float4 s_geo[kLanes];
-    __shared__ float4 s_aux[kLanes];
-    __shared__ float4 s_col[kLanes];   // r, g, b, entry (bits)
-    __shared__ float4 s_con[kLanes];   // a, b, c, 1 / o
+    __shared__ float4 s_geo[B];
+    __shared__ float4 s_aux[B];
+    __shared__ float4 s_col[B];   // r, g, b, entry (bits)
+    __shared__ float4 s_con[B];   // a, b, c, 1 / o
     if (gate_closed(gate)) return;
 
     const int tile = (int)order[blockIdx.x];
     if (tile >= total_tiles) return;   // order is a permutation of the tiles
-    const ViewDev& V = views.v[view_of_tile(views, tile)];
+    const ViewDev& V = views->v[view_of_tile(views, tile)];
     const int local = tile - V.tile_offset;
     const int tx = local % V.tiles_x, ty = local / V.tiles_x;
     const int tid = threadIdx.x;
     const int col = tid % TW, row0 = tid / TW;
-    const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
     const float lmin = rp.log2_alpha_min, amax = rp.alpha_max;
 
     const int64_t plane = (int64_t)V.width * V.height;
@@ -340,26 +435,29 @@ __global__ void __launch_bounds__(kLanes, 7) raster_backward_kernel(
         GS[k] = fmaf(G0[k], rp.bg[0], fmaf(G1[k], rp.bg[1], G2[k] * rp.bg[2])) * T[k];
         my_max = max(my_max, last[k]);
     }
-    const uint32_t stop = start + min(wave_max_u32(my_max), end - start);
+    const uint32_t stop = wave_max_u32(my_max);
 
-    for (uint32_t b_end = stop; b_end > start;) {
-        const uint32_t b0 = (b_end - start > (uint32_t)kLanes) ? b_end - kLanes : start;
-        const int cnt = (int)(b_end - b0);
+    // the tile's list chunks from the one holding its last blended position
+    // towards the front; chunk k holds list positions [k B, k B + count)
+    for (uint32_t ch = tile_head[tile]; ch < chunk_capacity;) {
+        const uint2 lk = links[ch];
+        const uint32_t b0 = (lk.y >> 9) * (uint32_t)B;
+        const uint32_t b_end = min(b0 + (lk.y & 511u), stop);
+        const int cnt = b_end > b0 ? (int)(b_end - b0) : 0;
         __syncthreads();
-        if (tid < cnt) {
-            const uint32_t idx = b_end - 1u - tid;
-            const uint32_t e = pentry[idx];
+        for (int k = tid; k < cnt; k += kLanes) {
+            const uint32_t e = min(chunks[(int64_t)ch * B + (cnt - 1 - k)], entries - 1u);
             const float4 r0 = rec[3 * (int64_t)e], r1 = rec[3 * (int64_t)e + 1],
                          r2 = rec[3 * (int64_t)e + 2];
-            stage_entry(r0, r1, tx * TW, ty * TH, TW, TH, s_geo[tid], s_aux[tid]);
-            s_col[tid] = make_float4(r2.x, r2.y, r2.z, __uint_as_float(e));
+            stage_entry(r0, r1, tx * TW, ty * TH, TW, TH, s_geo[k], s_aux[k]);
+            s_col[k] = make_float4(r2.x, r2.y, r2.z, __uint_as_float(e));
             // 1/o capped at FLT_MAX: an opacity that underflowed to 0 can only
             // take part with alpha' = 0 (alpha_min = 0), where M6 = 0
-            s_con[tid] = make_float4(r0.z, r0.w, r1.x, fminf(1.f / r1.y, 3.402823466e38f));
+            s_con[k] = make_float4(r0.z, r0.w, r1.x, fminf(1.f / r1.y, 3.402823466e38f));
         }
         __syncthreads();
         for (int j = 0; j < cnt; ++j) {
-            const uint32_t rel = b_end - 1u - (uint32_t)j - start;   // list position
+            const uint32_t rel = b_end - 1u - (uint32_t)j;   // list position
             const float4 G = s_geo[j];
             const float4 X = s_aux[j];
             // read once per Gaussian with the coefficients (the compiler would
@@ -425,7 +523,8 @@ __global__ void __launch_bounds__(kLanes, 7) raster_backward_kernel(
                 unsafeAtomicAdd(accum + (int64_t)kAccumFloats * __float_as_uint(s_col[j].w) + tid,
                                 tid == 8 ? t8 : t);
         }
-        b_end = b0;
+        // a chunk's predecessor was handed out before it: the walk ends
+        ch = lk.x < ch ? lk.x : kNoChunk;
     }
 }
 
@@ -437,40 +536,64 @@ __global__ void zero_f32_gated_kernel(float4* p, int64_t n4, const int32_t* gate
 
 }  // namespace
 
-hipError_t launch_rasterize(const Views& views, const RasterDev& rp, const Layout& L, char* ws,
-                            float* out_rgb, hipStream_t s) {
+// Kernel instantiations: tile shapes 16x16, 8x8, 32x8 and batches 32, 64,
+// 128, 256 (the shapes and batches the raster parameters accept).
+#define SGS_RASTER_DISPATCH(KERNEL, ...)                                              \
+    do {                                                                             \
+        const int tw_ = rp.tile_w, b_ = rp.batch;                                    \
+        if (tw_ == 16) {                                                             \
+            if (b_ == 32) SGS_LAUNCH((KERNEL<16, 16, 32>), __VA_ARGS__);               \
+            else if (b_ == 128) SGS_LAUNCH((KERNEL<16, 16, 128>), __VA_ARGS__);        \
+            else if (b_ == 256) SGS_LAUNCH((KERNEL<16, 16, 256>), __VA_ARGS__);        \
+            else SGS_LAUNCH((KERNEL<16, 16, 64>), __VA_ARGS__);                        \
+        } else if (tw_ == 8) {                                                       \
+            if (b_ == 32) SGS_LAUNCH((KERNEL<8, 8, 32>), __VA_ARGS__);                 \
+            else if (b_ == 128) SGS_LAUNCH((KERNEL<8, 8, 128>), __VA_ARGS__);          \
+            else if (b_ == 256) SGS_LAUNCH((KERNEL<8, 8, 256>), __VA_ARGS__);          \
+            else SGS_LAUNCH((KERNEL<8, 8, 64>), __VA_ARGS__);                          \
+        } else {                                                                     \
+            if (b_ == 32) SGS_LAUNCH((KERNEL<32, 8, 32>), __VA_ARGS__);                \
+            else if (b_ == 128) SGS_LAUNCH((KERNEL<32, 8, 128>), __VA_ARGS__);         \
+            else if (b_ == 256) SGS_LAUNCH((KERNEL<32, 8, 256>), __VA_ARGS__);         \
+            else SGS_LAUNCH((KERNEL<32, 8, 64>), __VA_ARGS__);                         \
+        }                                                                            \
+    } while (0)
+#define SGS_LAUNCH(K, ...) hipLaunchKernelGGL((K), grid, block, 0, s, __VA_ARGS__)
+
+hipError_t launch_rasterize(const RasterDev& rp, const Layout& L, char* ws, float* out_rgb,
+                            hipStream_t s) {
     if (L.total_tiles == 0) return hipSuccess;
-    const uint32_t* ranges = reinterpret_cast<const uint32_t*>(ws + L.ranges);
-    const uint32_t* pentry = reinterpret_cast<const uint32_t*>(ws + L.pair_entry[L.tile_result]);
+    const Views* views = reinterpret_cast<const Views*>(ws + L.views);
+    const uint32_t* ranges = reinterpret_cast<const uint32_t*>(ws + L.sup_ranges);
+    const uint32_t* sentry = reinterpret_cast<const uint32_t*>(ws + L.pair_entry[L.key_result]);
     const float4* rec = reinterpret_cast<const float4*>(ws + L.records);
     float* tf = reinterpret_cast<float*>(ws + L.t_final);
     uint32_t* nl = reinterpret_cast<uint32_t*>(ws + L.n_last);
     uint32_t* cnt = reinterpret_cast<uint32_t*>(ws + L.counters);
     uint32_t* cost = reinterpret_cast<uint32_t*>(ws + L.tile_cost);
+    uint32_t* chunks = reinterpret_cast<uint32_t*>(ws + L.chunks);
+    uint2* links = reinterpret_cast<uint2*>(ws + L.links);
+    uint32_t* head = reinterpret_cast<uint32_t*>(ws + L.tile_head);
+    const uint32_t cap = (uint32_t)L.chunk_capacity;
     const dim3 grid((unsigned)L.total_tiles), block(kLanes);
-    if (rp.tile_w == 16 && rp.tile_h == 16)
-        hipLaunchKernelGGL((raster_forward_kernel<16, 16>), grid, block, 0, s, views, rp, ranges,
-                           pentry, rec, out_rgb, tf, nl, cnt, cost);
-    else if (rp.tile_w == 8 && rp.tile_h == 8)
-        hipLaunchKernelGGL((raster_forward_kernel<8, 8>), grid, block, 0, s, views, rp, ranges,
-                           pentry, rec, out_rgb, tf, nl, cnt, cost);
-    else
-        hipLaunchKernelGGL((raster_forward_kernel<32, 8>), grid, block, 0, s, views, rp, ranges,
-                           pentry, rec, out_rgb, tf, nl, cnt, cost);
+    SGS_RASTER_DISPATCH(raster_forward_kernel, views, rp, ranges, sentry, rec, out_rgb, tf, nl, cnt,
+                        cost, chunks, links, head, cap, (uint32_t)L.capacity,
+                        (uint32_t)L.entries);
     return hipGetLastError();
 }
 
-hipError_t launch_rasterize_backward(const Views& views, const RasterDev& rp, const Layout& L,
-                                     char* ws, const float* dl_drgb, const int32_t* gate,
-                                     hipStream_t s) {
+hipError_t launch_rasterize_backward(const RasterDev& rp, const Layout& L, char* ws,
+                                     const float* dl_drgb, const int32_t* gate, hipStream_t s) {
     float* acc = reinterpret_cast<float*>(ws + L.accum);
     const int64_t n4 = L.entries * kAccumFloats / 4;
     if (n4 > 0)
         hipLaunchKernelGGL(zero_f32_gated_kernel, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0,
                            s, reinterpret_cast<float4*>(acc), n4, gate);
-    if (L.total_tiles == 0) return hipGetLastError();
-    const uint32_t* ranges = reinterpret_cast<const uint32_t*>(ws + L.ranges);
-    const uint32_t* pentry = reinterpret_cast<const uint32_t*>(ws + L.pair_entry[L.tile_result]);
+    if (L.total_tiles == 0 || L.entries == 0) return hipGetLastError();
+    const Views* views = reinterpret_cast<const Views*>(ws + L.views);
+    const uint32_t* chunks = reinterpret_cast<const uint32_t*>(ws + L.chunks);
+    const uint2* links = reinterpret_cast<const uint2*>(ws + L.links);
+    const uint32_t* head = reinterpret_cast<const uint32_t*>(ws + L.tile_head);
     const float4* rec = reinterpret_cast<const float4*>(ws + L.records);
     const float* tf = reinterpret_cast<const float*>(ws + L.t_final);
     const uint32_t* nl = reinterpret_cast<const uint32_t*>(ws + L.n_last);
@@ -483,16 +606,13 @@ hipError_t launch_rasterize_backward(const Views& views, const RasterDev& rp, co
         return err;
     const int tiles = (int)L.total_tiles;
     const dim3 grid((unsigned)L.total_tiles), block(kLanes);
-    if (rp.tile_w == 16 && rp.tile_h == 16)
-        hipLaunchKernelGGL((raster_backward_kernel<16, 16>), grid, block, 0, s, views, rp, ranges,
-                           pentry, rec, tf, nl, dl_drgb, gate, acc, order, tiles);
-    else if (rp.tile_w == 8 && rp.tile_h == 8)
-        hipLaunchKernelGGL((raster_backward_kernel<8, 8>), grid, block, 0, s, views, rp, ranges,
-                           pentry, rec, tf, nl, dl_drgb, gate, acc, order, tiles);
-    else
-        hipLaunchKernelGGL((raster_backward_kernel<32, 8>), grid, block, 0, s, views, rp, ranges,
-                           pentry, rec, tf, nl, dl_drgb, gate, acc, order, tiles);
+    SGS_RASTER_DISPATCH(raster_backward_kernel, views, rp, chunks, links, head, rec, tf, nl,
+                        dl_drgb, gate, acc, order, tiles, (uint32_t)L.chunk_capacity,
+                        (uint32_t)L.entries);
     return hipGetLastError();
 }
+
+#undef SGS_LAUNCH
+#undef SGS_RASTER_DISPATCH
 
 }  // namespace sgs

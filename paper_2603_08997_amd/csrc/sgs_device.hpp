@@ -162,6 +162,69 @@ __device__ __forceinline__ void tile_rect(float u, float v, int rx, int ry, int 
     *y1 = min(max(floordiv(fv + ry, th) + 1, 0), ty_n);
 }
 
+// Super-tiles [sx0, sx1) x [sy0, sy1) (edge S tiles) holding the non-empty
+// tile rectangle [x0, x1) x [y0, y1), and their number.
+__device__ __forceinline__ void super_rect(int x0, int x1, int y0, int y1, int S, int* sx0,
+                                           int* sx1, int* sy0, int* sy1) {
+    *sx0 = x0 / S;
+    *sx1 = (x1 - 1) / S + 1;
+    *sy0 = y0 / S;
+    *sy1 = (y1 - 1) / S + 1;
+}
+__device__ __forceinline__ uint32_t super_count(int x0, int x1, int y0, int y1, int S) {
+    int a, b, c, d;
+    super_rect(x0, x1, y0, y1, S, &a, &b, &c, &d);
+    return (uint32_t)((b - a) * (d - c));
+}
+
+// Reach test of one Gaussian on a rectangle of pixels: can alpha' = o exp(-q/2),
+// q = a dx^2 + 2 b dx dy + c dy^2, reach alpha_min at a pixel centre of the w x h
+// pixels starting at (px0, py0) that lies inside the overlap box? The
+// pixel-centre rectangle is clipped to the box (widened by 1e-3 px). If the
+// Gaussian's centre lies outside it, the minimum of the convex q over the
+// rectangle lies on an edge that faces the centre (moving from any other
+// boundary point towards the centre enters the rectangle and lowers q), at the
+// clamped stationary point of that edge: at most one vertical and one
+// horizontal edge to evaluate. The test passes when that minimum, less a bound
+// on its rounding error (8 ulp of the sum of the terms' magnitudes), is within
+// `lim`. With lim = 2 ln(o / alpha_min) (inflated, see reach_limit) a Gaussian
+// that fails cannot pass the compositing kernels' skip test at any pixel of
+// the rectangle.
+__device__ __forceinline__ float reach_limit(float o, const RasterDev& rp) {
+    return rp.alpha_min > 0.f ? 2.f * logf(o / rp.alpha_min) * 1.01f + 0.01f : INFINITY;
+}
+
+__device__ __forceinline__ bool rect_reachable(float u, float v, float a, float b, float c,
+                                               float lim, float rx, float ry, int px0, int py0,
+                                               int w, int h) {
+    // relative to the centre; the box widened by 1e-3 px
+    const float m = 1e-3f;
+    const float bx = (float)px0 - u, by = (float)py0 - v;
+    const float x0 = fmaxf(bx + 0.5f, -rx - m), x1 = fminf(bx + ((float)w - 0.5f), rx + m);
+    const float y0 = fmaxf(by + 0.5f, -ry - m), y1 = fminf(by + ((float)h - 0.5f), ry + m);
+    if (x0 > x1 || y0 > y1) return false;   // no pixel centre of the rectangle in the box
+    const bool in_x = x0 <= 0.f && 0.f <= x1, in_y = y0 <= 0.f && 0.f <= y1;
+    if (in_x && in_y) return true;
+    if (lim == INFINITY) return true;
+    constexpr float kErr = 8.f * 5.96046448e-8f;
+    float best = INFINITY;
+    auto at = [&](float dx, float dy) {
+        const float bxy = b * dx * dy;
+        const float q = a * dx * dx + 2.f * bxy + c * dy * dy;
+        const float mag = a * dx * dx + 2.f * fabsf(bxy) + c * dy * dy;
+        best = fminf(best, q - kErr * mag);
+    };
+    if (!in_x) {   // the vertical edge facing the centre
+        const float ex = x0 > 0.f ? x0 : x1;
+        at(ex, fminf(fmaxf(-b * ex * __builtin_amdgcn_rcpf(c), y0), y1));
+    }
+    if (!in_y) {   // the horizontal edge facing the centre
+        const float ey = y0 > 0.f ? y0 : y1;
+        at(fminf(fmaxf(-b * ey * __builtin_amdgcn_rcpf(a), x0), x1), ey);
+    }
+    return best <= lim;
+}
+
 // Adam element update, shared by the plain step and the fused backward step
 // so both give identical results. The bias corrections enter as reciprocals
 // formed once per step; the square root and the final reciprocal use the

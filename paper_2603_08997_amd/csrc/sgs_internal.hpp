@@ -14,8 +14,13 @@ constexpr int kWave = 64;
 constexpr uint32_t kMaxExtent = 1u << 24;   // |u|, |v|, radius beyond this: degenerate, culled
 constexpr int kRecordFloats = 12;           // u v a b | c o rx ry | r g b clamp-mask
 constexpr int kAccumFloats = 12;            // du dv da db | dc do dr dg | db - - -
+constexpr int kDefaultSuperTile = 8;        // super-tile edge in tiles
+constexpr int kDefaultBatch = 64;           // list entries per compositing batch
 
-// Per-view constants, passed by value to every kernel of a multi-view batch.
+// Per-view constants. A call's views live in device memory (the workspace's
+// view table): a one-thread kernel stores them there at the start of every
+// call, from its arguments or from a camera table picked by a device-side
+// view index, and every other kernel reads them through a pointer.
 struct ViewDev {
     float R[9];
     float t[3];
@@ -24,7 +29,8 @@ struct ViewDev {
     float lim_x, lim_y;  // clamp of tx/tz, ty/tz in the EWA Jacobian (inf: off)
     int32_t width, height, tiles_x, tiles_y;
     int32_t tile_offset; // first global tile index of the view
-    int32_t pad;
+    int32_t sup_x, sup_y;   // super-tiles per row and column
+    int32_t sup_offset;     // first global super-tile index of the view
     int64_t px_offset;   // first global pixel index of the view
 };
 
@@ -33,10 +39,14 @@ struct Views {
     int32_t n;
     int32_t total_tiles;
     int64_t total_pixels;
+    int32_t total_supers;
+    int32_t pad;
 };
 
 struct RasterDev {
     int32_t tile_w, tile_h;
+    int32_t super_tile;    // super-tile edge in tiles
+    int32_t batch;         // list entries per compositing batch (and per list chunk)
     float bg[3];
     float near_z, dilation, alpha_min, alpha_max, t_min;
     float log2_alpha_min;  // log2(alpha_min), rounded from binary64 (-inf for 0)
@@ -57,20 +67,24 @@ AdamDev make_adam(const sgs_adam_params* p);
 enum Counter : int {
     kStatus = 0,        // SGS_STATUS_* bits
     kVisible = 1,       // visible entries of the last forward
-    kPairs = 2,         // (tile, entry) pairs needed by the last forward
+    kPairs = 2,         // (super-tile, entry) pairs needed by the last forward (saturating)
     kPairsWritten = 3,  // min(pairs, capacity)
     kBlended = 4,       // uint64 at words 4-5: blended (pixel, Gaussian) pairs of the last rasterize
     kEvaluated = 6,     // uint64 at words 6-7: (pixel, list entry) pairs the forward examined
-    kPairsKept = 8,     // pairs left after the exact tile test (length of the sorted lists)
+    kPairsKept = 8,     // super-tile pairs left after the reach test (length of the sorted lists)
+    kChunks = 9,        // list chunks the forward asked for (saturating)
+    kListed = 10,       // tile-list entries the forward listed (its compositing batches)
+    kWalked = 11,       // super-tile list entries the forward examined for its tiles
     kNumCounters = 16
 };
 
-// Tile key of an emitted pair whose Gaussian cannot reach alpha_min at any
-// pixel centre of the tile; the first pass of the tile sort drops such pairs.
-// Batches of fewer than 65535 tiles keep tile keys in uint16 (kCulledTile16).
+// Key of an emitted pair whose Gaussian cannot reach alpha_min at any pixel
+// centre of the super-tile; the first pass of the super-tile sort drops such
+// pairs. Batches of fewer than 65535 super-tiles keep keys in uint16.
 constexpr uint32_t kCulledTile = 0xffffffffu;
 constexpr uint16_t kCulledTile16 = 0xffffu;
 constexpr int64_t kMaxTiles16 = 0xffff;
+constexpr uint32_t kNoChunk = 0xffffffffu;
 
 // Emission units: each visible Gaussian (in depth order) owns kEmitHead
 // header units followed by one unit per pair; a workgroup of the emission
@@ -83,42 +97,52 @@ constexpr int64_t emit_windows(int64_t entries, int64_t capacity) {
     return (capacity + kEmitHead * entries + kEmitWindow - 1) / kEmitWindow;
 }
 
+// Tile lists are recorded by the compositing forward in chunks of `batch`
+// entry indices: the list storage holds pair_capacity entries plus one
+// partly filled chunk per tile.
+constexpr int64_t list_chunks(int64_t capacity, int64_t tiles, int batch) {
+    return (capacity + batch - 1) / batch + tiles;
+}
+
 struct Layout {
-    int64_t entries, total_tiles, total_pixels, capacity;
+    int64_t entries, total_tiles, total_pixels, total_supers, capacity, chunk_capacity;
+    int n_views;
     int64_t scan_blocks, sort_blocks;
-    int tile_bits, tile_passes, tile_result;  // result buffer index (0/1) of the tile sort
-    int tile_key_bytes;                        // 2 (total_tiles < kMaxTiles16) or 4
-    size_t records, tiles, depth, dkey[2], dval[2], offsets, window_first, scan_sums, pair_tile[2],
-        pair_entry[2],
-        sort_hist, sort_totals, ranges, tile_cost, tile_order, t_final, n_last, accum, counters,
-        total;
+    int key_bits, key_passes, key_result;  // result buffer index (0/1) of the super-tile sort
+    int key_bytes;                         // 2 (total_supers < kMaxTiles16) or 4
+    int batch;
+    size_t views, records, tiles, depth, dkey[2], dval[2], offsets, window_first, scan_sums,
+        pair_key[2], pair_entry[2], sort_hist, sort_totals, sup_ranges, chunks, links, tile_head,
+        tile_cost, tile_order, t_final, n_last, accum, counters, total;
 };
 
 bool make_views(const sgs_camera* cams, int n_views, const sgs_raster_params* rp, Views* out,
                 const char** err);
-void make_layout(const Views& views, int64_t n, int64_t capacity, Layout* L);
+void make_layout(const Views& views, const RasterDev& rp, int64_t n, int64_t capacity, Layout* L);
 RasterDev make_raster(const sgs_raster_params* rp);
 
-// ---- launch wrappers (all asynchronous on `s`) ----
+// The call's views into the workspace's view table: from the host (by value)
+// or, when `table` is non-null, view `*d_view` of a device camera table
+// (clamped into [0, n_table)) as the batch's single view.
+hipError_t launch_store_views(const Views& views, const ViewDev* table, int n_table,
+                              const int32_t* d_view, Views* dst, hipStream_t s);
+
+// ---- launch wrappers (all asynchronous on `s`). Kernels read the views from
+// the workspace's view table (ws + L.views); L carries the sizes. ----
 hipError_t launch_project(const float* planes, int64_t n, int64_t stride, int sh_degree,
-                          const Views& views, const RasterDev& rp, float* records,
-                          uint32_t* tiles, uint32_t* dkey, hipStream_t s);
-hipError_t launch_load_records(int64_t entries, const float* u, const float* v,
-                               const float* depth, const int32_t* extent, const float* conic,
-                               const float* opacity, const float* rgb, int64_t n,
-                               const Views& views, const RasterDev& rp, float* records,
-                               uint32_t* tiles, uint32_t* dkey, hipStream_t s);
-hipError_t launch_bin(const Views& views, const RasterDev& rp, int64_t n, const Layout& L,
-                      char* ws, hipStream_t s);
-hipError_t launch_rasterize(const Views& views, const RasterDev& rp, const Layout& L, char* ws,
-                            float* out_rgb, hipStream_t s);
-hipError_t launch_rasterize_backward(const Views& views, const RasterDev& rp, const Layout& L,
-                                     char* ws, const float* dl_drgb, const int32_t* gate,
-                                     hipStream_t s);
+                          const RasterDev& rp, const Layout& L, char* ws, hipStream_t s);
+hipError_t launch_load_records(const float* u, const float* v, const float* depth,
+                               const int32_t* extent, const float* conic, const float* opacity,
+                               const float* rgb, int64_t n, const RasterDev& rp, const Layout& L,
+                               char* ws, hipStream_t s);
+hipError_t launch_bin(const RasterDev& rp, int64_t n, const Layout& L, char* ws, hipStream_t s);
+hipError_t launch_rasterize(const RasterDev& rp, const Layout& L, char* ws, float* out_rgb,
+                            hipStream_t s);
+hipError_t launch_rasterize_backward(const RasterDev& rp, const Layout& L, char* ws,
+                                     const float* dl_drgb, const int32_t* gate, hipStream_t s);
 hipError_t launch_project_backward(const float* planes, int64_t n, int64_t stride,
-                                   int sh_degree, const Views& views, const RasterDev& rp,
-                                   const Layout& L, char* ws, const int32_t* gate, float* grads,
-                                   hipStream_t s);
+                                   int sh_degree, const RasterDev& rp, const Layout& L, char* ws,
+                                   const int32_t* gate, float* grads, hipStream_t s);
 
 // p[0..n) = v on stream s (a kernel, so that callers can be captured).
 hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
@@ -145,24 +169,37 @@ hipError_t radix_sort(K* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int6
 int64_t radix_blocks(int64_t n_max);
 
 // Loss / gate / Adam
-hipError_t launch_loss_forward(const float* rgb, const float* target, int w, int h, float lambda,
+// target: the reference image, or with d_view non-null the image
+// *d_view (clamped into [0, n_targets)) of an array of n_targets images.
+struct TargetRef {
+    const float* base;
+    const int32_t* d_view;
+    int32_t n_targets;
+};
+hipError_t launch_loss_forward(const float* rgb, TargetRef target, int w, int h, float lambda,
                                char* ws, float* d_loss, hipStream_t s);
-hipError_t launch_loss_backward(const float* rgb, const float* target, int w, int h, float lambda,
+hipError_t launch_loss_backward(const float* rgb, TargetRef target, int w, int h, float lambda,
                                 char* ws, const int32_t* gate, float* dl, hipStream_t s);
 size_t loss_workspace_bytes(int w, int h);
 
 hipError_t launch_gate_init(const sgs_gate_params* p, void* state, hipStream_t s);
-hipError_t launch_gate_update(const sgs_gate_params* p, void* state, int view, const float* loss,
-                              int32_t* gate, hipStream_t s);
+hipError_t launch_gate_update(const sgs_gate_params* p, void* state, const int32_t* view,
+                              const float* loss, int32_t* gate, hipStream_t s);
 size_t gate_state_bytes(const sgs_gate_params* p);
+// *d_view = seq[*d_iter % len]; *d_iter += 1.
+hipError_t launch_sequence_next(const int32_t* seq, int64_t len, int64_t* d_iter, int32_t* d_view,
+                                hipStream_t s);
 
 hipError_t launch_adam(const sgs_adam_params* p, float* params, float* grads, float* m, float* v,
                        int64_t n, int64_t stride, int n_planes, int32_t* step,
                        const int32_t* gate, hipStream_t s);
 hipError_t launch_adam_count(int32_t* step, const int32_t* gate, hipStream_t s);
+// sparse: update only the Gaussians visible in a view of the batch (the
+// others keep their parameters and moments); dense otherwise.
 hipError_t launch_project_backward_adam(float* planes, int64_t n, int64_t stride, int sh_degree,
-                                        const Views& views, const RasterDev& rp, const Layout& L,
-                                        char* ws, const sgs_adam_params* prm, float* m, float* v,
-                                        int32_t* step, const int32_t* gate, hipStream_t s);
+                                        const RasterDev& rp, const Layout& L, char* ws,
+                                        const sgs_adam_params* prm, bool sparse, float* m,
+                                        float* v, int32_t* step, const int32_t* gate,
+                                        hipStream_t s);
 
 }  // namespace sgs

@@ -21,6 +21,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libskipgs.
 SGS_OK = 0
 STATUS_PAIR_OVERFLOW = 0x1
 STATUS_NONFINITE_LOSS = 0x2
+STATUS_BAD_VIEW = 0x4
 MAX_VIEWS = 16
 MAX_PLANES = 59
 
@@ -32,7 +33,7 @@ class SkipGSError(RuntimeError):
 
 
 class GaussiansC(C.Structure):
-    _fields_ = [("data", C.c_void_p), ("n", C.c_int64), ("stride", C.c_int64),
+    _fields_ = [("struct_size", C.c_uint32), ("data", C.c_void_p), ("n", C.c_int64), ("stride", C.c_int64),
                 ("sh_degree", C.c_int32)]
 
 
@@ -42,21 +43,23 @@ class CameraC(C.Structure):
 
 
 class RasterParamsC(C.Structure):
-    _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("bg", C.c_float * 3),
+    _fields_ = [("struct_size", C.c_uint32), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
+                ("super_tile", C.c_int32), ("lds_batch", C.c_int32), ("bg", C.c_float * 3),
                 ("near_z", C.c_float), ("dilation", C.c_float), ("alpha_min", C.c_float),
                 ("alpha_max", C.c_float), ("t_min", C.c_float), ("jac_clamp", C.c_float)]
 
 
 class WorkspaceLayoutC(C.Structure):
-    _fields_ = [(k, C.c_size_t) for k in ("records", "tiles", "depth", "pair_tile", "pair_entry",
-                                            "ranges", "t_final", "n_last", "accum",
-                                            "counters")] + \
-               [("entries", C.c_int64), ("total_tiles", C.c_int64), ("total_pixels", C.c_int64),
-                ("pair_tile_bytes", C.c_int32)]
+    _fields_ = [(k, C.c_size_t) for k in ("records", "tiles", "depth", "sup_key", "sup_entry",
+                                            "sup_ranges", "chunks", "links", "tile_head",
+                                            "t_final", "n_last", "accum", "counters")] + \
+               [(k, C.c_int64) for k in ("entries", "total_tiles", "total_pixels",
+                                         "total_supers", "chunk_capacity")] + \
+               [("key_bytes", C.c_int32), ("batch", C.c_int32), ("super_tile", C.c_int32)]
 
 
 class GateParamsC(C.Structure):
-    _fields_ = [("beta", C.c_double), ("eps", C.c_double), ("delta", C.c_double),
+    _fields_ = [("struct_size", C.c_uint32), ("beta", C.c_double), ("eps", C.c_double), ("delta", C.c_double),
                 ("rho_lo", C.c_double), ("warmup", C.c_int32), ("window", C.c_int32),
                 ("calibrate", C.c_int32), ("budget", C.c_int32), ("n_views", C.c_int32)]
 
@@ -69,8 +72,8 @@ class GateSnapshotC(C.Structure):
 
 
 class AdamParamsC(C.Structure):
-    _fields_ = [("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
-                ("lr", C.c_float * MAX_PLANES)]
+    _fields_ = [("struct_size", C.c_uint32), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double), ("lr", C.c_float * MAX_PLANES), ("visible_only", C.c_int32)]
 
 
 EXPORTS = [
@@ -80,7 +83,8 @@ EXPORTS = [
     "sgs_project_backward", "sgs_get_workspace_layout", "sgs_loss_workspace_size",
     "sgs_photometric_loss", "sgs_photometric_loss_backward", "sgs_gate_state_size",
     "sgs_gate_init", "sgs_gate_update", "sgs_gate_read", "sgs_adam_step",
-    "sgs_project_backward_adam", "sgs_render_backward_adam",
+    "sgs_project_backward_adam", "sgs_render_backward_adam", "sgs_camera_table_size",
+    "sgs_camera_table_init", "sgs_view_sequence_next", "sgs_train_iteration",
 ]
 
 
@@ -117,13 +121,19 @@ def _load():
         "sgs_photometric_loss_backward": (i32, [vp, vp, i32, i32, f32, vp, sz, vp, vp, vp]),
         "sgs_gate_state_size": (i32, [P(GateParamsC), P(sz)]),
         "sgs_gate_init": (i32, [P(GateParamsC), vp, vp]),
-        "sgs_gate_update": (i32, [P(GateParamsC), vp, i32, vp, vp, vp]),
+        "sgs_gate_update": (i32, [P(GateParamsC), vp, vp, vp, vp, vp]),
         "sgs_gate_read": (i32, [P(GateParamsC), vp, P(GateSnapshotC), vp, vp, vp]),
         "sgs_adam_step": (i32, [P(AdamParamsC), vp, vp, vp, vp, i64, i64, i32, vp, vp, vp]),
         "sgs_project_backward_adam": (i32, [P(GaussiansC), P(CameraC), i32, P(RasterParamsC), vp,
                                             sz, i64, P(AdamParamsC), vp, vp, vp, vp, vp]),
         "sgs_render_backward_adam": (i32, [P(GaussiansC), P(CameraC), i32, P(RasterParamsC), vp,
                                            sz, i64, vp, P(AdamParamsC), vp, vp, vp, vp, vp]),
+        "sgs_camera_table_size": (i32, [i32, P(sz)]),
+        "sgs_camera_table_init": (i32, [P(CameraC), i32, P(RasterParamsC), vp, sz, vp]),
+        "sgs_view_sequence_next": (i32, [vp, i64, vp, vp, vp]),
+        "sgs_train_iteration": (i32, [P(GaussiansC), P(CameraC), vp, i32, vp, P(RasterParamsC),
+                                      vp, sz, i64, vp, f32, vp, sz, vp, vp, vp, P(GateParamsC),
+                                      vp, vp, P(AdamParamsC), vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -164,6 +174,8 @@ def _stream(stream=None) -> int:
 class RasterParams:
     tile_w: int = 16
     tile_h: int = 16
+    super_tile: int = 8
+    lds_batch: int = 64
     bg: tuple = (0.0, 0.0, 0.0)
     near_z: float = 0.2
     dilation: float = 0.3
@@ -174,7 +186,9 @@ class RasterParams:
 
     def c(self) -> RasterParamsC:
         r = RasterParamsC()
+        r.struct_size = C.sizeof(RasterParamsC)
         r.tile_w, r.tile_h = self.tile_w, self.tile_h
+        r.super_tile, r.lds_batch = self.super_tile, self.lds_batch
         for k in range(3):
             r.bg[k] = self.bg[k]
         r.near_z, r.dilation = self.near_z, self.dilation
@@ -207,6 +221,7 @@ def gaussians_c(planes: torch.Tensor, n: int, sh_degree: int) -> GaussiansC:
     if planes.dtype != torch.float32 or planes.dim() != 2:
         raise ValueError("planes must be a 2-D float32 tensor [F][stride]")
     g = GaussiansC()
+    g.struct_size = C.sizeof(GaussiansC)
     g.data = _ptr(planes)
     g.n = int(n)
     g.stride = int(planes.shape[1])
@@ -314,7 +329,8 @@ def read_counters(workspace, stream=None) -> dict:
     u64 = lambda i: int(w[i]) | (int(w[i + 1]) << 32)
     return {"status": int(w[0]), "visible": int(w[1]), "pairs": int(w[2]),
             "pairs_written": int(w[3]), "blended": u64(4), "evaluated": u64(6),
-            "pairs_kept": int(w[8])}
+            "pairs_kept": int(w[8]), "chunks": int(w[9]), "listed": int(w[10]),
+            "walked": int(w[11])}
 
 
 def clear_status(workspace, stream=None):
@@ -353,7 +369,7 @@ class GateParams:
     budget: bool = True
 
     def c(self) -> GateParamsC:
-        return GateParamsC(self.beta, self.eps, self.delta, self.rho_lo, self.warmup, self.window,
+        return GateParamsC(C.sizeof(GateParamsC), self.beta, self.eps, self.delta, self.rho_lo, self.warmup, self.window,
                            int(self.calibrate), int(self.budget), self.n_views)
 
 
@@ -378,8 +394,9 @@ def gate_init(p: GateParams, d_state, stream=None):
     _check(LIB.sgs_gate_init(C.byref(p.c()), _ptr(d_state), _stream(stream)))
 
 
-def gate_update(p: GateParams, d_state, view: int, d_loss, d_gate, stream=None):
-    _check(LIB.sgs_gate_update(C.byref(p.c()), _ptr(d_state), int(view), _ptr(d_loss),
+def gate_update(p: GateParams, d_state, d_view, d_loss, d_gate, stream=None):
+    """d_view: device int32 tensor holding the view index of the iteration."""
+    _check(LIB.sgs_gate_update(C.byref(p.c()), _ptr(d_state), _ptr(d_view), _ptr(d_loss),
                                _ptr(d_gate), _stream(stream)))
 
 
@@ -402,10 +419,13 @@ class AdamParams:
     beta1: float = 0.9
     beta2: float = 0.999
     eps: float = 1e-15
+    visible_only: bool = False
 
     def c(self) -> AdamParamsC:
         a = AdamParamsC()
+        a.struct_size = C.sizeof(AdamParamsC)
         a.beta1, a.beta2, a.eps = self.beta1, self.beta2, self.eps
+        a.visible_only = int(self.visible_only)
         for k, v in enumerate(self.lr):
             a.lr[k] = float(v)
         return a
@@ -486,3 +506,51 @@ class Prepared:
         _check(LIB.sgs_project_backward(C.byref(self.g), self.cams[view], 1, C.byref(self.rp),
                                         self.ws, self.ws_bytes, self.cap, gate_ptr, grads_ptr,
                                         stream))
+
+
+# ---------------------------------------------------------------------------
+# Device-side view selection and the training iteration
+# ---------------------------------------------------------------------------
+def camera_table(cams, rp: RasterParams, device="cuda") -> torch.Tensor:
+    """Device camera table of cameras of one resolution (synchronises)."""
+    n = C.c_size_t()
+    _check(LIB.sgs_camera_table_size(len(cams), C.byref(n)))
+    t = alloc_bytes(n.value, device)
+    _check(LIB.sgs_camera_table_init(cameras_c(cams), len(cams), C.byref(rp.c()), _ptr(t),
+                                     t.numel(), _stream(None)))
+    return t
+
+
+def view_sequence_next(d_sequence, d_iter, d_view, stream=None):
+    _check(LIB.sgs_view_sequence_next(_ptr(d_sequence), int(d_sequence.numel()), _ptr(d_iter),
+                                      _ptr(d_view), _stream(stream)))
+
+
+class TrainStep:
+    """Pre-marshalled arguments of sgs_train_iteration (one call per
+    iteration; the view index is read on the device)."""
+
+    def __init__(self, planes, n, sh_degree, cams, table, d_view, rp: RasterParams, workspace,
+                 pair_capacity, targets, lam, loss_ws, rgb, dl, d_loss, gate: "GateParams | None",
+                 gate_state, d_gate, adam: "AdamParams", m, v, d_step):
+        self.g = gaussians_c(planes, n, sh_degree)
+        self.cams = cameras_c(cams)
+        self.rp = rp.c()
+        self.gp = gate.c() if gate is not None else None
+        self.adam = adam.c()
+        self.args = (_ptr(table), len(cams), _ptr(d_view), workspace.numel(), int(pair_capacity),
+                     _ptr(targets), float(lam), _ptr(loss_ws), loss_ws.numel(), _ptr(rgb),
+                     _ptr(dl), _ptr(d_loss), _ptr(gate_state) if gate is not None else None,
+                     _ptr(d_gate), _ptr(m), _ptr(v), _ptr(d_step))
+        self.ws = _ptr(workspace)
+        self._keep = (planes, table, d_view, workspace, targets, loss_ws, rgb, dl, d_loss,
+                      gate_state, d_gate, m, v, d_step)
+
+    def __call__(self, stream):
+        (tab, ncam, dview, wsb, cap, tgt, lam, lws, lwsb, rgb, dl, dloss, gst, dgate, m, v,
+         step) = self.args
+        gp = C.byref(self.gp) if self.gp is not None else None
+        _check(LIB.sgs_train_iteration(C.byref(self.g), self.cams, tab, ncam, dview,
+                                       C.byref(self.rp), self.ws, wsb, cap, tgt, lam, lws, lwsb,
+                                       rgb, dl, dloss, gp, gst, dgate, C.byref(self.adam), m, v,
+                                       step, stream))

@@ -46,11 +46,18 @@ class StageTimer:
 
 class Trainer:
     """Holds the device state of one training run: parameters, Adam moments,
-    gradient buffer, gate state, per-view targets and workspaces."""
+    gradient buffer, gate state, per-view targets, workspaces, the device
+    camera table and the device view sequence.
+
+    Two ways to run an iteration, with identical kernels and results:
+    ``step()`` enqueues one sgs_train_iteration (the view is read on the
+    device from the sequence, so the call can be captured in a graph and
+    replayed); ``iteration()`` calls the stages one by one, with optional
+    HIP events between them, for the stage breakdown."""
 
     def __init__(self, init: S.Scene, cams, targets: torch.Tensor, rp: sk.RasterParams,
                  gate: sk.GateParams | None, capacity: int, lrs=None, gated: bool = True,
-                 fused: bool = True, device="cuda"):
+                 fused: bool = True, sequence=None, visible_only: bool = False, device="cuda"):
         self.dev = torch.device(device)
         self.cams = list(cams)
         self.rp = rp
@@ -64,7 +71,7 @@ class Trainer:
         self.m = torch.zeros_like(self.planes)
         self.v = torch.zeros_like(self.planes)
         self.step_count = torch.zeros(1, dtype=torch.int32, device=self.dev)
-        self.adam = sk.AdamParams(lr=lrs or sk.default_lrs(self.deg))
+        self.adam = sk.AdamParams(lr=lrs or sk.default_lrs(self.deg), visible_only=visible_only)
         self.targets = targets            # [views][3 H W]
         W, H = self.cams[0].width, self.cams[0].height
         assert all(c.width == W and c.height == H for c in self.cams)
@@ -75,12 +82,23 @@ class Trainer:
         self.rgb = torch.zeros(3 * W * H, device=self.dev)
         self.dl = torch.zeros_like(self.rgb)
         self.loss = torch.zeros(1, device=self.dev)
+        self.gate = torch.zeros(1, dtype=torch.int32, device=self.dev)
         self.gp = gate
         if gated:
             self.gstate = sk.alloc_bytes(sk.gate_state_size(gate))
             sk.gate_init(gate, self.gstate)
-        self.ones = torch.ones(1, dtype=torch.int32, device=self.dev)
-        # pre-marshalled arguments for the hot loop
+        # device view sequence and the slot the iteration reads its view from
+        seq = np.zeros(1, np.int32) if sequence is None else np.asarray(sequence, np.int32)
+        self.seq = torch.as_tensor(seq).to(self.dev)
+        self.seq_pos = torch.zeros(1, dtype=torch.int64, device=self.dev)
+        self.view = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        self.table = sk.camera_table(self.cams, rp)
+        self.train_step = sk.TrainStep(
+            self.planes, self.n, self.deg, self.cams, self.table, self.view, rp, self.ws, self.cap,
+            self.targets, 0.2, self.lws, self.rgb, self.dl, self.loss,
+            gate if gated else None, self.gstate if gated else None, self.gate, self.adam, self.m,
+            self.v, self.step_count)
+        # pre-marshalled arguments for the stage-by-stage path
         self.prep = sk.Prepared(self.planes, self.n, self.deg, self.cams, rp, self.ws, self.cap)
         self.rgb_p, self.dl_p = self.rgb.data_ptr(), self.dl.data_ptr()
         self.lws_p, self.lws_n = self.lws.data_ptr(), self.lws.numel()
@@ -93,10 +111,20 @@ class Trainer:
             self.gpc = gate.c()
             self.gstate_p = self.gstate.data_ptr()
 
-    def iteration(self, view: int, gate_slot: torch.Tensor, loss_slot: torch.Tensor | None = None,
-                  timer: StageTimer | None = None):
-        """Enqueue one iteration. gate_slot: a device int32[1] that receives
-        the decision (forced to 1 in a full run)."""
+    def step(self, stream=None):
+        """Enqueue the next iteration of the sequence (two calls, no host
+        synchronisation; capturable)."""
+        s = torch.cuda.current_stream().cuda_stream if stream is None else stream
+        sk._check(sk.LIB.sgs_view_sequence_next(self.seq.data_ptr(), int(self.seq.numel()),
+                                                self.seq_pos.data_ptr(), self.view.data_ptr(), s))
+        self.train_step(s)
+
+    def iteration(self, view: int, d_view: torch.Tensor, gate_slot: torch.Tensor,
+                  loss_slot: torch.Tensor | None = None, timer: StageTimer | None = None):
+        """Enqueue one iteration stage by stage. view: the host view index;
+        d_view: a device int32[1] holding the same index (the gate reads it);
+        gate_slot: a device int32[1] that receives the decision (forced to 1
+        in a full run)."""
         P, s = self.prep, torch.cuda.current_stream().cuda_stream
         gate = gate_slot.data_ptr()
         loss = self.loss if loss_slot is None else loss_slot
@@ -114,8 +142,8 @@ class Trainer:
                                               self.lws_p, self.lws_n, lossp, s))
         e4 = mark()
         if self.gated:
-            sk._check(sk.LIB.sgs_gate_update(C.byref(self.gpc), self.gstate_p, int(view), lossp,
-                                             gate, s))
+            sk._check(sk.LIB.sgs_gate_update(C.byref(self.gpc), self.gstate_p, d_view.data_ptr(),
+                                             lossp, gate, s))
         else:
             gate_slot.fill_(1)
         e5 = mark()
@@ -139,6 +167,13 @@ class Trainer:
         if timer is not None:
             es = [e0, e1, e2, e3, e4, e5, e6, e7, e8, e9]
             timer.events.append({k: (es[i], es[i + 1]) for i, k in enumerate(timer.names)})
+
+    def backward_count(self) -> tuple[int, int]:
+        """(executed backward passes, iterations) the gate has seen (syncs)."""
+        if not self.gated:
+            return int(self.step_count.item()), int(self.step_count.item())
+        snap = sk.gate_read(self.gp, self.gstate)
+        return int(snap["b"]), int(snap["t"])
 
     def render(self, view: int, out: torch.Tensor):
         self.prep.render_forward(view, out.data_ptr(), torch.cuda.current_stream().cuda_stream)

@@ -57,10 +57,19 @@ def test_workspace_size_and_bad_tile_shape():
     sg = _lib()
     cams = [_cam()]
     nbytes = sg.forward_workspace_size(sg.RasterParams(), 1000, cams, 50_000)
-    assert nbytes > 50_000 * 12   # two (uint16 tile, uint32 entry) pair buffers
+    assert nbytes > 50_000 * 12   # two (uint16 key, uint32 entry) pair buffers
     with pytest.raises(sg.SkipGSError) as e:
         sg.forward_workspace_size(sg.RasterParams(tile_w=12, tile_h=12), 1000, cams, 10)
     assert e.value.status == 2 and "tile shape" in str(e.value)
+    with pytest.raises(sg.SkipGSError) as e:
+        sg.forward_workspace_size(sg.RasterParams(lds_batch=48), 1000, cams, 10)
+    assert e.value.status == 2 and "lds_batch" in str(e.value)
+    with pytest.raises(sg.SkipGSError) as e:
+        sg.forward_workspace_size(sg.RasterParams(super_tile=65), 1000, cams, 10)
+    assert e.value.status == 2 and "super_tile" in str(e.value)
+    # 0 selects the defaults (super-tiles of 8 tiles, batches of 64)
+    a = sg.get_workspace_layout(sg.RasterParams(super_tile=0, lds_batch=0), 1000, cams, 10)
+    assert (a.super_tile, a.batch) == (8, 64)
 
 
 def test_invalid_arguments_rejected_before_launch():
@@ -68,6 +77,7 @@ def test_invalid_arguments_rejected_before_launch():
     rp = sg.RasterParams().c()
     cams = sg.cameras_c([_cam()])
     g = sg.GaussiansC()
+    g.struct_size = C.sizeof(sg.GaussiansC)
     g.data = 256
     g.n = 10
     g.stride = 60        # not a multiple of 64
@@ -89,10 +99,11 @@ def test_invalid_arguments_rejected_before_launch():
     st = sg.LIB.sgs_render_forward(C.byref(g), cams, 17, C.byref(rp), C.c_void_p(256), 1 << 20, 100,
                                    C.c_void_p(256), None)
     assert st == 1
-    # gate: view out of range
+    # gate: the view index lives on the device; a null one is rejected
     gp = sg.GateParams(n_views=4).c()
-    st = sg.LIB.sgs_gate_update(C.byref(gp), C.c_void_p(256), 7, C.c_void_p(256), C.c_void_p(256), None)
-    assert st == 1 and b"view" in sg.LIB.sgs_last_error()
+    st = sg.LIB.sgs_gate_update(C.byref(gp), C.c_void_p(256), None, C.c_void_p(256),
+                                C.c_void_p(256), None)
+    assert st == 1 and b"null" in sg.LIB.sgs_last_error()
     gp.beta = 1.5
     out = C.c_size_t()
     assert sg.LIB.sgs_gate_state_size(C.byref(gp), C.byref(out)) == 1
@@ -101,6 +112,11 @@ def test_invalid_arguments_rejected_before_launch():
     st = sg.LIB.sgs_adam_step(C.byref(ap), C.c_void_p(256), C.c_void_p(256), C.c_void_p(256),
                               C.c_void_p(256), 10, 64, 60, C.c_void_p(256), None, None)
     assert st == 1
+    # adam: the visible-only step needs the fused backward
+    ap = sg.AdamParams(lr=(1e-3,) * 14, visible_only=True).c()
+    st = sg.LIB.sgs_adam_step(C.byref(ap), C.c_void_p(256), C.c_void_p(256), C.c_void_p(256),
+                              C.c_void_p(256), 10, 64, 14, C.c_void_p(256), None, None)
+    assert st == 2 and b"visible_only" in sg.LIB.sgs_last_error()
     # loss: bad lambda
     st = sg.LIB.sgs_photometric_loss(C.c_void_p(256), C.c_void_p(256), 8, 8, C.c_float(1.5),
                                      C.c_void_p(256), 1 << 20, C.c_void_p(256), None)
@@ -116,19 +132,79 @@ def test_gate_state_size():
 def test_layout_regions_fit_and_do_not_overlap():
     sg = _lib()
     cams = [_cam(64, 48), _cam(40, 24)]
-    rp = sg.RasterParams(tile_w=8, tile_h=8)
+    rp = sg.RasterParams(tile_w=8, tile_h=8, super_tile=3, lds_batch=128)
     L = sg.get_workspace_layout(rp, 500, cams, 30_000)
     total = sg.forward_workspace_size(rp, 500, cams, 30_000)
     assert L.entries == 1000
     assert L.total_tiles == 8 * 6 + 5 * 3
+    assert L.total_supers == 3 * 2 + 2 * 1
     assert L.total_pixels == 64 * 48 + 40 * 24
-    assert L.pair_tile_bytes == 2   # fewer than 65535 tiles: uint16 tile keys
+    assert L.key_bytes == 2   # fewer than 65535 super-tiles: uint16 keys
+    assert (L.batch, L.super_tile) == (128, 3)
+    # list storage: the capacity in chunks plus one partly filled chunk per tile
+    assert L.chunk_capacity == (30_000 + 127) // 128 + L.total_tiles
     regions = sorted([(L.records, 48 * 1000), (L.tiles, 4 * 1000), (L.depth, 4 * 1000),
-                      (L.pair_tile, L.pair_tile_bytes * 30_000),
-                      (L.pair_entry, 4 * 30_000), (L.ranges, 8 * L.total_tiles),
+                      (L.sup_key, L.key_bytes * 30_000), (L.sup_entry, 4 * 30_000),
+                      (L.sup_ranges, 8 * L.total_supers),
+                      (L.chunks, 4 * L.batch * L.chunk_capacity), (L.links, 8 * L.chunk_capacity),
+                      (L.tile_head, 4 * L.total_tiles),
                       (L.t_final, 4 * L.total_pixels), (L.n_last, 4 * L.total_pixels),
                       (L.accum, 48 * 1000), (L.counters, 64)])
     for (o1, s1), (o2, _) in zip(regions, regions[1:]):
         assert o1 + s1 <= o2
     assert regions[-1][0] + regions[-1][1] <= total
     assert all(o % 256 == 0 for o, _ in regions)
+
+
+def test_struct_sizes_are_checked():
+    """A struct whose struct_size is not the library's sizeof is rejected
+    before anything is enqueued."""
+    sg = _lib()
+    cams = sg.cameras_c([_cam()])
+    rp = sg.RasterParams().c()
+    rp.struct_size -= 4
+    out = C.c_size_t()
+    assert sg.LIB.sgs_forward_workspace_size(C.byref(rp), 10, cams, 1, 100, C.byref(out)) == 1
+    assert b"struct_size" in sg.LIB.sgs_last_error()
+    gp = sg.GateParams(n_views=4).c()
+    gp.struct_size = 0
+    assert sg.LIB.sgs_gate_state_size(C.byref(gp), C.byref(out)) == 1
+    ap = sg.AdamParams(lr=(1e-3,)).c()
+    ap.struct_size += 8
+    st = sg.LIB.sgs_adam_step(C.byref(ap), C.c_void_p(256), C.c_void_p(256), C.c_void_p(256),
+                              C.c_void_p(256), 10, 64, 1, C.c_void_p(256), None, None)
+    assert st == 1 and b"struct_size" in sg.LIB.sgs_last_error()
+    g = sg.GaussiansC()
+    g.struct_size = 7
+    rp = sg.RasterParams().c()
+    st = sg.LIB.sgs_render_forward(C.byref(g), cams, 1, C.byref(rp), C.c_void_p(256), 1 << 20,
+                                   100, C.c_void_p(256), None)
+    assert st == 1 and b"struct_size" in sg.LIB.sgs_last_error()
+
+
+def test_camera_table_and_train_iteration_validation():
+    sg = _lib()
+    out = C.c_size_t()
+    assert sg.LIB.sgs_camera_table_size(3, C.byref(out)) == 0 and out.value > 0
+    per = out.value // 3
+    assert out.value == 3 * per
+    assert sg.LIB.sgs_camera_table_size(0, C.byref(out)) == 1
+    # cameras of different sizes cannot share a table (rejected before any copy)
+    cams = sg.cameras_c([_cam(64, 48), _cam(40, 24)])
+    rp = sg.RasterParams().c()
+    st = sg.LIB.sgs_camera_table_init(cams, 2, C.byref(rp), C.c_void_p(256), 2 * per, None)
+    assert st == 1 and b"camera 1" in sg.LIB.sgs_last_error()
+    # a missing table is rejected
+    g = sg.GaussiansC()
+    g.struct_size = C.sizeof(sg.GaussiansC)
+    g.data, g.n, g.stride, g.sh_degree = 256, 10, 64, 0
+    ap = sg.AdamParams(lr=(1e-3,) * 14).c()
+    st = sg.LIB.sgs_train_iteration(C.byref(g), cams, None, 2, C.c_void_p(256), C.byref(rp),
+                                    C.c_void_p(256), 1 << 30, 100, C.c_void_p(256),
+                                    C.c_float(0.2), C.c_void_p(256), 1 << 30, C.c_void_p(256),
+                                    C.c_void_p(256), C.c_void_p(256), None, None,
+                                    C.c_void_p(256), C.byref(ap), C.c_void_p(256),
+                                    C.c_void_p(256), C.c_void_p(256), None)
+    assert st == 1 and b"table" in sg.LIB.sgs_last_error()
+    assert sg.LIB.sgs_view_sequence_next(C.c_void_p(256), 0, C.c_void_p(256), C.c_void_p(256),
+                                         None) == 1

@@ -63,9 +63,10 @@ def _gpu_gate_run(p, views, losses):
     state = m.alloc_bytes(m.gate_state_size(p))
     m.gate_init(p, state)
     d_losses = to_dev(np.asarray(losses, np.float32))
+    d_views = to_dev(np.asarray(views, np.int32))
     gates = torch.full((len(views),), -1, dtype=torch.int32, device="cuda")
-    for t, v in enumerate(views):
-        m.gate_update(p, state, int(v), d_losses[t:t + 1], gates[t:t + 1])
+    for t in range(len(views)):
+        m.gate_update(p, state, d_views[t:t + 1], d_losses[t:t + 1], gates[t:t + 1])
     snap = m.gate_read(p, state)
     return gates.cpu().numpy(), snap
 
@@ -118,6 +119,25 @@ def test_gate_nonfinite_loss():
     st, res = Gt.run(_oracle_params(p), views, losses)
     assert list(g_gpu) == [r.g for r in res] == [1, 0, 1, 0, 0]
     assert snap["flags"] & m.STATUS_NONFINITE_LOSS
+    assert np.array_equal(snap["ema"], np.asarray(st.ema))
+
+
+def test_gate_out_of_range_view_is_flagged_and_not_an_iteration():
+    """A device view index outside [0, n_views) leaves the state as it was
+    (no clock tick, no count, no EMA change), gives g = 0 and sets the bad-view
+    flag; the following iterations match the oracle run without it."""
+    require_gpu()
+    m = sg()
+    p = m.GateParams(n_views=3, warmup=2)
+    views = [0, 1, 7, 2, -1, 0, 1]
+    losses = np.array([0.5, 0.4, 0.3, 0.45, 0.2, 0.49, 0.41], np.float32)
+    g_gpu, snap = _gpu_gate_run(p, views, losses)
+    keep = [i for i, v in enumerate(views) if 0 <= v < 3]
+    st, res = Gt.run(_oracle_params(p), [views[i] for i in keep], losses[keep])
+    assert [int(g_gpu[i]) for i in (2, 4)] == [0, 0]
+    assert [int(g_gpu[i]) for i in keep] == [r.g for r in res]
+    assert snap["t"] == st.t == 5 and snap["b"] == st.b
+    assert snap["flags"] & m.STATUS_BAD_VIEW
     assert np.array_equal(snap["ema"], np.asarray(st.ema))
 
 

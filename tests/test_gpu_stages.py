@@ -1,13 +1,17 @@
-"""Stage parity on identical float32 records: tile binning and sort (bit
-exact), compositing forward (1e-5) and backward (1e-3) against the oracle."""
+"""Stage parity on identical float32 records: super-tile binning and sort
+(bit exact without the reach test, an ordered subsequence keeping every
+contributing entry with it), the tile lists the compositing forward records,
+compositing forward (1e-5) and backward (1e-3) against the oracle, with only
+pixels the oracle itself calls decision-sensitive left out."""
 import numpy as np
 import pytest
 import torch
 
 from oracle import render as R
 from paper_2603_08997_amd import scenes as S
-from tests.gpu_util import (region, rel_max_err, rel_norm_err, require_gpu, say, sg, split_views,
-                            to_dev)
+from tests.gpu_util import (last_blended, recorded_tile_lists, region, rel_max_err, rel_norm_err,
+                            require_gpu, say, sg, split_views, to_dev)
+from tests.sensitivity import decision_sensitive
 
 pytestmark = pytest.mark.gpu
 
@@ -36,21 +40,25 @@ class Stage:
                        d["conic"], d["opacity"], d["rgb"])
         m.bin(cams, n, rp, self.ws, capacity)
         self.flags, self.vis, self.pairs = m.read_status(self.ws)
-        self.kept = m.read_counters(self.ws)["pairs_kept"]
+        cnt = m.read_counters(self.ws)
+        self.kept, self.needed = cnt["pairs_kept"], cnt["pairs"]
 
     def lists(self):
+        """The sorted super-tile lists: key per pair, entry per pair, ranges."""
         P = self.kept
-        kt = np.uint16 if self.L.pair_tile_bytes == 2 else np.uint32
-        tiles = region(self.ws, self.L.pair_tile, P, kt).astype(np.uint32)
-        ents = region(self.ws, self.L.pair_entry, P, np.uint32)
-        ranges = region(self.ws, self.L.ranges, 2 * self.L.total_tiles, np.uint32).reshape(-1, 2)
-        return tiles, ents, ranges
+        kt = np.uint16 if self.L.key_bytes == 2 else np.uint32
+        keys = region(self.ws, self.L.sup_key, P, kt).astype(np.uint32)
+        ents = region(self.ws, self.L.sup_entry, P, np.uint32)
+        ranges = region(self.ws, self.L.sup_ranges, 2 * self.L.total_supers,
+                        np.uint32).reshape(-1, 2)
+        return keys, ents, ranges
 
     def rasterize(self):
         px = sum(c.width * c.height for c in self.cams)
         self.rgb = torch.zeros(3 * px, dtype=torch.float32, device="cuda")
         self.m.rasterize(self.cams, self.n, self.rp, self.ws, self.cap, self.rgb)
         torch.cuda.synchronize()
+        self.flags = self.m.read_status(self.ws)[0]
         tf = region(self.ws, self.L.t_final, self.L.total_pixels, np.float32)
         nl = region(self.ws, self.L.n_last, self.L.total_pixels, np.uint32)
         return self.rgb.cpu().numpy(), tf, nl
@@ -61,79 +69,117 @@ class Stage:
         return region(self.ws, self.L.accum, 12 * self.L.entries, np.float32).reshape(-1, 12)
 
 
-def _oracle_bins(recs, cams, n, tw, th):
-    keys, vals, ranges = [], [], []
+def _tiles_of(cam, tw, th):
+    return ((cam.width + tw - 1) // tw) * ((cam.height + th - 1) // th)
+
+
+def _supers_of(cam, tw, th, S_):
+    return (((cam.width + tw - 1) // tw + S_ - 1) // S_) * (((cam.height + th - 1) // th + S_ - 1) // S_)
+
+
+def _oracle_super_lists(recs, cams, n, tw, th, S_):
+    sups, vals, ranges = [], [], []
     off = 0
     for v, (r, c) in enumerate(zip(recs, cams)):
-        k, val, rg = R.bin_and_sort(r["u"], r["v"], r["depth"], r["extent"], v * n + np.arange(n),
-                                    c.width, c.height, tw, th, tile_offset=off)
-        base = sum(len(x) for x in keys)
+        k, val, rg = R.super_tile_lists(r["u"], r["v"], r["depth"], r["extent"],
+                                        v * n + np.arange(n), c.width, c.height, tw, th, S_,
+                                        super_offset=off)
+        base = sum(len(x) for x in sups)
         rg = np.where(rg[:, 1:2] > rg[:, 0:1], rg + base, 0)
-        keys.append(k); vals.append(val); ranges.append(rg)
-        off += ((c.width + tw - 1) // tw) * ((c.height + th - 1) // th)
-    return np.concatenate(keys), np.concatenate(vals), np.concatenate(ranges)
+        sups.append(k); vals.append(val); ranges.append(rg)
+        off += _supers_of(c, tw, th, S_)
+    return np.concatenate(sups), np.concatenate(vals), np.concatenate(ranges)
+
+
+def _oracle_tile_lists(recs, cams, n, tw, th):
+    """tile (global index) -> oracle tile list (entry indices)."""
+    out, off = {}, 0
+    for v, (r, c) in enumerate(zip(recs, cams)):
+        _, val, rg = R.bin_and_sort(r["u"], r["v"], r["depth"], r["extent"],
+                                    v * n + np.arange(n), c.width, c.height, tw, th)
+        for t in range(len(rg)):
+            out[off + t] = val[rg[t, 0]:rg[t, 1]]
+        off += _tiles_of(c, tw, th)
+    return out
 
 
 @pytest.mark.parametrize("tile", TILES)
 @pytest.mark.parametrize("ties", [0.0, 0.4])
-def test_binning_bit_exact(tile, ties):
+def test_binning_matches_oracle(tile, ties):
     require_gpu()
     st = _check_binning(_views(), tile, ties, 1500, 100 + int(ties * 10))
-    assert st.L.pair_tile_bytes == 2   # few tiles: uint16 tile keys
+    assert st.L.key_bytes == 2   # few super-tiles: uint16 keys
 
 
-def test_binning_bit_exact_wide_tile_keys():
-    """79,800 tiles (three 1600x1060 views, 8x8 tiles): uint32 tile keys."""
+@pytest.mark.parametrize("tile,S_", [((16, 16), 8), ((8, 8), 3), ((32, 8), 1), ((16, 16), 2)])
+def test_binning_bit_exact_without_reach_test(tile, S_):
+    """alpha_min = 0 (no reach test): super-tile keys, entry order (float32
+    depth, then index) and ranges equal the oracle's super-tile lists bit for
+    bit, for several super-tile sizes (1: the tile lists themselves)."""
+    require_gpu()
+    _check_binning(_views(), tile, 0.3, 1200, 77, super_tile=S_, alpha_min=0.0)
+
+
+def test_binning_bit_exact_wide_keys():
+    """79,800 tiles of 8x8 in super-tiles of one tile (three 1600x1060 views):
+    uint32 keys."""
     require_gpu()
     cams = [S.look_at_camera(p, 1600, 1060) for p in ((3.0, 1.0, 1.0), (0.5, -3.0, 2.0),
                                                         (-2.0, 2.0, 1.5))]
-    st = _check_binning(cams, (8, 8), 0.2, 1500, 131)
-    assert st.L.pair_tile_bytes == 4
+    st = _check_binning(cams, (8, 8), 0.2, 1500, 131, super_tile=1)
+    assert st.L.key_bytes == 4
 
 
-def _check_binning(cams, tile, ties, n, seed):
+def _check_binning(cams, tile, ties, n, seed, super_tile=8, alpha_min=None):
     m = sg()
     tw, th = tile
     recs, cat = _records(n, cams, seed, max_radius=20, tie_fraction=ties)
-    say(f"binning tile={tile} ties={ties} n={n} views={len(cams)}")
-    rp = m.RasterParams(tile_w=tw, tile_h=th)
+    extra = {} if alpha_min is None else {"alpha_min": alpha_min}
+    say(f"binning tile={tile} S={super_tile} ties={ties} n={n} views={len(cams)} {extra}")
+    rp = m.RasterParams(tile_w=tw, tile_h=th, super_tile=super_tile, **extra)
     st = Stage(n, cams, rp, cat, 400_000)
     assert st.flags == 0
-    keys, vals, ranges = _oracle_bins(recs, cams, n, tw, th)
-    tiles, ents, granges = st.lists()
+    sups, vals, ranges = _oracle_super_lists(recs, cams, n, tw, th, super_tile)
+    keys, ents, granges = st.lists()
     # the pair count the capacity must cover is that of the box lists
-    assert st.pairs == len(keys)
-    assert st.kept <= st.pairs and len(ents) == st.kept
-    # the GPU lists are the box lists less entries that fail the exact tile
-    # test: per tile, a subsequence of the oracle's list that keeps every
-    # entry able to contribute to a pixel of the tile, in the same order
-    orp = R.RasterParams(tile_w=tw, tile_h=th)
-    gtiles = (keys >> np.uint64(32)).astype(np.int64)
-    assert np.array_equal(tiles.astype(np.int64),
+    assert st.needed == len(vals)
+    assert st.kept <= st.needed and len(ents) == st.kept
+    assert np.array_equal(keys.astype(np.int64),
                           np.repeat(np.arange(len(granges)), granges[:, 1] - granges[:, 0]))
-    toff, dropped, dropped_dead, dead = 0, 0, 0, 0
+    if alpha_min == 0.0:
+        # no reach test: bit-exact lists
+        assert np.array_equal(keys.astype(np.int64), sups)
+        assert np.array_equal(ents.astype(np.int64), vals)
+        assert np.array_equal(granges.astype(np.int64), ranges)
+        return st
+    # the GPU lists are the box lists less entries that cannot reach
+    # alpha_min on the super-tile: per super-tile, an ordered subsequence of
+    # the oracle's list that keeps every entry able to contribute to a pixel
+    orp = R.RasterParams(tile_w=tw, tile_h=th, alpha_min=rp.alpha_min)
+    soff, dropped, dead = 0, 0, 0
     for v, (rec, cam) in enumerate(zip(recs, cams)):
-        tx_n = (cam.width + tw - 1) // tw
-        ty_n = (cam.height + th - 1) // th
-        for t in range(toff, toff + tx_n * ty_n):
-            lo, hi = ranges[t]
+        sx_n = ((cam.width + tw - 1) // tw + super_tile - 1) // super_tile
+        for sidx in range(soff, soff + _supers_of(cam, tw, th, super_tile)):
+            lo, hi = ranges[sidx]
             olist = vals[lo:hi]
-            glist = ents[granges[t][0]:granges[t][1]].astype(np.int64)
-            assert np.all(gtiles[lo:hi] == t)
+            glist = ents[granges[sidx][0]:granges[sidx][1]].astype(np.int64)
             keep = np.isin(olist, glist)
             assert np.array_equal(olist[keep], glist)          # ordered subsequence
-            tx, ty = (t - toff) % tx_n, (t - toff) // tx_n
+            sx, sy = (sidx - soff) % sx_n, (sidx - soff) // sx_n
+            x0, y0 = sx * super_tile * tw, sy * super_tile * th
             for e, kept in zip(olist, keep):
                 i = e - v * n
-                live = R.tile_contributes(rec["u"][i], rec["v"][i], *rec["conic"][i],
-                                          rec["opacity"][i], *rec["extent"][i], tx, ty, tw, th,
-                                          cam.width, cam.height, orp)
-                assert kept or not live, (t, e)
+                live = R.rect_contributes(rec["u"][i], rec["v"][i], *rec["conic"][i],
+                                          rec["opacity"][i], *rec["extent"][i], x0,
+                                          min(x0 + super_tile * tw, cam.width), y0,
+                                          min(y0 + super_tile * th, cam.height), orp)
+                assert kept or not live, (sidx, e)
                 dead += int(not live)
                 dropped += int(not kept)
-        toff += tx_n * ty_n
-    say(f"  box pairs {len(vals)}, kept {len(ents)}, non-contributing {dead}, dropped {dropped}")
-    assert dropped >= 0.5 * dead
+        soff += _supers_of(cam, tw, th, super_tile)
+    say(f"  super-tile pairs {len(vals)}, kept {len(ents)}, non-contributing {dead}, "
+        f"dropped {dropped}")
+    assert dropped >= 0.3 * dead
     return st
 
 
@@ -148,10 +194,42 @@ def test_binning_empty_and_capacity_overflow():
     assert st.flags == 0 and st.vis == 0 and st.pairs == 0
     _, _, ranges = st.lists()
     assert not ranges.any()
+    rgb, tf, nl = st.rasterize()
+    assert st.flags == 0 and not nl.any() and np.all(tf == 1.0) and not rgb.any()
     recs, cat = _records(n, cams, 8, max_radius=15)
-    st = Stage(n, cams, m.RasterParams(), cat, 64)   # far too small
+    st = Stage(n, cams, m.RasterParams(super_tile=1), cat, 64)   # far too small
     assert st.flags & m.STATUS_PAIR_OVERFLOW
     assert st.pairs > 64
+
+
+def test_list_storage_overflow_keeps_the_image():
+    """Enough super-tile pairs but too little list storage (super-tiles of
+    16x16 small tiles hold few pairs while the tile lists are long): the
+    forward flags the overflow, reports the capacity it needed, and still
+    composites every pixel right (the lists it could not record only matter
+    to the backward)."""
+    require_gpu()
+    m = sg()
+    cams = [S.look_at_camera((3.0, 1.0, 1.0), 255, 255)]
+    n = 20000
+    recs, cat = _records(n, cams, 21, max_radius=24)
+    rp = m.RasterParams(tile_w=8, tile_h=8, super_tile=16, lds_batch=32)
+    probe = Stage(n, cams, rp, cat, 400_000)
+    rgb_ref, _, _ = probe.rasterize()
+    assert probe.flags == 0
+    lists = recorded_tile_lists(probe.ws, probe.L)
+    chunks_needed = sum((len(x) + 31) // 32 for x in lists.values())
+    tiles = probe.L.total_tiles
+    need_pairs = probe.needed
+    # the largest capacity that still holds the pairs but not the chunks
+    cap = need_pairs
+    assert (cap + 31) // 32 + tiles < chunks_needed, (need_pairs, tiles, chunks_needed)
+    st = Stage(n, cams, rp, cat, cap)
+    assert st.flags == 0          # the pairs fit
+    rgb, _, _ = st.rasterize()
+    assert st.flags & m.STATUS_PAIR_OVERFLOW
+    assert np.array_equal(rgb, rgb_ref)
+    assert m.read_status(st.ws)[2] >= m.read_counters(probe.ws)["listed"]
 
 
 def _oracle_composite(rec, cam, rp, n, view, leaf=False):
@@ -164,58 +242,74 @@ def _oracle_composite(rec, cam, rp, n, view, leaf=False):
     return out, t
 
 
-@pytest.mark.parametrize("tile", TILES)
-def test_raster_forward_and_backward_match_oracle(tile):
+@pytest.mark.parametrize("tile,S_,B", [((16, 16), 8, 64), ((8, 8), 4, 32), ((32, 8), 2, 128),
+                                       ((16, 16), 1, 256)])
+def test_raster_forward_and_backward_match_oracle(tile, S_, B):
     require_gpu()
-    _check_raster(tile)
+    _check_raster(tile, super_tile=S_, lds_batch=B)
 
 
 def test_raster_nondefault_params_match_oracle():
-    """alpha_min = 0 (no skip threshold: log2 alpha_min = -inf, no exact tile
-    culling), alpha_max = 0.9 and t_min = 1e-3."""
+    """alpha_min = 0 (no skip threshold: log2 alpha_min = -inf, no reach
+    test), alpha_max = 0.9 and t_min = 1e-3."""
     require_gpu()
     _check_raster((16, 16), alpha_min=0.0, alpha_max=0.9, t_min=1e-3)
 
 
-def _check_raster(tile, **params):
+DECISION_REL = 3e-5
+
+
+def _check_raster(tile, super_tile=8, lds_batch=64, **params):
     m = sg()
     tw, th = tile
     cams = _views()
     n = 900
     recs, cat = _records(n, cams, 300, max_radius=14)
     bg = (0.2, 0.4, 0.6)
-    say(f"raster tile={tile} n={n} {params}")
-    st = Stage(n, cams, m.RasterParams(tile_w=tw, tile_h=th, bg=bg, **params), cat, 400_000)
+    say(f"raster tile={tile} S={super_tile} B={lds_batch} n={n} {params}")
+    st = Stage(n, cams, m.RasterParams(tile_w=tw, tile_h=th, bg=bg, super_tile=super_tile,
+                                       lds_batch=lds_batch, **params), cat, 400_000)
     rgb, tf, nl = st.rasterize()
+    assert st.flags == 0
     orp = R.RasterParams(tile_w=tw, tile_h=th, bg=bg, **params)
-    _, ents, granges = st.lists()
+    lists = recorded_tile_lists(st.ws, st.L)
+    olists = _oracle_tile_lists(recs, cams, n, tw, th)
+    # recorded lists: a prefix of the tile's oracle list (bit-exact without
+    # the reach test; otherwise an ordered subsequence that keeps every entry
+    # able to contribute within the recorded span)
+    for t, glist in lists.items():
+        ol = olists[t]
+        if orp.alpha_min == 0:
+            assert np.array_equal(glist, ol[:len(glist)]), t
+        else:
+            keep = np.isin(ol, glist)
+            assert np.array_equal(ol[keep], glist), t
     rng = np.random.default_rng(5)
-    dls, flips_total = [], 0
+    dls, excl_total = [], 0
+    toff = 0
     for v, (rec, cam, img, T, NL) in enumerate(zip(recs, cams, split_views(rgb, cams, 3),
                                                    split_views(tf, cams), split_views(nl, cams))):
-        out, _ = _oracle_composite(rec, cam, orp, n, v)
+        comp = lambda rp_: _oracle_composite(rec, cam, rp_, n, v)[0]
+        out, sens = decision_sensitive(comp, orp, DECISION_REL, 1e-5)
         ref_img = out["rgb"].detach().numpy()
-        # the GPU's last blended Gaussian: entry at position n_last - 1 of the
-        # pixel's tile list
         px, py = R.pixel_grid(cam.width, cam.height)
-        tiles_x = (cam.width + tw - 1) // tw
-        toff = sum(((c.width + tw - 1) // tw) * ((c.height + th - 1) // th) for c in cams[:v])
-        t = toff + (py.numpy() // th) * tiles_x + px.numpy() // tw
-        nlv = NL.astype(np.int64)
-        g_last = np.full(len(nlv), -1, np.int64)
-        has = nlv > 0
-        g_last[has] = ents[granges[t[has], 0].astype(np.int64) + nlv[has] - 1].astype(np.int64)
-        flips = g_last != out["last"].numpy()
-        flips_total += int(flips.sum())
-        ok = ~flips
-        assert flips.mean() < 1e-3
+        t = toff + (py.numpy() // th) * ((cam.width + tw - 1) // tw) + px.numpy() // tw
+        g_last = last_blended(lists, NL.astype(np.int64), t)
+        ok_last = ~sens["last"]
+        # no unexplained mismatch: the last blended Gaussian agrees on every
+        # pixel the oracle does not call decision-sensitive
+        assert np.array_equal(g_last[ok_last], out["last"].numpy()[ok_last]), v
+        ok = ~sens["colour"]
         assert rel_max_err(img.reshape(3, -1)[:, ok], ref_img[:, ok]) < 1e-5
         assert rel_max_err(T[ok], out["T_final"].detach().numpy()[ok]) < 1e-5
+        excl_total += int(sens["last"].sum())
+        assert sens["last"].mean() < 1e-2
         dl = rng.normal(0, 1, (3, cam.width * cam.height))
-        dl[:, flips] = 0.0
+        dl[:, sens["last"]] = 0.0
         dls.append(dl)
-    say(f"  decision flips: {flips_total}")
-    # backward on the same records, cotangents zero on flipped pixels
+        toff += _tiles_of(cam, tw, th)
+    say(f"  decision-sensitive pixels (oracle): {excl_total}")
+    # backward on the same records, cotangents zero on sensitive pixels
     dl_all = np.concatenate([d.reshape(-1) for d in dls]).astype(np.float32)
     acc = st.backward(dl_all)
     for v, (rec, cam) in enumerate(zip(recs, cams)):

@@ -215,6 +215,44 @@ def test_bins_cover_exactly_the_rect_and_sort_by_depth_then_index():
     assert np.all(np.diff(keys.astype(np.float64)) >= 0)
 
 
+@pytest.mark.parametrize("S_", [1, 2, 3, 8])
+def test_super_tile_list_is_the_depth_ordered_union_of_its_tile_lists(S_):
+    """Each super-tile list holds, once each and in (float32 depth, index)
+    order, exactly the Gaussians of the lists of its tiles; every tile list
+    is the subsequence of its super-tile's list whose rectangles contain the
+    tile; with super-tiles of one tile the lists are the tile lists."""
+    w, h, tw, th = 75, 41, 8, 8
+    rec = S.random_records(17, 120, w, h, max_radius=12, tie_fraction=0.3)
+    ids = np.arange(120)
+    _, tvals, tranges = R.bin_and_sort(rec["u"], rec["v"], rec["depth"], rec["extent"], ids, w, h,
+                                       tw, th)
+    sups, svals, sranges = R.super_tile_lists(rec["u"], rec["v"], rec["depth"], rec["extent"],
+                                              ids, w, h, tw, th, S_)
+    tx_n, ty_n = (w + tw - 1) // tw, (h + th - 1) // th
+    sx_n = (tx_n + S_ - 1) // S_
+    dbits = R.float32_bits(rec["depth"])
+    key = lambda i: (int(dbits[i]), int(i))
+    x0, x1, y0, y1 = (a.numpy() for a in R.tile_rect(rec["u"].astype(np.float64),
+                                                       rec["v"].astype(np.float64), rec["extent"],
+                                                       tw, th, tx_n, ty_n))
+    for sidx in range(len(sranges)):
+        sx, sy = sidx % sx_n, sidx // sx_n
+        members = set()
+        for ty in range(sy * S_, min((sy + 1) * S_, ty_n)):
+            for tx in range(sx * S_, min((sx + 1) * S_, tx_n)):
+                t = ty * tx_n + tx
+                tl = list(tvals[tranges[t, 0]:tranges[t, 1]])
+                members |= set(tl)
+                sl = list(svals[sranges[sidx, 0]:sranges[sidx, 1]])
+                inside = [i for i in sl if x0[i] <= tx < x1[i] and y0[i] <= ty < y1[i]]
+                assert inside == tl
+        got = list(svals[sranges[sidx, 0]:sranges[sidx, 1]])
+        assert got == sorted(members, key=key)
+        assert np.all(sups[sranges[sidx, 0]:sranges[sidx, 1]] == sidx)
+    if S_ == 1:
+        assert np.array_equal(svals, tvals) and np.array_equal(sranges, tranges)
+
+
 def test_tile_lists_contain_every_overlapping_gaussian():
     """Every Gaussian overlapping a pixel is in the list of that pixel's tile,
     so compositing over tile lists equals compositing over all Gaussians."""
