@@ -236,8 +236,10 @@ sgs_status sgs_project_backward(const sgs_gaussians* g, const sgs_camera* cams, 
  * records:    float32 [entries][12]  u v a b | c o rx ry | r g b clamp-mask(bits)
  * tiles:      uint32  [entries]      super-tiles touched (0 = not visible)
  * depth:      float32 [entries]      camera depth (the sort key) of visible entries
- * sup_key:    uint16 or uint32 (key_bytes: 2 when total_supers < 65535)
- *             [pair_capacity] sorted global super-tile index per pair
+ * sup_key:    uint32  [pair_capacity] per pair, sorted by the global super-tile
+ *             index in the low key_bits bits; above them the pair's tile
+ *             rectangle inside the super-tile (first and last column, first
+ *             and last row relative to it, rect_bits bits each)
  * sup_entry:  uint32  [pair_capacity] entry index per pair (sorted with the keys)
  * sup_ranges: uint32  [total_supers][2] [start, end) into the pair arrays
  * chunks:     uint32  [chunk_capacity][batch] recorded tile-list entries
@@ -254,7 +256,8 @@ typedef struct {
     size_t records, tiles, depth, sup_key, sup_entry, sup_ranges, chunks, links, tile_head,
         t_final, n_last, accum, counters;
     int64_t entries, total_tiles, total_pixels, total_supers, chunk_capacity;
-    int32_t key_bytes;   /* 2 or 4 */
+    int32_t key_bits;    /* bits of the super-tile index in sup_key */
+    int32_t rect_bits;   /* bits per tile-rectangle coordinate in sup_key */
     int32_t batch;       /* entries per chunk (lds_batch) */
     int32_t super_tile;  /* super-tile edge in tiles */
 } sgs_workspace_layout;

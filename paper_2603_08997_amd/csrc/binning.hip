@@ -13,8 +13,8 @@
 // their (super-tile, entry) pairs in that order, and sorts the pairs stably
 // by super-tile alone: stability keeps the depth order inside each
 // super-tile, as a sort of 64-bit (super-tile << 32 | depth) keys would, on
-// ceil(log2(super-tiles)) bits (uint16 keys when a batch has fewer than
-// 65535 super-tiles).
+// the bits of the super-tile index (the tile rectangle inside the super-tile
+// rides along in the key's upper bits).
 #include <algorithm>
 
 #include "sgs_internal.hpp"
@@ -197,11 +197,12 @@ __device__ __forceinline__ float super_limit(float lim) {
 // workgroups in flight hide the dependent loads of each). Their super-tile
 // rectangles are staged in LDS, a max-scan of their start positions gives
 // every window position its Gaussian, and every thread expands its pairs to
-// (super-tile, entry) with coalesced stores. Pair q of a Gaussian is
-// super-tile (x0 + q % w, y0 + q / w) of its rectangle, row-major; with
-// alpha_min > 0, pairs whose Gaussian cannot reach alpha_min on the
-// super-tile's pixels in the image get the all-ones key (kCulledTile, or
-// kCulledTile16 when the batch keeps uint16 keys).
+// (key, entry) with coalesced stores. Pair q of a Gaussian is super-tile
+// (x0 + q % w, y0 + q / w) of its super-tile rectangle, row-major; its key
+// packs the super-tile index and the part of the Gaussian's tile rectangle
+// inside that super-tile. With alpha_min > 0, pairs whose Gaussian cannot
+// reach alpha_min on the super-tile's pixels in the image get the all-ones
+// key (kCulledTile).
 constexpr int kEmitThreads = 256;
 constexpr int kEmitItems = 4;
 constexpr int kEmitTile = kEmitThreads * kEmitItems;
@@ -209,12 +210,11 @@ static_assert(kEmitTile == kEmitWindow, "emission window size");
 // Gaussians meeting one window: each owns at least kEmitHead + 1 units.
 constexpr int kEmitMaxG = kEmitTile / (kEmitHead + 1) + 2;
 
-template <typename K>
 __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     const uint32_t* __restrict__ sorted_entry, const uint32_t* __restrict__ offsets,
     const uint32_t* __restrict__ window_first, const float4* __restrict__ rec,
     uint32_t* __restrict__ counters, int64_t n, const Views* __restrict__ views, RasterDev rp,
-    int64_t capacity, K* __restrict__ ptile, uint32_t* __restrict__ pentry) {
+    int64_t capacity, uint32_t* __restrict__ pkey, uint32_t* __restrict__ pentry) {
     __shared__ uint32_t s_off[kEmitMaxG];
     __shared__ uint32_t s_ent[kEmitMaxG];
     __shared__ uint32_t s_base[kEmitMaxG];   // global super-tile of the rectangle's first one
@@ -224,6 +224,7 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     __shared__ uint16_t s_y0[kEmitMaxG];
     __shared__ uint16_t s_iw[kEmitMaxG];     // image size of the Gaussian's view
     __shared__ uint16_t s_ih[kEmitMaxG];
+    __shared__ uint16_t s_tr[kEmitMaxG][4];  // tile rectangle [x0, x1) x [y0, y1)
     __shared__ float s_lim[kEmitMaxG];       // reach limit on a super-tile
     __shared__ uint32_t s_own[kEmitTile];    // window position -> owning Gaussian
     __shared__ uint32_t s_scan[kEmitThreads / 64 + 1];
@@ -269,6 +270,10 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
         s_y0[j] = (uint16_t)sy0;
         s_iw[j] = (uint16_t)V.width;
         s_ih[j] = (uint16_t)V.height;
+        s_tr[j][0] = (uint16_t)x0;
+        s_tr[j][1] = (uint16_t)x1;
+        s_tr[j][2] = (uint16_t)y0;
+        s_tr[j][3] = (uint16_t)y1;
         s_lim[j] = super_limit(reach_limit(r1.y, rp));
         // mark where this Gaussian's units start inside the window
         const uint64_t first = (uint64_t)off + (uint64_t)kEmitHead * k;
@@ -333,31 +338,41 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
                           rect_reachable(g0[it].x, g0[it].y, g0[it].z, g0[it].w, g1[it].x,
                                          s_lim[j], g1[it].z, g1[it].w, px0, py0,
                                          min(sw, (int)s_iw[j] - px0), min(sh, (int)s_ih[j] - py0));
-        ptile[p] = keep ? (K)(s_base[j] + qy * s_tx[j] + (uint32_t)qx) : (K)~(K)0;
+        // the tile rectangle inside the super-tile, relative to its first tile
+        const int S = rp.super_tile;
+        const int ox = ((int)s_x0[j] + qx) * S, oy = ((int)s_y0[j] + (int)qy) * S;
+        const uint32_t lx0 = (uint32_t)(max((int)s_tr[j][0], ox) - ox);
+        const uint32_t lx1 = (uint32_t)(min((int)s_tr[j][1], ox + S) - 1 - ox);
+        const uint32_t ly0 = (uint32_t)(max((int)s_tr[j][2], oy) - oy);
+        const uint32_t ly1 = (uint32_t)(min((int)s_tr[j][3], oy + S) - 1 - oy);
+        const int rb = rp.rect_bits;
+        const uint32_t rect = lx0 | (lx1 << rb) | (ly0 << (2 * rb)) | (ly1 << (3 * rb));
+        const uint32_t sup = s_base[j] + qy * s_tx[j] + (uint32_t)qx;
+        pkey[p] = keep ? (sup | (rect << rp.key_bits)) : kCulledTile;
         pentry[p] = s_ent[j];
     }
 }
 
 // [start, end) of every super-tile by binary search in the sorted keys
-// (empty super-tiles: [0, 0)).
-template <typename K>
-__global__ void __launch_bounds__(256) ranges_kernel(const K* __restrict__ ptile,
+// (the super-tile index is the low key_bits bits; empty super-tiles: [0, 0)).
+__global__ void __launch_bounds__(256) ranges_kernel(const uint32_t* __restrict__ pkey,
                                                      const uint32_t* __restrict__ counters,
-                                                     int64_t total_tiles,
+                                                     int64_t total_supers, int key_bits,
                                                      uint32_t* __restrict__ ranges) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= total_tiles) return;
+    if (t >= total_supers) return;
+    const uint32_t mask = (uint32_t)((1ull << key_bits) - 1ull);
     const uint32_t P = counters[kPairsKept];
     uint32_t lo = 0, hi = P;
     while (lo < hi) {  // first key >= t
         const uint32_t mid = (lo + hi) >> 1;
-        if (ptile[mid] < (uint32_t)t) lo = mid + 1; else hi = mid;
+        if ((pkey[mid] & mask) < (uint32_t)t) lo = mid + 1; else hi = mid;
     }
     const uint32_t a = lo;
     hi = P;
     while (lo < hi) {  // first key > t
         const uint32_t mid = (lo + hi) >> 1;
-        if (ptile[mid] <= (uint32_t)t) lo = mid + 1; else hi = mid;
+        if ((pkey[mid] & mask) <= (uint32_t)t) lo = mid + 1; else hi = mid;
     }
     const bool empty = lo == a;
     ranges[2 * t] = empty ? 0u : a;
@@ -449,9 +464,6 @@ hipError_t launch_bin(const RasterDev& rp, int64_t n, const Layout& L, char* ws,
     uint32_t* totals = reinterpret_cast<uint32_t*>(ws + L.sort_totals);
     uint32_t* pkey[2] = {reinterpret_cast<uint32_t*>(ws + L.pair_key[0]),
                          reinterpret_cast<uint32_t*>(ws + L.pair_key[1])};
-    uint16_t* pkey16[2] = {reinterpret_cast<uint16_t*>(ws + L.pair_key[0]),
-                           reinterpret_cast<uint16_t*>(ws + L.pair_key[1])};
-    const bool key16 = L.key_bytes == 2;
     uint32_t* pentry[2] = {reinterpret_cast<uint32_t*>(ws + L.pair_entry[0]),
                            reinterpret_cast<uint32_t*>(ws + L.pair_entry[1])};
     uint32_t* ranges = reinterpret_cast<uint32_t*>(ws + L.sup_ranges);
@@ -483,31 +495,21 @@ hipError_t launch_bin(const RasterDev& rp, int64_t n, const Layout& L, char* ws,
         if (err != hipSuccess) return err;
         // at least one workgroup: block 0 also records the written pair count
         const dim3 egrid((unsigned)std::max<int64_t>(1, emit_windows(E, L.capacity)));
-        if (key16)
-            hipLaunchKernelGGL(emit_kernel<uint16_t>, egrid, dim3(kEmitThreads), 0, s, dval[res],
-                               offsets, window_first, rec, counters, n, views, rp, L.capacity,
-                               pkey16[0], pentry[0]);
-        else
-            hipLaunchKernelGGL(emit_kernel<uint32_t>, egrid, dim3(kEmitThreads), 0, s, dval[res],
-                               offsets, window_first, rec, counters, n, views, rp, L.capacity,
-                               pkey[0], pentry[0]);
+        hipLaunchKernelGGL(emit_kernel, egrid, dim3(kEmitThreads), 0, s, dval[res], offsets,
+                           window_first, rec, counters, n, views, rp, L.capacity, pkey[0],
+                           pentry[0]);
         if ((err = hipGetLastError()) != hipSuccess) return err;
         // stable sort of the pairs by super-tile; the first pass drops culled
         // pairs and counts the rest into counters[kPairsKept]
         int kres = 0;
-        err = key16 ? radix_sort(pkey16, pentry, counters + kPairsWritten, L.capacity, L.key_bits,
-                                 hist, totals, s, &kres, counters + kPairsKept)
-                    : radix_sort(pkey, pentry, counters + kPairsWritten, L.capacity, L.key_bits,
-                                 hist, totals, s, &kres, counters + kPairsKept);
+        err = radix_sort(pkey, pentry, counters + kPairsWritten, L.capacity, L.key_bits, hist,
+                         totals, s, &kres, counters + kPairsKept);
         if (err != hipSuccess) return err;
     }
     const dim3 rgrid((unsigned)((L.total_supers + 255) / 256));
-    if (L.total_supers > 0 && key16)
-        hipLaunchKernelGGL(ranges_kernel<uint16_t>, rgrid, dim3(256), 0, s, pkey16[L.key_result],
-                           counters, L.total_supers, ranges);
-    else if (L.total_supers > 0)
-        hipLaunchKernelGGL(ranges_kernel<uint32_t>, rgrid, dim3(256), 0, s, pkey[L.key_result],
-                           counters, L.total_supers, ranges);
+    if (L.total_supers > 0)
+        hipLaunchKernelGGL(ranges_kernel, rgrid, dim3(256), 0, s, pkey[L.key_result], counters,
+                           L.total_supers, L.key_bits, ranges);
     return hipGetLastError();
 }
 

@@ -88,6 +88,12 @@ sgs_status prepare(const sgs_raster_params* rp, int64_t n, const sgs_camera* cam
     sgs::make_layout(P->views, P->rd, n, capacity, &P->L);
     if (P->L.chunk_capacity > (int64_t)0xfffffffe)
         return fail(SGS_ERR_INVALID_ARG, "pair_capacity too large for the list storage");
+    if (P->L.key_bits + 4 * P->L.rect_bits > 32)
+        return fail(SGS_ERR_UNSUPPORTED,
+                    "%lld super-tiles of %d tiles do not fit a 32-bit pair key; use smaller "
+                    "super-tiles", (long long)P->L.total_supers, P->rd.super_tile);
+    P->rd.key_bits = P->L.key_bits;
+    P->rd.rect_bits = P->L.rect_bits;
     return SGS_OK;
 }
 
@@ -184,6 +190,8 @@ RasterDev make_raster(const sgs_raster_params* rp) {
     r.tile_h = rp->tile_h;
     r.super_tile = rp->super_tile > 0 ? rp->super_tile : kDefaultSuperTile;
     r.batch = rp->lds_batch > 0 ? rp->lds_batch : kDefaultBatch;
+    r.key_bits = 0;   // set with the layout
+    r.rect_bits = 0;
     for (int k = 0; k < 3; ++k) r.bg[k] = rp->bg[k];
     r.near_z = rp->near_z;
     r.dilation = rp->dilation;
@@ -205,13 +213,16 @@ void make_layout(const Views& views, const RasterDev& rp, int64_t n, int64_t cap
     L->chunk_capacity = list_chunks(capacity, L->total_tiles, rp.batch);
     L->scan_blocks = (L->entries + 2047) / 2048;
     L->sort_blocks = radix_blocks(std::max(L->entries, capacity));
-    // at least one pass: the first pass of the super-tile sort drops culled pairs
+    // super-tile index bits: 2^bits > total_supers, so that no index has all
+    // bits set (at least one: the first sort pass drops culled pairs)
     int bits = 1;
-    while ((int64_t(1) << bits) < L->total_supers) ++bits;
+    while ((int64_t(1) << bits) <= L->total_supers) ++bits;
+    int rbits = 0;
+    while ((1 << rbits) < rp.super_tile) ++rbits;
     L->key_bits = bits;
+    L->rect_bits = rbits;
     L->key_passes = radix_passes(bits);
     L->key_result = L->key_passes & 1;
-    L->key_bytes = L->total_supers < kMaxTiles16 ? 2 : 4;
     const int64_t E = L->entries;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -232,8 +243,8 @@ void make_layout(const Views& views, const RasterDev& rp, int64_t n, int64_t cap
     L->offsets = take(sizeof(uint32_t) * (size_t)E);
     L->window_first = take(sizeof(uint32_t) * (size_t)(emit_windows(E, capacity) + 1));
     L->scan_sums = take(sizeof(uint32_t) * (size_t)(L->scan_blocks + 1));
-    L->pair_key[0] = take((size_t)L->key_bytes * (size_t)capacity);
-    L->pair_key[1] = take((size_t)L->key_bytes * (size_t)capacity);
+    L->pair_key[0] = take(sizeof(uint32_t) * (size_t)capacity);
+    L->pair_key[1] = take(sizeof(uint32_t) * (size_t)capacity);
     L->pair_entry[0] = take(sizeof(uint32_t) * (size_t)capacity);
     L->pair_entry[1] = take(sizeof(uint32_t) * (size_t)capacity);
     L->sort_hist = take(sizeof(uint32_t) * 256 * (size_t)L->sort_blocks);
@@ -312,7 +323,8 @@ sgs_status sgs_get_workspace_layout(const sgs_raster_params* rp, int64_t n, cons
     out->total_pixels = L.total_pixels;
     out->total_supers = L.total_supers;
     out->chunk_capacity = L.chunk_capacity;
-    out->key_bytes = L.key_bytes;
+    out->key_bits = L.key_bits;
+    out->rect_bits = L.rect_bits;
     out->batch = L.batch;
     out->super_tile = P.rd.super_tile;
     return SGS_OK;

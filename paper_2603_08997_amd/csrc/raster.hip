@@ -48,14 +48,19 @@ constexpr float kNegHalfLog2e = -0.721347520444481703680f;  // -log2(e) / 2
 constexpr float kNegLog2e = -1.44269504088896340736f;       // -log2(e)
 
 // Bit q set iff the pixel origin + q (centre origin + q + 0.5) of an n-pixel
-// tile span lies in the overlap box |p - centre| <= r. In binary64 every
-// step is exact for float inputs, so this is the box test of the reals.
+// tile span lies in the overlap box |p - centre| <= r (r an integer). With
+// f = floor(centre) and t = centre - f (both exact in FP32, |centre| < 2^24),
+// the first such pixel is f - r + [t > 1/2] and the last f + r - [t < 1/2]:
+// the box test of the reals in integer arithmetic.
 __device__ __forceinline__ uint32_t box_mask(float centre, float r, int origin, int n) {
-    const double lo = ceil((double)centre - (double)r - 0.5) - (double)origin;
-    const double hi = floor((double)centre + (double)r - 0.5) - (double)origin;
-    const double l = fmax(lo, 0.0), h = fmin(hi, (double)(n - 1));
-    if (!(l <= h)) return 0u;
-    return (0xffffffffu >> (31 - (int)h)) & (0xffffffffu << (int)l);
+    const float f = floorf(centre);
+    const float t = centre - f;
+    const int fi = (int)f, ri = (int)r;
+    const int lo = fi - ri + (t > 0.5f ? 1 : 0) - origin;
+    const int hi = fi + ri - (t < 0.5f ? 1 : 0) - origin;
+    const int l = max(lo, 0), h = min(hi, n - 1);
+    if (l > h) return 0u;
+    return (0xffffffffu >> (31 - h)) & (0xffffffffu << l);
 }
 
 // Staged record of one list entry for one tile: geo = (u, v, A, B), aux = (C,
@@ -163,23 +168,26 @@ __device__ __forceinline__ uint32_t wave_add_u32(uint32_t v) {
 }
 
 // Forward of one tile. The wave walks its super-tile's list 64 entries at a
-// time; every lane tests one entry against the tile (the tile lies in the
-// entry's tile rectangle and, with alpha_min > 0, the entry passes the reach
-// test on the tile's pixels), and the entries that pass are appended, staged,
-// to a queue in LDS in list order: the queue receives the tile's own list. Each time the queue
-// holds B entries (or the list ends) the batch is composited, and recorded as
-// the tile's next list chunk of B entry indices (chunk storage handed out by
-// an atomic counter; each chunk links to the tile's previous one). The walk
-// stops when every pixel of the tile has terminated, so only the part of the
-// list the tile composites is formed.
+// time, the next keys and entry indices loaded while the current ones are
+// tested. A list entry belongs to the tile when the tile lies in the tile
+// rectangle its key carries and, with alpha_min > 0, it passes the reach test
+// on the tile's pixels in the image (the record is gathered only for entries
+// whose rectangle holds the tile). Entries that belong are appended, staged,
+// to a queue in LDS in list order: the queue receives the tile's own list.
+// Each time the queue holds B entries (or the list ends) the batch is
+// composited, and recorded as the tile's next list chunk of B entry indices
+// (chunk storage handed out by an atomic counter; each chunk links to the
+// tile's previous one). The walk stops when every pixel of the tile has
+// terminated, so only the part of the list the tile composites is formed.
 template <int TW, int TH, int B>
 __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
     const Views* __restrict__ views, RasterDev rp, const uint32_t* __restrict__ sup_ranges,
-    const uint32_t* __restrict__ sentry, const float4* __restrict__ rec,
-    float* __restrict__ out_rgb, float* __restrict__ t_final, uint32_t* __restrict__ n_last,
-    uint32_t* __restrict__ counters, uint32_t* __restrict__ tile_cost,
-    uint32_t* __restrict__ chunks, uint2* __restrict__ links, uint32_t* __restrict__ tile_head,
-    uint32_t chunk_capacity, uint32_t pair_capacity, uint32_t entries) {
+    const uint32_t* __restrict__ skey, const uint32_t* __restrict__ sentry,
+    const float4* __restrict__ rec, float* __restrict__ out_rgb, float* __restrict__ t_final,
+    uint32_t* __restrict__ n_last, uint32_t* __restrict__ counters,
+    uint32_t* __restrict__ tile_cost, uint32_t* __restrict__ chunks, uint2* __restrict__ links,
+    uint32_t* __restrict__ tile_head, uint32_t chunk_capacity, uint32_t pair_capacity,
+    uint32_t entries) {
     constexpr int PIX = TW * TH / kLanes;
     constexpr int RS = kLanes / TW;   // row step between a lane's pixels
     constexpr int Q = B + kLanes;     // queue: one batch plus one walk step
@@ -195,12 +203,17 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
     const int tx = local % V.tiles_x, ty = local / V.tiles_x;
     const int tid = threadIdx.x;
     const int col = tid % TW, row0 = tid / TW;
-    const int sup = V.sup_offset + (ty / rp.super_tile) * V.sup_x + tx / rp.super_tile;
+    const int S = rp.super_tile;
+    const int sup = V.sup_offset + (ty / S) * V.sup_x + tx / S;
     // (bounded by the pair storage, whatever the workspace holds)
     const uint32_t w_end = min(sup_ranges[2 * sup + 1], pair_capacity);
     uint32_t w = sup_ranges[2 * sup];
     const float lmin = rp.log2_alpha_min, amax = rp.alpha_max, tmin = rp.t_min;
     const int px0 = tx * TW, py0 = ty * TH;
+    // the tile's position inside its super-tile, and the rectangle fields
+    const uint32_t lx = (uint32_t)(tx % S), ly = (uint32_t)(ty % S);
+    const int kb = rp.key_bits, rb = rp.rect_bits;
+    const uint32_t rmask = (1u << rb) - 1u;
 
     const float px = (float)(px0 + col) + 0.5f;
     float py[PIX], T[PIX], C0[PIX], C1[PIX], C2[PIX];
@@ -220,41 +233,57 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
     // walked, the previous chunk, the chunk of the latest blend, chunk ordinal
     uint32_t qn = 0, listed = 0, walked = 0, prev = kNoChunk, head = kNoChunk, ordinal = 0;
     bool overflow = false;
+    // the next walk step's key and entry (all-ones key: none)
+    uint32_t nk = kCulledTile, ne = 0;
+    if (w + (uint32_t)tid < w_end) {
+        nk = skey[w + tid];
+        ne = sentry[w + tid];
+    }
+    // one loop, one walk step or one batch per turn (a nested fill loop
+    // keeps two copies of the pixel state alive across the compositing)
     for (;;) {
-        if (ballot(live != 0u) == 0) break;
-        // fill the queue from the super-tile list
-        while (qn < (uint32_t)B && w < w_end) {
-            const uint32_t idx = w + (uint32_t)tid;
-            bool pass = false;
-            uint32_t e = 0;
-            float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
-            if (idx < w_end) e = sentry[idx];
-            if (idx < w_end && e < entries) {
-                r0 = rec[3 * (int64_t)e];
-                r1 = rec[3 * (int64_t)e + 1];
-                // the tile lies in the entry's tile rectangle and, with a skip
-                // threshold, the entry can reach alpha_min on the tile's pixels
-                int x0, x1, y0, y1;
-                tile_rect(r0.x, r0.y, (int)r1.z, (int)r1.w, TW, TH, V.tiles_x, V.tiles_y, &x0,
-                          &x1, &y0, &y1);
-                pass = x0 <= tx && tx < x1 && y0 <= ty && ty < y1;
-                const float lim = reach_limit(r1.y, rp);
-                if (pass && lim != INFINITY)
-                    pass = rect_reachable(r0.x, r0.y, r0.z, r0.w, r1.x, lim, r1.z, r1.w, px0, py0,
-                                          min(TW, V.width - px0), min(TH, V.height - py0));
+        // one walk step of the super-tile list into the queue (after a batch
+        // fewer than 64 entries remain; with B < 64 the queue may still hold
+        // a batch, which is composited first)
+        if ((B >= kLanes || qn < (uint32_t)B) && w < w_end) {
+            const uint32_t ck = nk, ce = ne;
+            const uint32_t n_step = min((uint32_t)kLanes, w_end - w);
+            walked += n_step;
+            w += n_step;
+            nk = kCulledTile;
+            if (w + (uint32_t)tid < w_end) {
+                nk = skey[w + tid];
+                ne = sentry[w + tid];
             }
-            const uint64_t m = ballot(pass);
-            if (pass) {
-                const uint32_t slot = qn + (uint32_t)popc64(m & lanemask_lt());
-                stage_entry(r0, r1, px0, py0, TW, TH, s_geo[slot], s_aux[slot]);
-                s_col[slot] = rec[3 * (int64_t)e + 2];
-                s_ent[slot] = e;
+            const uint32_t r = ck >> kb;
+            bool pass = ck != kCulledTile && ce < entries && (r & rmask) <= lx &&
+                        lx <= ((r >> rb) & rmask) && ((r >> (2 * rb)) & rmask) <= ly &&
+                        ly <= ((r >> (3 * rb)) & rmask);
+            if (ballot(pass) != 0) {
+                float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+                if (pass) {
+                    r0 = rec[3 * (int64_t)ce];
+                    r1 = rec[3 * (int64_t)ce + 1];
+                    r2 = rec[3 * (int64_t)ce + 2];
+                    if (rp.alpha_min > 0.f)
+                        pass = rect_reachable(r0.x, r0.y, r0.z, r0.w, r1.x,
+                                              reach_limit(r1.y, rp), r1.z, r1.w, px0, py0,
+                                              min(TW, V.width - px0), min(TH, V.height - py0));
+                }
+                const uint64_t m = ballot(pass);
+                if (pass) {
+                    const uint32_t slot = qn + (uint32_t)popc64(m & lanemask_lt());
+                    stage_entry(r0, r1, px0, py0, TW, TH, s_geo[slot], s_aux[slot]);
+                    s_col[slot] = r2;
+                    s_ent[slot] = ce;
+                }
+                qn += (uint32_t)popc64(m);
             }
-            qn += (uint32_t)popc64(m);
-            walked += min((uint32_t)kLanes, w_end - w);
-            w += kLanes;
         }
-        if (qn == 0) break;
+        const bool alive = ballot(live != 0u) != 0;
+        if (!alive || (w >= w_end && qn == 0)) break;
+        if (qn < (uint32_t)B && w < w_end) continue;
+        // a full batch, or the rest of the list
         __syncthreads();
         const int cnt = (int)min(qn, (uint32_t)B);
         // the batch becomes the tile's next list chunk
@@ -295,10 +324,10 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
                     // a pixel whose transmittance would fall below t_min stops
                     // before this Gaussian; otherwise the Gaussian is blended
                     const float alpha = fminf(__builtin_amdgcn_exp2f(e), amax);
-                    const float w = alpha * T[k];
-                    const float tn = T[k] - w;
+                    const float wgt = alpha * T[k];
+                    const float tn = T[k] - wgt;
                     const bool stop = tn < tmin;
-                    const float wv = stop ? 0.f : w;
+                    const float wv = stop ? 0.f : wgt;
                     C0[k] = fmaf(c.x, wv, C0[k]);
                     C1[k] = fmaf(c.y, wv, C1[k]);
                     C2[k] = fmaf(c.z, wv, C2[k]);
@@ -334,6 +363,7 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
         __syncthreads();
         qn = (uint32_t)rem;
     }
+
     const int64_t plane = (int64_t)V.width * V.height;
     float* img = out_rgb + 3 * V.px_offset;
     const int x = px0 + col;
@@ -355,7 +385,7 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
     for (int k = 0; k < PIX; ++k) my_last = max(my_last, last[k]);
     const uint32_t tile_last = wave_max_u32(my_last);
     // work counters: one atomic each per tile
-    const uint32_t nb = wave_add_u32(n_blend), ne = wave_add_u32(n_eval);
+    const uint32_t nb = wave_add_u32(n_blend), ne2 = wave_add_u32(n_eval);
     if (tid == 0) {
         tile_cost[tile] = tile_last;
         // a tile whose list did not fit the chunk storage has no usable list
@@ -366,7 +396,7 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
         atomicAdd(reinterpret_cast<unsigned long long*>(counters + kBlended),
                   (unsigned long long)nb);
         atomicAdd(reinterpret_cast<unsigned long long*>(counters + kEvaluated),
-                  (unsigned long long)ne);
+                  (unsigned long long)ne2);
     }
 }
 
@@ -565,6 +595,7 @@ hipError_t launch_rasterize(const RasterDev& rp, const Layout& L, char* ws, floa
     if (L.total_tiles == 0) return hipSuccess;
     const Views* views = reinterpret_cast<const Views*>(ws + L.views);
     const uint32_t* ranges = reinterpret_cast<const uint32_t*>(ws + L.sup_ranges);
+    const uint32_t* skey = reinterpret_cast<const uint32_t*>(ws + L.pair_key[L.key_result]);
     const uint32_t* sentry = reinterpret_cast<const uint32_t*>(ws + L.pair_entry[L.key_result]);
     const float4* rec = reinterpret_cast<const float4*>(ws + L.records);
     float* tf = reinterpret_cast<float*>(ws + L.t_final);
@@ -576,7 +607,7 @@ hipError_t launch_rasterize(const RasterDev& rp, const Layout& L, char* ws, floa
     uint32_t* head = reinterpret_cast<uint32_t*>(ws + L.tile_head);
     const uint32_t cap = (uint32_t)L.chunk_capacity;
     const dim3 grid((unsigned)L.total_tiles), block(kLanes);
-    SGS_RASTER_DISPATCH(raster_forward_kernel, views, rp, ranges, sentry, rec, out_rgb, tf, nl, cnt,
+    SGS_RASTER_DISPATCH(raster_forward_kernel, views, rp, ranges, skey, sentry, rec, out_rgb, tf, nl, cnt,
                         cost, chunks, links, head, cap, (uint32_t)L.capacity,
                         (uint32_t)L.entries);
     return hipGetLastError();

@@ -189,9 +189,12 @@ __device__ __forceinline__ uint32_t super_count(int x0, int x1, int y0, int y1, 
 // on its rounding error (8 ulp of the sum of the terms' magnitudes), is within
 // `lim`. With lim = 2 ln(o / alpha_min) (inflated, see reach_limit) a Gaussian
 // that fails cannot pass the compositing kernels' skip test at any pixel of
-// the rectangle.
+// the rectangle. The limit 2 ln(o / alpha_min) = 2 ln 2 (log2 o - log2 alpha_min)
+// is formed with the hardware log2 and inflated by 1% + 0.01, far more than
+// the rounding of either; +inf for alpha_min = 0 (log2 alpha_min = -inf).
 __device__ __forceinline__ float reach_limit(float o, const RasterDev& rp) {
-    return rp.alpha_min > 0.f ? 2.f * logf(o / rp.alpha_min) * 1.01f + 0.01f : INFINITY;
+    constexpr float kTwoLn2 = 1.38629436111989061883f;
+    return (kTwoLn2 * 1.01f) * (__builtin_amdgcn_logf(o) - rp.log2_alpha_min) + 0.01f;
 }
 
 __device__ __forceinline__ bool rect_reachable(float u, float v, float a, float b, float c,

@@ -47,6 +47,8 @@ struct RasterDev {
     int32_t tile_w, tile_h;
     int32_t super_tile;    // super-tile edge in tiles
     int32_t batch;         // list entries per compositing batch (and per list chunk)
+    int32_t key_bits;      // low bits of a pair key: the super-tile index
+    int32_t rect_bits;     // bits per coordinate of the tile rectangle above them
     float bg[3];
     float near_z, dilation, alpha_min, alpha_max, t_min;
     float log2_alpha_min;  // log2(alpha_min), rounded from binary64 (-inf for 0)
@@ -78,12 +80,16 @@ enum Counter : int {
     kNumCounters = 16
 };
 
-// Key of an emitted pair whose Gaussian cannot reach alpha_min at any pixel
-// centre of the super-tile; the first pass of the super-tile sort drops such
-// pairs. Batches of fewer than 65535 super-tiles keep keys in uint16.
+// Pair key (uint32): the super-tile index in the low key_bits bits (a value
+// below 2^key_bits - 1, so that no key has all bits set), and above them the
+// entry's tile rectangle inside the super-tile, four coordinates of
+// rect_bits bits (first column, last column, first row, last row, relative to
+// the super-tile). Only the index is sorted on; the rectangle rides along, so
+// the compositing forward tests a list entry against its tile without
+// reading the entry's record. The key of an emitted pair whose Gaussian
+// cannot reach alpha_min on the super-tile has all bits set; the first pass
+// of the super-tile sort drops such pairs.
 constexpr uint32_t kCulledTile = 0xffffffffu;
-constexpr uint16_t kCulledTile16 = 0xffffu;
-constexpr int64_t kMaxTiles16 = 0xffff;
 constexpr uint32_t kNoChunk = 0xffffffffu;
 
 // Emission units: each visible Gaussian (in depth order) owns kEmitHead
@@ -108,8 +114,7 @@ struct Layout {
     int64_t entries, total_tiles, total_pixels, total_supers, capacity, chunk_capacity;
     int n_views;
     int64_t scan_blocks, sort_blocks;
-    int key_bits, key_passes, key_result;  // result buffer index (0/1) of the super-tile sort
-    int key_bytes;                         // 2 (total_supers < kMaxTiles16) or 4
+    int key_bits, rect_bits, key_passes, key_result;  // result buffer (0/1) of the super-tile sort
     int batch;
     size_t views, records, tiles, depth, dkey[2], dval[2], offsets, window_first, scan_sums,
         pair_key[2], pair_entry[2], sort_hist, sort_totals, sup_ranges, chunks, links, tile_head,
@@ -155,10 +160,9 @@ hipError_t launch_order_tiles(const uint32_t* cost, int64_t tiles, int shift, ui
 // n is read on the device from *n_dev; n_max bounds it for the grid size.
 // Returns the index (0/1) of the buffer holding the result.
 int radix_passes(int bits);
-// K is uint32_t or uint16_t. kept_dev (nullable, must hold 0): the first
-// pass drops keys with all bits set (kCulledTile, or kCulledTile16 for uint16
-// keys) and adds the number of remaining pairs there; later passes sort that
-// many.
+// K is uint32_t. kept_dev (nullable, must hold 0): the first
+// pass drops keys with all bits set (kCulledTile) and adds the number of
+// remaining pairs there; later passes sort that many.
 // gather_dst (nullable): the last pass also writes gather_src[value] at each
 // sorted position.
 template <typename K>

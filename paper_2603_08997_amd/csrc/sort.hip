@@ -1,7 +1,6 @@
-// Stable least-significant-digit radix sort of (key, uint32 value) pairs,
-// keys uint32 or uint16 (tile keys of batches with fewer than 65535 tiles,
-// which halves the key traffic and the LDS a scatter block needs), digits of
-// at most 8 bits, reduce-then-scan:
+// Stable least-significant-digit radix sort of (key, uint32 value) pairs over
+// the low bits of uint32 keys (the kernels are templates over the key type),
+// digits of at most 8 bits, reduce-then-scan:
 //   hist:    per-block digit counts, stored digit-major [256][blocks];
 //   scan:    one block per digit row scans the row and records its total;
 //   scatter: each block ranks its keys stably (each wave ranks a contiguous
@@ -302,9 +301,6 @@ hipError_t radix_sort(K* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int6
 }
 
 template hipError_t radix_sort<uint32_t>(uint32_t* keys[2], uint32_t* vals[2], const uint32_t*,
-                                         int64_t, int, uint32_t*, uint32_t*, hipStream_t, int*,
-                                         uint32_t*, const uint32_t*, uint32_t*);
-template hipError_t radix_sort<uint16_t>(uint16_t* keys[2], uint32_t* vals[2], const uint32_t*,
                                          int64_t, int, uint32_t*, uint32_t*, hipStream_t, int*,
                                          uint32_t*, const uint32_t*, uint32_t*);
 

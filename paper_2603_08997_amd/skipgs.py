@@ -55,7 +55,8 @@ class WorkspaceLayoutC(C.Structure):
                                             "t_final", "n_last", "accum", "counters")] + \
                [(k, C.c_int64) for k in ("entries", "total_tiles", "total_pixels",
                                          "total_supers", "chunk_capacity")] + \
-               [("key_bytes", C.c_int32), ("batch", C.c_int32), ("super_tile", C.c_int32)]
+               [("key_bits", C.c_int32), ("rect_bits", C.c_int32), ("batch", C.c_int32),
+                ("super_tile", C.c_int32)]
 
 
 class GateParamsC(C.Structure):

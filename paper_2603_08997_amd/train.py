@@ -205,16 +205,28 @@ def render_targets(gt: S.Scene, cams, rp, capacity, device="cuda") -> torch.Tens
     return out
 
 
-def measure_pairs(scene: S.Scene, cams, rp, device="cuda", probe_capacity=None) -> int:
-    """Largest number of (tile, Gaussian) pairs over the views (one sync per view)."""
+def measure_capacity(scene: S.Scene, cams, rp, device="cuda", probe_capacity=1 << 16) -> int:
+    """Largest pair capacity a forward of one view needs over the views (the
+    larger of its super-tile pairs and the tile-list entries it records; one
+    synchronisation per view). Each view is rendered with a capacity that
+    suffices, probing again with the reported need when the first try
+    overflows."""
     planes = torch.as_tensor(scene.to_planes()).to(device)
-    cap = probe_capacity or 1
-    ws = sk.alloc_bytes(sk.forward_workspace_size(rp, scene.n, [cams[0]], cap)).zero_()
+    out = torch.empty(3 * cams[0].width * cams[0].height, device=device)
+    cap = int(probe_capacity)
+    ws = None
     best = 0
     for c in cams:
-        sk.project(planes, scene.n, scene.sh_degree, [c], rp, ws, cap)
-        sk.bin([c], scene.n, rp, ws, cap)
-        _, _, pairs = sk.read_status(ws)
-        sk.clear_status(ws)
-        best = max(best, pairs)
+        for _ in range(3):
+            if ws is None:
+                ws = sk.alloc_bytes(sk.forward_workspace_size(rp, scene.n, [c], cap)).zero_()
+            sk.clear_status(ws)
+            sk.render_forward(planes, scene.n, scene.sh_degree, [c], rp, ws, cap, out)
+            flags, _, need = sk.read_status(ws)
+            if not flags & sk.STATUS_PAIR_OVERFLOW:
+                break
+            cap = int(need * 1.25) + 4096
+            ws = None
+        best = max(best, need)
+    del ws, planes, out
     return best

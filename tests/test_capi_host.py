@@ -139,12 +139,13 @@ def test_layout_regions_fit_and_do_not_overlap():
     assert L.total_tiles == 8 * 6 + 5 * 3
     assert L.total_supers == 3 * 2 + 2 * 1
     assert L.total_pixels == 64 * 48 + 40 * 24
-    assert L.key_bytes == 2   # fewer than 65535 super-tiles: uint16 keys
+    # super-tile index bits (2^bits > 8 super-tiles) and 2 bits per rectangle coordinate
+    assert (L.key_bits, L.rect_bits) == (4, 2)
     assert (L.batch, L.super_tile) == (128, 3)
     # list storage: the capacity in chunks plus one partly filled chunk per tile
     assert L.chunk_capacity == (30_000 + 127) // 128 + L.total_tiles
     regions = sorted([(L.records, 48 * 1000), (L.tiles, 4 * 1000), (L.depth, 4 * 1000),
-                      (L.sup_key, L.key_bytes * 30_000), (L.sup_entry, 4 * 30_000),
+                      (L.sup_key, 4 * 30_000), (L.sup_entry, 4 * 30_000),
                       (L.sup_ranges, 8 * L.total_supers),
                       (L.chunks, 4 * L.batch * L.chunk_capacity), (L.links, 8 * L.chunk_capacity),
                       (L.tile_head, 4 * L.total_tiles),
@@ -154,6 +155,18 @@ def test_layout_regions_fit_and_do_not_overlap():
         assert o1 + s1 <= o2
     assert regions[-1][0] + regions[-1][1] <= total
     assert all(o % 256 == 0 for o, _ in regions)
+
+
+def test_super_tiles_must_fit_the_pair_key():
+    """16 views of 2048x2048 in 8x8 tiles, super-tiles of 64 tiles: 24 bits of
+    rectangle leave too few bits for the 256 super-tile indices."""
+    sg = _lib()
+    cams = [_cam(2048, 2048)] * 16
+    with pytest.raises(sg.SkipGSError) as e:
+        sg.forward_workspace_size(sg.RasterParams(tile_w=8, tile_h=8, super_tile=64), 10, cams,
+                                  1000)
+    assert e.value.status == 2 and "pair key" in str(e.value)
+    sg.forward_workspace_size(sg.RasterParams(tile_w=8, tile_h=8, super_tile=8), 10, cams, 1000)
 
 
 def test_struct_sizes_are_checked():

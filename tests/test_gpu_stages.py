@@ -44,10 +44,16 @@ class Stage:
         self.kept, self.needed = cnt["pairs_kept"], cnt["pairs"]
 
     def lists(self):
-        """The sorted super-tile lists: key per pair, entry per pair, ranges."""
+        """The sorted super-tile lists: super-tile index, tile rectangle
+        inside the super-tile (x0, x1, y0, y1, last inclusive) and entry per
+        pair, and the ranges."""
         P = self.kept
-        kt = np.uint16 if self.L.key_bytes == 2 else np.uint32
-        keys = region(self.ws, self.L.sup_key, P, kt).astype(np.uint32)
+        raw = region(self.ws, self.L.sup_key, P, np.uint32).astype(np.int64)
+        kb, rb = self.L.key_bits, self.L.rect_bits
+        keys = raw & ((1 << kb) - 1)
+        r = raw >> kb
+        rect = np.stack([(r >> (k * rb)) & ((1 << rb) - 1) for k in range(4)], 1)
+        self.rect = rect
         ents = region(self.ws, self.L.sup_entry, P, np.uint32)
         ranges = region(self.ws, self.L.sup_ranges, 2 * self.L.total_supers,
                         np.uint32).reshape(-1, 2)
@@ -91,6 +97,29 @@ def _oracle_super_lists(recs, cams, n, tw, th, S_):
     return np.concatenate(sups), np.concatenate(vals), np.concatenate(ranges)
 
 
+def _oracle_rects(recs, cams, n, tw, th, S_, sups, vals):
+    """Per pair: the entry's tile rectangle (oracle) inside the pair's
+    super-tile, relative to its first tile, last column and row inclusive."""
+    out = np.zeros((len(vals), 4), np.int64)
+    soff = 0
+    for v, (r, c) in enumerate(zip(recs, cams)):
+        tx_n, ty_n = (c.width + tw - 1) // tw, (c.height + th - 1) // th
+        sx_n = (tx_n + S_ - 1) // S_
+        x0, x1, y0, y1 = (a.numpy() for a in R.tile_rect(r["u"].astype(np.float64),
+                                                           r["v"].astype(np.float64), r["extent"],
+                                                           tw, th, tx_n, ty_n))
+        nsup = _supers_of(c, tw, th, S_)
+        sel = np.nonzero((sups >= soff) & (sups < soff + nsup))[0]
+        for k in sel:
+            i = vals[k] - v * n
+            s = sups[k] - soff
+            ox, oy = (s % sx_n) * S_, (s // sx_n) * S_
+            out[k] = (max(x0[i], ox) - ox, min(x1[i], ox + S_) - 1 - ox,
+                      max(y0[i], oy) - oy, min(y1[i], oy + S_) - 1 - oy)
+        soff += nsup
+    return out
+
+
 def _oracle_tile_lists(recs, cams, n, tw, th):
     """tile (global index) -> oracle tile list (entry indices)."""
     out, off = {}, 0
@@ -108,7 +137,7 @@ def _oracle_tile_lists(recs, cams, n, tw, th):
 def test_binning_matches_oracle(tile, ties):
     require_gpu()
     st = _check_binning(_views(), tile, ties, 1500, 100 + int(ties * 10))
-    assert st.L.key_bytes == 2   # few super-tiles: uint16 keys
+    assert st.L.rect_bits == 3   # super-tiles of 8 tiles
 
 
 @pytest.mark.parametrize("tile,S_", [((16, 16), 8), ((8, 8), 3), ((32, 8), 1), ((16, 16), 2)])
@@ -122,12 +151,12 @@ def test_binning_bit_exact_without_reach_test(tile, S_):
 
 def test_binning_bit_exact_wide_keys():
     """79,800 tiles of 8x8 in super-tiles of one tile (three 1600x1060 views):
-    uint32 keys."""
+    17-bit super-tile indices, no rectangle bits."""
     require_gpu()
     cams = [S.look_at_camera(p, 1600, 1060) for p in ((3.0, 1.0, 1.0), (0.5, -3.0, 2.0),
                                                         (-2.0, 2.0, 1.5))]
-    st = _check_binning(cams, (8, 8), 0.2, 1500, 131, super_tile=1)
-    assert st.L.key_bytes == 4
+    st = _check_binning(cams, (8, 8), 0.2, 1500, 131, super_tile=1, alpha_min=0.0)
+    assert st.L.key_bits == 17 and st.L.rect_bits == 0
 
 
 def _check_binning(cams, tile, ties, n, seed, super_tile=8, alpha_min=None):
@@ -147,10 +176,12 @@ def _check_binning(cams, tile, ties, n, seed, super_tile=8, alpha_min=None):
     assert np.array_equal(keys.astype(np.int64),
                           np.repeat(np.arange(len(granges)), granges[:, 1] - granges[:, 0]))
     if alpha_min == 0.0:
-        # no reach test: bit-exact lists
+        # no reach test: bit-exact lists, and every key's rectangle is the
+        # entry's tile rectangle clipped to the super-tile
         assert np.array_equal(keys.astype(np.int64), sups)
         assert np.array_equal(ents.astype(np.int64), vals)
         assert np.array_equal(granges.astype(np.int64), ranges)
+        assert np.array_equal(st.rect, _oracle_rects(recs, cams, n, tw, th, super_tile, sups, vals))
         return st
     # the GPU lists are the box lists less entries that cannot reach
     # alpha_min on the super-tile: per super-tile, an ordered subsequence of
