@@ -302,7 +302,7 @@ def stage_pass(args, st, tr, start):
 def train_counters(tr, views):
     """Per-view work of the forward, averaged over a few views."""
     from paper_2603_08997_amd import skipgs as sk
-    keys = ("blended", "evaluated", "pairs", "pairs_kept", "listed", "walked", "visible")
+    keys = ("blended", "evaluated", "pairs", "pairs_kept", "items", "used", "visible")
     acc = {k: [] for k in keys}
     for v in views:
         tr.render(v, tr.rgb)

@@ -98,7 +98,7 @@ typedef struct {
     uint32_t struct_size;    /* sizeof(sgs_raster_params)                           */
     int32_t tile_w, tile_h;  /* 8x8, 16x16 or 32x8                                  */
     int32_t super_tile;      /* binning granularity: squares of super_tile tiles,   */
-                             /* 1..64 (0: 8)                                        */
+                             /* 1..8 (0: 8)                                         */
     int32_t lds_batch;       /* list entries per compositing batch staged in LDS:   */
                              /* 32, 64, 128 or 256 (0: 64)                          */
     float bg[3];             /* background colour, added with weight T_final        */
@@ -126,24 +126,22 @@ void sgs_default_raster_params(sgs_raster_params* rp);
  * centre (C(p) = sum c_i alpha'_i T_i + bg T_final).
  *
  * Binning works on super-tiles (squares of super_tile tiles): their
- * depth-ordered lists are sorted once, and the compositing of each tile walks
- * its super-tile's list, keeps the entries that can reach alpha_min on the
- * tile (its own depth-ordered list), and stops when every pixel has
- * terminated. The part of each tile list it composites is recorded, in chunks
- * of lds_batch entries, for the backward.
+ * depth-ordered lists are sorted once and then split into the depth-ordered
+ * lists of their tiles, keeping on each tile the entries that can reach
+ * alpha_min there. The compositing of each tile walks its list in batches of
+ * lds_batch entries and stops when every pixel has terminated.
  *
  * The workspace holds everything the backward needs (projected records, the
- * recorded tile lists, per-pixel final transmittance and last contributor).
+ * tile lists, per-pixel final transmittance and last contributor).
  * It is valid for sgs_render_backward until it is reused; the backward must
  * see the same Gaussians, cameras and parameters. The status word (sticky,
  * see sgs_read_status) of a newly allocated workspace is undefined: clear it
  * once with sgs_clear_status before the first forward.
  *
  * pair_capacity bounds both the (super-tile, Gaussian) pairs of the batch and
- * the tile-list entries the compositing records. If either is exceeded, the
- * device sets SGS_STATUS_PAIR_OVERFLOW and records the required capacity
- * (sgs_read_status); with too few pairs the image is incomplete, with too
- * little list storage the image is right but the backward is not.
+ * the entries of its tile lists. If either is exceeded, the device sets
+ * SGS_STATUS_PAIR_OVERFLOW and records the required capacity
+ * (sgs_read_status); the image and the gradients are then incomplete.
  * ------------------------------------------------------------------------- */
 sgs_status sgs_forward_workspace_size(const sgs_raster_params* rp, int64_t n,
                                       const sgs_camera* cams /* host */, int32_t n_views,
@@ -204,15 +202,18 @@ sgs_status sgs_load_records(const sgs_camera* cams, int32_t n_views, int64_t n,
                             const float* depth, const int32_t* extent, const float* conic,
                             const float* opacity, const float* rgb, void* stream);
 
-/* Binning: depth-ordered, per-super-tile lists of the visible entries whose
- * overlap box reaches the super-tile and that can reach alpha_min at one of
- * its pixel centres, ties in depth broken by ascending entry index. Also
- * clears the counters the compositing forward accumulates into: every
- * sgs_rasterize follows an sgs_bin. */
+/* Binning: the depth-ordered list of every tile (ties in depth broken by
+ * ascending entry index): the visible entries whose overlap box reaches the
+ * tile and that can reach alpha_min at one of its pixel centres. Built from
+ * per-super-tile lists (S x S tiles, S = super_tile) that are sorted once and
+ * then split into the lists of their tiles. pair_capacity bounds both the
+ * super-tile pairs and the tile-list entries (sgs_read_status reports the
+ * larger need). Also clears the counters the compositing forward accumulates
+ * into: every sgs_rasterize follows an sgs_bin. */
 sgs_status sgs_bin(const sgs_camera* cams, int32_t n_views, int64_t n, const sgs_raster_params* rp,
                    void* workspace, size_t workspace_bytes, int64_t pair_capacity, void* stream);
 
-/* Compositing forward of every tile (Eqs. 4-5); records the tile lists. */
+/* Compositing forward of every tile (Eqs. 4-5) over its list. */
 sgs_status sgs_rasterize(const sgs_camera* cams, int32_t n_views, int64_t n,
                          const sgs_raster_params* rp, void* workspace, size_t workspace_bytes,
                          int64_t pair_capacity, float* out_rgb, void* stream);
@@ -242,23 +243,22 @@ sgs_status sgs_project_backward(const sgs_gaussians* g, const sgs_camera* cams, 
  *             and last row relative to it, rect_bits bits each)
  * sup_entry:  uint32  [pair_capacity] entry index per pair (sorted with the keys)
  * sup_ranges: uint32  [total_supers][2] [start, end) into the pair arrays
- * chunks:     uint32  [chunk_capacity][batch] recorded tile-list entries
- * links:      uint32  [chunk_capacity][2] previous chunk of the tile (all ones:
- *                                     none), (chunk ordinal << 9) | entries
- * tile_head:  uint32  [total_tiles]   chunk holding the tile's last blended position
+ * tile_entry: uint32  [pair_capacity] entry indices of the tile lists
+ * tile_ranges: uint32 [total_tiles][2] [start, end) of each tile's list in tile_entry
  * t_final:    float32 [total_pixels]  final transmittance per pixel
  * n_last:     uint32  [total_pixels]  1 + list position of the last blended entry (0: none)
  * accum:      float32 [entries][12]   du dv da db | dc do dr dg | db 0 0 0
  * counters:   uint32  [16]            status, visible, pairs needed, pairs written,
  *                                     blended (u64), examined (u64), pairs kept,
- *                                     chunks, listed entries, walked entries */
+ *                                     tile-list entries needed, list segments,
+ *                                     tile-list entries up to the last blend */
 typedef struct {
-    size_t records, tiles, depth, sup_key, sup_entry, sup_ranges, chunks, links, tile_head,
+    size_t records, tiles, depth, sup_key, sup_entry, sup_ranges, tile_entry, tile_ranges,
         t_final, n_last, accum, counters;
-    int64_t entries, total_tiles, total_pixels, total_supers, chunk_capacity;
+    int64_t entries, total_tiles, total_pixels, total_supers;
     int32_t key_bits;    /* bits of the super-tile index in sup_key */
     int32_t rect_bits;   /* bits per tile-rectangle coordinate in sup_key */
-    int32_t batch;       /* entries per chunk (lds_batch) */
+    int32_t batch;       /* list entries per compositing batch (lds_batch) */
     int32_t super_tile;  /* super-tile edge in tiles */
 } sgs_workspace_layout;
 

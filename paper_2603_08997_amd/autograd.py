@@ -17,11 +17,13 @@ from . import skipgs as sk
 
 
 def _forward(planes, n, sh_degree, cams, rp, capacity):
-    """Forward into a fresh workspace; grows the pair capacity once if the
-    first launch reports an overflow (one host synchronisation)."""
+    """Forward into a fresh workspace (one host synchronisation); on an
+    overflow the pair capacity grows to the reported need and the forward runs
+    again (twice at most: the tile-list need is exact once the super-tile pairs
+    fit)."""
     px = sum(c.width * c.height for c in cams)
     rgb = torch.empty(3 * px, dtype=torch.float32, device=planes.device)
-    for _ in range(2):
+    for _ in range(3):
         ws = sk.alloc_bytes(sk.forward_workspace_size(rp, n, cams, capacity))
         sk.clear_status(ws)
         sk.render_forward(planes, n, sh_degree, cams, rp, ws, capacity, rgb)

@@ -1,20 +1,23 @@
-// Binning: the depth-ordered lists the tile-based rasteriser composites.
+// Binning: the depth-ordered tile lists the tile-based rasteriser composites.
 //
-// The lists are built at the granularity of super-tiles (squares of S x S
-// tiles): a super-tile's list holds, in ascending (depth, entry) order, the
-// visible entries whose overlap box reaches it and that can reach alpha_min
-// at one of its pixel centres. The compositing forward walks its tile's
-// super-tile list and keeps the entries that pass the same test on the tile
-// alone, which is the tile's own list in the same order, and stops when every
-// pixel of the tile has terminated; the tile lists are therefore never sorted
-// as a whole, and only the prefix a tile actually composites is ever formed.
+// The lists are built in two levels. First at the granularity of super-tiles
+// (squares of S x S tiles): the stage sorts the visible entries once by depth
+// (a short array), emits their (super-tile, entry) pairs in that order, and
+// sorts the pairs stably by super-tile alone; stability keeps the depth order
+// inside each super-tile, as a sort of 64-bit (super-tile << 32 | depth) keys
+// would, on the bits of the super-tile index (the entry's tile rectangle
+// inside the super-tile rides along in the key's upper bits). A super-tile's
+// list holds the visible entries whose overlap box reaches it and that can
+// reach alpha_min at one of its pixel centres.
 //
-// The stage sorts the visible entries once by depth (a short array), emits
-// their (super-tile, entry) pairs in that order, and sorts the pairs stably
-// by super-tile alone: stability keeps the depth order inside each
-// super-tile, as a sort of 64-bit (super-tile << 32 | depth) keys would, on
-// the bits of the super-tile index (the tile rectangle inside the super-tile
-// rides along in the key's upper bits).
+// Then every super-tile list is split into the lists of its S x S tiles, in
+// list order: per segment of a super-tile list, each pair's tile mask (the
+// tiles of its rectangle on which the entry can reach alpha_min), per-tile
+// counts, one scan over all (super-tile, tile, segment) counts for the list
+// positions, and a stable scatter of the entries. A tile's list is therefore
+// its depth-ordered list of entries whose overlap box reaches it and that can
+// reach alpha_min on it; the sort never sees the (far more numerous) tile
+// pairs.
 #include <algorithm>
 
 #include "sgs_internal.hpp"
@@ -432,6 +435,341 @@ __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
     if (i < n) p[i] = v;
 }
 
+// ---- the split of the super-tile lists into tile lists ----
+
+// Segments of every super-tile's list (the scan numbers them).
+struct SegCountSrc {
+    const uint32_t* ranges;
+    int64_t n;
+    __device__ int64_t count() const { return n; }
+    __device__ uint32_t operator()(int64_t s) const {
+        const uint32_t len = ranges[2 * s + 1] - ranges[2 * s];
+        return (uint32_t)((len + kSegPairs - 1) / kSegPairs);
+    }
+};
+struct FirstSink {
+    uint32_t* first;
+    __device__ void operator()(int64_t k, uint32_t, uint32_t pos) const { first[k] = pos; }
+};
+// (super-tile, tile, segment) counts, in that order, for the list positions.
+struct ItemCountSrc {
+    const uint32_t* cnt;
+    const uint32_t* n_seg;
+    int tt;
+    __device__ int64_t count() const { return (int64_t)*n_seg * tt; }
+    __device__ uint32_t operator()(int64_t i) const { return cnt[i]; }
+};
+struct ItemOffSink {
+    uint32_t* off;
+    __device__ void operator()(int64_t k, uint32_t, uint32_t pos) const { off[k] = pos; }
+};
+
+// Segment g of the split: super-tile s (global index), segment k of nseg in
+// its list, pairs [a, b), the super-tile's first tile (tx0, ty0) in its view.
+struct Segment {
+    int s;
+    uint32_t k, nseg, a, b;
+    int tx0, ty0;
+    const ViewDev* V;
+};
+
+__device__ __forceinline__ bool locate_segment(const Views* views, const uint32_t* seg_first,
+                                               const uint32_t* sup_ranges, int S, uint32_t g,
+                                               Segment* out) {
+    const int ns = views->total_supers;
+    if (g >= seg_first[ns]) return false;
+    int lo = 0, hi = ns;   // first super-tile whose first segment lies past g
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (seg_first[mid] <= g) lo = mid + 1; else hi = mid;
+    }
+    const int s = lo - 1;
+    int vi = 0;
+    while (vi + 1 < views->n && s >= views->v[vi + 1].sup_offset) ++vi;
+    const ViewDev* V = &views->v[vi];
+    const int ls = s - V->sup_offset;
+    out->s = s;
+    out->k = g - seg_first[s];
+    out->nseg = seg_first[s + 1] - seg_first[s];
+    out->a = sup_ranges[2 * s] + out->k * (uint32_t)kSegPairs;
+    out->b = min(sup_ranges[2 * s + 1], out->a + (uint32_t)kSegPairs);
+    out->tx0 = (ls % V->sup_x) * S;
+    out->ty0 = (ls / V->sup_x) * S;
+    out->V = V;
+    return true;
+}
+
+// Orders this wave's LDS accesses before and after (the lanes of one wave
+// exchange data through their own rows of the LDS arrays).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint64_t wave_or64(uint64_t m) {
+    uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        lo |= (uint32_t)__shfl_xor((int)lo, d, 64);
+        hi |= (uint32_t)__shfl_xor((int)hi, d, 64);
+    }
+    return (uint64_t)__builtin_amdgcn_readfirstlane(lo) |
+           ((uint64_t)__builtin_amdgcn_readfirstlane(hi) << 32);
+}
+
+// Transpose of the 64 x 64 bit matrix whose row l is lane l's word: returns,
+// in lane t, the word whose bit l is bit t of lane l's input. Six stages
+// swap the off-diagonal blocks of size 32, 16, ..., 1: a lane in the upper
+// half of a block pair keeps its bits of the left half and takes its
+// partner's left-half bits into the right half, and the other way round.
+__device__ __forceinline__ uint64_t wave_transpose64(uint64_t x) {
+    const int l = __lane_id();
+    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    {
+        const uint32_t plo = (uint32_t)__shfl_xor((int)lo, 32, 64);
+        const uint32_t phi = (uint32_t)__shfl_xor((int)hi, 32, 64);
+        const bool up = (l & 32) != 0;
+        lo = up ? phi : lo;
+        hi = up ? hi : plo;
+    }
+    constexpr uint32_t kKeep[5] = {0x0000ffffu, 0x00ff00ffu, 0x0f0f0f0fu, 0x33333333u,
+                                   0x55555555u};
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const int j = 16 >> i;
+        const uint32_t M = kKeep[i];
+        const bool up = (l & j) != 0;
+        const uint32_t plo = (uint32_t)__shfl_xor((int)lo, j, 64);
+        const uint32_t phi = (uint32_t)__shfl_xor((int)hi, j, 64);
+        const uint32_t slo = up ? (plo >> j) : (plo << j), shi = up ? (phi >> j) : (phi << j);
+        lo = up ? ((lo & ~M) | (slo & M)) : ((lo & M) | (slo & ~M));
+        hi = up ? ((hi & ~M) | (shi & M)) : ((hi & M) | (shi & ~M));
+    }
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+constexpr int kSplitWaves = 4;
+
+// Reach of one entry by rows: q = a dx^2 + 2 b dx dy + c dy^2 <= lim is, for
+// dy fixed, the interval |dx - s dy| <= sqrt((lim - k dy^2) / a) (s = -b/a,
+// k = det/a, det = ac - b^2), so over a band of rows its right end is largest
+// at the band point nearest the dy of the ellipse's rightmost point,
+// dy_r = -b sqrt(lim / (c det)) (the right end is concave in dy), and its left
+// end smallest at -dy_r. Formed once per entry, in float, with margins that
+// keep the test conservative: det by Kahan's fused form (error a few ulp of
+// det); lim raised by a bound on the rounding of the compositing kernels' own
+// float evaluation of q (16 ulp of its terms' magnitudes, at most
+// 2 (a + c)^2 lim / det on the ellipse); every interval end widened by 1e-3 px
+// plus the worst effect of the rounding of lim - k dy^2 near the ellipse's
+// top or bottom, sqrt(4 eps lim / a), plus relative rounding.
+struct Reach {
+    float s, k, inv_a, lim, ym, dyr, slack;
+    bool conic;   // false: no reach limit or a degenerate conic (box only)
+};
+
+// (The hardware reciprocal and square root, 1 ulp each, are covered by the
+// relative margins.)
+__device__ __forceinline__ Reach make_reach(float a, float b, float c, float lim) {
+    Reach r;
+    const float bb = b * b;
+    const float det = fmaf(a, c, -bb) - fmaf(b, b, -bb);
+    r.conic = lim != INFINITY && a > 0.f && c > 0.f && det > 0.f;
+    const float inv_det = __builtin_amdgcn_rcpf(det);
+    const float ac = a + c;
+    r.lim = lim * (1.f + 2e-6f * (ac * ac * inv_det));
+    r.conic = r.conic && r.lim < INFINITY;
+    r.inv_a = __builtin_amdgcn_rcpf(a);
+    r.s = -b * r.inv_a;
+    r.k = det * r.inv_a;
+    r.ym = __builtin_amdgcn_sqrtf(r.lim * a * inv_det) * (1.f + 1e-5f) + 1e-3f;
+    r.dyr = -b * __builtin_amdgcn_sqrtf(r.lim * __builtin_amdgcn_rcpf(c) * inv_det);
+    r.slack = 1e-3f + 2.f * __builtin_amdgcn_sqrtf(4.8e-7f * r.lim * r.inv_a);
+    return r;
+}
+
+// Tile columns [*c0, *c1] (view tile indices; *c0 > *c1: none) of the tiles in
+// the row band of pixel rows [py0, py0 + h) that hold a pixel centre inside
+// the overlap box (widened by 1e-3 px) within the entry's reach; tile width
+// 2^tw_log2.
+__device__ __forceinline__ void band_columns(const Reach& R, float u, float v, float rx, float ry,
+                                             int py0, int h, int tw_log2, int width, int* c0,
+                                             int* c1) {
+    const float m = 1e-3f;
+    float lo = fmaxf((float)py0 + 0.5f - v, -ry - m);
+    float hi = fminf((float)(py0 + h) - 0.5f - v, ry + m);
+    float xl = -rx - m, xr = rx + m;
+    if (R.conic) {
+        lo = fmaxf(lo, -R.ym);
+        hi = fminf(hi, R.ym);
+        const float y1 = fminf(fmaxf(R.dyr, lo), hi), y2 = fminf(fmaxf(-R.dyr, lo), hi);
+        const float h1 = __builtin_amdgcn_sqrtf(fmaxf(fmaf(-R.k * y1, y1, R.lim), 0.f) * R.inv_a);
+        const float h2 = __builtin_amdgcn_sqrtf(fmaxf(fmaf(-R.k * y2, y2, R.lim), 0.f) * R.inv_a);
+        const float t1 = R.s * y1, t2 = R.s * y2;
+        const float rel = 1e-5f * (fabsf(t1) + fabsf(t2) + h1 + h2);
+        xl = fmaxf(xl, t2 - h2 - R.slack - rel);
+        xr = fminf(xr, t1 + h1 + R.slack + rel);
+    }
+    *c0 = 1;
+    *c1 = 0;
+    if (!(lo <= hi) || !(xl <= xr)) return;
+    // pixel columns whose centre lies in [u + xl, u + xr] (the sums' rounding,
+    // below an ulp of |u| + |x|, widened away)
+    const float ru = 2.4e-7f * (fabsf(u) + fabsf(xl) + fabsf(xr));
+    const float fl = fmaxf(ceilf(u + xl - 0.5f - ru), 0.f);
+    const float fr = fminf(floorf(u + xr - 0.5f + ru), (float)(width - 1));
+    if (!(fl <= fr)) return;
+    *c0 = (int)fl >> tw_log2;
+    *c1 = (int)fr >> tw_log2;
+}
+
+// Tile masks and per-tile counts of one segment per wave. A pair's mask has
+// bit (y S + x) for tile (x, y) of its super-tile when the tile lies in the
+// pair's tile rectangle and, with alpha_min > 0, the entry can reach alpha_min
+// on the tile's pixels in the image (row by row of the rectangle: the tile
+// columns of each row band the entry reaches).
+__global__ void __launch_bounds__(kSplitWaves * 64) split_count_kernel(
+    const Views* __restrict__ views, RasterDev rp, const uint32_t* __restrict__ seg_first,
+    const uint32_t* __restrict__ sup_ranges, const uint32_t* __restrict__ skey,
+    const uint32_t* __restrict__ sentry, const float4* __restrict__ rec, uint32_t entries,
+    uint64_t* __restrict__ mask, uint32_t* __restrict__ seg_cnt) {
+    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int S = rp.super_tile, TT = S * S;
+    Segment sg;
+    if (!locate_segment(views, seg_first, sup_ranges, S, blockIdx.x * kSplitWaves + w, &sg))
+        return;   // uniform across the wave
+    const ViewDev& V = *sg.V;
+    const int rb = rp.rect_bits;
+    const uint32_t rmask = (1u << rb) - 1u;
+    const bool reach = rp.alpha_min > 0.f;
+    const int tw_log2 = __builtin_ctz((unsigned)rp.tile_w);
+    const float inv_th = 1.f / (float)rp.tile_h;
+    uint32_t cnt = 0;   // lane t: pairs of the segment on tile t
+    for (uint32_t p0 = sg.a; p0 < sg.b; p0 += 64) {
+        const uint32_t p = p0 + (uint32_t)lane;
+        const bool valid = p < sg.b;
+        const uint32_t r = valid ? skey[p] >> rp.key_bits : 0u;
+        const int x0 = (int)(r & rmask), x1 = (int)((r >> rb) & rmask);
+        const int y0 = (int)((r >> (2 * rb)) & rmask), y1 = (int)((r >> (3 * rb)) & rmask);
+        uint64_t M = 0;
+        if (valid && !reach) {
+            const uint64_t row = ((1ull << (x1 - x0 + 1)) - 1ull) << x0;
+            for (int y = y0; y <= y1; ++y) M |= row << (y * S);
+        } else if (valid) {
+            const int64_t e = min(sentry[p], entries - 1u);
+            const float4 g0 = rec[3 * e], g1 = rec[3 * e + 1];
+            const Reach R = make_reach(g0.z, g0.w, g1.x, reach_limit(g1.y, rp));
+            // only the rows the ellipse's height reaches
+            int ya = y0, yb = y1;
+            if (R.conic) {
+                const float top = fmaxf(floorf((g0.y - R.ym) * inv_th), -1e6f);
+                const float bot = fminf(floorf((g0.y + R.ym) * inv_th), 1e6f);
+                ya = max(ya, (int)top - sg.ty0 - 1);
+                yb = min(yb, (int)bot - sg.ty0 + 1);
+            }
+            for (int y = ya; y <= yb; ++y) {
+                const int py0 = (sg.ty0 + y) * rp.tile_h;
+                int c0, c1;
+                band_columns(R, g0.x, g0.y, g1.z, g1.w, py0, min(rp.tile_h, V.height - py0),
+                             tw_log2, V.width, &c0, &c1);
+                c0 = max(c0 - sg.tx0, x0);
+                c1 = min(c1 - sg.tx0, x1);
+                if (c0 <= c1) M |= (((1ull << (c1 - c0 + 1)) - 1ull) << c0) << (y * S);
+            }
+        }
+        if (valid) mask[p] = M;
+        // lane t counts the pairs of this step whose mask has tile t
+        cnt += (uint32_t)popc64(wave_transpose64(M));
+    }
+    if (lane < TT)
+        seg_cnt[(size_t)seg_first[sg.s] * TT + (size_t)lane * sg.nseg + sg.k] = cnt;
+}
+
+// Stable scatter of one segment per wave into the tile lists, 64 pairs per
+// step. The transposed masks give lane t the set of the step's pairs on tile
+// t; the step's entries and their list positions are grouped by tile in LDS
+// (tile t's after those of the tiles before it, in pair order), and the wave
+// then stores the group with consecutive lanes on consecutive items, so that
+// stores of neighbouring lanes mostly share cache lines. A step of more than
+// kStepItems items (a few pairs covering most of their super-tile) is stored
+// directly by the tile lanes.
+constexpr int kWriteWaves = 4;
+constexpr int kStepItems = 1024;
+__global__ void __launch_bounds__(kWriteWaves * 64) split_write_kernel(
+    const Views* __restrict__ views, RasterDev rp, const uint32_t* __restrict__ seg_first,
+    const uint32_t* __restrict__ sup_ranges, const uint32_t* __restrict__ sentry,
+    const uint64_t* __restrict__ mask, const uint32_t* __restrict__ seg_off,
+    const uint32_t* __restrict__ counters, int64_t capacity, uint32_t* __restrict__ tile_entry) {
+    __shared__ uint32_t s_ent[kWriteWaves][64];
+    __shared__ uint32_t s_item[kWriteWaves][kStepItems];
+    __shared__ uint32_t s_pos[kWriteWaves][kStepItems];
+    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int S = rp.super_tile, TT = S * S;
+    Segment sg;
+    if (!locate_segment(views, seg_first, sup_ranges, S, blockIdx.x * kWriteWaves + w, &sg))
+        return;
+    if ((int64_t)counters[kItems] > capacity) return;   // overflow: the tile lists stay empty
+    // lane t: next list position of tile t
+    uint32_t run = lane < TT ? seg_off[(size_t)seg_first[sg.s] * TT + (size_t)lane * sg.nseg + sg.k]
+                             : 0u;
+    for (uint32_t p0 = sg.a; p0 < sg.b; p0 += 64) {
+        const uint32_t p = p0 + (uint32_t)lane;
+        const bool valid = p < sg.b;
+        const uint64_t M = valid ? mask[p] : 0ull;
+        s_ent[w][lane] = valid ? sentry[p] : 0u;
+        uint64_t T = wave_transpose64(M);
+        const uint32_t cnt = (uint32_t)popc64(T);
+        const uint32_t incl = wave_incl_scan(cnt);
+        const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
+        if (total > (uint32_t)kStepItems) {
+            wave_lds_sync();
+            for (; T != 0ull; T &= T - 1ull) tile_entry[run++] = s_ent[w][__builtin_ctzll(T)];
+            wave_lds_sync();
+            continue;
+        }
+        wave_lds_sync();
+        // group the step's entries by tile, with their list positions
+        for (uint32_t o = incl - cnt; T != 0ull; T &= T - 1ull, ++o) {
+            s_item[w][o] = s_ent[w][__builtin_ctzll(T)];
+            s_pos[w][o] = run++;
+        }
+        wave_lds_sync();
+        for (uint32_t i = (uint32_t)lane; i < total; i += 64) tile_entry[s_pos[w][i]] = s_item[w][i];
+        wave_lds_sync();
+    }
+}
+
+// [start, end) of every tile's list; flags a tile-list overflow (all lists
+// empty then) and records the segment count.
+__global__ void __launch_bounds__(256) tile_ranges_kernel(
+    const Views* __restrict__ views, RasterDev rp, const uint32_t* __restrict__ seg_first,
+    const uint32_t* __restrict__ seg_cnt, const uint32_t* __restrict__ seg_off,
+    uint32_t* __restrict__ counters, int64_t capacity, uint32_t* __restrict__ tile_ranges) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool overflow = (int64_t)counters[kItems] > capacity;
+    if (t == 0) {
+        counters[kSegments] = seg_first[views->total_supers];
+        if (overflow) atomicOr(&counters[kStatus], (uint32_t)SGS_STATUS_PAIR_OVERFLOW);
+    }
+    if (t >= views->total_tiles) return;
+    int vi = 0;
+    while (vi + 1 < views->n && t >= views->v[vi + 1].tile_offset) ++vi;
+    const ViewDev& V = views->v[vi];
+    const int local = (int)t - V.tile_offset;
+    const int tx = local % V.tiles_x, ty = local / V.tiles_x;
+    const int S = rp.super_tile, TT = S * S;
+    const int s = V.sup_offset + (ty / S) * V.sup_x + tx / S;
+    const uint32_t nseg = seg_first[s + 1] - seg_first[s];
+    uint32_t a = 0, b = 0;
+    if (nseg > 0 && !overflow) {
+        const size_t i0 = (size_t)seg_first[s] * TT + (size_t)((ty % S) * S + tx % S) * nseg;
+        a = seg_off[i0];
+        b = seg_off[i0 + nseg - 1] + seg_cnt[i0 + nseg - 1];
+    }
+    tile_ranges[2 * t] = a;
+    tile_ranges[2 * t + 1] = b;
+}
+
 }  // namespace
 
 hipError_t launch_store_views(const Views& views, const ViewDev* table, int n_table,
@@ -444,6 +782,47 @@ hipError_t launch_store_views(const Views& views, const ViewDev* table, int n_ta
 hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// The split of the sorted super-tile lists into the tile lists.
+static hipError_t launch_split(const RasterDev& rp, const Layout& L, char* ws, hipStream_t s) {
+    if (L.total_supers == 0 || L.total_tiles == 0) return hipSuccess;
+    const Views* views = reinterpret_cast<const Views*>(ws + L.views);
+    uint32_t* counters = reinterpret_cast<uint32_t*>(ws + L.counters);
+    const uint32_t* ranges = reinterpret_cast<const uint32_t*>(ws + L.sup_ranges);
+    const uint32_t* skey = reinterpret_cast<const uint32_t*>(ws + L.pair_key[L.key_result]);
+    const uint32_t* sentry = reinterpret_cast<const uint32_t*>(ws + L.pair_entry[L.key_result]);
+    const float4* rec = reinterpret_cast<const float4*>(ws + L.records);
+    uint32_t* seg_first = reinterpret_cast<uint32_t*>(ws + L.seg_first);
+    uint32_t* seg_cnt = reinterpret_cast<uint32_t*>(ws + L.seg_cnt);
+    uint32_t* seg_off = reinterpret_cast<uint32_t*>(ws + L.seg_off);
+    uint64_t* mask = reinterpret_cast<uint64_t*>(ws + L.pair_mask);
+    uint32_t* tile_entry = reinterpret_cast<uint32_t*>(ws + L.tile_entry);
+    uint32_t* tile_ranges = reinterpret_cast<uint32_t*>(ws + L.tile_ranges);
+    uint32_t* sums = reinterpret_cast<uint32_t*>(ws + L.scan_sums);
+    const int tt = rp.super_tile * rp.super_tile;
+    hipError_t err;
+    // segments of every super-tile list; their total -> seg_first[total_supers]
+    err = device_scan(SegCountSrc{ranges, L.total_supers}, FirstSink{seg_first}, L.total_supers,
+                      sums, seg_first + L.total_supers, s);
+    if (err != hipSuccess) return err;
+    const dim3 sgrid((unsigned)((L.seg_slots + kSplitWaves - 1) / kSplitWaves));
+    const uint32_t entries = (uint32_t)std::max<int64_t>(1, L.entries);
+    hipLaunchKernelGGL(split_count_kernel, sgrid, dim3(kSplitWaves * 64), 0, s, views, rp,
+                       seg_first, ranges, skey, sentry, rec, entries, mask, seg_cnt);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    // list positions; the number of tile-list entries -> counters[kItems]
+    err = device_scan(ItemCountSrc{seg_cnt, seg_first + L.total_supers, tt}, ItemOffSink{seg_off},
+                      L.seg_slots * tt, sums, counters + kItems, s);
+    if (err != hipSuccess) return err;
+    const dim3 wgrid((unsigned)((L.seg_slots + kWriteWaves - 1) / kWriteWaves));
+    hipLaunchKernelGGL(split_write_kernel, wgrid, dim3(kWriteWaves * 64), 0, s, views, rp,
+                       seg_first, ranges, sentry, mask, seg_off, counters, L.capacity, tile_entry);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    hipLaunchKernelGGL(tile_ranges_kernel, dim3((unsigned)((L.total_tiles + 255) / 256)), dim3(256),
+                       0, s, views, rp, seg_first, seg_cnt, seg_off, counters, L.capacity,
+                       tile_ranges);
     return hipGetLastError();
 }
 
@@ -469,7 +848,7 @@ hipError_t launch_bin(const RasterDev& rp, int64_t n, const Layout& L, char* ws,
     uint32_t* ranges = reinterpret_cast<uint32_t*>(ws + L.sup_ranges);
     hipError_t err;
     // counters this stage and the compositing forward accumulate into
-    constexpr int kClear = kWalked + 1 - kVisible;
+    constexpr int kClear = kUsed + 1 - kVisible;
 
     // visible entries -> (depth, entry), entry order; count -> counters[kVisible]
     // (the first scan kernel also clears the counters)
@@ -510,7 +889,8 @@ hipError_t launch_bin(const RasterDev& rp, int64_t n, const Layout& L, char* ws,
     if (L.total_supers > 0)
         hipLaunchKernelGGL(ranges_kernel, rgrid, dim3(256), 0, s, pkey[L.key_result], counters,
                            L.total_supers, L.key_bits, ranges);
-    return hipGetLastError();
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    return launch_split(rp, L, ws, s);
 }
 
 hipError_t launch_order_tiles(const uint32_t* cost, int64_t tiles, int shift, uint32_t* order,

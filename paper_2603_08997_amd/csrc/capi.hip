@@ -48,9 +48,9 @@ sgs_status check_raster(const sgs_raster_params* rp) {
                     (rp->tile_w == 32 && rp->tile_h == 8);
     if (!ok) return fail(SGS_ERR_UNSUPPORTED, "tile shape %dx%d not in {16x16, 8x8, 32x8}",
                          rp->tile_w, rp->tile_h);
-    if (rp->super_tile < 0 || rp->super_tile > 64)
-        return fail(SGS_ERR_UNSUPPORTED, "super_tile %d not in [1, 64] (0: default)",
-                    rp->super_tile);
+    if (rp->super_tile < 0 || rp->super_tile > sgs::kMaxSuperTile)
+        return fail(SGS_ERR_UNSUPPORTED, "super_tile %d not in [1, %d] (0: default)",
+                    rp->super_tile, sgs::kMaxSuperTile);
     if (rp->lds_batch != 0 && rp->lds_batch != 32 && rp->lds_batch != 64 &&
         rp->lds_batch != 128 && rp->lds_batch != 256)
         return fail(SGS_ERR_UNSUPPORTED, "lds_batch %d not in {32, 64, 128, 256} (0: default)",
@@ -86,8 +86,6 @@ sgs_status prepare(const sgs_raster_params* rp, int64_t n, const sgs_camera* cam
     if (!sgs::make_views(cams, n_views, rp, &P->views, &err)) return fail(SGS_ERR_INVALID_ARG, "%s", err);
     P->rd = sgs::make_raster(rp);
     sgs::make_layout(P->views, P->rd, n, capacity, &P->L);
-    if (P->L.chunk_capacity > (int64_t)0xfffffffe)
-        return fail(SGS_ERR_INVALID_ARG, "pair_capacity too large for the list storage");
     if (P->L.key_bits + 4 * P->L.rect_bits > 32)
         return fail(SGS_ERR_UNSUPPORTED,
                     "%lld super-tiles of %d tiles do not fit a 32-bit pair key; use smaller "
@@ -210,8 +208,10 @@ void make_layout(const Views& views, const RasterDev& rp, int64_t n, int64_t cap
     L->total_pixels = views.total_pixels;
     L->capacity = capacity;
     L->batch = rp.batch;
-    L->chunk_capacity = list_chunks(capacity, L->total_tiles, rp.batch);
-    L->scan_blocks = (L->entries + 2047) / 2048;
+    L->seg_slots = segment_slots(capacity, L->total_supers);
+    const int64_t tt = (int64_t)rp.super_tile * rp.super_tile;
+    // the scans run over the entries and over the (segment, tile) counts
+    L->scan_blocks = (std::max(L->entries, L->seg_slots * tt) + 2047) / 2048;
     L->sort_blocks = radix_blocks(std::max(L->entries, capacity));
     // super-tile index bits: 2^bits > total_supers, so that no index has all
     // bits set (at least one: the first sort pass drops culled pairs)
@@ -250,10 +250,14 @@ void make_layout(const Views& views, const RasterDev& rp, int64_t n, int64_t cap
     L->sort_hist = take(sizeof(uint32_t) * 256 * (size_t)L->sort_blocks);
     L->sort_totals = take(sizeof(uint32_t) * 256);
     L->sup_ranges = take(sizeof(uint32_t) * 2 * (size_t)L->total_supers);
-    L->chunks = take(sizeof(uint32_t) * (size_t)rp.batch * (size_t)L->chunk_capacity);
-    L->links = take(sizeof(uint32_t) * 2 * (size_t)L->chunk_capacity);
-    L->tile_head = take(sizeof(uint32_t) * (size_t)L->total_tiles);
+    L->seg_first = take(sizeof(uint32_t) * (size_t)(L->total_supers + 1));
+    L->seg_cnt = take(sizeof(uint32_t) * (size_t)(L->seg_slots * tt));
+    L->seg_off = take(sizeof(uint32_t) * (size_t)(L->seg_slots * tt));
+    L->pair_mask = take(sizeof(uint64_t) * (size_t)capacity);
+    L->tile_entry = take(sizeof(uint32_t) * (size_t)capacity);
+    L->tile_ranges = take(sizeof(uint32_t) * 2 * (size_t)L->total_tiles);
     L->tile_cost = take(sizeof(uint32_t) * (size_t)L->total_tiles);
+    L->tile_stats = take(sizeof(uint32_t) * 2 * (size_t)L->total_tiles);
     L->tile_order = take(sizeof(uint32_t) * (size_t)L->total_tiles);
     L->t_final = take(sizeof(float) * (size_t)L->total_pixels);
     L->n_last = take(sizeof(uint32_t) * (size_t)L->total_pixels);
@@ -311,9 +315,8 @@ sgs_status sgs_get_workspace_layout(const sgs_raster_params* rp, int64_t n, cons
     out->sup_key = L.pair_key[L.key_result];
     out->sup_entry = L.pair_entry[L.key_result];
     out->sup_ranges = L.sup_ranges;
-    out->chunks = L.chunks;
-    out->links = L.links;
-    out->tile_head = L.tile_head;
+    out->tile_entry = L.tile_entry;
+    out->tile_ranges = L.tile_ranges;
     out->t_final = L.t_final;
     out->n_last = L.n_last;
     out->accum = L.accum;
@@ -322,7 +325,6 @@ sgs_status sgs_get_workspace_layout(const sgs_raster_params* rp, int64_t n, cons
     out->total_tiles = L.total_tiles;
     out->total_pixels = L.total_pixels;
     out->total_supers = L.total_supers;
-    out->chunk_capacity = L.chunk_capacity;
     out->key_bits = L.key_bits;
     out->rect_bits = L.rect_bits;
     out->batch = L.batch;
@@ -493,7 +495,7 @@ sgs_status sgs_read_status(const void* workspace, uint32_t* flags_out, int64_t* 
     SGS_HIP(hipMemcpy(c, workspace, sizeof(c), hipMemcpyDeviceToHost), "read counters");
     if (flags_out) *flags_out = c[sgs::kStatus];
     if (visible_out) *visible_out = c[sgs::kVisible];
-    if (pairs_out) *pairs_out = std::max(c[sgs::kPairs], c[sgs::kListed]);
+    if (pairs_out) *pairs_out = std::max(c[sgs::kPairs], c[sgs::kItems]);
     return SGS_OK;
 }
 

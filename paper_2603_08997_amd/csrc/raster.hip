@@ -4,10 +4,10 @@
 // One wavefront (64 lanes) per tile; lane l owns column l % TW of the tile
 // and the rows l / TW + k * 64 / TW, k < TW*TH/64 (pixel k of lane l is
 // tile-local index l + 64 k, so every per-pixel load or store of the wave is a
-// run of contiguous row segments). The tile's list is staged through LDS 64
-// records at a time; while staging, each lane turns one record into the
-// coefficients the inner loop needs. Every lane then walks the batch with
-// broadcast LDS reads.
+// run of contiguous row segments). The tile's list is staged through LDS B
+// records at a time (B = lds_batch); while staging, each lane turns records
+// into the coefficients the inner loop needs. Every lane then walks the batch
+// with broadcast LDS reads.
 //
 // The exponent of Eq. 5 is evaluated in base 2 with the opacity folded in,
 // E = log2(o) + A dx^2 + B dx dy + C dy^2 (A = -a log2(e)/2, B = -b log2(e),
@@ -36,6 +36,8 @@
 // (the longest prefix of the list any pixel blends), and the backward takes
 // the tiles in decreasing order of it: consecutive workgroups land on
 // different SIMDs, so every SIMD gets a mix of long and short tiles.
+#include <algorithm>
+
 #include "sgs_internal.hpp"
 #include "sgs_device.hpp"
 
@@ -167,35 +169,21 @@ __device__ __forceinline__ uint32_t wave_add_u32(uint32_t v) {
     return v;
 }
 
-// Forward of one tile. The wave walks its super-tile's list 64 entries at a
-// time, the next keys and entry indices loaded while the current ones are
-// tested. A list entry belongs to the tile when the tile lies in the tile
-// rectangle its key carries and, with alpha_min > 0, it passes the reach test
-// on the tile's pixels in the image (the record is gathered only for entries
-// whose rectangle holds the tile). Entries that belong are appended, staged,
-// to a queue in LDS in list order: the queue receives the tile's own list.
-// Each time the queue holds B entries (or the list ends) the batch is
-// composited, and recorded as the tile's next list chunk of B entry indices
-// (chunk storage handed out by an atomic counter; each chunk links to the
-// tile's previous one). The walk stops when every pixel of the tile has
-// terminated, so only the part of the list the tile composites is formed.
+// Forward of one tile: the wave composites its tile list front to back in
+// batches of B entries (records gathered and staged in LDS per batch) and
+// stops when every pixel of the tile has terminated.
 template <int TW, int TH, int B>
 __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
-    const Views* __restrict__ views, RasterDev rp, const uint32_t* __restrict__ sup_ranges,
-    const uint32_t* __restrict__ skey, const uint32_t* __restrict__ sentry,
-    const float4* __restrict__ rec, float* __restrict__ out_rgb, float* __restrict__ t_final,
-    uint32_t* __restrict__ n_last, uint32_t* __restrict__ counters,
-    uint32_t* __restrict__ tile_cost, uint32_t* __restrict__ chunks, uint2* __restrict__ links,
-    uint32_t* __restrict__ tile_head, uint32_t chunk_capacity, uint32_t pair_capacity,
-    uint32_t entries) {
+    const Views* __restrict__ views, RasterDev rp, const uint32_t* __restrict__ tile_ranges,
+    const uint32_t* __restrict__ tile_entry, const float4* __restrict__ rec,
+    float* __restrict__ out_rgb, float* __restrict__ t_final, uint32_t* __restrict__ n_last,
+    uint32_t* __restrict__ tile_stats, uint32_t* __restrict__ tile_cost, uint32_t entries) {
     constexpr int PIX = TW * TH / kLanes;
     constexpr int RS = kLanes / TW;   // row step between a lane's pixels
-    constexpr int Q = B + kLanes;     // queue: one batch plus one walk step
     static_assert(B % 32 == 0 && B >= 32 && B <= 256, "batch size");
-    __shared__ float4 s_geo[Q];
-    __shared__ float4 s_aux[Q];
-    __shared__ float4 s_col[Q];   // r, g, b, -
-    __shared__ uint32_t s_ent[Q];
+    __shared__ float4 s_geo[B];
+    __shared__ float4 s_aux[B];
+    __shared__ float4 s_col[B];   // r, g, b, -
 
     const int tile = blockIdx.x;
     const ViewDev& V = views->v[view_of_tile(views, tile)];
@@ -203,17 +191,9 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
     const int tx = local % V.tiles_x, ty = local / V.tiles_x;
     const int tid = threadIdx.x;
     const int col = tid % TW, row0 = tid / TW;
-    const int S = rp.super_tile;
-    const int sup = V.sup_offset + (ty / S) * V.sup_x + tx / S;
-    // (bounded by the pair storage, whatever the workspace holds)
-    const uint32_t w_end = min(sup_ranges[2 * sup + 1], pair_capacity);
-    uint32_t w = sup_ranges[2 * sup];
+    const uint32_t start = tile_ranges[2 * tile], end = tile_ranges[2 * tile + 1];
     const float lmin = rp.log2_alpha_min, amax = rp.alpha_max, tmin = rp.t_min;
     const int px0 = tx * TW, py0 = ty * TH;
-    // the tile's position inside its super-tile, and the rectangle fields
-    const uint32_t lx = (uint32_t)(tx % S), ly = (uint32_t)(ty % S);
-    const int kb = rp.key_bits, rb = rp.rect_bits;
-    const uint32_t rmask = (1u << rb) - 1u;
 
     const float px = (float)(px0 + col) + 0.5f;
     float py[PIX], T[PIX], C0[PIX], C1[PIX], C2[PIX];
@@ -229,78 +209,57 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
         if (px0 + col < V.width && y < V.height) live |= 1u << (RS * k);
     }
     uint32_t n_blend = 0, n_eval = 0;
-    // wave-uniform: queued entries, list positions composited, entries
-    // walked, the previous chunk, the chunk of the latest blend, chunk ordinal
-    uint32_t qn = 0, listed = 0, walked = 0, prev = kNoChunk, head = kNoChunk, ordinal = 0;
-    bool overflow = false;
-    // the next walk step's key and entry (all-ones key: none)
-    uint32_t nk = kCulledTile, ne = 0;
-    if (w + (uint32_t)tid < w_end) {
-        nk = skey[w + tid];
-        ne = sentry[w + tid];
+    // Software pipeline over the batches: the entry indices are loaded two
+    // batches ahead and (one entry per lane, B <= 64) the records one batch
+    // ahead, so the gathers of a batch run while the previous one composites
+    // (a tile whose pixels stay live walks its whole list, and its time is
+    // otherwise a chain of two memory round trips per batch).
+    constexpr int NE = (B + kLanes - 1) / kLanes;   // entries per lane per batch
+    auto entry_at = [&](uint32_t b, int i) -> uint32_t {
+        const uint32_t k = b + (uint32_t)(i * kLanes + tid);
+        return k < end ? min(tile_entry[k], entries - 1u) : 0u;
+    };
+    uint32_t e_cur[NE], e_next[NE];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+        e_cur[i] = entry_at(start, i);
+        e_next[i] = entry_at(start + (uint32_t)B, i);
     }
-    // one loop, one walk step or one batch per turn (a nested fill loop
-    // keeps two copies of the pixel state alive across the compositing)
-    for (;;) {
-        // one walk step of the super-tile list into the queue (after a batch
-        // fewer than 64 entries remain; with B < 64 the queue may still hold
-        // a batch, which is composited first)
-        if ((B >= kLanes || qn < (uint32_t)B) && w < w_end) {
-            const uint32_t ck = nk, ce = ne;
-            const uint32_t n_step = min((uint32_t)kLanes, w_end - w);
-            walked += n_step;
-            w += n_step;
-            nk = kCulledTile;
-            if (w + (uint32_t)tid < w_end) {
-                nk = skey[w + tid];
-                ne = sentry[w + tid];
-            }
-            const uint32_t r = ck >> kb;
-            bool pass = ck != kCulledTile && ce < entries && (r & rmask) <= lx &&
-                        lx <= ((r >> rb) & rmask) && ((r >> (2 * rb)) & rmask) <= ly &&
-                        ly <= ((r >> (3 * rb)) & rmask);
-            if (ballot(pass) != 0) {
-                float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
-                if (pass) {
-                    r0 = rec[3 * (int64_t)ce];
-                    r1 = rec[3 * (int64_t)ce + 1];
-                    r2 = rec[3 * (int64_t)ce + 2];
-                    if (rp.alpha_min > 0.f)
-                        pass = rect_reachable(r0.x, r0.y, r0.z, r0.w, r1.x,
-                                              reach_limit(r1.y, rp), r1.z, r1.w, px0, py0,
-                                              min(TW, V.width - px0), min(TH, V.height - py0));
-                }
-                const uint64_t m = ballot(pass);
-                if (pass) {
-                    const uint32_t slot = qn + (uint32_t)popc64(m & lanemask_lt());
-                    stage_entry(r0, r1, px0, py0, TW, TH, s_geo[slot], s_aux[slot]);
-                    s_col[slot] = r2;
-                    s_ent[slot] = ce;
-                }
-                qn += (uint32_t)popc64(m);
-            }
-        }
-        const bool alive = ballot(live != 0u) != 0;
-        if (!alive || (w >= w_end && qn == 0)) break;
-        if (qn < (uint32_t)B && w < w_end) continue;
-        // a full batch, or the rest of the list
+    float4 q0, q1, q2;   // records of the lane's entry of the current batch (NE == 1)
+    if constexpr (NE == 1) {
+        q0 = rec[3 * (int64_t)e_cur[0]];
+        q1 = rec[3 * (int64_t)e_cur[0] + 1];
+        q2 = rec[3 * (int64_t)e_cur[0] + 2];
+    }
+    for (uint32_t b0 = start; b0 < end; b0 += (uint32_t)B) {
+        if (ballot(live != 0u) == 0) break;
         __syncthreads();
-        const int cnt = (int)min(qn, (uint32_t)B);
-        // the batch becomes the tile's next list chunk
-        uint32_t chunk = kNoChunk;
-        if (!overflow) {
-            uint32_t c = 0;
-            if (tid == 0) c = atomicAdd(&counters[kChunks], 1u);
-            c = (uint32_t)__shfl((int)c, 0, kLanes);
-            if (c < chunk_capacity) chunk = c;
-            else overflow = true;
+        const int cnt = (int)min((uint32_t)B, end - b0);
+        if constexpr (NE == 1) {
+            if (tid < cnt) {
+                stage_entry(q0, q1, px0, py0, TW, TH, s_geo[tid], s_aux[tid]);
+                s_col[tid] = q2;
+            }
+            const uint32_t e2 = entry_at(b0 + 2u * (uint32_t)B, 0);
+            q0 = rec[3 * (int64_t)e_next[0]];
+            q1 = rec[3 * (int64_t)e_next[0] + 1];
+            q2 = rec[3 * (int64_t)e_next[0] + 2];
+            e_next[0] = e2;
+        } else {
+#pragma unroll
+            for (int i = 0; i < NE; ++i) {
+                const int j = i * kLanes + tid;
+                if (j < cnt) {
+                    const int64_t e = e_cur[i];
+                    const float4 r0 = rec[3 * e], r1 = rec[3 * e + 1];
+                    stage_entry(r0, r1, px0, py0, TW, TH, s_geo[j], s_aux[j]);
+                    s_col[j] = rec[3 * e + 2];
+                }
+                e_cur[i] = e_next[i];
+                e_next[i] = entry_at(b0 + 2u * (uint32_t)B, i);
+            }
         }
-        if (chunk != kNoChunk) {
-            for (int j = tid; j < cnt; j += kLanes) chunks[(int64_t)chunk * B + j] = s_ent[j];
-            if (tid == 0) links[chunk] = make_uint2(prev, (ordinal << 9) | (uint32_t)cnt);
-            prev = chunk;
-        }
-        bool blended = false;
+        __syncthreads();
         // the next entry's LDS reads are issued before the current entry is
         // processed, so a wave running alone does not wait on them
         float4 Gn = s_geo[0], Xn = s_aux[0], Cn = s_col[0];
@@ -315,7 +274,7 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
             Cn = s_col[jn];
             const LaneTerms L = lane_terms(G, X, px, col, row0);
             const uint32_t m = L.m & live;
-            const uint32_t pos = listed + (uint32_t)j + 1u;
+            const uint32_t pos = b0 - start + (uint32_t)j + 1u;
             n_eval += (uint32_t)__builtin_popcount(live);
 #pragma unroll
             for (int k = 0; k < PIX; ++k) {
@@ -334,34 +293,10 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
                     T[k] = stop ? T[k] : tn;
                     last[k] = stop ? last[k] : pos;
                     n_blend += stop ? 0u : 1u;
-                    blended |= !stop;
                     live &= stop ? ~(1u << (RS * k)) : ~0u;
                 }
             }
         }
-        if (ballot(blended) != 0) head = chunk;
-        listed += (uint32_t)cnt;
-        ordinal += 1;
-        // the entries past the batch move to the front of the queue (fewer
-        // than one walk step)
-        const int rem = (int)qn - cnt;
-        float4 g = make_float4(0.f, 0.f, 0.f, 0.f), a = g, cc = g;
-        uint32_t en = 0;
-        if (tid < rem) {
-            g = s_geo[cnt + tid];
-            a = s_aux[cnt + tid];
-            cc = s_col[cnt + tid];
-            en = s_ent[cnt + tid];
-        }
-        __syncthreads();
-        if (tid < rem) {
-            s_geo[tid] = g;
-            s_aux[tid] = a;
-            s_col[tid] = cc;
-            s_ent[tid] = en;
-        }
-        __syncthreads();
-        qn = (uint32_t)rem;
     }
 
     const int64_t plane = (int64_t)V.width * V.height;
@@ -384,19 +319,53 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
 #pragma unroll
     for (int k = 0; k < PIX; ++k) my_last = max(my_last, last[k]);
     const uint32_t tile_last = wave_max_u32(my_last);
-    // work counters: one atomic each per tile
+    // work counters per tile, summed by a small kernel after the launch
+    // (atomics of every tile on the one counters line serialise across the
+    // chip and would lengthen the launch by a fifth)
     const uint32_t nb = wave_add_u32(n_blend), ne2 = wave_add_u32(n_eval);
     if (tid == 0) {
         tile_cost[tile] = tile_last;
-        // a tile whose list did not fit the chunk storage has no usable list
-        tile_head[tile] = overflow ? kNoChunk : head;
-        if (overflow) atomicOr(&counters[kStatus], SGS_STATUS_PAIR_OVERFLOW);
-        atomicAdd(&counters[kListed], listed);
-        atomicAdd(&counters[kWalked], walked);
-        atomicAdd(reinterpret_cast<unsigned long long*>(counters + kBlended),
-                  (unsigned long long)nb);
-        atomicAdd(reinterpret_cast<unsigned long long*>(counters + kEvaluated),
-                  (unsigned long long)ne2);
+        tile_stats[2 * tile] = nb;
+        tile_stats[2 * tile + 1] = ne2;
+    }
+}
+
+// counters[kBlended], [kEvaluated] (uint64) and [kUsed] (saturating uint32)
+// from the per-tile work of the last compositing forward.
+constexpr int kStatThreads = 1024;
+__global__ void __launch_bounds__(kStatThreads) sum_tile_stats_kernel(
+    const uint32_t* __restrict__ tile_stats, const uint32_t* __restrict__ tile_cost,
+    int64_t tiles, uint32_t* __restrict__ counters) {
+    __shared__ unsigned long long s_sum[3][kStatThreads / 64];
+    unsigned long long b = 0, e = 0, u = 0;
+    for (int64_t t = threadIdx.x; t < tiles; t += kStatThreads) {
+        b += tile_stats[2 * t];
+        e += tile_stats[2 * t + 1];
+        u += tile_cost[t];
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        b += __shfl_xor(b, d, 64);
+        e += __shfl_xor(e, d, 64);
+        u += __shfl_xor(u, d, 64);
+    }
+    const int w = threadIdx.x / 64;
+    if (threadIdx.x % 64 == 0) {
+        s_sum[0][w] = b;
+        s_sum[1][w] = e;
+        s_sum[2][w] = u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        b = e = u = 0;
+        for (int k = 0; k < kStatThreads / 64; ++k) {
+            b += s_sum[0][k];
+            e += s_sum[1][k];
+            u += s_sum[2][k];
+        }
+        reinterpret_cast<unsigned long long*>(counters + kBlended)[0] = b;
+        reinterpret_cast<unsigned long long*>(counters + kEvaluated)[0] = e;
+        counters[kUsed] = (uint32_t)min(u, 0xffffffffull);
     }
 }
 
@@ -416,12 +385,12 @@ constexpr int backward_waves(int batch) { return batch <= 64 ? 7 : (batch == 128
 
 template <int TW, int TH, int B>
 __global__ void __launch_bounds__(kLanes, backward_waves(B)) raster_backward_kernel(
-    const Views* __restrict__ views, RasterDev rp, const uint32_t* __restrict__ chunks,
-    const uint2* __restrict__ links, const uint32_t* __restrict__ tile_head,
-    const float4* __restrict__ rec, const float* __restrict__ t_final,
-    const uint32_t* __restrict__ n_last, const float* __restrict__ dl_drgb,
-    const int32_t* __restrict__ gate, float* __restrict__ accum, const uint32_t* __restrict__ order,
-    int total_tiles, uint32_t chunk_capacity, uint32_t entries) {
+    const Views* __restrict__ views, RasterDev rp, const uint32_t* __restrict__ tile_ranges,
+    const uint32_t* __restrict__ tile_entry, const float4* __restrict__ rec,
+    const float* __restrict__ t_final, const uint32_t* __restrict__ n_last,
+    const float* __restrict__ dl_drgb, const int32_t* __restrict__ gate,
+    float* __restrict__ accum, const uint32_t* __restrict__ order, int total_tiles,
+    uint32_t entries) {
     constexpr int PIX = TW * TH / kLanes;
     constexpr int RS = kLanes / TW;
     __shared__ float4 s_geo[B];
@@ -465,18 +434,17 @@ __global__ void __launch_bounds__(kLanes, backward_waves(B)) raster_backward_ker
         GS[k] = fmaf(G0[k], rp.bg[0], fmaf(G1[k], rp.bg[1], G2[k] * rp.bg[2])) * T[k];
         my_max = max(my_max, last[k]);
     }
-    const uint32_t stop = wave_max_u32(my_max);
+    const uint32_t start = tile_ranges[2 * tile], end = tile_ranges[2 * tile + 1];
+    const uint32_t stop = min(wave_max_u32(my_max), end - start);
 
-    // the tile's list chunks from the one holding its last blended position
-    // towards the front; chunk k holds list positions [k B, k B + count)
-    for (uint32_t ch = tile_head[tile]; ch < chunk_capacity;) {
-        const uint2 lk = links[ch];
-        const uint32_t b0 = (lk.y >> 9) * (uint32_t)B;
-        const uint32_t b_end = min(b0 + (lk.y & 511u), stop);
-        const int cnt = b_end > b0 ? (int)(b_end - b0) : 0;
+    // the list from the last blended position towards the front, B entries
+    // at a time (list positions [b0, b_end), staged last first)
+    for (uint32_t b_end = stop; b_end > 0u;) {
+        const uint32_t b0 = b_end > (uint32_t)B ? b_end - (uint32_t)B : 0u;
+        const int cnt = (int)(b_end - b0);
         __syncthreads();
         for (int k = tid; k < cnt; k += kLanes) {
-            const uint32_t e = min(chunks[(int64_t)ch * B + (cnt - 1 - k)], entries - 1u);
+            const uint32_t e = min(tile_entry[start + b_end - 1u - (uint32_t)k], entries - 1u);
             const float4 r0 = rec[3 * (int64_t)e], r1 = rec[3 * (int64_t)e + 1],
                          r2 = rec[3 * (int64_t)e + 2];
             stage_entry(r0, r1, tx * TW, ty * TH, TW, TH, s_geo[k], s_aux[k]);
@@ -553,8 +521,7 @@ __global__ void __launch_bounds__(kLanes, backward_waves(B)) raster_backward_ker
                 unsafeAtomicAdd(accum + (int64_t)kAccumFloats * __float_as_uint(s_col[j].w) + tid,
                                 tid == 8 ? t8 : t);
         }
-        // a chunk's predecessor was handed out before it: the walk ends
-        ch = lk.x < ch ? lk.x : kNoChunk;
+        b_end = b0;
     }
 }
 
@@ -594,22 +561,21 @@ hipError_t launch_rasterize(const RasterDev& rp, const Layout& L, char* ws, floa
                             hipStream_t s) {
     if (L.total_tiles == 0) return hipSuccess;
     const Views* views = reinterpret_cast<const Views*>(ws + L.views);
-    const uint32_t* ranges = reinterpret_cast<const uint32_t*>(ws + L.sup_ranges);
-    const uint32_t* skey = reinterpret_cast<const uint32_t*>(ws + L.pair_key[L.key_result]);
-    const uint32_t* sentry = reinterpret_cast<const uint32_t*>(ws + L.pair_entry[L.key_result]);
+    const uint32_t* ranges = reinterpret_cast<const uint32_t*>(ws + L.tile_ranges);
+    const uint32_t* entry = reinterpret_cast<const uint32_t*>(ws + L.tile_entry);
     const float4* rec = reinterpret_cast<const float4*>(ws + L.records);
     float* tf = reinterpret_cast<float*>(ws + L.t_final);
     uint32_t* nl = reinterpret_cast<uint32_t*>(ws + L.n_last);
     uint32_t* cnt = reinterpret_cast<uint32_t*>(ws + L.counters);
     uint32_t* cost = reinterpret_cast<uint32_t*>(ws + L.tile_cost);
-    uint32_t* chunks = reinterpret_cast<uint32_t*>(ws + L.chunks);
-    uint2* links = reinterpret_cast<uint2*>(ws + L.links);
-    uint32_t* head = reinterpret_cast<uint32_t*>(ws + L.tile_head);
-    const uint32_t cap = (uint32_t)L.chunk_capacity;
+    uint32_t* stats = reinterpret_cast<uint32_t*>(ws + L.tile_stats);
+    const uint32_t entries = (uint32_t)std::max<int64_t>(1, L.entries);
     const dim3 grid((unsigned)L.total_tiles), block(kLanes);
-    SGS_RASTER_DISPATCH(raster_forward_kernel, views, rp, ranges, skey, sentry, rec, out_rgb, tf, nl, cnt,
-                        cost, chunks, links, head, cap, (uint32_t)L.capacity,
-                        (uint32_t)L.entries);
+    SGS_RASTER_DISPATCH(raster_forward_kernel, views, rp, ranges, entry, rec, out_rgb, tf, nl,
+                        stats, cost, entries);
+    if (hipError_t err = hipGetLastError(); err != hipSuccess) return err;
+    hipLaunchKernelGGL(sum_tile_stats_kernel, dim3(1), dim3(kStatThreads), 0, s, stats, cost,
+                       L.total_tiles, cnt);
     return hipGetLastError();
 }
 
@@ -622,9 +588,8 @@ hipError_t launch_rasterize_backward(const RasterDev& rp, const Layout& L, char*
                            s, reinterpret_cast<float4*>(acc), n4, gate);
     if (L.total_tiles == 0 || L.entries == 0) return hipGetLastError();
     const Views* views = reinterpret_cast<const Views*>(ws + L.views);
-    const uint32_t* chunks = reinterpret_cast<const uint32_t*>(ws + L.chunks);
-    const uint2* links = reinterpret_cast<const uint2*>(ws + L.links);
-    const uint32_t* head = reinterpret_cast<const uint32_t*>(ws + L.tile_head);
+    const uint32_t* ranges = reinterpret_cast<const uint32_t*>(ws + L.tile_ranges);
+    const uint32_t* entry = reinterpret_cast<const uint32_t*>(ws + L.tile_entry);
     const float4* rec = reinterpret_cast<const float4*>(ws + L.records);
     const float* tf = reinterpret_cast<const float*>(ws + L.t_final);
     const uint32_t* nl = reinterpret_cast<const uint32_t*>(ws + L.n_last);
@@ -637,9 +602,8 @@ hipError_t launch_rasterize_backward(const RasterDev& rp, const Layout& L, char*
         return err;
     const int tiles = (int)L.total_tiles;
     const dim3 grid((unsigned)L.total_tiles), block(kLanes);
-    SGS_RASTER_DISPATCH(raster_backward_kernel, views, rp, chunks, links, head, rec, tf, nl,
-                        dl_drgb, gate, acc, order, tiles, (uint32_t)L.chunk_capacity,
-                        (uint32_t)L.entries);
+    SGS_RASTER_DISPATCH(raster_backward_kernel, views, rp, ranges, entry, rec, tf, nl, dl_drgb,
+                        gate, acc, order, tiles, (uint32_t)L.entries);
     return hipGetLastError();
 }
 

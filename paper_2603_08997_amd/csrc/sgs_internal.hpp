@@ -74,9 +74,9 @@ enum Counter : int {
     kBlended = 4,       // uint64 at words 4-5: blended (pixel, Gaussian) pairs of the last rasterize
     kEvaluated = 6,     // uint64 at words 6-7: (pixel, list entry) pairs the forward examined
     kPairsKept = 8,     // super-tile pairs left after the reach test (length of the sorted lists)
-    kChunks = 9,        // list chunks the forward asked for (saturating)
-    kListed = 10,       // tile-list entries the forward listed (its compositing batches)
-    kWalked = 11,       // super-tile list entries the forward examined for its tiles
+    kItems = 9,         // tile-list entries needed (saturating)
+    kSegments = 10,     // super-tile list segments of the tile-list split
+    kUsed = 11,         // tile-list entries up to each tile's last blended one (summed)
     kNumCounters = 16
 };
 
@@ -84,13 +84,12 @@ enum Counter : int {
 // below 2^key_bits - 1, so that no key has all bits set), and above them the
 // entry's tile rectangle inside the super-tile, four coordinates of
 // rect_bits bits (first column, last column, first row, last row, relative to
-// the super-tile). Only the index is sorted on; the rectangle rides along, so
-// the compositing forward tests a list entry against its tile without
-// reading the entry's record. The key of an emitted pair whose Gaussian
-// cannot reach alpha_min on the super-tile has all bits set; the first pass
-// of the super-tile sort drops such pairs.
+// the super-tile). Only the index is sorted on; the rectangle rides along to
+// the split of the super-tile lists into tile lists. The key of an emitted
+// pair whose Gaussian cannot reach alpha_min on the super-tile has all bits
+// set; the first pass of the super-tile sort drops such pairs.
 constexpr uint32_t kCulledTile = 0xffffffffu;
-constexpr uint32_t kNoChunk = 0xffffffffu;
+constexpr int kMaxSuperTile = 8;   // S x S tiles of a super-tile fit a 64-bit tile mask
 
 // Emission units: each visible Gaussian (in depth order) owns kEmitHead
 // header units followed by one unit per pair; a workgroup of the emission
@@ -103,22 +102,25 @@ constexpr int64_t emit_windows(int64_t entries, int64_t capacity) {
     return (capacity + kEmitHead * entries + kEmitWindow - 1) / kEmitWindow;
 }
 
-// Tile lists are recorded by the compositing forward in chunks of `batch`
-// entry indices: the list storage holds pair_capacity entries plus one
-// partly filled chunk per tile.
-constexpr int64_t list_chunks(int64_t capacity, int64_t tiles, int batch) {
-    return (capacity + batch - 1) / batch + tiles;
+// The split of the super-tile lists into tile lists works on segments of
+// kSegPairs consecutive pairs of one super-tile's list (a super-tile of L
+// pairs has ceil(L / kSegPairs) segments). Segment slots: an upper bound on
+// the number of segments of any batch with `capacity` pairs.
+constexpr int64_t kSegPairs = 512;
+constexpr int64_t segment_slots(int64_t capacity, int64_t supers) {
+    return (capacity + kSegPairs - 1) / kSegPairs + supers;
 }
 
 struct Layout {
-    int64_t entries, total_tiles, total_pixels, total_supers, capacity, chunk_capacity;
+    int64_t entries, total_tiles, total_pixels, total_supers, capacity, seg_slots;
     int n_views;
     int64_t scan_blocks, sort_blocks;
     int key_bits, rect_bits, key_passes, key_result;  // result buffer (0/1) of the super-tile sort
     int batch;
     size_t views, records, tiles, depth, dkey[2], dval[2], offsets, window_first, scan_sums,
-        pair_key[2], pair_entry[2], sort_hist, sort_totals, sup_ranges, chunks, links, tile_head,
-        tile_cost, tile_order, t_final, n_last, accum, counters, total;
+        pair_key[2], pair_entry[2], sort_hist, sort_totals, sup_ranges, seg_first, seg_cnt,
+        seg_off, pair_mask, tile_entry, tile_ranges, tile_cost, tile_stats, tile_order, t_final,
+        n_last, accum, counters, total;
 };
 
 bool make_views(const sgs_camera* cams, int n_views, const sgs_raster_params* rp, Views* out,

@@ -51,10 +51,10 @@ class RasterParamsC(C.Structure):
 
 class WorkspaceLayoutC(C.Structure):
     _fields_ = [(k, C.c_size_t) for k in ("records", "tiles", "depth", "sup_key", "sup_entry",
-                                            "sup_ranges", "chunks", "links", "tile_head",
+                                            "sup_ranges", "tile_entry", "tile_ranges",
                                             "t_final", "n_last", "accum", "counters")] + \
                [(k, C.c_int64) for k in ("entries", "total_tiles", "total_pixels",
-                                         "total_supers", "chunk_capacity")] + \
+                                         "total_supers")] + \
                [("key_bits", C.c_int32), ("rect_bits", C.c_int32), ("batch", C.c_int32),
                 ("super_tile", C.c_int32)]
 
@@ -322,16 +322,17 @@ def read_status(workspace, stream=None):
 
 def read_counters(workspace, stream=None) -> dict:
     """Synchronises and reads the workspace counters (offset 0): status bits,
-    visible entries, pairs, and the blended / examined (pixel, Gaussian)
-    pairs of the last bin + rasterize."""
+    visible entries, super-tile pairs (needed, written, kept), tile-list
+    entries (needed; up to each tile's last blend), list segments, and the
+    blended / examined (pixel, Gaussian) pairs of the last bin + rasterize."""
     s = torch.cuda.current_stream() if stream is None else stream
     s.synchronize()
     w = workspace[:64].cpu().numpy().view(np.uint32)
     u64 = lambda i: int(w[i]) | (int(w[i + 1]) << 32)
     return {"status": int(w[0]), "visible": int(w[1]), "pairs": int(w[2]),
             "pairs_written": int(w[3]), "blended": u64(4), "evaluated": u64(6),
-            "pairs_kept": int(w[8]), "chunks": int(w[9]), "listed": int(w[10]),
-            "walked": int(w[11])}
+            "pairs_kept": int(w[8]), "items": int(w[9]), "segments": int(w[10]),
+            "used": int(w[11])}
 
 
 def clear_status(workspace, stream=None):

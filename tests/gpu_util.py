@@ -100,32 +100,13 @@ class GpuRender:
         return region(self.ws, self.L.accum, 12 * self.L.entries, np.float32).reshape(-1, 12)
 
 
-NO_CHUNK = 0xFFFFFFFF
-
-
-def recorded_tile_lists(ws: torch.Tensor, L) -> dict:
-    """The tile lists the compositing forward recorded in the workspace: for
-    every tile whose pixels blended something, the entry indices of its list
-    chunks from the first up to the one holding its last blended position,
-    in list order (tile -> int64 array)."""
-    head = region(ws, L.tile_head, L.total_tiles, np.uint32)
-    used = int(min(L.chunk_capacity, max(0, int(region(ws, L.counters, 16, np.uint32)[9]))))
-    links = region(ws, L.links, 2 * used, np.uint32).reshape(-1, 2)
-    chunks = region(ws, L.chunks, used * L.batch, np.uint32).reshape(-1, L.batch)
-    out = {}
-    for t in np.nonzero(head != NO_CHUNK)[0]:
-        parts, c, expect = [], int(head[t]), None
-        while c != NO_CHUNK:
-            prev, info = int(links[c, 0]), int(links[c, 1])
-            ordinal, count = info >> 9, info & 511
-            assert expect is None or ordinal == expect, "chunk ordinals must descend by one"
-            assert count == L.batch or not parts, "only the last chunk may be partly filled"
-            parts.append(chunks[c, :count].astype(np.int64))
-            expect = ordinal - 1
-            c = prev
-        assert expect == -1, "the chunk chain must reach the tile's first chunk"
-        out[int(t)] = np.concatenate(parts[::-1])
-    return out
+def tile_lists(ws: torch.Tensor, L) -> dict:
+    """The tile lists binning left in the workspace: tile -> entry indices
+    (int64) in list order, for every tile with a non-empty list."""
+    rg = region(ws, L.tile_ranges, 2 * L.total_tiles, np.uint32).reshape(-1, 2).astype(np.int64)
+    end = int(rg[:, 1].max()) if len(rg) else 0
+    ent = region(ws, L.tile_entry, end, np.uint32).astype(np.int64)
+    return {int(t): ent[rg[t, 0]:rg[t, 1]] for t in np.nonzero(rg[:, 1] > rg[:, 0])[0]}
 
 
 def last_blended(lists: dict, n_last: np.ndarray, tiles: np.ndarray) -> np.ndarray:

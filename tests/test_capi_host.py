@@ -142,13 +142,10 @@ def test_layout_regions_fit_and_do_not_overlap():
     # super-tile index bits (2^bits > 8 super-tiles) and 2 bits per rectangle coordinate
     assert (L.key_bits, L.rect_bits) == (4, 2)
     assert (L.batch, L.super_tile) == (128, 3)
-    # list storage: the capacity in chunks plus one partly filled chunk per tile
-    assert L.chunk_capacity == (30_000 + 127) // 128 + L.total_tiles
     regions = sorted([(L.records, 48 * 1000), (L.tiles, 4 * 1000), (L.depth, 4 * 1000),
                       (L.sup_key, 4 * 30_000), (L.sup_entry, 4 * 30_000),
                       (L.sup_ranges, 8 * L.total_supers),
-                      (L.chunks, 4 * L.batch * L.chunk_capacity), (L.links, 8 * L.chunk_capacity),
-                      (L.tile_head, 4 * L.total_tiles),
+                      (L.tile_entry, 4 * 30_000), (L.tile_ranges, 8 * L.total_tiles),
                       (L.t_final, 4 * L.total_pixels), (L.n_last, 4 * L.total_pixels),
                       (L.accum, 48 * 1000), (L.counters, 64)])
     for (o1, s1), (o2, _) in zip(regions, regions[1:]):
@@ -157,16 +154,20 @@ def test_layout_regions_fit_and_do_not_overlap():
     assert all(o % 256 == 0 for o, _ in regions)
 
 
-def test_super_tiles_must_fit_the_pair_key():
-    """16 views of 2048x2048 in 8x8 tiles, super-tiles of 64 tiles: 24 bits of
-    rectangle leave too few bits for the 256 super-tile indices."""
+def test_super_tile_sizes():
+    """Super-tiles of 1 to 8 tiles (a tile mask per pair fits 64 bits); the
+    pair key fits 32 bits up to the 2^24-tile batch limit (16 views of
+    2048x2048 in 8x8 tiles: 2^20 tiles)."""
     sg = _lib()
     cams = [_cam(2048, 2048)] * 16
-    with pytest.raises(sg.SkipGSError) as e:
-        sg.forward_workspace_size(sg.RasterParams(tile_w=8, tile_h=8, super_tile=64), 10, cams,
-                                  1000)
-    assert e.value.status == 2 and "pair key" in str(e.value)
-    sg.forward_workspace_size(sg.RasterParams(tile_w=8, tile_h=8, super_tile=8), 10, cams, 1000)
+    for S_ in range(1, 9):
+        L = sg.get_workspace_layout(sg.RasterParams(tile_w=8, tile_h=8, super_tile=S_), 10, cams,
+                                    1000)
+        assert L.key_bits + 4 * L.rect_bits <= 32 and L.super_tile == S_
+    for S_ in (9, 16, 64):
+        with pytest.raises(sg.SkipGSError) as e:
+            sg.forward_workspace_size(sg.RasterParams(super_tile=S_), 10, cams[:1], 1000)
+        assert e.value.status == 2 and "super_tile" in str(e.value)
 
 
 def test_struct_sizes_are_checked():

@@ -30,7 +30,7 @@ from oracle import grad as G
 from oracle import render as R
 from paper_2603_08997_amd import scenes as S
 
-from .gpu_util import (last_blended, recorded_tile_lists, region, rel_max_err, rel_norm_err,
+from .gpu_util import (last_blended, tile_lists, region, rel_max_err, rel_norm_err,
                        require_gpu, say, sg, to_dev)
 from .sensitivity import decision_sensitive
 
@@ -62,8 +62,9 @@ CONFIGS = ["n1M_1245x825", "n3M_1600x1060", "dense6M_1600x1060", "n2M_batched8"]
 
 
 class FullRender:
-    """Forward of one configuration with a pair capacity sized by a probe
-    launch (the forward reports the pair count it needed)."""
+    """Forward of one configuration with a pair capacity sized by probe
+    launches (a forward reports the capacity it needed: first the super-tile
+    pairs, then, with those stored, the tile-list entries)."""
 
     def __init__(self, name):
         m = sg()
@@ -74,12 +75,16 @@ class FullRender:
         self.planes = to_dev(self.scene.to_planes())
         self.px = sum(c.width * c.height for c in self.cams)
         self.rgb = torch.zeros(3 * self.px, dtype=torch.float32, device="cuda")
-        probe = 1 << 16
-        ws = m.alloc_bytes(m.forward_workspace_size(self.rp, self.n, self.cams, probe)).zero_()
-        m.render_forward(self.planes, self.n, 3, self.cams, self.rp, ws, probe, self.rgb)
-        _, _, pairs = m.read_status(ws)
-        del ws
-        self.cap = int(pairs * 1.02) + 4096
+        cap = 1 << 16
+        for _ in range(3):
+            ws = m.alloc_bytes(m.forward_workspace_size(self.rp, self.n, self.cams, cap)).zero_()
+            m.render_forward(self.planes, self.n, 3, self.cams, self.rp, ws, cap, self.rgb)
+            flags, _, pairs = m.read_status(ws)
+            del ws
+            if not flags & m.STATUS_PAIR_OVERFLOW:
+                break
+            cap = int(pairs * 1.02) + 4096
+        self.cap = cap
         self.ws = m.alloc_bytes(m.forward_workspace_size(self.rp, self.n, self.cams, self.cap))
         self.ws.zero_()
         self.L = m.get_workspace_layout(self.rp, self.n, self.cams, self.cap)
@@ -92,7 +97,7 @@ class FullRender:
         self.rgb_np = self.rgb.cpu().numpy()
         self.tf = region(self.ws, self.L.t_final, self.L.total_pixels, np.float32)
         self.nl = region(self.ws, self.L.n_last, self.L.total_pixels, np.uint32)
-        self.lists = recorded_tile_lists(self.ws, self.L)
+        self.lists = tile_lists(self.ws, self.L)
         # per entry: projected centre and overlap box (0 where not visible)
         rec = region(self.ws, self.L.records, 12 * self.L.entries, np.float32).reshape(-1, 12)
         vis = region(self.ws, self.L.tiles, self.L.entries, np.uint32) != 0

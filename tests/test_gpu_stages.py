@@ -1,15 +1,15 @@
-"""Stage parity on identical float32 records: super-tile binning and sort
-(bit exact without the reach test, an ordered subsequence keeping every
-contributing entry with it), the tile lists the compositing forward records,
-compositing forward (1e-5) and backward (1e-3) against the oracle, with only
-pixels the oracle itself calls decision-sensitive left out."""
+"""Stage parity on identical float32 records: super-tile binning and sort and
+the tile lists split from it (bit exact without the reach test; with it, an
+ordered subsequence keeping every contributing entry), compositing forward
+(1e-5) and backward (1e-3) against the oracle, with only pixels the oracle
+itself calls decision-sensitive left out."""
 import numpy as np
 import pytest
 import torch
 
 from oracle import render as R
 from paper_2603_08997_amd import scenes as S
-from tests.gpu_util import (last_blended, recorded_tile_lists, region, rel_max_err, rel_norm_err,
+from tests.gpu_util import (last_blended, tile_lists, region, rel_max_err, rel_norm_err,
                             require_gpu, say, sg, split_views, to_dev)
 from tests.sensitivity import decision_sensitive
 
@@ -41,7 +41,7 @@ class Stage:
         m.bin(cams, n, rp, self.ws, capacity)
         self.flags, self.vis, self.pairs = m.read_status(self.ws)
         cnt = m.read_counters(self.ws)
-        self.kept, self.needed = cnt["pairs_kept"], cnt["pairs"]
+        self.kept, self.needed, self.items = cnt["pairs_kept"], cnt["pairs"], cnt["items"]
 
     def lists(self):
         """The sorted super-tile lists: super-tile index, tile rectangle
@@ -182,6 +182,7 @@ def _check_binning(cams, tile, ties, n, seed, super_tile=8, alpha_min=None):
         assert np.array_equal(ents.astype(np.int64), vals)
         assert np.array_equal(granges.astype(np.int64), ranges)
         assert np.array_equal(st.rect, _oracle_rects(recs, cams, n, tw, th, super_tile, sups, vals))
+        _check_tile_lists(st, recs, cams, n, tw, th, 0.0)
         return st
     # the GPU lists are the box lists less entries that cannot reach
     # alpha_min on the super-tile: per super-tile, an ordered subsequence of
@@ -211,7 +212,44 @@ def _check_binning(cams, tile, ties, n, seed, super_tile=8, alpha_min=None):
     say(f"  super-tile pairs {len(vals)}, kept {len(ents)}, non-contributing {dead}, "
         f"dropped {dropped}")
     assert dropped >= 0.3 * dead
+    _check_tile_lists(st, recs, cams, n, tw, th, rp.alpha_min)
     return st
+
+
+def _check_tile_lists(st, recs, cams, n, tw, th, alpha_min):
+    """The tile lists split from the super-tile lists: without the reach test
+    the oracle's tile lists bit for bit; with it, per tile, an ordered
+    subsequence of the oracle's list keeping every entry that can contribute
+    to a pixel of the tile."""
+    lists = tile_lists(st.ws, st.L)
+    olists = _oracle_tile_lists(recs, cams, n, tw, th)
+    orp = R.RasterParams(tile_w=tw, tile_h=th, alpha_min=alpha_min)
+    assert st.items == sum(len(x) for x in lists.values())
+    toff, dropped, dead = 0, 0, 0
+    empty = np.zeros(0, np.int64)
+    for v, (rec, cam) in enumerate(zip(recs, cams)):
+        tx_n = (cam.width + tw - 1) // tw
+        for t in range(toff, toff + _tiles_of(cam, tw, th)):
+            ol, gl = olists[t], lists.get(t, empty)
+            if alpha_min == 0.0:
+                assert np.array_equal(gl, ol), t
+                continue
+            keep = np.isin(ol, gl)
+            assert np.array_equal(ol[keep], gl), t
+            tx, ty = (t - toff) % tx_n, (t - toff) // tx_n
+            for e, kept in zip(ol, keep):
+                i = e - v * n
+                live = R.tile_contributes(rec["u"][i], rec["v"][i], *rec["conic"][i],
+                                          rec["opacity"][i], *rec["extent"][i], tx, ty, tw, th,
+                                          cam.width, cam.height, orp)
+                assert kept or not live, (t, e)
+                dead += int(not live)
+                dropped += int(not kept)
+        toff += _tiles_of(cam, tw, th)
+    say(f"  tile-list entries {st.items}, non-contributing {dead}, dropped {dropped}")
+    if alpha_min > 0.0:
+        assert dropped >= 0.3 * dead
+    return lists
 
 
 def test_binning_empty_and_capacity_overflow():
@@ -233,34 +271,29 @@ def test_binning_empty_and_capacity_overflow():
     assert st.pairs > 64
 
 
-def test_list_storage_overflow_keeps_the_image():
-    """Enough super-tile pairs but too little list storage (super-tiles of
-    16x16 small tiles hold few pairs while the tile lists are long): the
-    forward flags the overflow, reports the capacity it needed, and still
-    composites every pixel right (the lists it could not record only matter
-    to the backward)."""
+def test_tile_list_overflow():
+    """Capacity for the super-tile pairs but not for the tile lists (super-
+    tiles of 8x8 small tiles hold few pairs while the tile lists are long):
+    binning flags the overflow and reports the capacity the lists need; with
+    that capacity the image equals the one rendered with ample storage."""
     require_gpu()
     m = sg()
     cams = [S.look_at_camera((3.0, 1.0, 1.0), 255, 255)]
     n = 20000
     recs, cat = _records(n, cams, 21, max_radius=24)
-    rp = m.RasterParams(tile_w=8, tile_h=8, super_tile=16, lds_batch=32)
+    rp = m.RasterParams(tile_w=8, tile_h=8, super_tile=8, lds_batch=32)
     probe = Stage(n, cams, rp, cat, 400_000)
     rgb_ref, _, _ = probe.rasterize()
     assert probe.flags == 0
-    lists = recorded_tile_lists(probe.ws, probe.L)
-    chunks_needed = sum((len(x) + 31) // 32 for x in lists.values())
-    tiles = probe.L.total_tiles
-    need_pairs = probe.needed
-    # the largest capacity that still holds the pairs but not the chunks
-    cap = need_pairs
-    assert (cap + 31) // 32 + tiles < chunks_needed, (need_pairs, tiles, chunks_needed)
-    st = Stage(n, cams, rp, cat, cap)
-    assert st.flags == 0          # the pairs fit
-    rgb, _, _ = st.rasterize()
+    assert probe.needed < probe.items, (probe.needed, probe.items)
+    st = Stage(n, cams, rp, cat, probe.needed)
     assert st.flags & m.STATUS_PAIR_OVERFLOW
+    assert st.pairs == probe.items
+    assert not tile_lists(st.ws, st.L)          # no partial lists
+    st = Stage(n, cams, rp, cat, st.pairs)
+    rgb, _, _ = st.rasterize()
+    assert st.flags == 0
     assert np.array_equal(rgb, rgb_ref)
-    assert m.read_status(st.ws)[2] >= m.read_counters(probe.ws)["listed"]
 
 
 def _oracle_composite(rec, cam, rp, n, view, leaf=False):
@@ -303,18 +336,7 @@ def _check_raster(tile, super_tile=8, lds_batch=64, **params):
     rgb, tf, nl = st.rasterize()
     assert st.flags == 0
     orp = R.RasterParams(tile_w=tw, tile_h=th, bg=bg, **params)
-    lists = recorded_tile_lists(st.ws, st.L)
-    olists = _oracle_tile_lists(recs, cams, n, tw, th)
-    # recorded lists: a prefix of the tile's oracle list (bit-exact without
-    # the reach test; otherwise an ordered subsequence that keeps every entry
-    # able to contribute within the recorded span)
-    for t, glist in lists.items():
-        ol = olists[t]
-        if orp.alpha_min == 0:
-            assert np.array_equal(glist, ol[:len(glist)]), t
-        else:
-            keep = np.isin(ol, glist)
-            assert np.array_equal(ol[keep], glist), t
+    lists = _check_tile_lists(st, recs, cams, n, tw, th, orp.alpha_min)
     rng = np.random.default_rng(5)
     dls, excl_total = [], 0
     toff = 0
