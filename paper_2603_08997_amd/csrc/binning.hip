@@ -550,6 +550,7 @@ __device__ __forceinline__ uint64_t wave_transpose64(uint64_t x) {
 }
 
 constexpr int kSplitWaves = 4;
+constexpr int64_t kSplitBlocks = 2048;   // blocks of the split kernels' grid-stride loops
 
 // Reach of one entry by rows: q = a dx^2 + 2 b dx dy + c dy^2 <= lim is, for
 // dy fixed, the interval |dx - s dy| <= sqrt((lim - k dy^2) / a) (s = -b/a,
@@ -635,54 +636,57 @@ __global__ void __launch_bounds__(kSplitWaves * 64) split_count_kernel(
     uint64_t* __restrict__ mask, uint32_t* __restrict__ seg_cnt) {
     const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int S = rp.super_tile, TT = S * S;
-    Segment sg;
-    if (!locate_segment(views, seg_first, sup_ranges, S, blockIdx.x * kSplitWaves + w, &sg))
-        return;   // uniform across the wave
-    const ViewDev& V = *sg.V;
-    const int rb = rp.rect_bits;
-    const uint32_t rmask = (1u << rb) - 1u;
-    const bool reach = rp.alpha_min > 0.f;
-    const int tw_log2 = __builtin_ctz((unsigned)rp.tile_w);
-    const float inv_th = 1.f / (float)rp.tile_h;
-    uint32_t cnt = 0;   // lane t: pairs of the segment on tile t
-    for (uint32_t p0 = sg.a; p0 < sg.b; p0 += 64) {
-        const uint32_t p = p0 + (uint32_t)lane;
-        const bool valid = p < sg.b;
-        const uint32_t r = valid ? skey[p] >> rp.key_bits : 0u;
-        const int x0 = (int)(r & rmask), x1 = (int)((r >> rb) & rmask);
-        const int y0 = (int)((r >> (2 * rb)) & rmask), y1 = (int)((r >> (3 * rb)) & rmask);
-        uint64_t M = 0;
-        if (valid && !reach) {
-            const uint64_t row = ((1ull << (x1 - x0 + 1)) - 1ull) << x0;
-            for (int y = y0; y <= y1; ++y) M |= row << (y * S);
-        } else if (valid) {
-            const int64_t e = min(sentry[p], entries - 1u);
-            const float4 g0 = rec[3 * e], g1 = rec[3 * e + 1];
-            const Reach R = make_reach(g0.z, g0.w, g1.x, reach_limit(g1.y, rp));
-            // only the rows the ellipse's height reaches
-            int ya = y0, yb = y1;
-            if (R.conic) {
-                const float top = fmaxf(floorf((g0.y - R.ym) * inv_th), -1e6f);
-                const float bot = fminf(floorf((g0.y + R.ym) * inv_th), 1e6f);
-                ya = max(ya, (int)top - sg.ty0 - 1);
-                yb = min(yb, (int)bot - sg.ty0 + 1);
+    // segments in a grid-stride loop (the grid is sized for the machine, not
+    // for the capacity's bound on the segment count)
+    for (uint32_t g = blockIdx.x * kSplitWaves + w;; g += gridDim.x * kSplitWaves) {
+        Segment sg;
+        if (!locate_segment(views, seg_first, sup_ranges, S, g, &sg)) return;   // uniform
+        const ViewDev& V = *sg.V;
+        const int rb = rp.rect_bits;
+        const uint32_t rmask = (1u << rb) - 1u;
+        const bool reach = rp.alpha_min > 0.f;
+        const int tw_log2 = __builtin_ctz((unsigned)rp.tile_w);
+        const float inv_th = 1.f / (float)rp.tile_h;
+        uint32_t cnt = 0;   // lane t: pairs of the segment on tile t
+        for (uint32_t p0 = sg.a; p0 < sg.b; p0 += 64) {
+            const uint32_t p = p0 + (uint32_t)lane;
+            const bool valid = p < sg.b;
+            const uint32_t r = valid ? skey[p] >> rp.key_bits : 0u;
+            const int x0 = (int)(r & rmask), x1 = (int)((r >> rb) & rmask);
+            const int y0 = (int)((r >> (2 * rb)) & rmask), y1 = (int)((r >> (3 * rb)) & rmask);
+            uint64_t M = 0;
+            if (valid && !reach) {
+                const uint64_t row = ((1ull << (x1 - x0 + 1)) - 1ull) << x0;
+                for (int y = y0; y <= y1; ++y) M |= row << (y * S);
+            } else if (valid) {
+                const int64_t e = min(sentry[p], entries - 1u);
+                const float4 g0 = rec[3 * e], g1 = rec[3 * e + 1];
+                const Reach R = make_reach(g0.z, g0.w, g1.x, reach_limit(g1.y, rp));
+                // only the rows the ellipse's height reaches
+                int ya = y0, yb = y1;
+                if (R.conic) {
+                    const float top = fmaxf(floorf((g0.y - R.ym) * inv_th), -1e6f);
+                    const float bot = fminf(floorf((g0.y + R.ym) * inv_th), 1e6f);
+                    ya = max(ya, (int)top - sg.ty0 - 1);
+                    yb = min(yb, (int)bot - sg.ty0 + 1);
+                }
+                for (int y = ya; y <= yb; ++y) {
+                    const int py0 = (sg.ty0 + y) * rp.tile_h;
+                    int c0, c1;
+                    band_columns(R, g0.x, g0.y, g1.z, g1.w, py0, min(rp.tile_h, V.height - py0),
+                                 tw_log2, V.width, &c0, &c1);
+                    c0 = max(c0 - sg.tx0, x0);
+                    c1 = min(c1 - sg.tx0, x1);
+                    if (c0 <= c1) M |= (((1ull << (c1 - c0 + 1)) - 1ull) << c0) << (y * S);
+                }
             }
-            for (int y = ya; y <= yb; ++y) {
-                const int py0 = (sg.ty0 + y) * rp.tile_h;
-                int c0, c1;
-                band_columns(R, g0.x, g0.y, g1.z, g1.w, py0, min(rp.tile_h, V.height - py0),
-                             tw_log2, V.width, &c0, &c1);
-                c0 = max(c0 - sg.tx0, x0);
-                c1 = min(c1 - sg.tx0, x1);
-                if (c0 <= c1) M |= (((1ull << (c1 - c0 + 1)) - 1ull) << c0) << (y * S);
-            }
+            if (valid) mask[p] = M;
+            // lane t counts the pairs of this step whose mask has tile t
+            cnt += (uint32_t)popc64(wave_transpose64(M));
         }
-        if (valid) mask[p] = M;
-        // lane t counts the pairs of this step whose mask has tile t
-        cnt += (uint32_t)popc64(wave_transpose64(M));
+        if (lane < TT)
+            seg_cnt[(size_t)seg_first[sg.s] * TT + (size_t)lane * sg.nseg + sg.k] = cnt;
     }
-    if (lane < TT)
-        seg_cnt[(size_t)seg_first[sg.s] * TT + (size_t)lane * sg.nseg + sg.k] = cnt;
 }
 
 // Stable scatter of one segment per wave into the tile lists, 64 pairs per
@@ -705,37 +709,39 @@ __global__ void __launch_bounds__(kWriteWaves * 64) split_write_kernel(
     __shared__ uint32_t s_pos[kWriteWaves][kStepItems];
     const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int S = rp.super_tile, TT = S * S;
-    Segment sg;
-    if (!locate_segment(views, seg_first, sup_ranges, S, blockIdx.x * kWriteWaves + w, &sg))
-        return;
     if ((int64_t)counters[kItems] > capacity) return;   // overflow: the tile lists stay empty
-    // lane t: next list position of tile t
-    uint32_t run = lane < TT ? seg_off[(size_t)seg_first[sg.s] * TT + (size_t)lane * sg.nseg + sg.k]
-                             : 0u;
-    for (uint32_t p0 = sg.a; p0 < sg.b; p0 += 64) {
-        const uint32_t p = p0 + (uint32_t)lane;
-        const bool valid = p < sg.b;
-        const uint64_t M = valid ? mask[p] : 0ull;
-        s_ent[w][lane] = valid ? sentry[p] : 0u;
-        uint64_t T = wave_transpose64(M);
-        const uint32_t cnt = (uint32_t)popc64(T);
-        const uint32_t incl = wave_incl_scan(cnt);
-        const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
-        if (total > (uint32_t)kStepItems) {
+    for (uint32_t g = blockIdx.x * kWriteWaves + w;; g += gridDim.x * kWriteWaves) {
+        Segment sg;
+        if (!locate_segment(views, seg_first, sup_ranges, S, g, &sg)) return;
+        // lane t: next list position of tile t
+        const size_t base = (size_t)seg_first[sg.s] * TT + sg.k;
+        uint32_t run = lane < TT ? seg_off[base + (size_t)lane * sg.nseg] : 0u;
+        for (uint32_t p0 = sg.a; p0 < sg.b; p0 += 64) {
+            const uint32_t p = p0 + (uint32_t)lane;
+            const bool valid = p < sg.b;
+            const uint64_t M = valid ? mask[p] : 0ull;
+            s_ent[w][lane] = valid ? sentry[p] : 0u;
+            uint64_t T = wave_transpose64(M);
+            const uint32_t cnt = (uint32_t)popc64(T);
+            const uint32_t incl = wave_incl_scan(cnt);
+            const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
+            if (total > (uint32_t)kStepItems) {
+                wave_lds_sync();
+                for (; T != 0ull; T &= T - 1ull) tile_entry[run++] = s_ent[w][__builtin_ctzll(T)];
+                wave_lds_sync();
+                continue;
+            }
             wave_lds_sync();
-            for (; T != 0ull; T &= T - 1ull) tile_entry[run++] = s_ent[w][__builtin_ctzll(T)];
+            // group the step's entries by tile, with their list positions
+            for (uint32_t o = incl - cnt; T != 0ull; T &= T - 1ull, ++o) {
+                s_item[w][o] = s_ent[w][__builtin_ctzll(T)];
+                s_pos[w][o] = run++;
+            }
             wave_lds_sync();
-            continue;
+            for (uint32_t i = (uint32_t)lane; i < total; i += 64)
+                tile_entry[s_pos[w][i]] = s_item[w][i];
+            wave_lds_sync();
         }
-        wave_lds_sync();
-        // group the step's entries by tile, with their list positions
-        for (uint32_t o = incl - cnt; T != 0ull; T &= T - 1ull, ++o) {
-            s_item[w][o] = s_ent[w][__builtin_ctzll(T)];
-            s_pos[w][o] = run++;
-        }
-        wave_lds_sync();
-        for (uint32_t i = (uint32_t)lane; i < total; i += 64) tile_entry[s_pos[w][i]] = s_item[w][i];
-        wave_lds_sync();
     }
 }
 
@@ -807,7 +813,9 @@ static hipError_t launch_split(const RasterDev& rp, const Layout& L, char* ws, h
     err = device_scan(SegCountSrc{ranges, L.total_supers}, FirstSink{seg_first}, L.total_supers,
                       sums, seg_first + L.total_supers, s);
     if (err != hipSuccess) return err;
-    const dim3 sgrid((unsigned)((L.seg_slots + kSplitWaves - 1) / kSplitWaves));
+    // grid-stride over the segments: at most a few resident waves per SIMD
+    const dim3 sgrid((unsigned)std::min<int64_t>((L.seg_slots + kSplitWaves - 1) / kSplitWaves,
+                                                 kSplitBlocks));
     const uint32_t entries = (uint32_t)std::max<int64_t>(1, L.entries);
     hipLaunchKernelGGL(split_count_kernel, sgrid, dim3(kSplitWaves * 64), 0, s, views, rp,
                        seg_first, ranges, skey, sentry, rec, entries, mask, seg_cnt);
@@ -816,7 +824,8 @@ static hipError_t launch_split(const RasterDev& rp, const Layout& L, char* ws, h
     err = device_scan(ItemCountSrc{seg_cnt, seg_first + L.total_supers, tt}, ItemOffSink{seg_off},
                       L.seg_slots * tt, sums, counters + kItems, s);
     if (err != hipSuccess) return err;
-    const dim3 wgrid((unsigned)((L.seg_slots + kWriteWaves - 1) / kWriteWaves));
+    const dim3 wgrid((unsigned)std::min<int64_t>((L.seg_slots + kWriteWaves - 1) / kWriteWaves,
+                                                 kSplitBlocks));
     hipLaunchKernelGGL(split_write_kernel, wgrid, dim3(kWriteWaves * 64), 0, s, views, rp,
                        seg_first, ranges, sentry, mask, seg_off, counters, L.capacity, tile_entry);
     if ((err = hipGetLastError()) != hipSuccess) return err;

@@ -11,8 +11,8 @@
 //
 // Backward: per pixel p the SSIM value S(p) depends on x through mu_x(p),
 // E[x^2](p) and E[xy](p); the map derivatives dS/dmu_x, dS/dE[x^2],
-// dS/dE[xy] are written by the forward and filtered again by the backward
-// (the window is symmetric):
+// dS/dE[xy] are written by the forward (when a workspace holds them) and
+// filtered again by the backward (the window is symmetric):
 //   dSSIM/dx(q) = F[dS/dmu_x](q) + 2 x(q) F[dS/dE[x^2]](q) + y(q) F[dS/dE[xy]](q).
 #include "sgs_internal.hpp"
 #include "sgs_device.hpp"
@@ -116,9 +116,11 @@ __device__ __forceinline__ void moments(const float (*X)[kE], const float (*Y)[k
 }
 
 // Forward tile: sums of |x - y| and of S over the tile's 3 x 256 values into
-// partials[2 blk], and the maps dS/dmu_x, dS/dE[x^2], dS/dE[xy] the backward
-// filters (written on every forward, so that a backward needs no second pass
-// over the moments).
+// partials[2 blk] and, with kMaps, the maps dS/dmu_x, dS/dE[x^2], dS/dE[xy]
+// the backward filters. The maps are written on every forward: forming them
+// again in the backward would repeat the whole moment pass, which costs more
+// than the writes it saves on iterations whose backward is skipped.
+template <bool kMaps>
 __global__ void __launch_bounds__(kThreads) ssim_forward_kernel(
     const float* __restrict__ x, TargetRef target, int w, int h, Window W,
     float* __restrict__ partials, float* __restrict__ maps) {
@@ -151,11 +153,13 @@ __global__ void __launch_bounds__(kThreads) ssim_forward_kernel(
             const float b = sy[ch][tid / kT + kR][tid % kT + kR];
             s_l1 += fabsf(a - b);
             s_ssim += S;
-            const int64_t pix = (int64_t)oy * w + ox;
-            maps[(0 * 3 + ch) * plane + pix] =
-                2.f * my * (A2 - A1) / D - 2.f * mx * S * (1.f / B1 - 1.f / B2);
-            maps[(1 * 3 + ch) * plane + pix] = -S / B2;
-            maps[(2 * 3 + ch) * plane + pix] = 2.f * A1 / D;
+            if (kMaps) {
+                const int64_t pix = (int64_t)oy * w + ox;
+                maps[(0 * 3 + ch) * plane + pix] =
+                    2.f * my * (A2 - A1) / D - 2.f * mx * S * (1.f / B1 - 1.f / B2);
+                maps[(1 * 3 + ch) * plane + pix] = -S / B2;
+                maps[(2 * 3 + ch) * plane + pix] = 2.f * A1 / D;
+            }
         }
     }
     // fixed-order workgroup sum
@@ -267,13 +271,26 @@ __global__ void __launch_bounds__(kThreads) ssim_backward_kernel(
 
 size_t loss_workspace_bytes(int w, int h) { return loss_layout(w, h).total; }
 
+int64_t loss_partial_floats(int w, int h) { return 2 * loss_layout(w, h).blocks; }
+
+hipError_t launch_loss_partials(const float* rgb, TargetRef target, int w, int h, float lambda,
+                                float* partials, float* d_loss, hipStream_t s) {
+    const LossLayout L = loss_layout(w, h);
+    const dim3 grid((unsigned)((w + kT - 1) / kT), (unsigned)((h + kT - 1) / kT));
+    hipLaunchKernelGGL((ssim_forward_kernel<false>), grid, dim3(kThreads), 0, s, rgb, target, w, h,
+                       make_window(), partials, nullptr);
+    hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(1024), 0, s, partials, L.blocks,
+                       3.0 * (double)w * (double)h, lambda, d_loss);
+    return hipGetLastError();
+}
+
 hipError_t launch_loss_forward(const float* rgb, TargetRef target, int w, int h, float lambda,
                                char* ws, float* d_loss, hipStream_t s) {
     const LossLayout L = loss_layout(w, h);
     const dim3 grid((unsigned)((w + kT - 1) / kT), (unsigned)((h + kT - 1) / kT));
     float* partials = reinterpret_cast<float*>(ws + L.partials);
     float* maps = reinterpret_cast<float*>(ws + L.maps);
-    hipLaunchKernelGGL(ssim_forward_kernel, grid, dim3(kThreads), 0, s, rgb, target, w, h,
+    hipLaunchKernelGGL((ssim_forward_kernel<true>), grid, dim3(kThreads), 0, s, rgb, target, w, h,
                        make_window(), partials, maps);
     hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(1024), 0, s, partials, L.blocks,
                        3.0 * (double)w * (double)h, lambda, d_loss);

@@ -187,6 +187,11 @@ hipError_t launch_loss_forward(const float* rgb, TargetRef target, int w, int h,
 hipError_t launch_loss_backward(const float* rgb, TargetRef target, int w, int h, float lambda,
                                 char* ws, const int32_t* gate, float* dl, hipStream_t s);
 size_t loss_workspace_bytes(int w, int h);
+// The loss forward with the per-tile partial sums (loss_partial_floats(w, h)
+// floats) in caller-provided device memory.
+int64_t loss_partial_floats(int w, int h);
+hipError_t launch_loss_partials(const float* rgb, TargetRef target, int w, int h, float lambda,
+                                float* partials, float* d_loss, hipStream_t s);
 
 hipError_t launch_gate_init(const sgs_gate_params* p, void* state, hipStream_t s);
 hipError_t launch_gate_update(const sgs_gate_params* p, void* state, const int32_t* view,
