@@ -289,6 +289,20 @@ sgs_status sgs_photometric_loss_backward(const float* rgb, const float* target, 
                                          size_t workspace_bytes, const int32_t* d_gate,
                                          float* dl_drgb, void* stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * serving loops, harnesses that forbid allocation): sgs_photometric_loss
+ * without a workspace: the same loss value, bit for bit (it leaves no SSIM maps
+ * for a backward: use it where only the loss is wanted). The per-tile partial
+ * sums live in a file-scope device array of the library (one per GPU, 512 KiB,
+ * held until the process ends), so images are limited to 65536 tiles of 16x16 pixels
+ * (e.g. 4096x4096); larger ones fail with SGS_ERR_CAPACITY before anything is
+ * enqueued. Allocates nothing. All calls on one GPU share that array: calls
+ * that overlap in time on one GPU (different streams, or threads) race and
+ * must be serialised by the caller. */
+sgs_status sgs_photometric_loss_static(const float* rgb, const float* target, int32_t width,
+                                       int32_t height, float lambda, float* d_loss,
+                                       void* stream);
+
 /* ---------------------------------------------------------------------------
  * SkipGS backward gate (Sec. 4: Algorithm 1, Eqs. 7-13), one update per
  * post-densification iteration, executed on the device by a single thread in

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -268,6 +269,37 @@ void make_layout(const Views& views, const RasterDev& rp, int64_t n, int64_t cap
 
 using sgs::Layout;
 
+// Scratch of sgs_photometric_loss_static: the per-tile partial sums of the
+// loss forward (every call overwrites all it reads, so nothing needs
+// clearing). One copy per GPU, at its own device address, held until the
+// process ends; its address is looked up once per device and kept.
+constexpr int64_t kStaticLossPartials = int64_t(1) << 17;   // 65536 tiles of 16x16 pixels
+static __device__ __align__(256) float scratch[kStaticLossPartials];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+sgs_status static_scratch(float** out) {
+    int dev = -1;
+    SGS_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(SGS_ERR_UNSUPPORTED, "device %d beyond the %d the static scratch serves", dev,
+                    kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* p = nullptr;
+        SGS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return SGS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* sgs_last_error(void) { return g_err.c_str(); }
@@ -529,6 +561,27 @@ sgs_status sgs_photometric_loss(const float* rgb, const float* target, int32_t w
     SGS_HIP(sgs::launch_loss_forward(rgb, sgs::TargetRef{target, nullptr, 1}, width, height, lambda,
                                      static_cast<char*>(workspace), d_loss,
                                      static_cast<hipStream_t>(stream)),
+            "loss");
+    return SGS_OK;
+}
+
+sgs_status sgs_photometric_loss_static(const float* rgb, const float* target, int32_t width,
+                                       int32_t height, float lambda, float* d_loss,
+                                       void* stream) {
+    if (!rgb || !target || !d_loss) return fail(SGS_ERR_INVALID_ARG, "null pointer argument");
+    if (width <= 0 || height <= 0 || width > 32768 || height > 32768)
+        return fail(SGS_ERR_INVALID_ARG, "image size not in [1, 32768]");
+    if (!(lambda >= 0.f && lambda <= 1.f)) return fail(SGS_ERR_INVALID_ARG, "lambda not in [0, 1]");
+    if (sgs::loss_partial_floats(width, height) > kStaticLossPartials)
+        return fail(SGS_ERR_CAPACITY,
+                    "%dx%d image needs %lld partial sums; the static scratch holds %lld "
+                    "(images up to %lld tiles of 16x16 pixels)",
+                    width, height, (long long)sgs::loss_partial_floats(width, height),
+                    (long long)kStaticLossPartials, (long long)(kStaticLossPartials / 2));
+    float* partials = nullptr;
+    if (sgs_status st = static_scratch(&partials); st != SGS_OK) return st;
+    SGS_HIP(sgs::launch_loss_partials(rgb, sgs::TargetRef{target, nullptr, 1}, width, height,
+                                      lambda, partials, d_loss, static_cast<hipStream_t>(stream)),
             "loss");
     return SGS_OK;
 }

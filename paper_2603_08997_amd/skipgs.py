@@ -82,7 +82,8 @@ EXPORTS = [
     "sgs_render_forward", "sgs_read_status", "sgs_clear_status", "sgs_render_backward",
     "sgs_project", "sgs_load_records", "sgs_bin", "sgs_rasterize", "sgs_rasterize_backward",
     "sgs_project_backward", "sgs_get_workspace_layout", "sgs_loss_workspace_size",
-    "sgs_photometric_loss", "sgs_photometric_loss_backward", "sgs_gate_state_size",
+    "sgs_photometric_loss", "sgs_photometric_loss_backward", "sgs_photometric_loss_static",
+    "sgs_gate_state_size",
     "sgs_gate_init", "sgs_gate_update", "sgs_gate_read", "sgs_adam_step",
     "sgs_project_backward_adam", "sgs_render_backward_adam", "sgs_camera_table_size",
     "sgs_camera_table_init", "sgs_view_sequence_next", "sgs_train_iteration",
@@ -119,6 +120,7 @@ def _load():
                                            P(WorkspaceLayoutC)]),
         "sgs_loss_workspace_size": (i32, [i32, i32, P(sz)]),
         "sgs_photometric_loss": (i32, [vp, vp, i32, i32, f32, vp, sz, vp, vp]),
+        "sgs_photometric_loss_static": (i32, [vp, vp, i32, i32, f32, vp, vp]),
         "sgs_photometric_loss_backward": (i32, [vp, vp, i32, i32, f32, vp, sz, vp, vp, vp]),
         "sgs_gate_state_size": (i32, [P(GateParamsC), P(sz)]),
         "sgs_gate_init": (i32, [P(GateParamsC), vp, vp]),
@@ -349,6 +351,12 @@ def photometric_loss(rgb, target, width, height, lam, workspace, d_loss, stream=
     _check(LIB.sgs_photometric_loss(_ptr(rgb), _ptr(target), width, height, float(lam),
                                     _ptr(workspace), workspace.numel(), _ptr(d_loss),
                                     _stream(stream)))
+
+
+def photometric_loss_static(rgb, target, width, height, lam, d_loss, stream=None):
+    """sgs_photometric_loss without a workspace (the library's static scratch)."""
+    _check(LIB.sgs_photometric_loss_static(_ptr(rgb), _ptr(target), width, height, float(lam),
+                                           _ptr(d_loss), _stream(stream)))
 
 
 def photometric_loss_backward(rgb, target, width, height, lam, workspace, d_gate, dl_drgb,

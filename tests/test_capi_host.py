@@ -222,3 +222,14 @@ def test_camera_table_and_train_iteration_validation():
     assert st == 1 and b"table" in sg.LIB.sgs_last_error()
     assert sg.LIB.sgs_view_sequence_next(C.c_void_p(256), 0, C.c_void_p(256), C.c_void_p(256),
                                          None) == 1
+
+
+def test_static_loss_rejects_before_enqueueing():
+    """The workspace-free loss checks its arguments (and that the image fits
+    its static scratch of 65536 tiles) before touching the device."""
+    sg = _lib()
+    p = C.c_void_p(256)
+    assert sg.LIB.sgs_photometric_loss_static(p, p, 4097, 4096, C.c_float(0.2), p, None) == 3
+    assert "static scratch" in sg.LIB.sgs_last_error().decode()
+    assert sg.LIB.sgs_photometric_loss_static(None, p, 64, 64, C.c_float(0.2), p, None) == 1
+    assert sg.LIB.sgs_photometric_loss_static(p, p, 64, 64, C.c_float(1.5), p, None) == 1
