@@ -525,10 +525,15 @@ __global__ void __launch_bounds__(kLanes, backward_waves(B)) raster_backward_ker
     }
 }
 
+// Clears the accumulators in a grid-stride loop over a grid sized for the
+// machine (a closed gate then costs a launch of a few thousand blocks, not
+// one block per 256 float4).
+constexpr int kZeroBlocks = 2048;
 __global__ void zero_f32_gated_kernel(float4* p, int64_t n4, const int32_t* gate) {
     if (gate_closed(gate)) return;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n4) p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 }  // namespace
@@ -584,8 +589,9 @@ hipError_t launch_rasterize_backward(const RasterDev& rp, const Layout& L, char*
     float* acc = reinterpret_cast<float*>(ws + L.accum);
     const int64_t n4 = L.entries * kAccumFloats / 4;
     if (n4 > 0)
-        hipLaunchKernelGGL(zero_f32_gated_kernel, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0,
-                           s, reinterpret_cast<float4*>(acc), n4, gate);
+        hipLaunchKernelGGL(zero_f32_gated_kernel,
+                           dim3((unsigned)std::min<int64_t>((n4 + 255) / 256, kZeroBlocks)),
+                           dim3(256), 0, s, reinterpret_cast<float4*>(acc), n4, gate);
     if (L.total_tiles == 0 || L.entries == 0) return hipGetLastError();
     const Views* views = reinterpret_cast<const Views*>(ws + L.views);
     const uint32_t* ranges = reinterpret_cast<const uint32_t*>(ws + L.tile_ranges);

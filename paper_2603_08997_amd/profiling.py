@@ -31,7 +31,10 @@ ROOT = os.path.dirname(PKG)
 # each, and the start of the name the trace shows.
 TRAFFIC_KERNELS = {"project_backward_adam": "project_backward_adam_kernel",
                    "raster_backward": "raster_backward_kernel",
-                   "raster_forward": "raster_forward_kernel"}
+                   "raster_forward": "raster_forward_kernel",
+                   "emit": "emit_kernel",
+                   "split_count": "split_count_kernel",
+                   "split_write": "split_write_kernel"}
 COPY_KERNEL = "MulFunctor"
 
 
