@@ -229,6 +229,8 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     __shared__ uint16_t s_ih[kEmitMaxG];
     __shared__ uint16_t s_tr[kEmitMaxG][4];  // tile rectangle [x0, x1) x [y0, y1)
     __shared__ float s_lim[kEmitMaxG];       // reach limit on a super-tile
+    __shared__ float4 s_r0[kEmitMaxG];       // record words u v a b, c o rx ry
+    __shared__ float4 s_r1[kEmitMaxG];
     __shared__ uint32_t s_own[kEmitTile];    // window position -> owning Gaussian
     __shared__ uint32_t s_scan[kEmitThreads / 64 + 1];
     // pairs written = min(pairs needed, capacity); block 0 records it and
@@ -278,6 +280,8 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
         s_tr[j][2] = (uint16_t)y0;
         s_tr[j][3] = (uint16_t)y1;
         s_lim[j] = super_limit(reach_limit(r1.y, rp));
+        s_r0[j] = r0;
+        s_r1[j] = r1;
         // mark where this Gaussian's units start inside the window
         const uint64_t first = (uint64_t)off + (uint64_t)kEmitHead * k;
         if (j > 0 && first - c0 < (uint64_t)kEmitTile) s_own[first - c0] = j;
@@ -300,11 +304,8 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
         for (int i = 0; i < kEmitItems; ++i) s_own[tid * kEmitItems + i] = max(before, run[i]);
     }
     __syncthreads();
-    // gather every item's record first (one round of memory latency), then
-    // test and store; header units and units past the written pairs do nothing
-    uint32_t own[kEmitItems], qq[kEmitItems], pp[kEmitItems];
-    bool pair[kEmitItems];
-    float4 g0[kEmitItems], g1[kEmitItems];
+    // test and store every item (the records were staged in LDS once per
+    // Gaussian); header units and units past the written pairs do nothing
 #pragma unroll
     for (int it = 0; it < kEmitItems; ++it) {
         const uint64_t c = c0 + (uint64_t)(it * kEmitThreads + tid);
@@ -313,21 +314,8 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
         const bool is_pair = c < units && c >= first + (uint64_t)kEmitHead;
         const uint32_t q = is_pair ? (uint32_t)(c - first - (uint64_t)kEmitHead) : 0u;
         const uint32_t p = s_off[j] + q;
-        own[it] = j;
-        qq[it] = q;
-        pp[it] = p;
-        pair[it] = is_pair && p < P;
-        if (pair[it]) {
-            const int64_t e = s_ent[j];
-            g0[it] = rec[3 * e];
-            g1[it] = rec[3 * e + 1];
-        }
-    }
-#pragma unroll
-    for (int it = 0; it < kEmitItems; ++it) {
-        if (!pair[it]) continue;
-        const uint32_t j = own[it];
-        const uint32_t q = qq[it], p = pp[it];
+        if (!is_pair || p >= P) continue;
+        const float4 g0 = s_r0[j], g1 = s_r1[j];
         const uint32_t w = s_w[j];
         // q / w and q % w through a float reciprocal, corrected to exact
         uint32_t qy = (uint32_t)((float)q * __builtin_amdgcn_rcpf((float)w));
@@ -338,9 +326,9 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
         const int sw = rp.super_tile * rp.tile_w, sh = rp.super_tile * rp.tile_h;
         const int px0 = ((int)s_x0[j] + qx) * sw, py0 = ((int)s_y0[j] + (int)qy) * sh;
         const bool keep = s_lim[j] == INFINITY ||
-                          rect_reachable(g0[it].x, g0[it].y, g0[it].z, g0[it].w, g1[it].x,
-                                         s_lim[j], g1[it].z, g1[it].w, px0, py0,
-                                         min(sw, (int)s_iw[j] - px0), min(sh, (int)s_ih[j] - py0));
+                          rect_reachable(g0.x, g0.y, g0.z, g0.w, g1.x, s_lim[j], g1.z, g1.w, px0,
+                                         py0, min(sw, (int)s_iw[j] - px0),
+                                         min(sh, (int)s_ih[j] - py0));
         // the tile rectangle inside the super-tile, relative to its first tile
         const int S = rp.super_tile;
         const int ox = ((int)s_x0[j] + qx) * S, oy = ((int)s_y0[j] + (int)qy) * S;
