@@ -75,6 +75,9 @@ def parse():
                          "visible-only step")
     ap.add_argument("--super-tile", type=int, default=8)
     ap.add_argument("--lds-batch", type=int, default=64)
+    ap.add_argument("--split-prefix", type=int, default=8192,
+                    help="super-tile list pairs split into tile lists before compositing "
+                         "(0: whole lists)")
     ap.add_argument("--no-graph", action="store_true",
                     help="enqueue every timed iteration instead of replaying a captured graph")
     ap.add_argument("--stage-iters", type=int, default=200,
@@ -212,7 +215,8 @@ class Setup:
         self.init = S.perturb(self.gt, S.SEED_INIT_PERTURB)
         self.cams = S.hemisphere_cameras(S.SEED_CAMERAS, args.views, args.width, args.height)
         self.seq = S.view_sequence(S.SEED_VIEW_SEQUENCE, args.views, length)
-        self.rp = sk.RasterParams(super_tile=args.super_tile, lds_batch=args.lds_batch)
+        self.rp = sk.RasterParams(super_tile=args.super_tile, lds_batch=args.lds_batch,
+                             split_prefix=args.split_prefix)
         need = max(measure_capacity(self.gt, self.cams, self.rp),
                    measure_capacity(self.init, self.cams, self.rp))
         self.cap = int(need * 1.3) + 4096
@@ -306,7 +310,8 @@ def stage_pass(args, st, tr, start):
 def train_counters(tr, views):
     """Per-view work of the forward, averaged over a few views."""
     from paper_2603_08997_amd import skipgs as sk
-    keys = ("blended", "evaluated", "pairs", "pairs_kept", "items", "used", "visible")
+    keys = ("blended", "evaluated", "pairs", "pairs_kept", "items", "items_rest", "redo",
+            "segments", "used", "visible")
     acc = {k: [] for k in keys}
     for v in views:
         tr.render(v, tr.rgb)
@@ -337,12 +342,13 @@ def roofline(args, stages, bf, cnt, visible_only):
     # (read + write), the super-tile counts gathered and scanned, the records
     # the emission reads (32 B per visible entry) and the 8-byte pairs it
     # writes, one pass of the super-tile sort (read + write); the split reads
-    # every sorted pair (8 B) and its entry's record (32 B) and writes its
-    # tile mask (8 B), then reads mask and entry again (12 B) and writes every
-    # tile-list entry (4 B)
+    # every pair of the split prefixes (at most 512 per segment; 8 B) and its
+    # entry's record (32 B) and writes its tile mask (8 B), then reads mask and
+    # entry again (12 B) and writes every tile-list entry of the prefixes (4 B)
     P, I = cnt["pairs"], cnt["items"]
+    Ps = min(cnt["pairs_kept"], 512 * cnt["segments"])
     bin_bytes = (n * 4 + vis * 12 + 4 * vis * 16 + vis * 12 + vis * 32 + P * 8 + P * 16
-                 + P * (8 + 32 + 8) + P * 12 + I * 4)
+                 + Ps * (8 + 32 + 8) + Ps * 12 + I * 4)
     cands = {
         "raster_forward": dict(ms=allm["rasterize"], weight=1.0, bound="alu",
                                work=cnt["blended"] * FWD_FLOPS_PER_PAIR / 1e12, unit="TFLOP/s",
@@ -429,7 +435,8 @@ def run_train(args):
                    "gaussians": args.n, "views": args.views, "width": args.width,
                    "height": args.height, "gate": args.gate, "adam": args.adam,
                    "gate_preroll": args.gate_preroll, "super_tile": args.super_tile,
-                   "lds_batch": args.lds_batch, "graph": headline["graph"]},
+                   "lds_batch": args.lds_batch, "split_prefix": args.split_prefix,
+                   "graph": headline["graph"]},
         "skip_fraction": 1.0 - headline["backward_fraction"],
     }
     full = results.get("full")
@@ -555,7 +562,8 @@ def run_single(args):
     scene = S.mixture_scene(S.SEED_SCENE, n, 3)
     other = S.mixture_scene(S.SEED_TINY_TARGET, n, 3)
     cams = S.hemisphere_cameras(S.SEED_CAMERAS, V, W, H)
-    rp = sk.RasterParams(super_tile=args.super_tile, lds_batch=args.lds_batch)
+    rp = sk.RasterParams(super_tile=args.super_tile, lds_batch=args.lds_batch,
+                             split_prefix=args.split_prefix)
     cap = int(max(measure_capacity(scene, cams, rp), measure_capacity(other, cams, rp)) * 1.3) + 4096
     targets = render_targets(other, cams, rp, cap)
     tr = Trainer(scene, cams, targets, rp, None, cap, gated=False, sequence=np.arange(V))
@@ -599,7 +607,8 @@ def run_dense(args):
     n = 6_000_000
     scene = S.dense_cluster_scene(S.SEED_SCENE, n, 3)
     cam = S.hemisphere_cameras(S.SEED_CAMERAS, 1, 1600, 1060)[0]
-    rp = sk.RasterParams(super_tile=args.super_tile, lds_batch=args.lds_batch)
+    rp = sk.RasterParams(super_tile=args.super_tile, lds_batch=args.lds_batch,
+                             split_prefix=args.split_prefix)
     cap = int(measure_capacity(scene, [cam], rp) * 1.2) + 4096
     planes = torch.as_tensor(scene.to_planes()).cuda()
     # per-view work of the forward

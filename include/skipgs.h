@@ -101,6 +101,10 @@ typedef struct {
                              /* 1..8 (0: 8)                                         */
     int32_t lds_batch;       /* list entries per compositing batch staged in LDS:   */
                              /* 32, 64, 128 or 256 (0: 64)                          */
+    int32_t split_prefix;    /* pairs of a long super-tile list split into tile     */
+                             /* lists before compositing (rounded up to 512-pair    */
+                             /* segments), 0 <= split_prefix <= 2^30, 0: all; see   */
+                             /* sgs_render_forward (default 8192)                   */
     float bg[3];             /* background colour, added with weight T_final        */
     float near_z;            /* camera depth <= near_z culls                        */
     float dilation;          /* Sigma2D += dilation * I (pixels^2)                  */
@@ -130,6 +134,18 @@ void sgs_default_raster_params(sgs_raster_params* rp);
  * lists of their tiles, keeping on each tile the entries that can reach
  * alpha_min there. The compositing of each tile walks its list in batches of
  * lds_batch entries and stops when every pixel has terminated.
+ *
+ * A tile rarely composites more than the front of its list, so with
+ * split_prefix > 0 binning splits a super-tile list of more than
+ * 4 x split_prefix pairs (both counted in whole 512-pair segments) only in its
+ * first split_prefix pairs (shorter lists whole): a tile's list is then the prefix of its whole list made of the
+ * entries from those pairs. A tile whose pixels are not all terminated when
+ * its prefix runs out is marked, the whole lists of the marked tiles'
+ * super-tiles are split (after the prefix lists, in the same pair capacity)
+ * and the marked tiles resume their compositing over their whole lists, all
+ * on the device within the compositing call. The image, the per-pixel state
+ * and the gradients equal those of split_prefix = 0; only the tile lists a
+ * caller reads after sgs_bin alone differ (prefixes).
  *
  * The workspace holds everything the backward needs (projected records, the
  * tile lists, per-pixel final transmittance and last contributor).
@@ -208,12 +224,18 @@ sgs_status sgs_load_records(const sgs_camera* cams, int32_t n_views, int64_t n,
  * per-super-tile lists (S x S tiles, S = super_tile) that are sorted once and
  * then split into the lists of their tiles. pair_capacity bounds both the
  * super-tile pairs and the tile-list entries (sgs_read_status reports the
- * larger need). Also clears the counters the compositing forward accumulates
- * into: every sgs_rasterize follows an sgs_bin. */
+ * larger need). With split_prefix > 0 the list of a tile in a long
+ * super-tile list holds only the entries from the list's first split_prefix
+ * pairs; sgs_rasterize completes the lists its tiles need. Also clears the counters the
+ * compositing forward accumulates into: every sgs_rasterize follows an
+ * sgs_bin. */
 sgs_status sgs_bin(const sgs_camera* cams, int32_t n_views, int64_t n, const sgs_raster_params* rp,
                    void* workspace, size_t workspace_bytes, int64_t pair_capacity, void* stream);
 
-/* Compositing forward of every tile (Eqs. 4-5) over its list. */
+/* Compositing forward of every tile (Eqs. 4-5) over its list; with
+ * split_prefix > 0 it also splits the whole lists of the super-tiles of the
+ * tiles that reach the end of their prefix with live pixels, and composites
+ * those tiles again over their whole lists. */
 sgs_status sgs_rasterize(const sgs_camera* cams, int32_t n_views, int64_t n,
                          const sgs_raster_params* rp, void* workspace, size_t workspace_bytes,
                          int64_t pair_capacity, float* out_rgb, void* stream);

@@ -129,6 +129,11 @@ __global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(Src src, uint
     __shared__ uint32_t smem[kScanThreads / 64 + 1];
     if (blockIdx.x == 0 && (int)threadIdx.x < nclear) clear[threadIdx.x] = 0u;
     const int64_t n = src.count();
+    // blocks past the count (the grid covers a bound) contribute 0
+    if ((int64_t)blockIdx.x * kScanTile >= n) {
+        if (threadIdx.x == 0) sums[blockIdx.x] = 0u;
+        return;
+    }
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t s = 0;
 #pragma unroll
@@ -147,11 +152,15 @@ __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(Src src, Sink s
                                                                  const uint32_t* sums,
                                                                  uint32_t* total) {
     __shared__ uint32_t smem[kScanThreads / 64 + 1];
+    const int64_t n = src.count();
+    // blocks past the count have nothing to feed; the last one still writes
+    // the total
+    const bool last = blockIdx.x == gridDim.x - 1;
+    if ((int64_t)blockIdx.x * kScanTile >= n && !last) return;
     uint32_t before = 0;
     for (int i = threadIdx.x; i < (int)blockIdx.x; i += kScanThreads) before = sat_add(before, sums[i]);
     uint32_t prefix;
     block_excl_sat_scan<kScanThreads>(before, smem, &prefix);
-    const int64_t n = src.count();
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
     uint32_t s = 0;
@@ -167,7 +176,7 @@ __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(Src src, Sink s
         if (base + j < n) sink(base + j, v[j], pos);
         pos = sat_add(pos, v[j]);
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = sat_add(prefix, tot);
+    if (last && threadIdx.x == 0) *total = sat_add(prefix, tot);
 }
 
 template <class Src, class Sink>
@@ -425,19 +434,32 @@ __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
 
 // ---- the split of the super-tile lists into tile lists ----
 
-// Segments of every super-tile's list (the scan numbers them).
+__device__ __forceinline__ uint32_t list_segments(const uint32_t* ranges, int64_t s) {
+    const uint32_t len = ranges[2 * s + 1] - ranges[2 * s];
+    return (uint32_t)((len + kSegPairs - 1) / kSegPairs);
+}
+// Segments of every super-tile's list split before compositing (the scan
+// numbers them): all, or the first `prefix` of a long list.
 struct SegCountSrc {
     const uint32_t* ranges;
     int64_t n;
+    uint32_t prefix;   // 0: all
     __device__ int64_t count() const { return n; }
     __device__ uint32_t operator()(int64_t s) const {
-        const uint32_t len = ranges[2 * s + 1] - ranges[2 * s];
-        return (uint32_t)((len + kSegPairs - 1) / kSegPairs);
+        return split_segments(list_segments(ranges, s), prefix);
     }
 };
-struct FirstSink {
-    uint32_t* first;
-    __device__ void operator()(int64_t k, uint32_t, uint32_t pos) const { first[k] = pos; }
+// The completing split: every segment of the super-tiles flagged in
+// sup_redo, none of the others; nothing unless *redo is set.
+struct RestSegSrc {
+    const uint32_t* ranges;
+    const uint32_t* sup_redo;
+    const uint32_t* redo;
+    int64_t n;
+    __device__ int64_t count() const { return *redo ? n : 0; }
+    __device__ uint32_t operator()(int64_t s) const {
+        return sup_redo[s] ? list_segments(ranges, s) : 0u;
+    }
 };
 // (super-tile, tile, segment) counts, in that order, for the list positions.
 struct ItemCountSrc {
@@ -449,8 +471,47 @@ struct ItemCountSrc {
 };
 struct ItemOffSink {
     uint32_t* off;
-    __device__ void operator()(int64_t k, uint32_t, uint32_t pos) const { off[k] = pos; }
+    const uint32_t* base;   // nullable: list positions start there (after the prefix lists)
+    __device__ void operator()(int64_t k, uint32_t, uint32_t pos) const {
+        off[k] = base != nullptr ? sat_add(pos, *base) : pos;
+    }
 };
+
+// Tile-list entries of both splits (saturating).
+__device__ __forceinline__ uint32_t items_total(const uint32_t* counters) {
+    return sat_add(counters[kItems], counters[kItemsRest]);
+}
+
+// Exclusive saturating scan of the segment counts of all super-tiles in one
+// workgroup (a few hundred to a few ten thousand counts): first[s] for every
+// super-tile and the total in first[n].
+constexpr int kSegScanThreads = 1024;
+constexpr int kSegScanItems = 4;
+template <class Src>
+__global__ void __launch_bounds__(kSegScanThreads) seg_scan_kernel(Src src, uint32_t* first) {
+    __shared__ uint32_t smem[kSegScanThreads / 64 + 1];
+    const int64_t n = src.count();
+    constexpr int64_t kChunk = (int64_t)kSegScanThreads * kSegScanItems;
+    uint32_t carry = 0;
+    for (int64_t c0 = 0; c0 < n; c0 += kChunk) {
+        const int64_t base = c0 + (int64_t)threadIdx.x * kSegScanItems;
+        uint32_t v[kSegScanItems], sum = 0;
+#pragma unroll
+        for (int j = 0; j < kSegScanItems; ++j) {
+            v[j] = base + j < n ? src(base + j) : 0u;
+            sum = sat_add(sum, v[j]);
+        }
+        uint32_t tot;
+        uint32_t pos = sat_add(carry, block_excl_sat_scan<kSegScanThreads>(sum, smem, &tot));
+#pragma unroll
+        for (int j = 0; j < kSegScanItems; ++j) {
+            if (base + j < n) first[base + j] = pos;
+            pos = sat_add(pos, v[j]);
+        }
+        carry = sat_add(carry, tot);
+    }
+    if (threadIdx.x == 0) first[src.n] = carry;
+}
 
 // Segment g of the split: super-tile s (global index), segment k of nseg in
 // its list, pairs [a, b), the super-tile's first tile (tx0, ty0) in its view.
@@ -697,7 +758,7 @@ __global__ void __launch_bounds__(kWriteWaves * 64) split_write_kernel(
     __shared__ uint32_t s_pos[kWriteWaves][kStepItems];
     const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int S = rp.super_tile, TT = S * S;
-    if ((int64_t)counters[kItems] > capacity) return;   // overflow: the tile lists stay empty
+    if ((int64_t)items_total(counters) > capacity) return;   // overflow: the tile lists stay empty
     for (uint32_t g = blockIdx.x * kWriteWaves + w;; g += gridDim.x * kWriteWaves) {
         Segment sg;
         if (!locate_segment(views, seg_first, sup_ranges, S, g, &sg)) return;
@@ -733,19 +794,28 @@ __global__ void __launch_bounds__(kWriteWaves * 64) split_write_kernel(
     }
 }
 
-// [start, end) of every tile's list; flags a tile-list overflow (all lists
-// empty then) and records the segment count.
+// [start, end) of tile lists. After the split of the list prefixes (rest =
+// false): every tile's, with its state (whether its super-tile's list was
+// cut by the prefix); it also clears the super-tile redo flags, flags a
+// tile-list overflow (all lists empty then) and records the segment count.
+// After the completing split (rest = true): only the tiles marked
+// incomplete, which now take their whole lists (empty on overflow).
 __global__ void __launch_bounds__(256) tile_ranges_kernel(
-    const Views* __restrict__ views, RasterDev rp, const uint32_t* __restrict__ seg_first,
-    const uint32_t* __restrict__ seg_cnt, const uint32_t* __restrict__ seg_off,
-    uint32_t* __restrict__ counters, int64_t capacity, uint32_t* __restrict__ tile_ranges) {
+    const Views* __restrict__ views, RasterDev rp, const uint32_t* __restrict__ sup_ranges,
+    const uint32_t* __restrict__ seg_first, const uint32_t* __restrict__ seg_cnt,
+    const uint32_t* __restrict__ seg_off, uint32_t* __restrict__ counters, int64_t capacity,
+    uint32_t* __restrict__ tile_ranges, uint32_t* __restrict__ tile_state,
+    uint32_t* __restrict__ sup_redo, bool rest) {
+    if (rest && counters[kRedo] == 0u) return;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool overflow = (int64_t)counters[kItems] > capacity;
+    const bool overflow = (int64_t)items_total(counters) > capacity;
     if (t == 0) {
-        counters[kSegments] = seg_first[views->total_supers];
+        if (!rest) counters[kSegments] = seg_first[views->total_supers];
         if (overflow) atomicOr(&counters[kStatus], (uint32_t)SGS_STATUS_PAIR_OVERFLOW);
     }
+    if (!rest && t < views->total_supers) sup_redo[t] = 0u;
     if (t >= views->total_tiles) return;
+    if (rest && tile_state[t] != kTileIncomplete) return;
     int vi = 0;
     while (vi + 1 < views->n && t >= views->v[vi + 1].tile_offset) ++vi;
     const ViewDev& V = views->v[vi];
@@ -753,6 +823,11 @@ __global__ void __launch_bounds__(256) tile_ranges_kernel(
     const int tx = local % V.tiles_x, ty = local / V.tiles_x;
     const int S = rp.super_tile, TT = S * S;
     const int s = V.sup_offset + (ty / S) * V.sup_x + tx / S;
+    if (!rest)
+        tile_state[t] = split_segments(list_segments(sup_ranges, s), (uint32_t)rp.prefix_segs) <
+                                list_segments(sup_ranges, s)
+                            ? kTileTruncated
+                            : kTileWhole;
     const uint32_t nseg = seg_first[s + 1] - seg_first[s];
     uint32_t a = 0, b = 0;
     if (nseg > 0 && !overflow) {
@@ -779,8 +854,13 @@ hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
-// The split of the sorted super-tile lists into the tile lists.
-static hipError_t launch_split(const RasterDev& rp, const Layout& L, char* ws, hipStream_t s) {
+// The split of the sorted super-tile lists into tile lists: of the first
+// rp.prefix_segs segments of the long ones, the others whole, before
+// compositing (rest = false), or
+// of the whole lists of the super-tiles flagged by that compositing, placed
+// after the prefix lists (rest = true; predicated on counters[kRedo]).
+static hipError_t launch_split(const RasterDev& rp, const Layout& L, char* ws, hipStream_t s,
+                               bool rest) {
     if (L.total_supers == 0 || L.total_tiles == 0) return hipSuccess;
     const Views* views = reinterpret_cast<const Views*>(ws + L.views);
     uint32_t* counters = reinterpret_cast<uint32_t*>(ws + L.counters);
@@ -794,13 +874,20 @@ static hipError_t launch_split(const RasterDev& rp, const Layout& L, char* ws, h
     uint64_t* mask = reinterpret_cast<uint64_t*>(ws + L.pair_mask);
     uint32_t* tile_entry = reinterpret_cast<uint32_t*>(ws + L.tile_entry);
     uint32_t* tile_ranges = reinterpret_cast<uint32_t*>(ws + L.tile_ranges);
+    uint32_t* tile_state = reinterpret_cast<uint32_t*>(ws + L.tile_state);
+    uint32_t* sup_redo = reinterpret_cast<uint32_t*>(ws + L.sup_redo);
     uint32_t* sums = reinterpret_cast<uint32_t*>(ws + L.scan_sums);
     const int tt = rp.super_tile * rp.super_tile;
     hipError_t err;
-    // segments of every super-tile list; their total -> seg_first[total_supers]
-    err = device_scan(SegCountSrc{ranges, L.total_supers}, FirstSink{seg_first}, L.total_supers,
-                      sums, seg_first + L.total_supers, s);
-    if (err != hipSuccess) return err;
+    // segments to split; their total -> seg_first[total_supers]
+    if (rest)
+        hipLaunchKernelGGL(seg_scan_kernel<RestSegSrc>, dim3(1), dim3(kSegScanThreads), 0, s,
+                           RestSegSrc{ranges, sup_redo, counters + kRedo, L.total_supers},
+                           seg_first);
+    else
+        hipLaunchKernelGGL(seg_scan_kernel<SegCountSrc>, dim3(1), dim3(kSegScanThreads), 0, s,
+                           SegCountSrc{ranges, L.total_supers, (uint32_t)rp.prefix_segs}, seg_first);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
     // grid-stride over the segments: at most a few resident waves per SIMD
     const dim3 sgrid((unsigned)std::min<int64_t>((L.seg_slots + kSplitWaves - 1) / kSplitWaves,
                                                  kSplitBlocks));
@@ -808,9 +895,11 @@ static hipError_t launch_split(const RasterDev& rp, const Layout& L, char* ws, h
     hipLaunchKernelGGL(split_count_kernel, sgrid, dim3(kSplitWaves * 64), 0, s, views, rp,
                        seg_first, ranges, skey, sentry, rec, entries, mask, seg_cnt);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    // list positions; the number of tile-list entries -> counters[kItems]
-    err = device_scan(ItemCountSrc{seg_cnt, seg_first + L.total_supers, tt}, ItemOffSink{seg_off},
-                      L.seg_slots * tt, sums, counters + kItems, s);
+    // list positions (the completing split's after the prefix lists); the
+    // number of entries -> counters[kItems] or counters[kItemsRest]
+    err = device_scan(ItemCountSrc{seg_cnt, seg_first + L.total_supers, tt},
+                      ItemOffSink{seg_off, rest ? counters + kItems : nullptr}, L.seg_slots * tt,
+                      sums, counters + (rest ? kItemsRest : kItems), s);
     if (err != hipSuccess) return err;
     const dim3 wgrid((unsigned)std::min<int64_t>((L.seg_slots + kWriteWaves - 1) / kWriteWaves,
                                                  kSplitBlocks));
@@ -818,9 +907,13 @@ static hipError_t launch_split(const RasterDev& rp, const Layout& L, char* ws, h
                        seg_first, ranges, sentry, mask, seg_off, counters, L.capacity, tile_entry);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     hipLaunchKernelGGL(tile_ranges_kernel, dim3((unsigned)((L.total_tiles + 255) / 256)), dim3(256),
-                       0, s, views, rp, seg_first, seg_cnt, seg_off, counters, L.capacity,
-                       tile_ranges);
+                       0, s, views, rp, ranges, seg_first, seg_cnt, seg_off, counters, L.capacity,
+                       tile_ranges, tile_state, sup_redo, rest);
     return hipGetLastError();
+}
+
+hipError_t launch_split_rest(const RasterDev& rp, const Layout& L, char* ws, hipStream_t s) {
+    return launch_split(rp, L, ws, s, true);
 }
 
 hipError_t launch_bin(const RasterDev& rp, int64_t n, const Layout& L, char* ws, hipStream_t s) {
@@ -845,7 +938,7 @@ hipError_t launch_bin(const RasterDev& rp, int64_t n, const Layout& L, char* ws,
     uint32_t* ranges = reinterpret_cast<uint32_t*>(ws + L.sup_ranges);
     hipError_t err;
     // counters this stage and the compositing forward accumulate into
-    constexpr int kClear = kUsed + 1 - kVisible;
+    constexpr int kClear = kRedo + 1 - kVisible;
 
     // visible entries -> (depth, entry), entry order; count -> counters[kVisible]
     // (the first scan kernel also clears the counters)
@@ -887,7 +980,7 @@ hipError_t launch_bin(const RasterDev& rp, int64_t n, const Layout& L, char* ws,
         hipLaunchKernelGGL(ranges_kernel, rgrid, dim3(256), 0, s, pkey[L.key_result], counters,
                            L.total_supers, L.key_bits, ranges);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    return launch_split(rp, L, ws, s);
+    return launch_split(rp, L, ws, s, false);
 }
 
 hipError_t launch_order_tiles(const uint32_t* cost, int64_t tiles, int shift, uint32_t* order,

@@ -56,6 +56,8 @@ sgs_status check_raster(const sgs_raster_params* rp) {
         rp->lds_batch != 128 && rp->lds_batch != 256)
         return fail(SGS_ERR_UNSUPPORTED, "lds_batch %d not in {32, 64, 128, 256} (0: default)",
                     rp->lds_batch);
+    if (rp->split_prefix < 0 || rp->split_prefix > (1 << 30))
+        return fail(SGS_ERR_INVALID_ARG, "split_prefix %d not in [0, 2^30]", rp->split_prefix);
     if (!(rp->alpha_max > 0.f && rp->alpha_max <= 1.f) ||
         !(rp->alpha_min >= 0.f && rp->alpha_min <= rp->alpha_max) ||
         !(rp->t_min >= 0.f && rp->t_min < 1.f) || !(rp->near_z >= 0.f) || !(rp->dilation >= 0.f) ||
@@ -189,6 +191,7 @@ RasterDev make_raster(const sgs_raster_params* rp) {
     r.tile_h = rp->tile_h;
     r.super_tile = rp->super_tile > 0 ? rp->super_tile : kDefaultSuperTile;
     r.batch = rp->lds_batch > 0 ? rp->lds_batch : kDefaultBatch;
+    r.prefix_segs = (int32_t)((rp->split_prefix + kSegPairs - 1) / kSegPairs);
     r.key_bits = 0;   // set with the layout
     r.rect_bits = 0;
     for (int k = 0; k < 3; ++k) r.bg[k] = rp->bg[k];
@@ -257,6 +260,9 @@ void make_layout(const Views& views, const RasterDev& rp, int64_t n, int64_t cap
     L->pair_mask = take(sizeof(uint64_t) * (size_t)capacity);
     L->tile_entry = take(sizeof(uint32_t) * (size_t)capacity);
     L->tile_ranges = take(sizeof(uint32_t) * 2 * (size_t)L->total_tiles);
+    L->tile_state = take(sizeof(uint32_t) * (size_t)L->total_tiles);
+    L->tile_resume = take(sizeof(uint32_t) * (size_t)L->total_tiles);
+    L->sup_redo = take(sizeof(uint32_t) * (size_t)L->total_supers);
     L->tile_cost = take(sizeof(uint32_t) * (size_t)L->total_tiles);
     L->tile_stats = take(sizeof(uint32_t) * 2 * (size_t)L->total_tiles);
     L->tile_order = take(sizeof(uint32_t) * (size_t)L->total_tiles);
@@ -313,6 +319,7 @@ void sgs_default_raster_params(sgs_raster_params* rp) {
     rp->tile_h = 16;
     rp->super_tile = sgs::kDefaultSuperTile;
     rp->lds_batch = sgs::kDefaultBatch;
+    rp->split_prefix = sgs::kDefaultSplitPrefix;
     rp->bg[0] = rp->bg[1] = rp->bg[2] = 0.f;
     rp->near_z = 0.2f;
     rp->dilation = 0.3f;
@@ -527,7 +534,11 @@ sgs_status sgs_read_status(const void* workspace, uint32_t* flags_out, int64_t* 
     SGS_HIP(hipMemcpy(c, workspace, sizeof(c), hipMemcpyDeviceToHost), "read counters");
     if (flags_out) *flags_out = c[sgs::kStatus];
     if (visible_out) *visible_out = c[sgs::kVisible];
-    if (pairs_out) *pairs_out = std::max(c[sgs::kPairs], c[sgs::kItems]);
+    // list entries of both splits, saturating like the device's own sums
+    const uint32_t items = c[sgs::kItems] + c[sgs::kItemsRest] < c[sgs::kItems]
+                               ? 0xffffffffu
+                               : c[sgs::kItems] + c[sgs::kItemsRest];
+    if (pairs_out) *pairs_out = std::max(c[sgs::kPairs], items);
     return SGS_OK;
 }
 

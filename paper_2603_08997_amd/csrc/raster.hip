@@ -177,7 +177,9 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
     const Views* __restrict__ views, RasterDev rp, const uint32_t* __restrict__ tile_ranges,
     const uint32_t* __restrict__ tile_entry, const float4* __restrict__ rec,
     float* __restrict__ out_rgb, float* __restrict__ t_final, uint32_t* __restrict__ n_last,
-    uint32_t* __restrict__ tile_stats, uint32_t* __restrict__ tile_cost, uint32_t entries) {
+    uint32_t* __restrict__ tile_stats, uint32_t* __restrict__ tile_cost, uint32_t entries,
+    uint32_t* __restrict__ tile_state, uint32_t* __restrict__ tile_resume,
+    uint32_t* __restrict__ sup_redo, uint32_t* __restrict__ counters, bool redo) {
     constexpr int PIX = TW * TH / kLanes;
     constexpr int RS = kLanes / TW;   // row step between a lane's pixels
     static_assert(B % 32 == 0 && B >= 32 && B <= 256, "batch size");
@@ -186,6 +188,8 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
     __shared__ float4 s_col[B];   // r, g, b, -
 
     const int tile = blockIdx.x;
+    // the second pass goes on with the tiles the first left incomplete
+    if (redo && tile_state[tile] != kTileIncomplete) return;
     const ViewDev& V = views->v[view_of_tile(views, tile)];
     const int local = tile - V.tile_offset;
     const int tx = local % V.tiles_x, ty = local / V.tiles_x;
@@ -196,9 +200,15 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
     const int px0 = tx * TW, py0 = ty * TH;
 
     const float px = (float)(px0 + col) + 0.5f;
+    const int64_t plane = (int64_t)V.width * V.height;
+    float* img = out_rgb + 3 * V.px_offset;
     float py[PIX], T[PIX], C0[PIX], C1[PIX], C2[PIX];
     uint32_t last[PIX];
     uint32_t live = 0;   // bit RS*k: pixel k is in the view and has not stopped
+    // the second pass resumes each pixel where the first stopped, at the end
+    // of the tile's list prefix (which begins its whole list): transmittance,
+    // colour sums (stored without the background), last blended position and
+    // whether the pixel is still live (bit 31 of that position)
 #pragma unroll
     for (int k = 0; k < PIX; ++k) {
         const int y = py0 + row0 + RS * k;
@@ -206,9 +216,27 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
         T[k] = 1.f;
         C0[k] = C1[k] = C2[k] = 0.f;
         last[k] = 0;
-        if (px0 + col < V.width && y < V.height) live |= 1u << (RS * k);
+        if (px0 + col < V.width && y < V.height) {
+            if (redo) {
+                const int64_t pix = (int64_t)y * V.width + px0 + col;
+                T[k] = t_final[V.px_offset + pix];
+                C0[k] = img[pix];
+                C1[k] = img[plane + pix];
+                C2[k] = img[2 * plane + pix];
+                const uint32_t nl = n_last[V.px_offset + pix];
+                last[k] = nl & 0x7fffffffu;
+                if (nl >> 31) live |= 1u << (RS * k);
+            } else {
+                live |= 1u << (RS * k);
+            }
+        }
     }
+    const uint32_t begin = redo ? min(start + tile_resume[tile], end) : start;
     uint32_t n_blend = 0, n_eval = 0;
+    if (redo && tid == 0) {
+        n_blend = tile_stats[2 * tile];
+        n_eval = tile_stats[2 * tile + 1];
+    }
     // Software pipeline over the batches: the entry indices are loaded two
     // batches ahead and (one entry per lane, B <= 64) the records one batch
     // ahead, so the gathers of a batch run while the previous one composites
@@ -222,8 +250,8 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
     uint32_t e_cur[NE], e_next[NE];
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
-        e_cur[i] = entry_at(start, i);
-        e_next[i] = entry_at(start + (uint32_t)B, i);
+        e_cur[i] = entry_at(begin, i);
+        e_next[i] = entry_at(begin + (uint32_t)B, i);
     }
     float4 q0, q1, q2;   // records of the lane's entry of the current batch (NE == 1)
     if constexpr (NE == 1) {
@@ -231,7 +259,7 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
         q1 = rec[3 * (int64_t)e_cur[0] + 1];
         q2 = rec[3 * (int64_t)e_cur[0] + 2];
     }
-    for (uint32_t b0 = start; b0 < end; b0 += (uint32_t)B) {
+    for (uint32_t b0 = begin; b0 < end; b0 += (uint32_t)B) {
         if (ballot(live != 0u) == 0) break;
         __syncthreads();
         const int cnt = (int)min((uint32_t)B, end - b0);
@@ -299,19 +327,24 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
         }
     }
 
-    const int64_t plane = (int64_t)V.width * V.height;
-    float* img = out_rgb + 3 * V.px_offset;
+    // a pixel still live at the end of a list cut by the split prefix: the
+    // tile is resumed by the second pass over its whole list, after the whole
+    // lists of its super-tile have been split; until then its pixels hold the
+    // state to resume from
+    const bool suspend = !redo && tile_state != nullptr && ballot(live != 0u) != 0 &&
+                         tile_state[tile] == kTileTruncated;
     const int x = px0 + col;
 #pragma unroll
     for (int k = 0; k < PIX; ++k) {
         const int y = py0 + row0 + RS * k;
         if (x >= V.width || y >= V.height) continue;
         const int64_t pix = (int64_t)y * V.width + x;
-        img[pix] = fmaf(T[k], rp.bg[0], C0[k]);
-        img[plane + pix] = fmaf(T[k], rp.bg[1], C1[k]);
-        img[2 * plane + pix] = fmaf(T[k], rp.bg[2], C2[k]);
+        const bool lk = (live >> (RS * k)) & 1u;
+        img[pix] = suspend ? C0[k] : fmaf(T[k], rp.bg[0], C0[k]);
+        img[plane + pix] = suspend ? C1[k] : fmaf(T[k], rp.bg[1], C1[k]);
+        img[2 * plane + pix] = suspend ? C2[k] : fmaf(T[k], rp.bg[2], C2[k]);
         t_final[V.px_offset + pix] = T[k];
-        n_last[V.px_offset + pix] = last[k];
+        n_last[V.px_offset + pix] = suspend && lk ? last[k] | 0x80000000u : last[k];
     }
     // the backward walks every pixel's list up to its last blended Gaussian:
     // the tile's longest such prefix is its work
@@ -327,6 +360,15 @@ __global__ void __launch_bounds__(kLanes) raster_forward_kernel(
         tile_cost[tile] = tile_last;
         tile_stats[2 * tile] = nb;
         tile_stats[2 * tile + 1] = ne2;
+        if (redo) {
+            tile_state[tile] = kTileWhole;
+        } else if (suspend) {
+            const int S = rp.super_tile;
+            tile_state[tile] = kTileIncomplete;
+            tile_resume[tile] = end - start;
+            sup_redo[V.sup_offset + (ty / S) * V.sup_x + tx / S] = 1u;
+            counters[kRedo] = 1u;
+        }
     }
 }
 
@@ -575,10 +617,21 @@ hipError_t launch_rasterize(const RasterDev& rp, const Layout& L, char* ws, floa
     uint32_t* cost = reinterpret_cast<uint32_t*>(ws + L.tile_cost);
     uint32_t* stats = reinterpret_cast<uint32_t*>(ws + L.tile_stats);
     const uint32_t entries = (uint32_t)std::max<int64_t>(1, L.entries);
+    uint32_t* state = rp.prefix_segs > 0 ? reinterpret_cast<uint32_t*>(ws + L.tile_state) : nullptr;
+    uint32_t* sup_redo = reinterpret_cast<uint32_t*>(ws + L.sup_redo);
+    uint32_t* resume = reinterpret_cast<uint32_t*>(ws + L.tile_resume);
     const dim3 grid((unsigned)L.total_tiles), block(kLanes);
     SGS_RASTER_DISPATCH(raster_forward_kernel, views, rp, ranges, entry, rec, out_rgb, tf, nl,
-                        stats, cost, entries);
+                        stats, cost, entries, state, resume, sup_redo, cnt, false);
     if (hipError_t err = hipGetLastError(); err != hipSuccess) return err;
+    if (state != nullptr) {
+        // tiles whose list prefix ran out with live pixels: the whole lists of
+        // their super-tiles, then their compositing resumed
+        if (hipError_t err = launch_split_rest(rp, L, ws, s); err != hipSuccess) return err;
+        SGS_RASTER_DISPATCH(raster_forward_kernel, views, rp, ranges, entry, rec, out_rgb, tf, nl,
+                            stats, cost, entries, state, resume, sup_redo, cnt, true);
+        if (hipError_t err = hipGetLastError(); err != hipSuccess) return err;
+    }
     hipLaunchKernelGGL(sum_tile_stats_kernel, dim3(1), dim3(kStatThreads), 0, s, stats, cost,
                        L.total_tiles, cnt);
     return hipGetLastError();

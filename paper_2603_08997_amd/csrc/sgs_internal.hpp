@@ -16,6 +16,7 @@ constexpr int kRecordFloats = 12;           // u v a b | c o rx ry | r g b clamp
 constexpr int kAccumFloats = 12;            // du dv da db | dc do dr dg | db - - -
 constexpr int kDefaultSuperTile = 8;        // super-tile edge in tiles
 constexpr int kDefaultBatch = 64;           // list entries per compositing batch
+constexpr int kDefaultSplitPrefix = 8192;   // super-tile list pairs split before compositing
 
 // Per-view constants. A call's views live in device memory (the workspace's
 // view table): a one-thread kernel stores them there at the start of every
@@ -49,6 +50,7 @@ struct RasterDev {
     int32_t batch;         // list entries per compositing batch (and per list chunk)
     int32_t key_bits;      // low bits of a pair key: the super-tile index
     int32_t rect_bits;     // bits per coordinate of the tile rectangle above them
+    int32_t prefix_segs;   // segments of a long super-tile list split before compositing (0: all)
     float bg[3];
     float near_z, dilation, alpha_min, alpha_max, t_min;
     float log2_alpha_min;  // log2(alpha_min), rounded from binary64 (-inf for 0)
@@ -77,6 +79,8 @@ enum Counter : int {
     kItems = 9,         // tile-list entries needed (saturating)
     kSegments = 10,     // super-tile list segments of the tile-list split
     kUsed = 11,         // tile-list entries up to each tile's last blended one (summed)
+    kItemsRest = 12,    // tile-list entries of the completing split (saturating)
+    kRedo = 13,         // 1: a tile reached the end of its list prefix with live pixels
     kNumCounters = 16
 };
 
@@ -111,6 +115,21 @@ constexpr int64_t segment_slots(int64_t capacity, int64_t supers) {
     return (capacity + kSegPairs - 1) / kSegPairs + supers;
 }
 
+// With a split prefix, a super-tile list longer than kCutFactor prefixes is
+// split only in its first prefix_segs segments before compositing (the tiles
+// that composite a whole short list, often into the background, never wait
+// for a second split; long lists are where the split's work is).
+constexpr uint32_t kCutFactor = 4;
+__host__ __device__ constexpr uint32_t split_segments(uint32_t segs, uint32_t prefix_segs) {
+    return prefix_segs > 0 && segs > kCutFactor * prefix_segs ? prefix_segs : segs;
+}
+// Per tile (tile_state):
+enum TileState : uint32_t {
+    kTileWhole = 0,       // the tile's list is whole
+    kTileTruncated = 1,   // its super-tile's list is longer than the prefix
+    kTileIncomplete = 2,  // truncated, and a pixel was still live at the end of the list
+};
+
 struct Layout {
     int64_t entries, total_tiles, total_pixels, total_supers, capacity, seg_slots;
     int n_views;
@@ -119,8 +138,8 @@ struct Layout {
     int batch;
     size_t views, records, tiles, depth, dkey[2], dval[2], offsets, window_first, scan_sums,
         pair_key[2], pair_entry[2], sort_hist, sort_totals, sup_ranges, seg_first, seg_cnt,
-        seg_off, pair_mask, tile_entry, tile_ranges, tile_cost, tile_stats, tile_order, t_final,
-        n_last, accum, counters, total;
+        seg_off, pair_mask, tile_entry, tile_ranges, tile_state, tile_resume, sup_redo, tile_cost,
+        tile_stats, tile_order, t_final, n_last, accum, counters, total;
 };
 
 bool make_views(const sgs_camera* cams, int n_views, const sgs_raster_params* rp, Views* out,
@@ -143,6 +162,11 @@ hipError_t launch_load_records(const float* u, const float* v, const float* dept
                                const float* rgb, int64_t n, const RasterDev& rp, const Layout& L,
                                char* ws, hipStream_t s);
 hipError_t launch_bin(const RasterDev& rp, int64_t n, const Layout& L, char* ws, hipStream_t s);
+// After a compositing forward over list prefixes: the whole lists of the
+// super-tiles that have a tile marked incomplete (tile_state 2), appended
+// after the prefix lists, and the new ranges of the incomplete tiles. Every
+// kernel returns at once unless counters[kRedo] is set.
+hipError_t launch_split_rest(const RasterDev& rp, const Layout& L, char* ws, hipStream_t s);
 hipError_t launch_rasterize(const RasterDev& rp, const Layout& L, char* ws, float* out_rgb,
                             hipStream_t s);
 hipError_t launch_rasterize_backward(const RasterDev& rp, const Layout& L, char* ws,

@@ -44,7 +44,8 @@ class CameraC(C.Structure):
 
 class RasterParamsC(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
-                ("super_tile", C.c_int32), ("lds_batch", C.c_int32), ("bg", C.c_float * 3),
+                ("super_tile", C.c_int32), ("lds_batch", C.c_int32),
+                ("split_prefix", C.c_int32), ("bg", C.c_float * 3),
                 ("near_z", C.c_float), ("dilation", C.c_float), ("alpha_min", C.c_float),
                 ("alpha_max", C.c_float), ("t_min", C.c_float), ("jac_clamp", C.c_float)]
 
@@ -179,6 +180,7 @@ class RasterParams:
     tile_h: int = 16
     super_tile: int = 8
     lds_batch: int = 64
+    split_prefix: int = 8192
     bg: tuple = (0.0, 0.0, 0.0)
     near_z: float = 0.2
     dilation: float = 0.3
@@ -192,6 +194,7 @@ class RasterParams:
         r.struct_size = C.sizeof(RasterParamsC)
         r.tile_w, r.tile_h = self.tile_w, self.tile_h
         r.super_tile, r.lds_batch = self.super_tile, self.lds_batch
+        r.split_prefix = self.split_prefix
         for k in range(3):
             r.bg[k] = self.bg[k]
         r.near_z, r.dilation = self.near_z, self.dilation
@@ -325,8 +328,10 @@ def read_status(workspace, stream=None):
 def read_counters(workspace, stream=None) -> dict:
     """Synchronises and reads the workspace counters (offset 0): status bits,
     visible entries, super-tile pairs (needed, written, kept), tile-list
-    entries (needed; up to each tile's last blend), list segments, and the
-    blended / examined (pixel, Gaussian) pairs of the last bin + rasterize."""
+    entries (of the prefix split; up to each tile's last blend; of the
+    completing split), list segments, whether a tile needed more than its
+    list prefix, and the blended / examined (pixel, Gaussian) pairs of the
+    last bin + rasterize."""
     s = torch.cuda.current_stream() if stream is None else stream
     s.synchronize()
     w = workspace[:64].cpu().numpy().view(np.uint32)
@@ -334,7 +339,7 @@ def read_counters(workspace, stream=None) -> dict:
     return {"status": int(w[0]), "visible": int(w[1]), "pairs": int(w[2]),
             "pairs_written": int(w[3]), "blended": u64(4), "evaluated": u64(6),
             "pairs_kept": int(w[8]), "items": int(w[9]), "segments": int(w[10]),
-            "used": int(w[11])}
+            "used": int(w[11]), "items_rest": int(w[12]), "redo": int(w[13])}
 
 
 def clear_status(workspace, stream=None):

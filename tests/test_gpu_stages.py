@@ -165,7 +165,8 @@ def _check_binning(cams, tile, ties, n, seed, super_tile=8, alpha_min=None):
     recs, cat = _records(n, cams, seed, max_radius=20, tie_fraction=ties)
     extra = {} if alpha_min is None else {"alpha_min": alpha_min}
     say(f"binning tile={tile} S={super_tile} ties={ties} n={n} views={len(cams)} {extra}")
-    rp = m.RasterParams(tile_w=tw, tile_h=th, super_tile=super_tile, **extra)
+    # whole lists (no split prefix): the lists sgs_bin leaves are complete
+    rp = m.RasterParams(tile_w=tw, tile_h=th, super_tile=super_tile, split_prefix=0, **extra)
     st = Stage(n, cams, rp, cat, 400_000)
     assert st.flags == 0
     sups, vals, ranges = _oracle_super_lists(recs, cams, n, tw, th, super_tile)
@@ -281,7 +282,7 @@ def test_tile_list_overflow():
     cams = [S.look_at_camera((3.0, 1.0, 1.0), 255, 255)]
     n = 20000
     recs, cat = _records(n, cams, 21, max_radius=24)
-    rp = m.RasterParams(tile_w=8, tile_h=8, super_tile=8, lds_batch=32)
+    rp = m.RasterParams(tile_w=8, tile_h=8, super_tile=8, lds_batch=32, split_prefix=0)
     probe = Stage(n, cams, rp, cat, 400_000)
     rgb_ref, _, _ = probe.rasterize()
     assert probe.flags == 0
@@ -291,6 +292,110 @@ def test_tile_list_overflow():
     assert st.pairs == probe.items
     assert not tile_lists(st.ws, st.L)          # no partial lists
     st = Stage(n, cams, rp, cat, st.pairs)
+    rgb, _, _ = st.rasterize()
+    assert st.flags == 0
+    assert np.array_equal(rgb, rgb_ref)
+
+
+def _tile_need(nl, cams, tw, th):
+    """Per tile (global index): the largest list position any of its pixels
+    blends up to (n_last)."""
+    need, off, poff = {}, 0, 0
+    for cam in cams:
+        tx_n = (cam.width + tw - 1) // tw
+        ys, xs = np.divmod(np.arange(cam.width * cam.height), cam.width)
+        t = off + (ys // th) * tx_n + xs // tw
+        m = np.zeros(_tiles_of(cam, tw, th), np.int64)
+        np.maximum.at(m, t - off, nl[poff:poff + cam.width * cam.height].astype(np.int64))
+        need.update({off + k: int(x) for k, x in enumerate(m)})
+        off += _tiles_of(cam, tw, th)
+        poff += cam.width * cam.height
+    return need
+
+
+PREFIX = 2048
+
+
+def _prefix_scene():
+    # dense overlapping records in super-tiles of 8x8 small tiles: the
+    # super-tile lists run to thousands of pairs; in the small second view
+    # they are long enough to be cut by the prefix, and there some tiles
+    # terminate within it while others need their whole lists
+    cams = [S.look_at_camera((3.0, 1.0, 1.0), 255, 255), S.look_at_camera((0.5, -3.0, 2.0), 120, 90)]
+    n = 40000
+    recs, cat = _records(n, cams, 41, max_radius=24)
+    return cams, n, recs, cat
+
+
+def test_split_prefix_matches_whole_lists():
+    """Tile lists split from 2048-pair prefixes of the long super-tile lists
+    and completed on the device for the tiles that need more: image, T_final and
+    last positions bit-identical to those of whole lists, the same work
+    counters, every list after compositing a prefix of the whole list that
+    covers the tile's blended entries (some strictly shorter), gradients equal
+    up to the order of the float atomic additions."""
+    require_gpu()
+    m = sg()
+    cams, n, recs, cat = _prefix_scene()
+    base = dict(tile_w=8, tile_h=8, super_tile=8, lds_batch=32)
+    say(f"split prefix: n={n} views={len(cams)} {base}")
+    whole = Stage(n, cams, m.RasterParams(split_prefix=0, **base), cat, 3_000_000)
+    w_rgb, w_tf, w_nl = whole.rasterize()
+    pre = Stage(n, cams, m.RasterParams(split_prefix=PREFIX, **base), cat, 3_000_000)
+    p_rgb, p_tf, p_nl = pre.rasterize()
+    assert whole.flags == 0 and pre.flags == 0
+    cw, cp = m.read_counters(whole.ws), m.read_counters(pre.ws)
+    say(f"  whole: items {cw['items']}; prefix: items {cp['items']} + rest {cp['items_rest']}, "
+        f"redo {cp['redo']}")
+    assert cw["redo"] == 0 and cw["items_rest"] == 0
+    assert cp["redo"] == 1 and cp["items"] < cw["items"]
+    assert np.array_equal(p_rgb, w_rgb)
+    assert np.array_equal(p_tf, w_tf)
+    assert np.array_equal(p_nl, w_nl)
+    for k in ("blended", "evaluated", "used"):
+        assert cp[k] == cw[k], k
+    lw, lp = tile_lists(whole.ws, whole.L), tile_lists(pre.ws, pre.L)
+    need = _tile_need(w_nl, cams, 8, 8)
+    empty = np.zeros(0, np.int64)
+    cut = 0
+    for t, wl in lw.items():
+        pl = lp.get(t, empty)
+        assert np.array_equal(pl, wl[:len(pl)]), t
+        assert len(pl) >= need[t], t
+        cut += int(len(pl) < len(wl))
+    assert not set(lp) - set(lw)
+    say(f"  tiles with a strict prefix list: {cut} of {len(lw)}")
+    assert cut > 0
+    rng = np.random.default_rng(3)
+    dl = rng.normal(0, 1, len(w_rgb)).astype(np.float32)
+    gw, gp = whole.backward(dl), pre.backward(dl)
+    assert rel_max_err(gp, gw) < 1e-5, rel_max_err(gp, gw)
+
+
+def test_split_rest_overflow():
+    """Capacity for the prefix lists but not for the completing split: the
+    compositing call flags the overflow and reports the capacity both splits
+    need; with that capacity the image equals the whole-list image."""
+    require_gpu()
+    m = sg()
+    cams, n, recs, cat = _prefix_scene()
+    base = dict(tile_w=8, tile_h=8, super_tile=8, lds_batch=32)
+    ref = Stage(n, cams, m.RasterParams(split_prefix=0, **base), cat, 3_000_000)
+    rgb_ref, _, _ = ref.rasterize()
+    rp = m.RasterParams(split_prefix=PREFIX, **base)
+    probe = Stage(n, cams, rp, cat, 3_000_000)
+    probe.rasterize()
+    c = m.read_counters(probe.ws)
+    total = c["items"] + c["items_rest"]
+    cap = max(c["pairs"], c["items"])
+    say(f"  pairs {c['pairs']} prefix items {c['items']} rest {c['items_rest']} cap {cap}")
+    assert c["items_rest"] > 0 and cap < total
+    st = Stage(n, cams, rp, cat, cap)
+    assert st.flags == 0                       # the prefix lists fit
+    st.rasterize()
+    assert st.flags & m.STATUS_PAIR_OVERFLOW
+    assert m.read_status(st.ws)[2] == total
+    st = Stage(n, cams, rp, cat, total)
     rgb, _, _ = st.rasterize()
     assert st.flags == 0
     assert np.array_equal(rgb, rgb_ref)
