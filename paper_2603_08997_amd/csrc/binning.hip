@@ -889,8 +889,11 @@ static hipError_t launch_split(const RasterDev& rp, const Layout& L, char* ws, h
                            SegCountSrc{ranges, L.total_supers, (uint32_t)rp.prefix_segs}, seg_first);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     // grid-stride over the segments: at most a few resident waves per SIMD
+    // (the completing split, usually idle and otherwise a few super-tiles,
+    // on a quarter of the grid)
+    const int64_t blocks = rest ? kSplitBlocks / 4 : kSplitBlocks;
     const dim3 sgrid((unsigned)std::min<int64_t>((L.seg_slots + kSplitWaves - 1) / kSplitWaves,
-                                                 kSplitBlocks));
+                                                 blocks));
     const uint32_t entries = (uint32_t)std::max<int64_t>(1, L.entries);
     hipLaunchKernelGGL(split_count_kernel, sgrid, dim3(kSplitWaves * 64), 0, s, views, rp,
                        seg_first, ranges, skey, sentry, rec, entries, mask, seg_cnt);
@@ -902,7 +905,7 @@ static hipError_t launch_split(const RasterDev& rp, const Layout& L, char* ws, h
                       sums, counters + (rest ? kItemsRest : kItems), s);
     if (err != hipSuccess) return err;
     const dim3 wgrid((unsigned)std::min<int64_t>((L.seg_slots + kWriteWaves - 1) / kWriteWaves,
-                                                 kSplitBlocks));
+                                                 blocks));
     hipLaunchKernelGGL(split_write_kernel, wgrid, dim3(kWriteWaves * 64), 0, s, views, rp,
                        seg_first, ranges, sentry, mask, seg_off, counters, L.capacity, tile_entry);
     if ((err = hipGetLastError()) != hipSuccess) return err;
@@ -969,14 +972,17 @@ hipError_t launch_bin(const RasterDev& rp, int64_t n, const Layout& L, char* ws,
                            pentry[0]);
         if ((err = hipGetLastError()) != hipSuccess) return err;
         // stable sort of the pairs by super-tile; the first pass drops culled
-        // pairs and counts the rest into counters[kPairsKept]
+        // pairs and counts the rest into counters[kPairsKept]; a one-pass sort
+        // (at most 255 super-tiles) also writes the super-tile ranges
         int kres = 0;
+        const bool one_pass = L.key_passes == 1 && L.total_supers > 0;
         err = radix_sort(pkey, pentry, counters + kPairsWritten, L.capacity, L.key_bits, hist,
-                         totals, s, &kres, counters + kPairsKept);
+                         totals, s, &kres, counters + kPairsKept, nullptr, nullptr,
+                         one_pass ? ranges : nullptr, one_pass ? (int)L.total_supers : 0);
         if (err != hipSuccess) return err;
     }
     const dim3 rgrid((unsigned)((L.total_supers + 255) / 256));
-    if (L.total_supers > 0)
+    if (L.total_supers > 0 && (E == 0 || L.key_passes != 1))
         hipLaunchKernelGGL(ranges_kernel, rgrid, dim3(256), 0, s, pkey[L.key_result], counters,
                            L.total_supers, L.key_bits, ranges);
     if ((err = hipGetLastError()) != hipSuccess) return err;

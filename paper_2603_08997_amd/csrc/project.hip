@@ -1,6 +1,8 @@
 // Projection of 3D Gaussians (paper Sec. 3, Eqs. 2-3, SH colour) and its
 // adjoint. One thread per (view, Gaussian) entry; parameters are read as
 // coalesced planes of the [F][stride] layout.
+#include <algorithm>
+
 #include "sgs_internal.hpp"
 #include "sgs_device.hpp"
 
@@ -398,6 +400,7 @@ __device__ __forceinline__ bool geom_grads(const float mu[3], const float ls[3],
 #define SGS_UPDATE_BATCH 8
 #endif
 constexpr int kBackwardThreads = SGS_BACKWARD_THREADS;
+constexpr int64_t kAdamBlocks = 2048;   // grid of the fused backward + Adam step
 constexpr int kUpdateBatch = SGS_UPDATE_BATCH;
 
 // dL/d(mean) through the view direction of one view: with w_k = sum_c
@@ -568,11 +571,14 @@ __global__ void __launch_bounds__(kBackwardThreads) project_backward_adam_kernel
     __shared__ AdamStep s_as;
     if (threadIdx.x == 0) s_as = adam_bias_correction(ad, *step);
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     const AdamStep as = s_as;
-    gaussian_backward<sh_degree, true, kMulti, kSparse>(planes, n, stride, i, views, rp, rec,
-                                                        tiles, acc, nullptr, &ad, &as, m, v);
+    // grid-stride over the Gaussians on a grid sized for the machine, so that
+    // a closed gate costs a launch of a few thousand workgroups, not one per
+    // 256 Gaussians
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        gaussian_backward<sh_degree, true, kMulti, kSparse>(planes, n, stride, i, views, rp, rec,
+                                                            tiles, acc, nullptr, &ad, &as, m, v);
 }
 
 }  // namespace
@@ -652,7 +658,7 @@ hipError_t launch_project_backward_adam(float* planes, int64_t n, int64_t stride
     if (err != hipSuccess || n == 0) return err;
     const AdamDev ad = make_adam(prm);
     const int nt = kBackwardThreads;
-    const int64_t nb = (n + nt - 1) / nt;
+    const int64_t nb = std::min<int64_t>((n + nt - 1) / nt, kAdamBlocks);
     const Views* views = reinterpret_cast<const Views*>(ws + L.views);
     const float4* rec = reinterpret_cast<const float4*>(ws + L.records);
     const uint32_t* tl = reinterpret_cast<const uint32_t*>(ws + L.tiles);

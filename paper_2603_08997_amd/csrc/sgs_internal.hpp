@@ -191,11 +191,14 @@ int radix_passes(int bits);
 // remaining pairs there; later passes sort that many.
 // gather_dst (nullable): the last pass also writes gather_src[value] at each
 // sorted position.
+// ranges_out (nullable; one-pass sorts only): [start, end) of the run of each
+// digit d < n_ranges in the sorted output ([0, 0) when empty).
 template <typename K>
 hipError_t radix_sort(K* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int64_t n_max,
                       int bits, uint32_t* hist, uint32_t* totals, hipStream_t s, int* result,
                       uint32_t* kept_dev = nullptr, const uint32_t* gather_src = nullptr,
-                      uint32_t* gather_dst = nullptr);
+                      uint32_t* gather_dst = nullptr, uint32_t* ranges_out = nullptr,
+                      int n_ranges = 0);
 int64_t radix_blocks(int64_t n_max);
 
 // Loss / gate / Adam

@@ -163,7 +163,8 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
     K* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
     const uint32_t* __restrict__ n_dev, int shift, int bits, const uint32_t* __restrict__ hist,
     const uint32_t* __restrict__ totals, int nblocks, bool skip_culled,
-    const uint32_t* __restrict__ gather_src, uint32_t* __restrict__ gather_dst) {
+    const uint32_t* __restrict__ gather_src, uint32_t* __restrict__ gather_dst,
+    uint32_t* __restrict__ ranges_out, int n_ranges) {
     __shared__ K lkeys[kTile];
     __shared__ uint32_t lvals[kTile];
     __shared__ uint32_t gbase[kRadix];          // global start of this block's digit run
@@ -172,10 +173,22 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
 
     const uint32_t n = *n_dev;
     const int active = (int)(((int64_t)n + kTile - 1) / kTile);
+    const int tid = threadIdx.x, w = tid / 64, lane = tid % 64;
+    if (ranges_out != nullptr && blockIdx.x == 0) {
+        // a one-pass sort: [start, end) of every digit's run in the output
+        // (empty runs: [0, 0)), from the digit totals
+        uint32_t tot;
+        const bool used = tid < (1 << bits);
+        const uint32_t c = used ? totals[tid] : 0u;
+        const uint32_t ex = block_excl_scan<kThreads>(c, smem, &tot);
+        if (tid < n_ranges) {
+            ranges_out[2 * tid] = c ? ex : 0u;
+            ranges_out[2 * tid + 1] = c ? ex + c : 0u;
+        }
+    }
     if ((int)blockIdx.x >= active) return;  // uniform across the block
     const int blk = xcd_block(blockIdx.x, active);
     const int64_t base = (int64_t)blk * kTile;
-    const int tid = threadIdx.x, w = tid / 64, lane = tid % 64;
     const uint32_t mask = (1u << bits) - 1u;
     const int nvalid = (int)min((int64_t)kTile, (int64_t)n - base);
     constexpr int kPerWave = kTile / kWaves;
@@ -274,8 +287,11 @@ static int pass_bits(int bits, int p, int* shift) {
 template <typename K>
 hipError_t radix_sort(K* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int64_t n_max,
                       int bits, uint32_t* hist, uint32_t* totals, hipStream_t s, int* result,
-                      uint32_t* kept_dev, const uint32_t* gather_src, uint32_t* gather_dst) {
+                      uint32_t* kept_dev, const uint32_t* gather_src, uint32_t* gather_dst,
+                      uint32_t* ranges_out, int n_ranges) {
     const int passes = radix_passes(bits);
+    if (ranges_out != nullptr && (passes != 1 || n_ranges > (1 << bits)))
+        return hipErrorInvalidValue;   // digit runs are the sorted runs of one pass only
     const int nb = (int)radix_blocks(n_max);
     int cur = 0;
     for (int p = 0; p < passes; ++p) {
@@ -291,7 +307,8 @@ hipError_t radix_sort(K* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int6
         const bool last = p == passes - 1;
         hipLaunchKernelGGL(radix_scatter_kernel<K>, dim3(nb), dim3(kThreads), 0, s, keys[cur],
                            vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_p, shift, pb, hist, totals,
-                           nb, skip, last ? gather_src : nullptr, last ? gather_dst : nullptr);
+                           nb, skip, last ? gather_src : nullptr, last ? gather_dst : nullptr,
+                           ranges_out, n_ranges);
         cur ^= 1;
     }
     if (kept_dev != nullptr && passes == 0)
@@ -302,6 +319,6 @@ hipError_t radix_sort(K* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int6
 
 template hipError_t radix_sort<uint32_t>(uint32_t* keys[2], uint32_t* vals[2], const uint32_t*,
                                          int64_t, int, uint32_t*, uint32_t*, hipStream_t, int*,
-                                         uint32_t*, const uint32_t*, uint32_t*);
+                                         uint32_t*, const uint32_t*, uint32_t*, uint32_t*, int);
 
 }  // namespace sgs
