@@ -17,7 +17,7 @@ namespace sgs {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kItems = 16;
+constexpr int kItems = 8;
 constexpr int kTile = kThreads * kItems;  // keys per block
 constexpr int kRadix = 256;
 constexpr int kWaves = kThreads / 64;
