@@ -7,6 +7,7 @@ and the FP64 oracle timed on the host as a CPU reference.
     python bench.py --workload single      # 1M Gaussians, per-view stage medians
     python bench.py --workload dense       # 6M dense scene: backward GB/s, peak memory
     python bench.py --workload batched     # 8 mixed-resolution views per launch
+    python bench.py --workload densify     # clone / split / prune step and its statistic
 
 Workload (defaults): 3,000,000 Gaussians (SH degree 3, ground-plane + two
 clusters), 200 views at 1600x1060 on a hemisphere of radius 4-5, 16x16 tiles,
@@ -92,7 +93,8 @@ def parse():
                     help="batched workload: the tuner's JSON store (default ~/.cache/skipgs)")
     ap.add_argument("--retune", action="store_true",
                     help="batched workload: tune again even if a stored choice exists")
-    ap.add_argument("--workload", choices=["train", "matched", "single", "dense", "batched"],
+    ap.add_argument("--workload", choices=["train", "matched", "single", "dense", "batched",
+                                           "densify"],
                     default="train")
     return ap.parse_args()
 
@@ -658,6 +660,102 @@ def run_dense(args):
     print(json.dumps(out), flush=True)
 
 
+def run_densify(args):
+    """One adaptive-density-control step (clone / split / prune, Sec. 3) over
+    the 3,000,000-Gaussian SH-3 training set, and the view-space gradient
+    statistic gathered after a 1600x1060 render backward. Synthetic
+    statistic: view counts U{0..11} and sums count * threshold * U(0.2, 1.1),
+    so about a tenth of the seen Gaussians densify (about half of those
+    split); opacity logits as drawn (some prune)."""
+    from paper_2603_08997_amd import scenes as S
+    from paper_2603_08997_amd import skipgs as sk
+    from paper_2603_08997_amd.train import measure_capacity
+    n = args.n
+    scene = S.mixture_scene(S.SEED_SCENE, n, 3)
+    F = 11 + 3 * 16
+    rng = np.random.default_rng(11)
+    planes = torch.as_tensor(scene.to_planes()).cuda()
+    m = torch.zeros_like(planes)
+    v = torch.zeros_like(planes)
+    count = rng.integers(0, 12, n).astype(np.int32)
+    g = (count * 2e-4 * rng.uniform(0.2, 1.1, n)).astype(np.float32)
+    d_g, d_c = torch.as_tensor(g).cuda(), torch.as_tensor(count).cuda()
+    normals = torch.as_tensor(rng.standard_normal((n, 2, 3)).astype(np.float32)).cuda()
+    dp = sk.DensifyParams(scene_extent=6.0)
+    cap = S.padded_stride(2 * n)
+    outs = [torch.empty(F, cap, device="cuda") for _ in range(3)]
+    ws = sk.alloc_bytes(sk.densify_workspace_size(n))
+    d_n = torch.zeros(1, dtype=torch.int64, device="cuda")
+    step = lambda: sk.densify(dp, planes, n, 3, m, v, d_g, d_c, normals, *outs, ws, d_n)
+    steps = args.steps if args.steps is not None else 20
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        step()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    n_out = int(d_n.item())
+    # outcomes, for the algorithmic bytes: decision inputs (logit, three
+    # log-scales, statistic sum and count: 24 B) read by both passes; a kept
+    # Gaussian reads and writes parameters and both moments (3 x 4F each
+    # way); a clone writes 3 x 4F; a split Gaussian reads its parameters and
+    # draws (4F + 24 B) and writes two children (2 x 3 x 4F)
+    lg = planes[10, :n].cpu().numpy()
+    ls = planes[3:6, :n].cpu().numpy().max(axis=0)
+    dv = dp.c()
+    lgt = np.float32(np.log(dv.min_opacity / (1 - dv.min_opacity)))
+    lst = np.float32(np.log(np.float64(dv.percent_dense) * np.float64(dv.scene_extent)))
+    alive = lg >= lgt
+    cand = alive & (count > 0) & (g.astype(np.float64) >= np.float64(np.float32(2e-4)) * count)
+    S_ = int((cand & (ls > lst)).sum())
+    Cn = int((cand & ~(ls > lst)).sum())
+    K = int(alive.sum()) - S_
+    assert n_out == K + Cn + 2 * S_, (n_out, K, Cn, S_)
+    step_bytes = 48 * n + K * 24 * F + Cn * 12 * F + S_ * (4 * F + 24 + 24 * F)
+    # the statistic after one render backward of a view
+    cam = S.hemisphere_cameras(S.SEED_CAMERAS, 1, args.width, args.height)[0]
+    rp = sk.RasterParams(super_tile=args.super_tile, lds_batch=args.lds_batch,
+                         split_prefix=args.split_prefix)
+    pcap = int(measure_capacity(scene, [cam], rp) * 1.2) + 4096
+    fws = sk.alloc_bytes(sk.forward_workspace_size(rp, n, [cam], pcap))
+    sk.clear_status(fws)
+    img = torch.empty(3 * cam.width * cam.height, device="cuda")
+    sk.render_forward(planes, n, 3, [cam], rp, fws, pcap, img)
+    grads = torch.zeros_like(planes)
+    sk.render_backward(planes, n, 3, [cam], rp, fws, pcap, torch.ones_like(img) * 1e-3, None,
+                       grads)
+    gs = torch.zeros(n, device="cuda")
+    cs = torch.zeros(n, dtype=torch.int32, device="cuda")
+    sk.densify_stats([cam], n, rp, fws, pcap, gs, cs)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(steps):
+        sk.densify_stats([cam], n, rp, fws, pcap, gs, cs)
+    b.record()
+    torch.cuda.synchronize()
+    stats_ms = a.elapsed_time(b) / steps
+    vis = int(sk.read_counters(fws)["visible"])
+    stats_bytes = n * 4 + vis * 8 + n * 8 * 2   # visibility words, du dv, sum and count r/w
+    gbs = step_bytes / (ms * 1e-3) / 1e9
+    out = {"metric": "densification step throughput", "value": n / (ms * 1e-3), "unit": "Gaussians/s",
+           "n_gpus": 1, "steps": steps, "warmup": 2, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"clone / split / prune step over {n} Gaussians SH3 "
+                                  f"(mixture scene, synthetic statistic) and the view-space "
+                                  f"gradient statistic of a {args.width}x{args.height} view"},
+           "outcomes": {"kept": K, "cloned": Cn, "split": S_, "pruned": n - int(alive.sum()),
+                        "n_out": n_out},
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs / HBM_PEAK_GBS, "bytes_per_step": step_bytes},
+           "stats_kernel": {"ms": stats_ms, "bytes": stats_bytes,
+                            "GBps": stats_bytes / (stats_ms * 1e-3) / 1e9, "visible": vis}}
+    print(json.dumps(out), flush=True)
+
+
 def run_batched(args):
     """Forward + backward of eight views of four resolutions (two each of
     640x480, 1245x825, 1600x1060, 980x545) of 2M Gaussians, gradients summed
@@ -795,6 +893,8 @@ def main():
         return run_single(args)
     if args.workload == "dense":
         return run_dense(args)
+    if args.workload == "densify":
+        return run_densify(args)
     if args.steps is None:
         args.steps = 2000
     if args.warmup is None:

@@ -380,6 +380,67 @@ sgs_status sgs_gate_read(const sgs_gate_params* p, const void* d_state,
                          void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Adaptive density control of the densification phase (Sec. 3): before T_d
+ * Gaussians are periodically cloned (high view-space positional gradient,
+ * small extent), split (high gradient, large extent) and pruned (opacity
+ * below a small threshold); from T_d on the set is fixed and the gate of
+ * Algorithm 1 takes over.
+ *
+ * Statistic (sgs_densify_stats, after a render backward): for every
+ * Gaussian visible in a view of the batch, || (dL/du W/2, dL/dv H/2) || (the
+ * gradient of its screen position in normalised device units, the image
+ * spanning [-1, 1] on each axis) is added to grad_sum[i] and the view counted
+ * in count[i] (device float / int32 arrays of n, accumulated by the caller's
+ * schedule and reset after each step).
+ *
+ * Step (sgs_densify): Gaussian i produces nothing when its opacity is below
+ * min_opacity; otherwise, when grad_sum[i] >= grad_threshold * count[i]
+ * (count > 0), it is kept and cloned when its largest scale is at most
+ * percent_dense * scene_extent, and replaced by two children when larger:
+ * centres mu + R(q) diag(s) z_j with z_j = normals[6 i + 3 j .. + 3]
+ * (standard-normal draws supplied by the caller, n x 2 x 3 floats), scales
+ * s / split_scale, all other parameters copied; every other Gaussian is kept.
+ * The new set is written to out_params / out_m / out_v ([F][out_stride],
+ * the parameter layout) as the kept Gaussians in index order, then the
+ * clones, then the children (two per split Gaussian); kept Gaussians keep
+ * their Adam moments, new ones get zeros. The size of the new set goes to
+ * *d_n_out (device int64); when it exceeds out_stride nothing is written and
+ * the caller calls again with larger planes. The decisions compare float32
+ * log-scales and opacity logits with float32 thresholds formed in binary64
+ * (log(percent_dense * scene_extent), logit(min_opacity)) and the gradient
+ * sum with threshold * count in binary64. Inputs and outputs must not
+ * overlap. workspace: sgs_densify_workspace_size(n) bytes of device memory.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    uint32_t struct_size;    /* sizeof(sgs_densify_params)                       */
+    float grad_threshold;    /* mean view-space gradient that densifies (2e-4)  */
+    float percent_dense;     /* clone / split boundary as a fraction of the     */
+                             /* scene extent (0.01)                             */
+    float scene_extent;      /* world-space extent of the scene (> 0)           */
+    float min_opacity;       /* opacity below this prunes (0.005), in [0, 1)    */
+    float split_scale;       /* children's scales = parent's / split_scale (1.6)*/
+} sgs_densify_params;
+
+void sgs_default_densify_params(sgs_densify_params* p);
+
+/* Adds the statistic of the last render backward in `workspace` (the views
+ * and visibility its forward stored, the record gradients its backward
+ * left); cams / n_views / rp / pair_capacity describe that workspace.
+ * Predicated on d_gate (nullable). */
+sgs_status sgs_densify_stats(const sgs_camera* cams, int32_t n_views, int64_t n,
+                             const sgs_raster_params* rp, const void* workspace,
+                             size_t workspace_bytes, int64_t pair_capacity, const int32_t* d_gate,
+                             float* grad_sum, int32_t* count, void* stream);
+
+sgs_status sgs_densify_workspace_size(int64_t n, size_t* bytes_out);
+
+sgs_status sgs_densify(const sgs_densify_params* p, const sgs_gaussians* g, const float* m,
+                       const float* v, const float* grad_sum, const int32_t* count,
+                       const float* normals, float* out_params, float* out_m, float* out_v,
+                       int64_t out_stride, void* workspace, size_t workspace_bytes,
+                       int64_t* d_n_out, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Adam (Kingma & Ba, with bias correction): the optimiser the 3DGS parameters
  * are trained with (Sec. 3) and the standard update SkipGS applies whenever
  * the gate runs the backward (Sec. 4, Algorithm 1; Sec. 5.1), per element of

@@ -861,3 +861,102 @@ sgs_status sgs_train_iteration(const sgs_gaussians* g, const sgs_camera* cams,
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Adaptive density control
+// ---------------------------------------------------------------------------
+namespace {
+
+sgs_status check_densify(const sgs_densify_params* p) {
+    if (!p) return fail(SGS_ERR_INVALID_ARG, "densify params are null");
+    if (p->struct_size != sizeof(sgs_densify_params))
+        return fail(SGS_ERR_INVALID_ARG, "densify params struct_size %u, expected %zu",
+                    p->struct_size, sizeof(sgs_densify_params));
+    if (!(p->grad_threshold >= 0.f) || !std::isfinite(p->grad_threshold) ||
+        !(p->percent_dense > 0.f) || !(p->scene_extent > 0.f) ||
+        !std::isfinite(p->percent_dense * p->scene_extent) || !(p->min_opacity >= 0.f) ||
+        !(p->min_opacity < 1.f) || !(p->split_scale > 0.f) || !std::isfinite(p->split_scale))
+        return fail(SGS_ERR_INVALID_ARG, "densify params out of range");
+    return SGS_OK;
+}
+
+sgs::DensifyDev make_densify(const sgs_densify_params* p) {
+    sgs::DensifyDev d;
+    d.grad_threshold = p->grad_threshold;
+    d.log_size = (float)std::log((double)p->percent_dense * (double)p->scene_extent);
+    const double mo = (double)p->min_opacity;
+    // logit(0) = -inf: nothing prunes
+    d.logit_min = mo > 0.0 ? (float)std::log(mo / (1.0 - mo)) : -INFINITY;
+    d.log_split = (float)std::log((double)p->split_scale);
+    return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sgs_default_densify_params(sgs_densify_params* p) {
+    if (!p) return;
+    p->struct_size = sizeof(sgs_densify_params);
+    p->grad_threshold = 2e-4f;
+    p->percent_dense = 0.01f;
+    p->scene_extent = 1.f;
+    p->min_opacity = 0.005f;
+    p->split_scale = 1.6f;
+}
+
+sgs_status sgs_densify_stats(const sgs_camera* cams, int32_t n_views, int64_t n,
+                             const sgs_raster_params* rp, const void* workspace,
+                             size_t workspace_bytes, int64_t pair_capacity, const int32_t* d_gate,
+                             float* grad_sum, int32_t* count, void* stream) {
+    Prepared P;
+    sgs_status st = prepare(rp, n, cams, n_views, pair_capacity, &P);
+    if (st != SGS_OK) return st;
+    if ((st = check_ws(P, workspace, workspace_bytes)) != SGS_OK) return st;
+    if (n > 0 && (!grad_sum || !count)) return fail(SGS_ERR_INVALID_ARG, "grad_sum or count is null");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SGS_HIP(sgs::launch_densify_stats(P.L, static_cast<char*>(const_cast<void*>(workspace)), n,
+                                      d_gate, grad_sum, count, s),
+            "densify_stats");
+    return SGS_OK;
+}
+
+sgs_status sgs_densify_workspace_size(int64_t n, size_t* bytes_out) {
+    if (!bytes_out) return fail(SGS_ERR_INVALID_ARG, "bytes_out is null");
+    if (n < 0) return fail(SGS_ERR_INVALID_ARG, "n < 0");
+    *bytes_out = sizeof(uint32_t) * (size_t)sgs::densify_scratch_words(sgs::densify_blocks(n));
+    return SGS_OK;
+}
+
+sgs_status sgs_densify(const sgs_densify_params* p, const sgs_gaussians* g, const float* m,
+                       const float* v, const float* grad_sum, const int32_t* count,
+                       const float* normals, float* out_params, float* out_m, float* out_v,
+                       int64_t out_stride, void* workspace, size_t workspace_bytes,
+                       int64_t* d_n_out, void* stream) {
+    sgs_status st = check_densify(p);
+    if (st != SGS_OK) return st;
+    if ((st = check_gaussians(g)) != SGS_OK) return st;
+    if (!m || !v || !out_params || !out_m || !out_v || !d_n_out)
+        return fail(SGS_ERR_INVALID_ARG, "moments, outputs or d_n_out are null");
+    if (g->n > 0 && (!grad_sum || !count || !normals))
+        return fail(SGS_ERR_INVALID_ARG, "grad_sum, count or normals are null");
+    if (out_stride <= 0 || out_stride % 64 != 0 || out_stride >= (int64_t(1) << 29))
+        return fail(SGS_ERR_INVALID_ARG, "out_stride %lld must be > 0, < 2^29 and a multiple of 64",
+                    (long long)out_stride);
+    if (!aligned(out_params, 16) || !aligned(out_m, 16) || !aligned(out_v, 16) ||
+        !aligned(m, 16) || !aligned(v, 16))
+        return fail(SGS_ERR_INVALID_ARG, "planes not 16-byte aligned");
+    const size_t need = sizeof(uint32_t) * (size_t)sgs::densify_scratch_words(sgs::densify_blocks(g->n));
+    if (!workspace || workspace_bytes < need || !aligned(workspace, 16))
+        return fail(SGS_ERR_CAPACITY, "densify workspace null, unaligned or below %zu bytes", need);
+    const int F = 11 + 3 * (g->sh_degree + 1) * (g->sh_degree + 1);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SGS_HIP(sgs::launch_densify(make_densify(p), g->data, const_cast<float*>(m),
+                                const_cast<float*>(v), g->n, g->stride, F, grad_sum, count, normals,
+                                out_params, out_m, out_v, out_stride,
+                                static_cast<uint32_t*>(workspace), d_n_out, s),
+            "densify");
+    return SGS_OK;
+}
+
+}  // extern "C"

@@ -201,6 +201,24 @@ hipError_t radix_sort(K* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int6
                       int n_ranges = 0);
 int64_t radix_blocks(int64_t n_max);
 
+// Adaptive density control. Thresholds as the kernels compare them (float32
+// values formed in binary64 on the host).
+struct DensifyDev {
+    float grad_threshold;   // the statistic's mean at or above which a Gaussian densifies
+    float log_size;         // log(percent_dense * scene_extent): larger max log-scale splits
+    float logit_min;        // logit(min_opacity): a smaller opacity logit prunes
+    float log_split;        // log(split_scale), subtracted from the children's log-scales
+};
+int64_t densify_blocks(int64_t n);
+// Scratch words of a step over n Gaussians.
+constexpr int64_t densify_scratch_words(int64_t blocks) { return 4 * blocks + 3; }
+hipError_t launch_densify_stats(const Layout& L, char* ws, int64_t n, const int32_t* gate,
+                                float* grad_sum, int32_t* count, hipStream_t s);
+hipError_t launch_densify(const DensifyDev& d, float* params, float* m, float* v, int64_t n,
+                          int64_t stride, int F, const float* grad_sum, const int32_t* count,
+                          const float* normals, float* out_params, float* out_m, float* out_v,
+                          int64_t out_stride, uint32_t* scratch, int64_t* n_out, hipStream_t s);
+
 // Loss / gate / Adam
 // target: the reference image, or with d_view non-null the image
 // *d_view (clamped into [0, n_targets)) of an array of n_targets images.

@@ -73,6 +73,12 @@ class GateSnapshotC(C.Structure):
                                          "last_forced", "last_view")]
 
 
+class DensifyParamsC(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("grad_threshold", C.c_float),
+                ("percent_dense", C.c_float), ("scene_extent", C.c_float),
+                ("min_opacity", C.c_float), ("split_scale", C.c_float)]
+
+
 class AdamParamsC(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("beta1", C.c_double), ("beta2", C.c_double),
                 ("eps", C.c_double), ("lr", C.c_float * MAX_PLANES), ("visible_only", C.c_int32)]
@@ -88,6 +94,8 @@ EXPORTS = [
     "sgs_gate_init", "sgs_gate_update", "sgs_gate_read", "sgs_adam_step",
     "sgs_project_backward_adam", "sgs_render_backward_adam", "sgs_camera_table_size",
     "sgs_camera_table_init", "sgs_view_sequence_next", "sgs_train_iteration",
+    "sgs_default_densify_params", "sgs_densify_stats", "sgs_densify_workspace_size",
+    "sgs_densify",
 ]
 
 
@@ -138,6 +146,12 @@ def _load():
         "sgs_train_iteration": (i32, [P(GaussiansC), P(CameraC), vp, i32, vp, P(RasterParamsC),
                                       vp, sz, i64, vp, f32, vp, sz, vp, vp, vp, P(GateParamsC),
                                       vp, vp, P(AdamParamsC), vp, vp, vp, vp]),
+        "sgs_default_densify_params": (None, [P(DensifyParamsC)]),
+        "sgs_densify_stats": (i32, [P(CameraC), i32, i64, P(RasterParamsC), vp, sz, i64, vp, vp,
+                                    vp, vp]),
+        "sgs_densify_workspace_size": (i32, [i64, P(sz)]),
+        "sgs_densify": (i32, [P(DensifyParamsC), P(GaussiansC), vp, vp, vp, vp, vp, vp, vp, vp,
+                              i64, vp, sz, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -444,6 +458,47 @@ class AdamParams:
         for k, v in enumerate(self.lr):
             a.lr[k] = float(v)
         return a
+
+
+@dataclass
+class DensifyParams:
+    grad_threshold: float = 2e-4
+    percent_dense: float = 0.01
+    scene_extent: float = 1.0
+    min_opacity: float = 0.005
+    split_scale: float = 1.6
+
+    def c(self) -> DensifyParamsC:
+        d = DensifyParamsC()
+        d.struct_size = C.sizeof(DensifyParamsC)
+        d.grad_threshold, d.percent_dense = self.grad_threshold, self.percent_dense
+        d.scene_extent, d.min_opacity, d.split_scale = (self.scene_extent, self.min_opacity,
+                                                        self.split_scale)
+        return d
+
+
+def densify_stats(cams, n, rp, workspace, pair_capacity, grad_sum, count, d_gate=None,
+                  stream=None):
+    _check(LIB.sgs_densify_stats(cameras_c(cams), len(cams), int(n), C.byref(rp.c()),
+                                 _ptr(workspace), workspace.numel(), pair_capacity, _ptr(d_gate),
+                                 _ptr(grad_sum), _ptr(count), _stream(stream)))
+
+
+def densify_workspace_size(n: int) -> int:
+    out = C.c_size_t()
+    _check(LIB.sgs_densify_workspace_size(int(n), C.byref(out)))
+    return out.value
+
+
+def densify(p: DensifyParams, planes, n, sh_degree, m, v, grad_sum, count, normals, out_params,
+            out_m, out_v, workspace, d_n_out, stream=None):
+    """One clone / split / prune step into the output planes ([F][out_stride]);
+    the new set's size goes to d_n_out (device int64[1])."""
+    g = gaussians_c(planes, n, sh_degree)
+    _check(LIB.sgs_densify(C.byref(p.c()), C.byref(g), _ptr(m), _ptr(v), _ptr(grad_sum),
+                           _ptr(count), _ptr(normals), _ptr(out_params), _ptr(out_m), _ptr(out_v),
+                           int(out_params.shape[1]), _ptr(workspace), workspace.numel(),
+                           _ptr(d_n_out), _stream(stream)))
 
 
 def default_lrs(sh_degree: int, means_lr: float = 1.6e-4) -> tuple:

@@ -55,22 +55,28 @@ class Trainer:
     replayed); ``iteration()`` calls the stages one by one, with optional
     HIP events between them, for the stage breakdown."""
 
-    def __init__(self, init: S.Scene, cams, targets: torch.Tensor, rp: sk.RasterParams,
+    def __init__(self, init: S.Scene | None, cams, targets: torch.Tensor, rp: sk.RasterParams,
                  gate: sk.GateParams | None, capacity: int, lrs=None, gated: bool = True,
-                 fused: bool = True, sequence=None, visible_only: bool = False, device="cuda"):
+                 fused: bool = True, sequence=None, visible_only: bool = False, device="cuda",
+                 state=None):
+        """state: (planes, m, v, step_count, n, sh_degree) device tensors to
+        continue from (a set produced by densification) instead of ``init``."""
         self.dev = torch.device(device)
         self.cams = list(cams)
         self.rp = rp
-        self.n = init.n
-        self.deg = init.sh_degree
         self.cap = int(capacity)
         self.gated = gated
         self.fused = fused
-        self.planes = torch.as_tensor(init.to_planes()).to(self.dev)
+        if state is None:
+            self.n = init.n
+            self.deg = init.sh_degree
+            self.planes = torch.as_tensor(init.to_planes()).to(self.dev)
+            self.m = torch.zeros_like(self.planes)
+            self.v = torch.zeros_like(self.planes)
+            self.step_count = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        else:
+            self.planes, self.m, self.v, self.step_count, self.n, self.deg = state
         self.grads = torch.zeros_like(self.planes)
-        self.m = torch.zeros_like(self.planes)
-        self.v = torch.zeros_like(self.planes)
-        self.step_count = torch.zeros(1, dtype=torch.int32, device=self.dev)
         self.adam = sk.AdamParams(lr=lrs or sk.default_lrs(self.deg), visible_only=visible_only)
         self.targets = targets            # [views][3 H W]
         W, H = self.cams[0].width, self.cams[0].height
@@ -230,3 +236,73 @@ def measure_capacity(scene: S.Scene, cams, rp, device="cuda", probe_capacity=1 <
         best = max(best, need)
     del ws, planes, out
     return best
+
+
+def densify_step(tr: Trainer, dp: sk.DensifyParams, grad_sum: torch.Tensor, count: torch.Tensor,
+                 rng: np.random.Generator):
+    """One clone / split / prune step of the trainer's set (adaptive density
+    control, Sec. 3). Returns (planes, m, v, n) of the new set with a padded
+    stride; every Gaussian yields at most two, so the output cannot overflow."""
+    n, F = tr.n, tr.F
+    normals = torch.as_tensor(rng.standard_normal((max(n, 1), 2, 3)), dtype=torch.float32,
+                              device=tr.dev)
+    cap = S.padded_stride(max(2 * n, 1))
+    outs = [torch.empty(F, cap, device=tr.dev) for _ in range(3)]
+    ws = sk.alloc_bytes(sk.densify_workspace_size(n))
+    d_n = torch.zeros(1, dtype=torch.int64, device=tr.dev)
+    sk.densify(dp, tr.planes, n, tr.deg, tr.m, tr.v, grad_sum, count, normals, *outs, ws, d_n)
+    n_new = int(d_n.item())
+    stride = S.padded_stride(max(n_new, 1))
+    planes, m, v = (torch.zeros(F, stride, device=tr.dev) for _ in range(3))
+    for dst, src in zip((planes, m, v), outs):
+        dst[:, :n_new] = src[:, :n_new]
+    return planes, m, v, n_new
+
+
+def train_two_phase(init: S.Scene, cams, targets: torch.Tensor, rp: sk.RasterParams,
+                    gate: sk.GateParams, dp: sk.DensifyParams, densify_until: int,
+                    densify_every: int, post_iters: int, sequence, capacity_per_gaussian: int = 64,
+                    seed: int = 0, log=None) -> dict:
+    """Two-phase training (Sec. 3): full-backward iterations with the
+    view-space gradient statistic gathered after every backward and a clone /
+    split / prune step every ``densify_every`` iterations until
+    ``densify_until`` (T_d); from then on the set is fixed and the SkipGS gate
+    decides every backward (Algorithm 1), starting at t = 1. ``sequence``: the
+    view of every iteration (both phases)."""
+    rng = np.random.default_rng(seed)
+    seq = np.asarray(sequence, np.int64)
+    counts = [init.n]
+
+    def make(state, gated, seq_part):
+        n = init.n if state is None else state[4]
+        return Trainer(init if state is None else None, cams, targets, rp, gate if gated else None,
+                       max(4096, capacity_per_gaussian * n), gated=gated, sequence=seq_part,
+                       state=state)
+
+    tr = make(None, False, seq[:1])
+    gs = torch.zeros(tr.n, device=tr.dev)
+    cnt = torch.zeros(tr.n, dtype=torch.int32, device=tr.dev)
+    d_view = torch.zeros(1, dtype=torch.int32, device=tr.dev)
+    slot = torch.zeros(1, dtype=torch.int32, device=tr.dev)
+    for t in range(densify_until):
+        v = int(seq[t])
+        d_view.fill_(v)
+        tr.iteration(v, d_view, slot)
+        sk.densify_stats([cams[v]], tr.n, rp, tr.ws, tr.cap, gs, cnt)
+        if (t + 1) % densify_every == 0:
+            planes, m, vv, n_new = densify_step(tr, dp, gs, cnt, rng)
+            if log is not None:
+                log(f"densify at {t + 1}: {tr.n} -> {n_new}")
+            tr = make((planes, m, vv, tr.step_count, n_new, tr.deg), False, seq[:1])
+            gs = torch.zeros(n_new, device=tr.dev)
+            cnt = torch.zeros(n_new, dtype=torch.int32, device=tr.dev)
+            counts.append(n_new)
+    flags, _, _ = tr.status()
+    post = make((tr.planes, tr.m, tr.v, tr.step_count, tr.n, tr.deg), True,
+                seq[densify_until:densify_until + post_iters])
+    for _ in range(post_iters):
+        post.step()
+    torch.cuda.synchronize()
+    b, t_seen = post.backward_count()
+    return {"counts": counts, "n": post.n, "status_densify": flags, "status_post": post.status()[0],
+            "post_backward": b, "post_iterations": t_seen, "trainer": post}

@@ -233,3 +233,31 @@ def test_static_loss_rejects_before_enqueueing():
     assert "static scratch" in sg.LIB.sgs_last_error().decode()
     assert sg.LIB.sgs_photometric_loss_static(None, p, 64, 64, C.c_float(0.2), p, None) == 1
     assert sg.LIB.sgs_photometric_loss_static(p, p, 64, 64, C.c_float(1.5), p, None) == 1
+
+
+def test_densify_params_and_workspace():
+    """Densification arguments are validated on the host before anything is
+    enqueued (no device memory is touched here)."""
+    m = _lib()
+    assert m.densify_workspace_size(0) == 12
+    assert m.densify_workspace_size(1000) == 4 * (4 * 4 + 3)
+    d = m.DensifyParamsC()
+    m.LIB.sgs_default_densify_params(C.byref(d))
+    assert d.struct_size == C.sizeof(m.DensifyParamsC)
+    assert abs(d.grad_threshold - 2e-4) < 1e-9 and abs(d.split_scale - 1.6) < 1e-6
+    g = m.GaussiansC()
+    g.struct_size = C.sizeof(m.GaussiansC)
+    g.n, g.stride, g.sh_degree, g.data = 10, 64, 0, 256
+    dummy = C.c_void_p(256)
+    for bad in (dict(struct_size=3), dict(min_opacity=1.0), dict(scene_extent=0.0),
+                dict(split_scale=-1.0)):
+        p = m.DensifyParams().c()
+        for k, val in bad.items():
+            setattr(p, k, val)
+        rc = m.LIB.sgs_densify(C.byref(p), C.byref(g), dummy, dummy, dummy, dummy, dummy,
+                               dummy, dummy, dummy, 64, dummy, 1 << 20, dummy, None)
+        assert rc != 0, bad
+    p = m.DensifyParams().c()
+    rc = m.LIB.sgs_densify(C.byref(p), C.byref(g), dummy, dummy, dummy, dummy, dummy,
+                           dummy, dummy, dummy, 100, dummy, 1 << 20, dummy, None)   # stride % 64
+    assert rc != 0
