@@ -444,8 +444,9 @@ def run_train(args):
     full = results.get("full")
     if full and head != "full":
         out["full_iters_per_s"] = full["iters_per_s"]
-        out["gated_over_full"] = headline["iters_per_s"] / full["iters_per_s"]
         if out["skip_fraction"] > 0:
+            # only when the gate actually skipped in the timed run
+            out["gated_over_full"] = headline["iters_per_s"] / full["iters_per_s"]
             n_it = headline["iterations_before_timing"] + args.steps
             out["equal_iteration_loss"] = {
                 "iterations": n_it, "gated": headline["final_mean_loss"],
