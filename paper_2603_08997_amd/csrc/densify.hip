@@ -65,6 +65,13 @@ __global__ void __launch_bounds__(256) densify_stats_kernel(
     }
 }
 
+// Output stores through L2 with the default policy: the outputs of a wave
+// start at arbitrary positions, so their cache lines are filled by several
+// waves and are best merged in L2 before they go to HBM.
+__device__ __forceinline__ void put(const PlaneBuf& B, int j, uint32_t lane_off, float x) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), B.rsrc(j), (int)lane_off, 0, 0);
+}
+
 __device__ __forceinline__ uint32_t outcome(const PlaneBuf& P, uint32_t off, float g, int32_t c,
                                             const DensifyDev& d) {
     const float logit = P.load(10, off);
@@ -157,14 +164,14 @@ __global__ void __launch_bounds__(kDensifyThreads) densify_write_kernel(
                 const int f = f0 + k;
                 if (f >= F) break;
                 if (keep) {
-                    PO.store(f, pk * 4u, x[k]);
-                    MO.store(f, pk * 4u, mm[k]);
-                    VO.store(f, pk * 4u, vv[k]);
+                    put(PO, f, pk * 4u, x[k]);
+                    put(MO, f, pk * 4u, mm[k]);
+                    put(VO, f, pk * 4u, vv[k]);
                 }
                 if (clone) {
-                    PO.store(f, pc * 4u, x[k]);
-                    MO.store(f, pc * 4u, 0.f);
-                    VO.store(f, pc * 4u, 0.f);
+                    put(PO, f, pc * 4u, x[k]);
+                    put(MO, f, pc * 4u, 0.f);
+                    put(VO, f, pc * 4u, 0.f);
                 }
             }
         }
@@ -189,13 +196,13 @@ __global__ void __launch_bounds__(kDensifyThreads) densify_write_kernel(
             const float t[3] = {s[0] * zj[0], s[1] * zj[1], s[2] * zj[2]};
 #pragma unroll
             for (int r = 0; r < 3; ++r)
-                PO.store(r, po, mu[r] + (R[3 * r] * t[0] + R[3 * r + 1] * t[1] + R[3 * r + 2] * t[2]));
+                put(PO, r, po, mu[r] + (R[3 * r] * t[0] + R[3 * r + 1] * t[1] + R[3 * r + 2] * t[2]));
 #pragma unroll
-            for (int k = 0; k < 3; ++k) PO.store(3 + k, po, P.load(3 + k, off) - d.log_split);
-            for (int f = 6; f < F; ++f) PO.store(f, po, P.load(f, off));
+            for (int k = 0; k < 3; ++k) put(PO, 3 + k, po, P.load(3 + k, off) - d.log_split);
+            for (int f = 6; f < F; ++f) put(PO, f, po, P.load(f, off));
             for (int f = 0; f < F; ++f) {
-                MO.store(f, po, 0.f);
-                VO.store(f, po, 0.f);
+                put(MO, f, po, 0.f);
+                put(VO, f, po, 0.f);
             }
         }
     }
