@@ -18,6 +18,13 @@
 // its depth-ordered list of entries whose overlap box reaches it and that can
 // reach alpha_min on it; the sort never sees the (far more numerous) tile
 // pairs.
+//
+// A tile composites only the front of its list, so a long super-tile list is
+// split only in a prefix of its segments before compositing (a tile's list is
+// then a prefix of its whole list). The compositing marks the tiles whose
+// prefix ran out while pixels were still live; the completing split then
+// splits the whole lists of their super-tiles after the prefix lists and
+// points those tiles' ranges there, and the compositing resumes them.
 #include <algorithm>
 
 #include "sgs_internal.hpp"
@@ -678,13 +685,43 @@ __device__ __forceinline__ void band_columns(const Reach& R, float u, float v, f
 // pair's tile rectangle and, with alpha_min > 0, the entry can reach alpha_min
 // on the tile's pixels in the image (row by row of the rectangle: the tile
 // columns of each row band the entry reaches).
+//
+// With `local` (at most kLocalSupers super-tiles) every workgroup first forms
+// the segment index (the exclusive scan of src over the super-tiles) in LDS,
+// and workgroup 0 also stores it for the kernels after this one, which saves
+// the scan's own launch; otherwise seg_first holds it already.
+constexpr int kLocalSupers = 1024;
+template <class Src>
 __global__ void __launch_bounds__(kSplitWaves * 64) split_count_kernel(
-    const Views* __restrict__ views, RasterDev rp, const uint32_t* __restrict__ seg_first,
-    const uint32_t* __restrict__ sup_ranges, const uint32_t* __restrict__ skey,
-    const uint32_t* __restrict__ sentry, const float4* __restrict__ rec, uint32_t entries,
-    uint64_t* __restrict__ mask, uint32_t* __restrict__ seg_cnt) {
+    const Views* __restrict__ views, RasterDev rp, Src src, bool local,
+    uint32_t* __restrict__ seg_first_g, const uint32_t* __restrict__ sup_ranges,
+    const uint32_t* __restrict__ skey, const uint32_t* __restrict__ sentry,
+    const float4* __restrict__ rec, uint32_t entries, uint64_t* __restrict__ mask,
+    uint32_t* __restrict__ seg_cnt) {
+    constexpr int NT = kSplitWaves * 64;
+    __shared__ uint32_t s_first[kLocalSupers + 1];
+    __shared__ uint32_t s_scan[NT / 64 + 1];
     const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int S = rp.super_tile, TT = S * S;
+    const uint32_t* seg_first = seg_first_g;
+    if (local) {   // uniform
+        const int ns = views->total_supers;
+        const bool on = src.count() > 0;
+        uint32_t carry = 0;
+        for (int s0 = 0; s0 < ns; s0 += NT) {
+            const int s = s0 + (int)threadIdx.x;
+            const uint32_t v = (on && s < ns) ? src(s) : 0u;
+            uint32_t tot;
+            const uint32_t ex = sat_add(carry, block_excl_sat_scan<NT>(v, s_scan, &tot));
+            if (s < ns) s_first[s] = ex;
+            carry = sat_add(carry, tot);
+        }
+        if (threadIdx.x == 0) s_first[ns] = carry;
+        __syncthreads();
+        if (blockIdx.x == 0)
+            for (int s = threadIdx.x; s <= ns; s += NT) seg_first_g[s] = s_first[s];
+        seg_first = s_first;
+    }
     // segments in a grid-stride loop (the grid is sized for the machine, not
     // for the capacity's bound on the segment count)
     for (uint32_t g = blockIdx.x * kSplitWaves + w;; g += gridDim.x * kSplitWaves) {
@@ -879,15 +916,20 @@ static hipError_t launch_split(const RasterDev& rp, const Layout& L, char* ws, h
     uint32_t* sums = reinterpret_cast<uint32_t*>(ws + L.scan_sums);
     const int tt = rp.super_tile * rp.super_tile;
     hipError_t err;
-    // segments to split; their total -> seg_first[total_supers]
-    if (rest)
-        hipLaunchKernelGGL(seg_scan_kernel<RestSegSrc>, dim3(1), dim3(kSegScanThreads), 0, s,
-                           RestSegSrc{ranges, sup_redo, counters + kRedo, L.total_supers},
-                           seg_first);
-    else
-        hipLaunchKernelGGL(seg_scan_kernel<SegCountSrc>, dim3(1), dim3(kSegScanThreads), 0, s,
-                           SegCountSrc{ranges, L.total_supers, (uint32_t)rp.prefix_segs}, seg_first);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
+    // segments to split; their total -> seg_first[total_supers] (formed by
+    // the count kernel itself when the super-tiles are few)
+    const RestSegSrc rsrc{ranges, sup_redo, counters + kRedo, L.total_supers};
+    const SegCountSrc psrc{ranges, L.total_supers, (uint32_t)rp.prefix_segs};
+    const bool local = L.total_supers <= kLocalSupers;
+    if (!local) {
+        if (rest)
+            hipLaunchKernelGGL(seg_scan_kernel<RestSegSrc>, dim3(1), dim3(kSegScanThreads), 0, s,
+                               rsrc, seg_first);
+        else
+            hipLaunchKernelGGL(seg_scan_kernel<SegCountSrc>, dim3(1), dim3(kSegScanThreads), 0, s,
+                               psrc, seg_first);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+    }
     // grid-stride over the segments: at most a few resident waves per SIMD
     // (the completing split, usually idle and otherwise a few super-tiles,
     // on a quarter of the grid)
@@ -895,8 +937,14 @@ static hipError_t launch_split(const RasterDev& rp, const Layout& L, char* ws, h
     const dim3 sgrid((unsigned)std::min<int64_t>((L.seg_slots + kSplitWaves - 1) / kSplitWaves,
                                                  blocks));
     const uint32_t entries = (uint32_t)std::max<int64_t>(1, L.entries);
-    hipLaunchKernelGGL(split_count_kernel, sgrid, dim3(kSplitWaves * 64), 0, s, views, rp,
-                       seg_first, ranges, skey, sentry, rec, entries, mask, seg_cnt);
+    if (rest)
+        hipLaunchKernelGGL(split_count_kernel<RestSegSrc>, sgrid, dim3(kSplitWaves * 64), 0, s,
+                           views, rp, rsrc, local, seg_first, ranges, skey, sentry, rec, entries,
+                           mask, seg_cnt);
+    else
+        hipLaunchKernelGGL(split_count_kernel<SegCountSrc>, sgrid, dim3(kSplitWaves * 64), 0, s,
+                           views, rp, psrc, local, seg_first, ranges, skey, sentry, rec, entries,
+                           mask, seg_cnt);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     // list positions (the completing split's after the prefix lists); the
     // number of entries -> counters[kItems] or counters[kItemsRest]
