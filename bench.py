@@ -8,6 +8,7 @@ and the FP64 oracle timed on the host as a CPU reference.
     python bench.py --workload dense       # 6M dense scene: backward GB/s, peak memory
     python bench.py --workload batched     # 8 mixed-resolution views per launch
     python bench.py --workload densify     # clone / split / prune step and its statistic
+    python bench.py --workload atomics     # scattered FP32 atomic-add ceiling
 
 Workload (defaults): 3,000,000 Gaussians (SH degree 3, ground-plane + two
 clusters), 200 views at 1600x1060 on a hemisphere of radius 4-5, 16x16 tiles,
@@ -94,7 +95,7 @@ def parse():
     ap.add_argument("--retune", action="store_true",
                     help="batched workload: tune again even if a stored choice exists")
     ap.add_argument("--workload", choices=["train", "matched", "single", "dense", "batched",
-                                           "densify"],
+                                           "densify", "atomics"],
                     default="train")
     return ap.parse_args()
 
@@ -757,6 +758,38 @@ def run_densify(args):
     print(json.dumps(out), flush=True)
 
 
+def run_atomics(args):
+    """FP32 atomic-add throughput on the compositing backward's accumulator
+    shape, as a ceiling for its atomics: 3M entries x 12 floats, 1.03M
+    scattered rows of 9 floats added per launch (one list entry walked per
+    row, the backward's per-view count), through torch's index_add_ (one
+    float atomic per element on this device)."""
+    n_entries, rows, width = args.n, 1_030_000, 9
+    acc = torch.zeros(n_entries, width, device="cuda")
+    g = torch.Generator(device="cuda").manual_seed(5)
+    idx = torch.randint(0, n_entries, (rows,), device="cuda", generator=g)
+    src = torch.rand(rows, width, device="cuda", generator=g)
+    steps = args.steps if args.steps is not None else 50
+    for _ in range(3):
+        acc.index_add_(0, idx, src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        acc.index_add_(0, idx, src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    rate = rows * width / (ms * 1e-3)
+    out = {"metric": "scattered FP32 atomic-add throughput", "value": rate / 1e9,
+           "unit": "G float atomics/s", "n_gpus": 1, "steps": steps, "warmup": 3,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"index_add_ of {rows} random rows of {width} floats into a "
+                                  f"{n_entries} x {width} float32 array"}}
+    print(json.dumps(out), flush=True)
+
+
 def run_batched(args):
     """Forward + backward of eight views of four resolutions (two each of
     640x480, 1245x825, 1600x1060, 980x545) of 2M Gaussians, gradients summed
@@ -896,6 +929,8 @@ def main():
         return run_dense(args)
     if args.workload == "densify":
         return run_densify(args)
+    if args.workload == "atomics":
+        return run_atomics(args)
     if args.steps is None:
         args.steps = 2000
     if args.warmup is None:
