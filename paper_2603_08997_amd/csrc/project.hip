@@ -453,11 +453,15 @@ __device__ __forceinline__ void gaussian_backward(float* __restrict__ planes, in
                                                   float* __restrict__ v) {
     constexpr int K = (sh_degree + 1) * (sh_degree + 1);
     constexpr int NP = 11 + 3 * K;
+    // the visible-only step updates a scattered subset of each wave's lines:
+    // its accesses go through L2, where the partly written lines meet the
+    // full lines its loads brought in; the dense step streams every line
+    constexpr int kPlaneCP = kSparse ? 0 : SGS_PLANE_CPOL;
     const PlaneBuf P{planes, stride}, M{m, stride}, Vb{v, stride}, G{grads, stride};
     const uint32_t off = (uint32_t)i * 4u;
     float p[NP];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) p[j] = P.load(j, off);
+    for (int j = 0; j < NP; ++j) p[j] = P.template load<kPlaneCP>(j, off);
     const float* mu = p;
     const float* ls = p + 3;
     const float* q = p + 6;
@@ -511,8 +515,8 @@ __device__ __forceinline__ void gaussian_backward(float* __restrict__ planes, in
             const int j = b * B + t;
             if (j < NP) {
                 if constexpr (kFused) {
-                    ma[buf][t] = M.load(j, off);
-                    va[buf][t] = Vb.load(j, off);
+                    ma[buf][t] = M.template load<kPlaneCP>(j, off);
+                    va[buf][t] = Vb.template load<kPlaneCP>(j, off);
                 } else {
                     ma[buf][t] = G.load(j, off);
                 }
@@ -531,9 +535,9 @@ __device__ __forceinline__ void gaussian_backward(float* __restrict__ planes, in
                 if constexpr (kFused) {
                     float pj = p[j], mm = ma[b & 1][t], vv = va[b & 1][t];
                     adam_update(gj, pj, mm, vv, ad->lr[j], *ad, *as);
-                    P.store(j, off, pj);
-                    M.store(j, off, mm);
-                    Vb.store(j, off, vv);
+                    P.template store<kPlaneCP>(j, off, pj);
+                    M.template store<kPlaneCP>(j, off, mm);
+                    Vb.template store<kPlaneCP>(j, off, vv);
                 } else {
                     G.store(j, off, ma[b & 1][t] + gj);
                 }

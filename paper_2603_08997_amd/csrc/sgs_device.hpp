@@ -120,13 +120,16 @@ struct PlaneBuf {
         return __builtin_amdgcn_make_buffer_rsrc(b + (int64_t)j * stride, (short)0,
                                                  (int)(stride * 4), 0x00020000);
     }
+    // CP: cache policy of the access (the streaming default, or 0 where the
+    // lanes of a wave touch a line only in part and the line is best merged
+    // in L2)
+    template <int CP = SGS_PLANE_CPOL>
     __device__ __forceinline__ float load(int j, uint32_t lane_off) const {
-        return __uint_as_float(
-            __builtin_amdgcn_raw_buffer_load_b32(rsrc(j), (int)lane_off, 0, SGS_PLANE_CPOL));
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsrc(j), (int)lane_off, 0, CP));
     }
+    template <int CP = SGS_PLANE_CPOL>
     __device__ __forceinline__ void store(int j, uint32_t lane_off, float x) const {
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), rsrc(j), (int)lane_off, 0,
-                                              SGS_PLANE_CPOL);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), rsrc(j), (int)lane_off, 0, CP);
     }
 };
 
