@@ -380,11 +380,11 @@ sgs_status sgs_gate_read(const sgs_gate_params* p, const void* d_state,
                          void* stream);
 
 /* ---------------------------------------------------------------------------
- * Adaptive density control of the densification phase (Sec. 3): before T_d
- * Gaussians are periodically cloned (high view-space positional gradient,
- * small extent), split (high gradient, large extent) and pruned (opacity
- * below a small threshold); from T_d on the set is fixed and the gate of
- * Algorithm 1 takes over.
+ * Adaptive density control of the densification phase (Sec. 3): until T_d,
+ * every few iterations, a Gaussian whose screen position receives a large
+ * gradient is copied when it is small and replaced by two smaller ones when it
+ * is large, and one that is nearly transparent is removed; after T_d the set
+ * stays fixed and the gate of Algorithm 1 decides every backward pass.
  *
  * Statistic (sgs_densify_stats, after a render backward): for every
  * Gaussian visible in a view of the batch, || (dL/du W/2, dL/dv H/2) || (the

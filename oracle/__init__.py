@@ -8,8 +8,8 @@ from the seeded input generators, which hold none of the method's arithmetic.
 The oracle is a plain, slow statement of what the method computes:
 
 * ``render``  - 3D Gaussian density and covariance factorisation (Sec. 3,
-  Eqs. 1-2), EWA projection (Eq. 3), front-to-back compositing over the
-  depth-sorted Gaussians overlapping a pixel (Eqs. 4-5), SH colour, tile
+  Eqs. 1-2), EWA projection (Eq. 3), front-to-back compositing, in depth
+  order, of the Gaussians that cover a pixel (Eqs. 4-5), SH colour, tile
   binning as the order-defining step.
 * ``loss``    - the photometric loss (1-lambda) L1 + lambda (1 - SSIM), Eq. 6.
 * ``gate``    - SkipGS backward gating, Algorithm 1 with Eqs. 7-13.

@@ -2,8 +2,8 @@
 infrastructure only.
 
 Sec. 4 of the paper (Algorithm 1; Eqs. 7-13) gates the backward pass of each
-post-densification iteration t (t = 1 at the first iteration after
-densification stops). Here the gate is split into what it observes, what it
+post-densification iteration t, counted from t = 1 once densification has
+ended. Here the gate is split into what it observes, what it
 decides and how its state moves:
 
 * observation: the per-view deviation score of Eq. 8 against the EMA held

@@ -3,10 +3,11 @@
 Follows Sec. 3 of the paper: Gaussian density (Eq. 1), covariance
 factorisation Sigma = R S S^T R^T (Eq. 2), EWA projection
 Sigma2D = J W Sigma W^T J^T (Eq. 3), and front-to-back compositing
-C(p) = sum_i c_i alpha'_i T_i with T_i = prod_{j<i} (1 - alpha'_j) (Eq. 4) over
-the depth-sorted Gaussians overlapping p, with the effective opacity
-alpha'_i = alpha_i exp(-1/2 dp^T (Sigma2D)^-1 dp) (Eq. 5). The colour c_i is
-the SH-evaluated colour for the view direction (Sec. 3).
+C(p) = sum_i c_i alpha'_i T_i with T_i = prod_{j<i} (1 - alpha'_j) (Eq. 4), i
+running in depth order over the Gaussians that cover p, with the effective
+opacity alpha'_i = alpha_i exp(-1/2 dp^T (Sigma2D)^-1 dp) (Eq. 5); c_i is the
+spherical-harmonic expansion of Gaussian i evaluated at the viewing direction
+(Sec. 3).
 
 The paper leaves the camera model, culling, the screen-space low-pass, the
 cut-off radius, the SH basis, the overlap rule and the opacity/transmittance
