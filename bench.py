@@ -103,7 +103,7 @@ def parse():
 # ---------------------------------------------------------------------------
 # CPU baseline: the FP64 oracle on the host
 # ---------------------------------------------------------------------------
-def cpu_baseline(gt, init, cam, crop=24):
+def cpu_baseline(gt, init, cam, crop=64):
     """The FP64 oracle on a bounded sample of one training iteration of the
     benchmark workload: the projection of all Gaussians (forward and, once,
     backward) plus compositing, loss and backward of a crop x crop window at
